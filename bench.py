@@ -1,0 +1,195 @@
+#!/usr/bin/env python3
+"""Benchmark of the LiDAR bundle-adjustment hot path on one MI355X.
+
+A step is one complete LM solve of the single-window workload (500 scans on a
+2 km figure-eight, 200k planar voxels, 1..20 observers per voxel, 20..500
+points per observation, 20 LM iterations; synthetic, seeded): every
+iteration evaluates all voxel residuals at the trial poses, the surrogate
+gradient and Hessian at accepted poses, and solves the damped increment, all
+on the device.  The problem (clusters and plan) is built once before the
+timed region from device-resident points; its build time is reported apart.
+
+Prints one JSON line.  Progress goes to stderr.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0           # MI355X HBM3E, 8 TB/s
+CLUSTER_BYTES = 8 + 24 + 48 + 4  # N (f64), mu (3 f64), S (6 f64), scan or slot id (i32)
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def make_scene(workload: str):
+    import scenes
+    if workload == "window":
+        return scenes.window_config(seed=2000)
+    if workload == "tiny":
+        return scenes.tiny_config(seed=1000)
+    raise SystemExit(f"unknown workload {workload}")
+
+
+def cpu_baseline(sc, mode_name: str, iters: int):
+    """The FP64 oracle, single thread, on `iters` LM iterations of the same problem."""
+    import oracle
+    t0 = time.perf_counter()
+    cl = oracle.scene_clusters(sc)
+    t_build = time.perf_counter() - t0
+    mode = oracle.MM if mode_name == "mm" else oracle.COUPLED
+    t0 = time.perf_counter()
+    _, rep, _ = oracle.lm(mode, cl, sc.poses_init, iters)
+    dt = time.perf_counter() - t0
+    return dt, rep, t_build
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--iters", type=int, default=20, help="LM iterations per solve")
+    ap.add_argument("--mode", choices=["mm", "coupled"], default="mm")
+    ap.add_argument("--workload", choices=["window", "tiny"], default="window")
+    ap.add_argument("--cpu-iters", type=int, default=2, help="oracle LM iterations timed for cpu_baseline")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(see the sharding design notes); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import paper_2608_14266_amd as ba
+    from paper_2608_14266_amd import build as hb
+
+    if not os.path.exists(hb.LIB):
+        log("libba not built; building")
+        hb.build()
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+
+    t0 = time.perf_counter()
+    sc = make_scene(args.workload)
+    log(f"scene {sc.name}: {sc.n_points} points, {sc.n_clusters} clusters, generated in "
+        f"{time.perf_counter() - t0:.1f}s")
+    f = lambda a, dt: torch.as_tensor(np.ascontiguousarray(a), dtype=dt, device=dev)
+    xs, ys, zs = f(sc.x, torch.float64), f(sc.y, torch.float64), f(sc.z, torch.float64)
+    scan, vox = f(sc.scan, torch.int32), f(sc.voxel, torch.int32)
+    torch.cuda.synchronize()
+    # build once (a0), timed apart: several repeats, best reported
+    build_ms = []
+    prob = None
+    for _ in range(3):
+        if prob is not None:
+            prob.close()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        prob = ba.build_clusters(xs, ys, zs, scan, vox, sc.n_scans, sc.n_voxels)
+        torch.cuda.synchronize()
+        build_ms.append(1e3 * (time.perf_counter() - t0))
+    info = prob.info()
+    V, C, N = info["n_voxels"], info["n_clusters"], info["n_scans"]
+    log(f"built: {V} voxels, {C} clusters, {info['n_wave_groups']} wave groups, "
+        f"{info['n_pose_chunks']} pose chunks, build {min(build_ms):.1f} ms")
+    mode = ba.MODE_MM if args.mode == "mm" else ba.MODE_COUPLED
+    P0 = f(sc.poses_init, torch.float64)
+    P = P0.clone().contiguous()
+
+    def step():
+        P.copy_(P0)
+        reps, _ = ba.iterate(prob, P, mode, max_iters=args.iters, trace=False)
+        return reps
+
+    for w in range(args.warmup):
+        step()
+        log(f"warmup {w + 1}/{args.warmup}")
+    torch.cuda.synchronize()
+    ba.profile_reset()
+    ba.profile_enable(True)
+    t0 = time.perf_counter()
+    reps = None
+    for k in range(args.steps):
+        reps = step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ba.profile_enable(False)
+    vox_ms, vox_n = ba.profile_query("k_vox")
+    pose_ms, pose_n = ba.profile_query("k_pose")
+    ba.profile_reset()
+    elapsed = t1 - t0
+    ms_per_step = 1e3 * elapsed / args.steps
+    evals = V * args.iters * args.steps
+    value = evals / elapsed
+    lm_iters_s = args.iters * args.steps / elapsed
+    log(f"timed {args.steps} solves: {ms_per_step:.3f} ms/solve, cost {reps[0]['cost_initial']:.6e} -> "
+        f"{reps[0]['cost_final']:.6e}, accepted {reps[0]['n_accepted']}/{reps[0]['iters']}")
+
+    # roofline of the dominant kernel (algorithmic bytes / measured launch time)
+    n_groups, n_chunks = info["n_wave_groups"], info["n_pose_chunks"]
+    vox_bytes = C * CLUSTER_BYTES + V * 64 + N * 96 + n_groups * 8
+    pose_bytes = C * CLUSTER_BYTES + V * 56 + N * 96 + n_chunks * 27 * 8
+    # k_pose launches that did work: one per accepted iteration plus the start and final ones
+    pose_work = args.steps * (reps[0]["n_accepted"] + 1)
+    kern = {
+        "k_vox": dict(avg_us=1e3 * vox_ms / max(vox_n, 1), launches=vox_n, bytes=vox_bytes),
+        "k_pose": dict(avg_us=1e3 * pose_ms / max(pose_n, 1), launches=pose_n, bytes=pose_bytes,
+                       launches_with_work=pose_work),
+    }
+    for k, d in kern.items():
+        d["gbs"] = d["bytes"] / (d["avg_us"] * 1e-6) / 1e9 if d["avg_us"] > 0 else 0.0
+    dom = max(kern, key=lambda k: kern[k]["avg_us"] * kern[k]["launches"])
+    roof = {"kernel": dom, "bound": "hbm", "achieved": round(kern[dom]["gbs"], 2), "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": round(kern[dom]["gbs"] / HBM_PEAK_GBS, 4), "traffic": None,
+            "bytes_per_launch": kern[dom]["bytes"], "avg_launch_us": round(kern[dom]["avg_us"], 3)}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log(f"cpu baseline: oracle, {args.cpu_iters} LM iterations")
+        dt, rep, tb = cpu_baseline(sc, args.mode, args.cpu_iters)
+        cpu = {"value": V * args.cpu_iters / dt, "unit": "plane-voxel evals/s", "cores": 1, "kind": "oracle",
+               "sample": f"{args.cpu_iters} LM iterations ({args.mode}) of the full {sc.name} problem, "
+                         f"single thread, FP64; cluster build ({tb:.1f}s) untimed",
+               "seconds": round(dt, 3)}
+        log(f"cpu baseline {cpu['value']:.4g} evals/s ({dt:.2f}s)")
+
+    out = {
+        "metric": "plane-voxel evals/s",
+        "value": value,
+        "unit": "plane-voxel evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"{sc.name} ({args.mode}, {args.iters} LM iterations per step)",
+                   "poses": N, "voxels": V, "clusters": C, "points": sc.n_points, "lm_iters": args.iters,
+                   "mode": args.mode},
+        "lm_iters_per_s": lm_iters_s,
+        "build_ms": round(min(build_ms), 3),
+        "kernels": {k: {kk: (round(vv, 3) if isinstance(vv, float) else vv) for kk, vv in d.items()}
+                    for k, d in kern.items()},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "final_cost": reps[0]["cost_final"],
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

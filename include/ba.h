@@ -1,0 +1,226 @@
+/*
+ * libba: one Levenberg-Marquardt iteration of majorization-minimization LiDAR
+ * bundle adjustment on an AMD MI355X (gfx950).
+ *
+ * Method: Cai et al., "Accelerating Large-scale Bundle Adjustment for LiDAR
+ * Mapping via Parallel Computing".  Sec. III states the problem: scan poses
+ * T_j = (R_j, t_j) in SE(3), planar voxels i observed by scans j through point
+ * clusters (N_ij, sum p, sum p p^T) (Eq. 2), the cost
+ *     c(T) = sum_i lambda_min( P_i/N_i - v_i v_i^T / N_i^2 )          (Eq. 1)
+ * and the MM surrogate of Eq. 3 that decouples the poses.  Sec. IV-C / Alg. 2
+ * gives one iteration: residual (CalRes), Jacobian and Hessian per cluster
+ * reduced by pose (CalJH), and a damped per-pose increment solve (Solver).
+ *
+ * Conventions shared by every entry point
+ *   - Memory: array arguments marked "device" are device pointers owned by
+ *     the caller (e.g. PyTorch tensors); "host" arrays are host memory.  A
+ *     ba_problem owns the device-resident clusters and plan it builds; it is
+ *     released by ba_problem_destroy.
+ *   - Streams: work is enqueued on the given hipStream_t (0 = null stream).
+ *     Calls marked "synchronous" return after the stream has drained.
+ *   - Errors: every call returns a ba_status; BA_OK == 0, errors are
+ *     negative.  No call aborts; ba_last_error() returns a thread-local text.
+ *   - Pose layout: 12 doubles per scan, [R00 R01 R02 R10 R11 R12 R20 R21 R22
+ *     t0 t1 t2] (row-major rotation, then translation); a point p of scan j
+ *     maps to the world as R_j p + t_j.
+ *   - Increment layout: 6 doubles per scan, [phi0 phi1 phi2 dt0 dt1 dt2] in
+ *     the chart T (+) x = (Exp(phi) R, t + dt) (reading of the update
+ *     "T_i <- T_i + Delta T" of Alg. 2, which does not fix the chart).
+ *   - Symmetric 3x3 layout: [xx xy xz yy yz zz].
+ *   - Determinism: identical inputs give bitwise identical outputs (fixed
+ *     reduction orders, no floating-point atomics).
+ */
+#ifndef BA_H
+#define BA_H
+
+#include <stdint.h>
+#include <stddef.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t ba_status;
+#define BA_OK 0
+#define BA_E_ARG (-1)          /* invalid argument (null, size, label out of range, non-finite) */
+#define BA_E_WORKSPACE (-2)    /* workspace smaller than required */
+#define BA_E_HIP (-3)          /* a HIP runtime call failed; text in ba_last_error() */
+#define BA_E_NOT_SPD (-4)      /* a factorization met a non-positive pivot */
+#define BA_E_UNSUPPORTED (-5)  /* mode or size not supported */
+#define BA_E_NOMEM (-6)        /* device allocation failed */
+
+/* Hessian forms (mode arguments). */
+#define BA_MODE_MM 0       /* Eq. 3 surrogate: block-diagonal, [N][6][6] full symmetric */
+#define BA_MODE_COUPLED 1  /* Hessian of u^T A(T) u with u frozen: dense per window */
+
+typedef struct ba_problem ba_problem;
+
+/* Raw body-frame points (Sec. IV-A: points with their pose index and voxel
+ * index).  All arrays are device pointers of length n. */
+typedef struct ba_points {
+    int64_t n;
+    const double *x, *y, *z;   /* device: coordinates in the observing scan's body frame */
+    const int32_t *scan;       /* device: 0 <= scan < n_scans */
+    const int32_t *voxel;      /* device: 0 <= voxel < n_voxels (one planar voxel per id) */
+    int32_t n_scans;
+    int32_t n_voxels;
+} ba_points;
+
+/* Clusters in the paper's interchange form (Eq. 2), any order, at most one per
+ * (voxel, scan).  Device pointers of length n (sum: n x 3, sumsq: n x 6). */
+typedef struct ba_cluster_sums {
+    int64_t n;
+    const int32_t *voxel, *scan;
+    const int64_t *count;      /* device: N_ij >= 1 */
+    const double *sum;         /* device: sum p (AoS, 3 per cluster) */
+    const double *sumsq;       /* device: sum p p^T (AoS, 6 per cluster) */
+    int32_t n_scans;
+    int32_t n_voxels;
+} ba_cluster_sums;
+
+typedef struct ba_build_options {
+    int32_t chunk_len;          /* clusters per pose chunk of the derivative pass; 0 = default (1024) */
+    int32_t n_windows;          /* 0 or 1 = one problem; > 1 = independent windows (batched form) */
+    const int32_t *scan_window; /* host, n_scans entries, non-decreasing window id per scan; NULL if n_windows <= 1 */
+} ba_build_options;
+
+typedef struct ba_problem_info {
+    int64_t n_points;       /* points consumed by the build (0 for the sums form) */
+    int64_t n_clusters;     /* distinct (voxel, scan) clusters */
+    int32_t n_voxels;       /* voxels with at least one cluster */
+    int32_t n_scans;
+    int32_t n_windows;
+    int32_t max_m;          /* largest number of scans observing one voxel */
+    int64_t device_bytes;   /* device memory held by the problem */
+    int32_t n_wave_groups;  /* residual-pass wave groups (64 voxels of equal cluster count each) */
+    int32_t n_pose_chunks;  /* derivative-pass chunks (clusters of one scan each) */
+    int64_t padded_clusters; /* cluster slots of the wave-interleaved layout, incl. padding */
+} ba_problem_info;
+
+typedef struct ba_lm_options {
+    int32_t mode;        /* BA_MODE_MM or BA_MODE_COUPLED */
+    int32_t max_iters;   /* iterations (solves, accepted or not) */
+    double mu0;          /* initial damping (0 -> 1e-2) */
+    double nu0;          /* initial damping growth (0 -> 2) */
+    double tol_g;        /* stop a window once ||g||_2 < tol_g at its current poses (<= 0: never) */
+} ba_lm_options;
+
+typedef struct ba_lm_report {  /* one per window */
+    int32_t iters;        /* solves run */
+    int32_t n_accepted;
+    int32_t converged;    /* ||g|| < tol_g reached */
+    int32_t last_info;    /* pivot failure of the last solve (0 = none) */
+    double cost_initial;
+    double cost_final;
+    double gnorm_final;   /* ||g|| at the last evaluated point */
+    double mu_final;
+} ba_lm_report;
+
+/* ---------------------------------------------------------------------- */
+
+/* Text of a status code (static storage). */
+const char *ba_status_str(ba_status s);
+/* Thread-local description of the last error on this thread. */
+const char *ba_last_error(void);
+
+/*
+ * ba_build_clusters — Sec. IV-A (L1 clustering and Index Mapper, Alg. 1):
+ * group the points by (voxel, scan) with a stable device radix sort, reduce
+ * each group into a point cluster (Eq. 2) kept in centred form
+ * (N, mu = sum p / N, S = sum (p - mu)(p - mu)^T; compensated sums), and lay
+ * out the static plan of the iteration: a voxel-major wave-interleaved copy
+ * for the residual pass and a pose-major chunked copy for the derivative
+ * pass (the paper's mappers M_v, M_s, built once).
+ * pts: host struct of device arrays (not retained).  opt: may be NULL.
+ * *out receives a new problem owned by the caller.  Synchronous.
+ * Errors: BA_E_ARG for null pointers, n < 1, labels out of range, non-finite
+ * coordinates or windows that a voxel straddles; BA_E_NOMEM; BA_E_HIP.
+ */
+ba_status ba_build_clusters(const ba_points *pts, const ba_build_options *opt, ba_problem **out,
+                            hipStream_t stream);
+
+/* Same plan from clusters given as raw sums (Eq. 2); centring is done once
+ * in double-double arithmetic.  Errors as above, plus BA_E_ARG for duplicate
+ * (voxel, scan) pairs or counts < 1.  Synchronous. */
+ba_status ba_build_clusters_from_sums(const ba_cluster_sums *cs, const ba_build_options *opt, ba_problem **out,
+                                      hipStream_t stream);
+
+ba_status ba_problem_destroy(ba_problem *p);
+ba_status ba_problem_get_info(const ba_problem *p, ba_problem_info *info /* host */);
+
+/* Export the centred clusters sorted by (voxel, scan).  Device outputs of
+ * n_clusters entries (mu: 3 per cluster, S: 6 per cluster, AoS).  Any output
+ * may be NULL.  Asynchronous. */
+ba_status ba_problem_export_clusters(const ba_problem *p, int32_t *voxel, int32_t *scan, double *count,
+                                     double *mu, double *S, hipStream_t stream);
+
+/*
+ * ba_eval_residual_grad_hessian — Alg. 2, CalRes and CalJH, at poses T:
+ *   cost[w]  = sum over voxels of window w of lambda_min(A_i(T))        (Eq. 1)
+ *   grad     = d c / d x for every scan (6 per scan)                   (Eq. 3 is tangent to Eq. 1)
+ *   hess     = mode BA_MODE_MM: Hessian of the Eq. 3 surrogate, one full
+ *              symmetric 6x6 block per scan ([N][36]);
+ *              mode BA_MODE_COUPLED: Hessian of u^T A_i(T) u with u frozen
+ *              (adds -2 h_j h_k^T pose-pair blocks), one dense row-major
+ *              (6 N_w)^2 matrix per window, windows concatenated.
+ * poses: device [n_scans][12].  cost: device [n_windows].  grad: device
+ * [n_scans][6].  hess: device, layout above (NULL: skip the Hessian and the
+ * derivative pass entirely; grad must then be NULL too).  voxel_eig: device
+ * [n_voxels_input][4] = (lambda_min, u) per input voxel id, or NULL (voxels
+ * without clusters are left untouched).  Asynchronous.
+ */
+ba_status ba_eval_residual_grad_hessian(ba_problem *p, const double *poses, int32_t mode, double *cost,
+                                        double *grad, double *hess, double *voxel_eig, hipStream_t stream);
+
+/* Workspace needed by ba_solve_increment. */
+size_t ba_solve_increment_workspace(int32_t mode, int32_t n_scans);
+
+/*
+ * ba_solve_increment — Alg. 2, Solver: solve (H + mu D) dx = -g, with
+ * D = diag(H) floored at 1e-12 max_k H_kk (reading of "mu Diag(H)", which a
+ * scan no voxel constrains would otherwise make singular).
+ *   BA_MODE_MM: n_scans independent 6x6 LDL^T factorizations; hess is [N][36].
+ *   BA_MODE_COUPLED: one dense Cholesky of the (6N)^2 row-major hess,
+ *   blocked, trailing updates on FP64 matrix cores.
+ * hess, grad: device inputs (unchanged).  dx: device [N][6] output.
+ * info: device int32 output, 0 or the 1-based index of the first
+ * non-positive pivot (dx is then zero).  ws: device workspace of at least
+ * ba_solve_increment_workspace(mode, n_scans) bytes.  Asynchronous.
+ */
+ba_status ba_solve_increment(int32_t mode, int32_t n_scans, const double *hess, const double *grad, double mu,
+                             double *dx, int32_t *info, void *ws, size_t ws_bytes, hipStream_t stream);
+
+/*
+ * ba_iterate — the LM optimizer of Fig. 1 run on the device: per iteration,
+ * derivatives at the current poses (when they moved), the damped increment
+ * solve, the trial poses T (+) dx, the trial cost (Eq. 1), the gain ratio
+ * rho = (c - c_trial) / (-(g^T dx + dx^T H dx / 2)) and the damping update
+ * (reading of the unprinted PredResReduction / Adjust: accept when rho > 0,
+ * mu <- mu max(1/3, 1 - (2 rho - 1)^3), nu <- 2; otherwise mu <- mu nu,
+ * nu <- 2 nu; a failed factorization is a rejected step).  Windows iterate
+ * independently.
+ * poses_inout: device [n_scans][12], updated in place.  rep: host array of
+ * n_windows reports (may be NULL).  trace: host [max_iters][n_windows][8]
+ * (cost, cost_trial, rho, mu, accepted, gnorm, info, q) or NULL.
+ * Synchronous (returns after the stream has drained).
+ */
+ba_status ba_iterate(ba_problem *p, double *poses_inout, const ba_lm_options *opt, ba_lm_report *rep,
+                     double *trace, hipStream_t stream);
+
+/*
+ * Kernel timing (instrumentation, not part of the method): when enabled,
+ * later calls record a pair of HIP events on their stream around each launch
+ * of the residual kernel ("k_vox") and of the derivative kernel ("k_pose").
+ * ba_profile_query waits for the recorded events and returns the summed
+ * elapsed time and the launch count of one kernel; ba_profile_reset drops
+ * the records.  Process-wide, guarded by a mutex.
+ */
+ba_status ba_profile_enable(int32_t on);
+ba_status ba_profile_reset(void);
+ba_status ba_profile_query(const char *kernel, double *total_ms, int64_t *launches);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* BA_H */

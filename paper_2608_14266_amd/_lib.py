@@ -1,0 +1,292 @@
+"""ctypes marshalling for libba's C-ABI (include/ba.h).  Same names as the C
+entry points, minus the ``ba_`` prefix.  Inputs and outputs are torch tensors
+on the current HIP device; calls are enqueued on torch's current stream."""
+from __future__ import annotations
+
+import ctypes as ct
+import os
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "libba.so")
+
+MODE_MM = 0
+MODE_COUPLED = 1
+
+_STATUS = {0: "BA_OK", -1: "BA_E_ARG", -2: "BA_E_WORKSPACE", -3: "BA_E_HIP", -4: "BA_E_NOT_SPD",
+           -5: "BA_E_UNSUPPORTED", -6: "BA_E_NOMEM"}
+
+
+class BAError(RuntimeError):
+    def __init__(self, status: int, text: str):
+        super().__init__(f"{_STATUS.get(status, status)}: {text}")
+        self.status = status
+
+
+class _Points(ct.Structure):
+    _fields_ = [("n", ct.c_int64), ("x", ct.c_void_p), ("y", ct.c_void_p), ("z", ct.c_void_p),
+                ("scan", ct.c_void_p), ("voxel", ct.c_void_p), ("n_scans", ct.c_int32), ("n_voxels", ct.c_int32)]
+
+
+class _Sums(ct.Structure):
+    _fields_ = [("n", ct.c_int64), ("voxel", ct.c_void_p), ("scan", ct.c_void_p), ("count", ct.c_void_p),
+                ("sum", ct.c_void_p), ("sumsq", ct.c_void_p), ("n_scans", ct.c_int32), ("n_voxels", ct.c_int32)]
+
+
+class _BuildOpts(ct.Structure):
+    _fields_ = [("chunk_len", ct.c_int32), ("n_windows", ct.c_int32), ("scan_window", ct.c_void_p)]
+
+
+class _Info(ct.Structure):
+    _fields_ = [("n_points", ct.c_int64), ("n_clusters", ct.c_int64), ("n_voxels", ct.c_int32),
+                ("n_scans", ct.c_int32), ("n_windows", ct.c_int32), ("max_m", ct.c_int32),
+                ("device_bytes", ct.c_int64), ("n_wave_groups", ct.c_int32), ("n_pose_chunks", ct.c_int32),
+                ("padded_clusters", ct.c_int64)]
+
+
+class _LMOpts(ct.Structure):
+    _fields_ = [("mode", ct.c_int32), ("max_iters", ct.c_int32), ("mu0", ct.c_double), ("nu0", ct.c_double),
+                ("tol_g", ct.c_double)]
+
+
+class _LMReport(ct.Structure):
+    _fields_ = [("iters", ct.c_int32), ("n_accepted", ct.c_int32), ("converged", ct.c_int32),
+                ("last_info", ct.c_int32), ("cost_initial", ct.c_double), ("cost_final", ct.c_double),
+                ("gnorm_final", ct.c_double), ("mu_final", ct.c_double)]
+
+
+_lib = None
+
+
+def lib_path() -> str:
+    return _LIB_PATH
+
+
+def load():
+    """Load libba; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH):
+        raise RuntimeError(f"libba is not built ({_LIB_PATH} missing); run "
+                           "`python -m paper_2608_14266_amd.build`")
+    L = ct.CDLL(_LIB_PATH)
+    P, i32, i64, dbl, sz = ct.c_void_p, ct.c_int32, ct.c_int64, ct.c_double, ct.c_size_t
+    L.ba_status_str.restype = ct.c_char_p
+    L.ba_status_str.argtypes = [i32]
+    L.ba_last_error.restype = ct.c_char_p
+    L.ba_last_error.argtypes = []
+    L.ba_build_clusters.restype = i32
+    L.ba_build_clusters.argtypes = [ct.POINTER(_Points), ct.POINTER(_BuildOpts), ct.POINTER(P), P]
+    L.ba_build_clusters_from_sums.restype = i32
+    L.ba_build_clusters_from_sums.argtypes = [ct.POINTER(_Sums), ct.POINTER(_BuildOpts), ct.POINTER(P), P]
+    L.ba_problem_destroy.restype = i32
+    L.ba_problem_destroy.argtypes = [P]
+    L.ba_problem_get_info.restype = i32
+    L.ba_problem_get_info.argtypes = [P, ct.POINTER(_Info)]
+    L.ba_problem_export_clusters.restype = i32
+    L.ba_problem_export_clusters.argtypes = [P, P, P, P, P, P, P]
+    L.ba_eval_residual_grad_hessian.restype = i32
+    L.ba_eval_residual_grad_hessian.argtypes = [P, P, i32, P, P, P, P, P]
+    L.ba_solve_increment_workspace.restype = sz
+    L.ba_solve_increment_workspace.argtypes = [i32, i32]
+    L.ba_solve_increment.restype = i32
+    L.ba_solve_increment.argtypes = [i32, i32, P, P, dbl, P, P, P, sz, P]
+    L.ba_profile_enable.restype = i32
+    L.ba_profile_enable.argtypes = [i32]
+    L.ba_profile_reset.restype = i32
+    L.ba_profile_reset.argtypes = []
+    L.ba_profile_query.restype = i32
+    L.ba_profile_query.argtypes = [ct.c_char_p, ct.POINTER(ct.c_double), ct.POINTER(ct.c_int64)]
+    L.ba_iterate.restype = i32
+    L.ba_iterate.argtypes = [P, P, ct.POINTER(_LMOpts), ct.POINTER(_LMReport), P, P]
+    _lib = L
+    return L
+
+
+def _check(st: int):
+    if st != 0:
+        raise BAError(st, load().ba_last_error().decode(errors="replace"))
+
+
+def _stream():
+    return ct.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dev(t: torch.Tensor, dtype, name: str) -> torch.Tensor:
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a device tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    return t.contiguous()
+
+
+def _ptr(t):
+    return ct.c_void_p(t.data_ptr()) if t is not None else ct.c_void_p(0)
+
+
+class Problem:
+    """A device-resident problem built by :func:`build_clusters`."""
+
+    def __init__(self, handle: ct.c_void_p, n_voxels_input: int):
+        self._h = handle
+        self.n_voxels_input = int(n_voxels_input)
+
+    @property
+    def handle(self):
+        return self._h
+
+    def info(self) -> dict:
+        inf = _Info()
+        _check(load().ba_problem_get_info(self._h, ct.byref(inf)))
+        return {k: getattr(inf, k) for k, _ in _Info._fields_}
+
+    def export_clusters(self):
+        """(voxel, scan, count, mu (C,3), S (C,6)) sorted by (voxel, scan)."""
+        C = self.info()["n_clusters"]
+        dev = torch.cuda.current_device()
+        vox = torch.empty(C, dtype=torch.int32, device=dev)
+        scan = torch.empty(C, dtype=torch.int32, device=dev)
+        cnt = torch.empty(C, dtype=torch.float64, device=dev)
+        mu = torch.empty((C, 3), dtype=torch.float64, device=dev)
+        S = torch.empty((C, 6), dtype=torch.float64, device=dev)
+        _check(load().ba_problem_export_clusters(self._h, _ptr(vox), _ptr(scan), _ptr(cnt), _ptr(mu), _ptr(S),
+                                                 _stream()))
+        return vox, scan, cnt, mu, S
+
+    def close(self):
+        if self._h:
+            load().ba_problem_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _opts(chunk_len, n_windows, scan_window):
+    o = _BuildOpts()
+    o.chunk_len = int(chunk_len)
+    o.n_windows = int(n_windows)
+    keep = None
+    if scan_window is not None:
+        keep = np.ascontiguousarray(np.asarray(scan_window, dtype=np.int32))
+        o.scan_window = keep.ctypes.data_as(ct.c_void_p)
+    else:
+        o.scan_window = None
+    return o, keep
+
+
+def build_clusters(x, y, z, scan, voxel, n_scans: int, n_voxels: int, chunk_len: int = 0, n_windows: int = 1,
+                   scan_window=None) -> Problem:
+    """ba_build_clusters: points (device tensors) -> problem.  Synchronous."""
+    x = _dev(x, torch.float64, "x"); y = _dev(y, torch.float64, "y"); z = _dev(z, torch.float64, "z")
+    scan = _dev(scan, torch.int32, "scan"); voxel = _dev(voxel, torch.int32, "voxel")
+    n = x.numel()
+    if not (y.numel() == n and z.numel() == n and scan.numel() == n and voxel.numel() == n):
+        raise ValueError("point arrays must have equal length")
+    p = _Points(n, x.data_ptr(), y.data_ptr(), z.data_ptr(), scan.data_ptr(), voxel.data_ptr(), int(n_scans),
+                int(n_voxels))
+    o, keep = _opts(chunk_len, n_windows, scan_window)
+    h = ct.c_void_p()
+    _check(load().ba_build_clusters(ct.byref(p), ct.byref(o), ct.byref(h), _stream()))
+    return Problem(h, n_voxels)
+
+
+def build_clusters_from_sums(voxel, scan, count, sums, sumsq, n_scans: int, n_voxels: int, chunk_len: int = 0,
+                             n_windows: int = 1, scan_window=None) -> Problem:
+    """ba_build_clusters_from_sums: raw-sum clusters (device tensors) -> problem.  Synchronous."""
+    voxel = _dev(voxel, torch.int32, "voxel"); scan = _dev(scan, torch.int32, "scan")
+    count = _dev(count, torch.int64, "count")
+    sums = _dev(sums, torch.float64, "sum"); sumsq = _dev(sumsq, torch.float64, "sumsq")
+    n = voxel.numel()
+    if not (scan.numel() == n and count.numel() == n and sums.numel() == 3 * n and sumsq.numel() == 6 * n):
+        raise ValueError("cluster arrays have inconsistent sizes")
+    s = _Sums(n, voxel.data_ptr(), scan.data_ptr(), count.data_ptr(), sums.data_ptr(), sumsq.data_ptr(),
+              int(n_scans), int(n_voxels))
+    o, keep = _opts(chunk_len, n_windows, scan_window)
+    h = ct.c_void_p()
+    _check(load().ba_build_clusters_from_sums(ct.byref(s), ct.byref(o), ct.byref(h), _stream()))
+    return Problem(h, n_voxels)
+
+
+def eval_residual_grad_hessian(problem: Problem, poses, mode: int = MODE_MM, derivatives: bool = True,
+                               voxel_eig: bool = False):
+    """ba_eval_residual_grad_hessian.  Returns (cost[n_windows], grad (N,6) or None,
+    hess ((N,6,6) for MM, dense per-window for COUPLED) or None, eig (V_in,4) or None)."""
+    poses = _dev(poses, torch.float64, "poses")
+    inf = problem.info()
+    N, W = inf["n_scans"], inf["n_windows"]
+    if poses.numel() != 12 * N:
+        raise ValueError("poses must hold 12 doubles per scan")
+    dev = poses.device
+    cost = torch.empty(W, dtype=torch.float64, device=dev)
+    grad = hess = eig = None
+    if derivatives:
+        grad = torch.empty((N, 6), dtype=torch.float64, device=dev)
+        if mode == MODE_MM:
+            hess = torch.empty((N, 6, 6), dtype=torch.float64, device=dev)
+        else:
+            if W != 1:
+                raise ValueError("dense coupled Hessian export supports one window")
+            hess = torch.empty((6 * N, 6 * N), dtype=torch.float64, device=dev)
+    if voxel_eig:
+        eig = torch.full((problem.n_voxels_input, 4), float("nan"), dtype=torch.float64, device=dev)
+    _check(load().ba_eval_residual_grad_hessian(problem.handle, _ptr(poses), int(mode), _ptr(cost), _ptr(grad),
+                                                _ptr(hess), _ptr(eig), _stream()))
+    return cost, grad, hess, eig
+
+
+def solve_increment_workspace(mode: int, n_scans: int) -> int:
+    return int(load().ba_solve_increment_workspace(int(mode), int(n_scans)))
+
+
+def solve_increment(mode: int, hess, grad, mu: float):
+    """ba_solve_increment: returns (dx (N,6), info (int32 device scalar))."""
+    hess = _dev(hess, torch.float64, "hess"); grad = _dev(grad, torch.float64, "grad")
+    N = grad.numel() // 6
+    dev = grad.device
+    dx = torch.empty((N, 6), dtype=torch.float64, device=dev)
+    info = torch.empty(1, dtype=torch.int32, device=dev)
+    wsb = solve_increment_workspace(mode, N)
+    ws = torch.empty(max(wsb, 1), dtype=torch.uint8, device=dev)
+    _check(load().ba_solve_increment(int(mode), N, _ptr(hess), _ptr(grad), float(mu), _ptr(dx), _ptr(info),
+                                     _ptr(ws), wsb, _stream()))
+    return dx, info
+
+
+def iterate(problem: Problem, poses, mode: int = MODE_MM, max_iters: int = 10, mu0: float = 1e-2,
+            nu0: float = 2.0, tol_g: float = 0.0, trace: bool = True):
+    """ba_iterate: LM on the device, poses updated in place.  Synchronous.
+    Returns (reports: list of dicts per window, trace ndarray (iters, W, 8) or None)."""
+    if not (poses.is_cuda and poses.dtype == torch.float64 and poses.is_contiguous()):
+        raise TypeError("poses must be a contiguous float64 device tensor (updated in place)")
+    W = problem.info()["n_windows"]
+    o = _LMOpts(int(mode), int(max_iters), float(mu0), float(nu0), float(tol_g))
+    reps = (_LMReport * W)()
+    tr = np.zeros((max(int(max_iters), 1), W, 8)) if trace else None
+    trp = tr.ctypes.data_as(ct.c_void_p) if trace else ct.c_void_p(0)
+    _check(load().ba_iterate(problem.handle, _ptr(poses), ct.byref(o), reps, trp, _stream()))
+    out = [{k: getattr(r, k) for k, _ in _LMReport._fields_} for r in reps]
+    return out, (tr[: int(max_iters)] if trace else None)
+
+
+def profile_enable(on: bool = True):
+    """ba_profile_enable: time later launches of the eval kernels with HIP events."""
+    _check(load().ba_profile_enable(1 if on else 0))
+
+
+def profile_reset():
+    _check(load().ba_profile_reset())
+
+
+def profile_query(kernel: str):
+    """ba_profile_query: (total milliseconds, launches) of one kernel ("k_vox", "k_pose")."""
+    ms = ct.c_double(0.0)
+    n = ct.c_int64(0)
+    _check(load().ba_profile_query(kernel.encode(), ct.byref(ms), ct.byref(n)))
+    return ms.value, n.value

@@ -1,0 +1,370 @@
+// C-ABI entry points of libba (declared in include/ba.h).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "ba.h"
+#include "ba_internal.hpp"
+#include "ba_kernels.hpp"
+
+struct ba_problem {
+    ba::Problem P;
+};
+
+namespace ba {
+
+static thread_local char g_last_error[1024] = "";
+
+void set_error(const char *fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_last_error, sizeof g_last_error, fmt, ap);
+    va_end(ap);
+}
+
+// dense coupled path (ba_dense.hip)
+size_t dense_solve_workspace(int64_t n);
+ba_status dense_assemble(Problem *P, const double *poses, double *hess_out, bool use_lm, hipStream_t s);
+ba_status dense_solve(int64_t n, const double *A, const double *g, double mu, double *dx, int32_t *info, void *ws,
+                      size_t ws_bytes, hipStream_t s);
+ba_status dense_lm_step(Problem *P, const double *poses, hipStream_t s);
+ba_status dense_prepare(Problem *P);
+
+// ---------------------------------------------------------------- profiling
+struct ProfRec {
+    const char *name;
+    hipEvent_t a, b;
+};
+static bool g_prof_on = false;
+static std::vector<ProfRec> g_prof;
+static std::vector<hipEvent_t> g_prof_pool;
+static std::mutex g_prof_mu;
+
+static hipEvent_t prof_event() {
+    if (!g_prof_pool.empty()) {
+        hipEvent_t e = g_prof_pool.back();
+        g_prof_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+void prof_begin(const char *name, hipStream_t s) {
+    if (!g_prof_on) return;
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    ProfRec r;
+    r.name = name;
+    r.a = prof_event();
+    r.b = prof_event();
+    if (!r.a || !r.b) return;
+    (void)hipEventRecord(r.a, s);
+    g_prof.push_back(r);
+}
+
+void prof_end(hipStream_t s) {
+    if (!g_prof_on) return;
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    if (!g_prof.empty()) (void)hipEventRecord(g_prof.back().b, s);
+}
+
+}  // namespace ba
+
+using namespace ba;
+
+extern "C" {
+
+const char *ba_status_str(ba_status s) {
+    switch (s) {
+        case BA_OK: return "ok";
+        case BA_E_ARG: return "invalid argument";
+        case BA_E_WORKSPACE: return "workspace too small";
+        case BA_E_HIP: return "HIP runtime error";
+        case BA_E_NOT_SPD: return "matrix not positive definite";
+        case BA_E_UNSUPPORTED: return "unsupported";
+        case BA_E_NOMEM: return "out of device memory";
+        default: return "unknown status";
+    }
+}
+
+const char *ba_last_error(void) { return g_last_error; }
+
+ba_status ba_profile_enable(int32_t on) {
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    g_prof_on = on != 0;
+    return BA_OK;
+}
+
+ba_status ba_profile_reset(void) {
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    for (auto &r : g_prof) {
+        g_prof_pool.push_back(r.a);
+        g_prof_pool.push_back(r.b);
+    }
+    g_prof.clear();
+    return BA_OK;
+}
+
+ba_status ba_profile_query(const char *kernel, double *total_ms, int64_t *launches) {
+    if (!kernel || !total_ms || !launches) {
+        set_error("null argument to ba_profile_query");
+        return BA_E_ARG;
+    }
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    double tot = 0.0;
+    int64_t cnt = 0;
+    for (auto &r : g_prof) {
+        if (std::strcmp(r.name, kernel) != 0) continue;
+        BA_HIP(hipEventSynchronize(r.b));
+        float ms = 0.f;
+        BA_HIP(hipEventElapsedTime(&ms, r.a, r.b));
+        tot += ms;
+        cnt++;
+    }
+    *total_ms = tot;
+    *launches = cnt;
+    return BA_OK;
+}
+
+static ba_status build_common(ba_problem **out, hipStream_t stream,
+                              ba_status (*fn)(const void *, const ba_build_options *, Problem *, DevArena &,
+                                              hipStream_t),
+                              const void *src, const ba_build_options *opt) {
+    if (!out) {
+        set_error("out is null");
+        return BA_E_ARG;
+    }
+    *out = nullptr;
+    if (opt && opt->n_windows > 1 && !opt->scan_window) {
+        set_error("n_windows > 1 needs scan_window");
+        return BA_E_ARG;
+    }
+    ba_problem *p = new (std::nothrow) ba_problem();
+    if (!p) {
+        set_error("host allocation failed");
+        return BA_E_NOMEM;
+    }
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) {
+        delete p;
+        set_error("no HIP device");
+        return BA_E_HIP;
+    }
+    p->P.device = dev;
+    ba_status st = fn(src, opt, &p->P, p->P.mem, stream);
+    if (st != BA_OK) {
+        (void)hipStreamSynchronize(stream);
+        delete p;
+        return st;
+    }
+    *out = p;
+    return BA_OK;
+}
+
+static ba_status fn_points(const void *src, const ba_build_options *opt, Problem *P, DevArena &keep, hipStream_t s) {
+    const ba_points *pts = (const ba_points *)src;
+    P->n_points = pts->n;
+    return build_from_points(pts, opt, P, keep, s);
+}
+
+static ba_status fn_sums(const void *src, const ba_build_options *opt, Problem *P, DevArena &keep, hipStream_t s) {
+    return build_from_sums((const ba_cluster_sums *)src, opt, P, keep, s);
+}
+
+ba_status ba_build_clusters(const ba_points *pts, const ba_build_options *opt, ba_problem **out, hipStream_t stream) {
+    if (!pts) {
+        set_error("pts is null");
+        return BA_E_ARG;
+    }
+    return build_common(out, stream, fn_points, pts, opt);
+}
+
+ba_status ba_build_clusters_from_sums(const ba_cluster_sums *cs, const ba_build_options *opt, ba_problem **out,
+                                      hipStream_t stream) {
+    if (!cs) {
+        set_error("cs is null");
+        return BA_E_ARG;
+    }
+    return build_common(out, stream, fn_sums, cs, opt);
+}
+
+ba_status ba_problem_destroy(ba_problem *p) {
+    if (!p) return BA_OK;
+    (void)hipDeviceSynchronize();
+    delete p;
+    return BA_OK;
+}
+
+ba_status ba_problem_get_info(const ba_problem *p, ba_problem_info *info) {
+    if (!p || !info) {
+        set_error("null argument");
+        return BA_E_ARG;
+    }
+    const Problem &P = p->P;
+    info->n_points = P.n_points;
+    info->n_clusters = P.n_clusters;
+    info->n_voxels = P.n_vox;
+    info->n_scans = P.n_poses;
+    info->n_windows = P.n_windows;
+    info->max_m = P.max_m;
+    info->device_bytes = (int64_t)P.mem.bytes;
+    info->n_wave_groups = P.n_groups;
+    info->n_pose_chunks = P.n_chunks;
+    info->padded_clusters = P.c_pad;
+    return BA_OK;
+}
+
+ba_status ba_problem_export_clusters(const ba_problem *p, int32_t *voxel, int32_t *scan, double *count, double *mu,
+                                     double *S, hipStream_t stream) {
+    if (!p) {
+        set_error("null problem");
+        return BA_E_ARG;
+    }
+    const Problem &P = p->P;
+    const int64_t C = P.n_clusters;
+    if (voxel) BA_HIP(hipMemcpyAsync(voxel, P.c_vox, sizeof(int32_t) * C, hipMemcpyDeviceToDevice, stream));
+    if (scan) BA_HIP(hipMemcpyAsync(scan, P.c_scan, sizeof(int32_t) * C, hipMemcpyDeviceToDevice, stream));
+    if (count) BA_HIP(hipMemcpyAsync(count, P.c_N, sizeof(double) * C, hipMemcpyDeviceToDevice, stream));
+    if (mu) BA_HIP(hipMemcpyAsync(mu, P.c_mu, sizeof(double) * 3 * C, hipMemcpyDeviceToDevice, stream));
+    if (S) BA_HIP(hipMemcpyAsync(S, P.c_S, sizeof(double) * 6 * C, hipMemcpyDeviceToDevice, stream));
+    return BA_OK;
+}
+
+ba_status ba_eval_residual_grad_hessian(ba_problem *p, const double *poses, int32_t mode, double *cost, double *grad,
+                                        double *hess, double *voxel_eig, hipStream_t stream) {
+    if (!p || !poses || !cost) {
+        set_error("null problem, poses or cost");
+        return BA_E_ARG;
+    }
+    if (mode != BA_MODE_MM && mode != BA_MODE_COUPLED) {
+        set_error("unknown mode %d", mode);
+        return BA_E_UNSUPPORTED;
+    }
+    if ((grad == nullptr) != (hess == nullptr)) {
+        set_error("grad and hess must both be given or both be null");
+        return BA_E_ARG;
+    }
+    Problem *P = &p->P;
+    launch_vox(P, poses, false, false, stream);
+    launch_window_cost(P, cost, stream);
+    if (voxel_eig) launch_voxel_eig(P, voxel_eig, stream);
+    if (grad) {
+        double *Hmm = (mode == BA_MODE_MM) ? hess : P->H;
+        launch_pose_derivs(P, poses, false, grad, Hmm, stream);
+        if (mode == BA_MODE_COUPLED) BA_TRY(dense_assemble(P, poses, hess, false, stream));
+    }
+    BA_HIP(hipGetLastError());
+    return BA_OK;
+}
+
+size_t ba_solve_increment_workspace(int32_t mode, int32_t n_scans) {
+    if (n_scans < 1) return 0;
+    if (mode == BA_MODE_MM) return solve_mm_workspace(n_scans);
+    if (mode == BA_MODE_COUPLED) return dense_solve_workspace(6LL * n_scans);
+    return 0;
+}
+
+ba_status ba_solve_increment(int32_t mode, int32_t n_scans, const double *hess, const double *grad, double mu,
+                             double *dx, int32_t *info, void *ws, size_t ws_bytes, hipStream_t stream) {
+    if (n_scans < 1 || !hess || !grad || !dx || !info || !(mu >= 0.0) || !std::isfinite(mu)) {
+        set_error("invalid argument to ba_solve_increment");
+        return BA_E_ARG;
+    }
+    const size_t need = ba_solve_increment_workspace(mode, n_scans);
+    if (mode != BA_MODE_MM && mode != BA_MODE_COUPLED) {
+        set_error("unknown mode %d", mode);
+        return BA_E_UNSUPPORTED;
+    }
+    if (!ws || ws_bytes < need) {
+        set_error("workspace of %zu bytes given, %zu needed", ws_bytes, need);
+        return BA_E_WORKSPACE;
+    }
+    if (mode == BA_MODE_MM) {
+        launch_solve_mm_plain(n_scans, hess, grad, mu, dx, info, ws, stream);
+        BA_HIP(hipGetLastError());
+        return BA_OK;
+    }
+    return dense_solve(6LL * n_scans, hess, grad, mu, dx, info, ws, ws_bytes, stream);
+}
+
+ba_status ba_iterate(ba_problem *p, double *poses_inout, const ba_lm_options *opt, ba_lm_report *rep, double *trace,
+                     hipStream_t stream) {
+    if (!p || !poses_inout || !opt) {
+        set_error("null argument to ba_iterate");
+        return BA_E_ARG;
+    }
+    if (opt->mode != BA_MODE_MM && opt->mode != BA_MODE_COUPLED) {
+        set_error("unknown mode %d", opt->mode);
+        return BA_E_UNSUPPORTED;
+    }
+    if (opt->max_iters < 0) {
+        set_error("max_iters < 0");
+        return BA_E_ARG;
+    }
+    Problem *P = &p->P;
+    const int W = P->n_windows;
+    const int iters = opt->max_iters;
+    const double mu0 = opt->mu0 > 0 ? opt->mu0 : 1e-2;
+    const double nu0 = opt->nu0 > 0 ? opt->nu0 : 2.0;
+    if (opt->mode == BA_MODE_COUPLED) BA_TRY(dense_prepare(P));
+    double *dtrace = nullptr;
+    if (trace && iters > 0) {
+        if (P->trace_cap < iters) {
+            BA_TRY(P->mem.alloc(&P->trace, (int64_t)iters * W * 8));
+            P->trace_cap = iters;
+        }
+        dtrace = P->trace;
+        BA_HIP(hipMemsetAsync(dtrace, 0, sizeof(double) * (size_t)iters * W * 8, stream));
+    }
+    launch_lm_reset(P, mu0, nu0, stream);
+    launch_vox(P, poses_inout, true, false, stream);
+    launch_lm_cost(P, stream);
+    std::vector<LMState> st0(W);
+    for (int it = 0; it < iters; it++) {
+        launch_pose_derivs(P, poses_inout, true, P->g, P->H, stream);
+        if (opt->mode == BA_MODE_MM) {
+            launch_window_stats(P, opt->tol_g, stream);
+            launch_solve_mm_lm(P, poses_inout, stream);
+        } else {
+            BA_TRY(dense_assemble(P, poses_inout, nullptr, true, stream));
+            launch_window_stats(P, opt->tol_g, stream);
+            BA_TRY(dense_lm_step(P, poses_inout, stream));
+        }
+        launch_vox(P, P->poses_trial, true, true, stream);
+        launch_decide(P, dtrace, it, stream);
+        launch_commit(P, poses_inout, stream);
+    }
+    // derivatives at the final poses (windows whose last step was accepted),
+    // so that the reported gradient norm belongs to the returned poses
+    launch_pose_derivs(P, poses_inout, true, P->g, P->H, stream);
+    launch_window_stats(P, opt->tol_g, stream);
+    BA_HIP(hipGetLastError());
+    std::vector<LMState> st(W);
+    BA_HIP(hipMemcpyAsync(st.data(), P->lm, sizeof(LMState) * W, hipMemcpyDeviceToHost, stream));
+    if (dtrace) BA_HIP(hipMemcpyAsync(trace, dtrace, sizeof(double) * (size_t)iters * W * 8, hipMemcpyDeviceToHost, stream));
+    BA_HIP(hipStreamSynchronize(stream));
+    if (rep) {
+        for (int w = 0; w < W; w++) {
+            rep[w].iters = st[w].iters;
+            rep[w].n_accepted = st[w].n_accepted;
+            rep[w].converged = st[w].done;
+            rep[w].last_info = st[w].info;
+            rep[w].cost_final = st[w].cost;
+            rep[w].gnorm_final = st[w].gnorm;
+            rep[w].mu_final = st[w].mu;
+            rep[w].cost_initial = st[w].cost0;
+        }
+    }
+    return BA_OK;
+}
+
+}  // extern "C"

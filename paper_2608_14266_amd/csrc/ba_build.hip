@@ -1,0 +1,540 @@
+// Problem build: raw points (or raw-sum clusters) -> centred point clusters
+// (Eq. 2) -> static plan of the iteration.  Runs once per problem.
+//
+// Paper Sec. IV-A groups points by (voxel, pose) with sort_by_key and
+// reduce_by_key and builds two index mappers, M_v (cluster -> voxel) and M_s
+// (voxel-sorted -> pose-sorted order), consumed every iteration (Alg. 2).
+// Here the same grouping runs as a stable device radix sort plus one
+// wavefront per cluster, and the mappers are materialised once as two
+// physical copies of the clusters:
+//   * a voxel-major, wave-interleaved copy: voxels of equal cluster count m
+//     are packed 64 to a wave group, cluster k of lane l at cbase + 64 k + l,
+//     so the residual pass reads fully coalesced with no divergence;
+//   * a pose-major copy cut into chunks of one pose, so the derivative pass
+//     reduces per pose in registers without scatter or atomics.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+#include <vector>
+
+#include "ba.h"
+#include "ba_device.hpp"
+#include "ba_internal.hpp"
+#include "ba_host.hpp"
+
+namespace ba {
+
+// ---------------------------------------------------------------- kernels
+__global__ void k_validate_points(int64_t n, const double *__restrict__ x, const double *__restrict__ y,
+                                  const double *__restrict__ z, const int32_t *__restrict__ scan,
+                                  const int32_t *__restrict__ voxel, int32_t n_scans, int32_t n_voxels,
+                                  int32_t *__restrict__ err) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int bad = 0;
+    if (!(isfinite(x[i]) && isfinite(y[i]) && isfinite(z[i]))) bad |= 1;
+    if (scan[i] < 0 || scan[i] >= n_scans) bad |= 2;
+    if (voxel[i] < 0 || voxel[i] >= n_voxels) bad |= 4;
+    if (bad) atomicOr(err, bad);
+}
+
+__global__ void k_make_keys(int64_t n, const int32_t *__restrict__ scan, const int32_t *__restrict__ voxel,
+                            int32_t n_scans, uint64_t *__restrict__ keys, uint32_t *__restrict__ vals) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    keys[i] = (uint64_t)voxel[i] * (uint64_t)n_scans + (uint64_t)scan[i];
+    vals[i] = (uint32_t)i;
+}
+
+__global__ void k_head_flags(int64_t n, const uint64_t *__restrict__ keys, int64_t *__restrict__ flags) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    flags[i] = (i == 0 || keys[i] != keys[i - 1]) ? 1 : 0;
+}
+
+// after an exclusive scan of the head flags: starts[cid] = i for every head
+__global__ void k_segment_starts(int64_t n, const uint64_t *__restrict__ keys, const int64_t *__restrict__ excl,
+                                 int64_t *__restrict__ starts, int64_t n_seg) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    if (i == 0 || keys[i] != keys[i - 1]) starts[excl[i]] = i;
+    if (i == 0) starts[n_seg] = n;
+}
+
+__global__ void k_gather_xyz(int64_t n, const uint32_t *__restrict__ idx, const double *__restrict__ x,
+                             const double *__restrict__ y, const double *__restrict__ z, double *__restrict__ xs,
+                             double *__restrict__ ys, double *__restrict__ zs) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    uint32_t j = idx[i];
+    xs[i] = x[j];
+    ys[i] = y[j];
+    zs[i] = z[j];
+}
+
+__device__ __forceinline__ double dd_div_int(double hi, double lo, double n) {
+    double q = hi / n;
+    double r = fma(-q, n, hi) + lo;
+    return q + r / n;
+}
+
+// One wavefront per cluster: compensated centroid, then centred scatter.
+__global__ __launch_bounds__(256) void k_cluster_stats(int64_t C, const int64_t *__restrict__ starts,
+                                                       const double *__restrict__ xs, const double *__restrict__ ys,
+                                                       const double *__restrict__ zs,
+                                                       const uint64_t *__restrict__ skeys, int32_t n_scans,
+                                                       double *__restrict__ cN, double *__restrict__ cmu,
+                                                       double *__restrict__ cS, int32_t *__restrict__ cvox,
+                                                       int32_t *__restrict__ cscan) {
+    int64_t c = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    int lane = threadIdx.x & 63;
+    if (c >= C) return;
+    int64_t a = starts[c], b = starts[c + 1];
+    double hx = 0, lx = 0, hy = 0, ly = 0, hz = 0, lz = 0;
+    for (int64_t i = a + lane; i < b; i += 64) {
+        dd_add(hx, lx, xs[i]);
+        dd_add(hy, ly, ys[i]);
+        dd_add(hz, lz, zs[i]);
+    }
+    wave_dd_sum(hx, lx);
+    wave_dd_sum(hy, ly);
+    wave_dd_sum(hz, lz);
+    double n = (double)(b - a);
+    double mx = dd_div_int(hx, lx, n), my = dd_div_int(hy, ly, n), mz = dd_div_int(hz, lz, n);
+    double sxx = 0, sxy = 0, sxz = 0, syy = 0, syz = 0, szz = 0;
+    for (int64_t i = a + lane; i < b; i += 64) {
+        double dx = xs[i] - mx, dy = ys[i] - my, dz = zs[i] - mz;
+        sxx = fma(dx, dx, sxx); sxy = fma(dx, dy, sxy); sxz = fma(dx, dz, sxz);
+        syy = fma(dy, dy, syy); syz = fma(dy, dz, syz); szz = fma(dz, dz, szz);
+    }
+    sxx = wave_sum(sxx); sxy = wave_sum(sxy); sxz = wave_sum(sxz);
+    syy = wave_sum(syy); syz = wave_sum(syz); szz = wave_sum(szz);
+    if (lane == 0) {
+        uint64_t key = skeys[a];
+        cN[c] = n;
+        cmu[3 * c + 0] = mx; cmu[3 * c + 1] = my; cmu[3 * c + 2] = mz;
+        cS[6 * c + 0] = sxx; cS[6 * c + 1] = sxy; cS[6 * c + 2] = sxz;
+        cS[6 * c + 3] = syy; cS[6 * c + 4] = syz; cS[6 * c + 5] = szz;
+        cvox[c] = (int32_t)(key / (uint64_t)n_scans);
+        cscan[c] = (int32_t)(key % (uint64_t)n_scans);
+    }
+}
+
+__global__ void k_validate_sums(int64_t n, const int32_t *__restrict__ voxel, const int32_t *__restrict__ scan,
+                                const int64_t *__restrict__ count, const double *__restrict__ s1,
+                                const double *__restrict__ s2, int32_t n_scans, int32_t n_voxels,
+                                int32_t *__restrict__ err) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int bad = 0;
+    if (scan[i] < 0 || scan[i] >= n_scans) bad |= 2;
+    if (voxel[i] < 0 || voxel[i] >= n_voxels) bad |= 4;
+    if (count[i] < 1) bad |= 8;
+    for (int k = 0; k < 3; k++) if (!isfinite(s1[3 * i + k])) bad |= 1;
+    for (int k = 0; k < 6; k++) if (!isfinite(s2[6 * i + k])) bad |= 1;
+    if (bad) atomicOr(err, bad);
+}
+
+__global__ void k_dup_keys(int64_t n, const uint64_t *__restrict__ keys, int32_t *__restrict__ err) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n || i == 0) return;
+    if (keys[i] == keys[i - 1]) atomicOr(err, 16);
+}
+
+// Centre raw sums once in double-double: mu = s / N, S = Q - s s^T / N.
+__device__ __forceinline__ double centre_entry(double q, double sa, double sb, double n) {
+    double ph = sa * sb;
+    double pl = fma(sa, sb, -ph);
+    double qh = ph / n;
+    double rem = fma(-qh, n, ph) + pl;
+    double ql = rem / n;
+    double s, e;
+    two_sum(q, -qh, s, e);
+    return s + (e - ql);
+}
+
+__global__ void k_center_sums(int64_t C, const uint32_t *__restrict__ order, const uint64_t *__restrict__ skeys,
+                              const int64_t *__restrict__ count, const double *__restrict__ s1,
+                              const double *__restrict__ s2, int32_t n_scans, double *__restrict__ cN,
+                              double *__restrict__ cmu, double *__restrict__ cS, int32_t *__restrict__ cvox,
+                              int32_t *__restrict__ cscan) {
+    int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= C) return;
+    uint32_t j = order[c];
+    double n = (double)count[j];
+    double s[3] = {s1[3 * (int64_t)j], s1[3 * (int64_t)j + 1], s1[3 * (int64_t)j + 2]};
+    for (int k = 0; k < 3; k++) {
+        double q = s[k] / n;
+        double r = fma(-q, n, s[k]);
+        cmu[3 * c + k] = q + r / n;
+    }
+    const double *Q = s2 + 6 * (int64_t)j;
+    cS[6 * c + 0] = centre_entry(Q[0], s[0], s[0], n);
+    cS[6 * c + 1] = centre_entry(Q[1], s[0], s[1], n);
+    cS[6 * c + 2] = centre_entry(Q[2], s[0], s[2], n);
+    cS[6 * c + 3] = centre_entry(Q[3], s[1], s[1], n);
+    cS[6 * c + 4] = centre_entry(Q[4], s[1], s[2], n);
+    cS[6 * c + 5] = centre_entry(Q[5], s[2], s[2], n);
+    cN[c] = n;
+    uint64_t key = skeys[c];
+    cvox[c] = (int32_t)(key / (uint64_t)n_scans);
+    cscan[c] = (int32_t)(key % (uint64_t)n_scans);
+}
+
+// Scatter centred clusters into the voxel-major wave-interleaved layout.
+__global__ void k_scatter_vox(int64_t C, const int64_t *__restrict__ dst, int64_t c_pad,
+                              const double *__restrict__ cN, const double *__restrict__ cmu,
+                              const double *__restrict__ cS, const int32_t *__restrict__ cscan,
+                              double *__restrict__ vN, double *__restrict__ vmu, double *__restrict__ vS,
+                              int32_t *__restrict__ vpose) {
+    int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= C) return;
+    int64_t d = dst[c];
+    vN[d] = cN[c];
+    vpose[d] = cscan[c];
+#pragma unroll
+    for (int k = 0; k < 3; k++) vmu[k * c_pad + d] = cmu[3 * c + k];
+#pragma unroll
+    for (int k = 0; k < 6; k++) vS[k * c_pad + d] = cS[6 * c + k];
+}
+
+// Gather centred clusters into the pose-major layout.
+__global__ void k_gather_pose(int64_t C, const int32_t *__restrict__ order, const int32_t *__restrict__ slot_of,
+                              const double *__restrict__ cN, const double *__restrict__ cmu,
+                              const double *__restrict__ cS, double *__restrict__ pN, double *__restrict__ pmu,
+                              double *__restrict__ pS, int32_t *__restrict__ pslot) {
+    int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= C) return;
+    int64_t c = order[q];
+    pN[q] = cN[c];
+    pslot[q] = slot_of[c];
+#pragma unroll
+    for (int k = 0; k < 3; k++) pmu[k * C + q] = cmu[3 * c + k];
+#pragma unroll
+    for (int k = 0; k < 6; k++) pS[k * C + q] = cS[6 * c + k];
+}
+
+static inline unsigned nblk(int64_t n, int t = 256) { return (unsigned)((n + t - 1) / t); }
+
+static int bit_length(uint64_t v) {
+    int b = 0;
+    while (v) { b++; v >>= 1; }
+    return b;
+}
+
+// ---------------------------------------------------------------- host plan
+// Builds every static table from the cluster labels (voxel-major order).
+static ba_status make_plan(Problem *P, const std::vector<int32_t> &cvox, const std::vector<int32_t> &cscan,
+                           const std::vector<int32_t> &scan_window, DevArena &keep, hipStream_t s) {
+    const int64_t C = (int64_t)cvox.size();
+    const int32_t N = P->n_poses;
+    const int32_t W = P->n_windows;
+    // voxel runs
+    std::vector<int64_t> vstart;
+    vstart.reserve((size_t)C / 2 + 2);
+    for (int64_t c = 0; c < C; c++)
+        if (c == 0 || cvox[c] != cvox[c - 1]) vstart.push_back(c);
+    const int32_t V = (int32_t)vstart.size();
+    vstart.push_back(C);
+    P->n_vox = V;
+    std::vector<int32_t> m(V), minpose(V), win(V);
+    int32_t max_m = 0;
+    for (int32_t v = 0; v < V; v++) {
+        m[v] = (int32_t)(vstart[v + 1] - vstart[v]);
+        minpose[v] = cscan[vstart[v]];
+        win[v] = scan_window[minpose[v]];
+        for (int64_t c = vstart[v]; c < vstart[v + 1]; c++)
+            if (scan_window[cscan[c]] != win[v]) {
+                set_error("voxel %d is observed by scans of different windows", cvox[vstart[v]]);
+                return BA_E_ARG;
+            }
+        max_m = std::max(max_m, m[v]);
+    }
+    P->max_m = max_m;
+    // voxel order: (window, m, first observing scan, voxel id)
+    std::vector<int32_t> vorder(V);
+    std::iota(vorder.begin(), vorder.end(), 0);
+    std::stable_sort(vorder.begin(), vorder.end(), [&](int32_t a, int32_t b) {
+        if (win[a] != win[b]) return win[a] < win[b];
+        if (m[a] != m[b]) return m[a] < m[b];
+        return minpose[a] < minpose[b];
+    });
+    // wave groups
+    std::vector<GroupDesc> groups;
+    std::vector<int32_t> win_group_ptr(W + 1, 0);
+    std::vector<int64_t> dst(C);
+    std::vector<int32_t> slot_of(C);
+    std::vector<int32_t> slot_vox;
+    int64_t cbase = 0;
+    for (int32_t i = 0; i < V;) {
+        int32_t j = i;
+        while (j < V && win[vorder[j]] == win[vorder[i]] && m[vorder[j]] == m[vorder[i]] && j - i < 64) j++;
+        GroupDesc g;
+        g.cbase = cbase;
+        g.m = m[vorder[i]];
+        g.nvox = j - i;
+        g.window = win[vorder[i]];
+        g.pad = 0;
+        int32_t gi = (int32_t)groups.size();
+        for (int32_t l = 0; l < 64; l++) slot_vox.push_back(l < g.nvox ? cvox[vstart[vorder[i + l]]] : -1);
+        for (int32_t l = 0; l < g.nvox; l++) {
+            int32_t v = vorder[i + l];
+            for (int32_t k = 0; k < g.m; k++) {
+                int64_t c = vstart[v] + k;
+                dst[c] = cbase + 64LL * k + l;
+                slot_of[c] = gi * 64 + l;
+            }
+        }
+        groups.push_back(g);
+        win_group_ptr[g.window + 1] = (int32_t)groups.size();
+        cbase += 64LL * g.m;
+        i = j;
+    }
+    for (int32_t w = 0; w < W; w++) win_group_ptr[w + 1] = std::max(win_group_ptr[w + 1], win_group_ptr[w]);
+    P->n_groups = (int32_t)groups.size();
+    P->c_pad = cbase;
+    // pose-major order: (scan, slot)
+    std::vector<int32_t> porder(C);
+    std::iota(porder.begin(), porder.end(), 0);
+    std::stable_sort(porder.begin(), porder.end(), [&](int32_t a, int32_t b) {
+        if (cscan[a] != cscan[b]) return cscan[a] < cscan[b];
+        return slot_of[a] < slot_of[b];
+    });
+    std::vector<ChunkDesc> chunks;
+    std::vector<int32_t> chunk_ptr(N + 1, 0);
+    {
+        int64_t q = 0;
+        for (int32_t j = 0; j < N; j++) {
+            chunk_ptr[j] = (int32_t)chunks.size();
+            int64_t a = q;
+            while (q < C && cscan[porder[q]] == j) q++;
+            for (int64_t s0 = a; s0 < q; s0 += P->chunk_len) {
+                ChunkDesc ch;
+                ch.start = s0;
+                ch.count = (int32_t)std::min<int64_t>(P->chunk_len, q - s0);
+                ch.pose = j;
+                chunks.push_back(ch);
+            }
+        }
+        chunk_ptr[N] = (int32_t)chunks.size();
+    }
+    P->n_chunks = (int32_t)chunks.size();
+    std::vector<int32_t> win_pose_ptr(W + 1, 0), pose_window(N);
+    for (int32_t j = 0; j < N; j++) {
+        pose_window[j] = scan_window[j];
+        win_pose_ptr[scan_window[j] + 1] = j + 1;
+    }
+    for (int32_t w = 0; w < W; w++) win_pose_ptr[w + 1] = std::max(win_pose_ptr[w + 1], win_pose_ptr[w]);
+
+    // device allocations owned by the problem
+    const int64_t CP = P->c_pad;
+    const int64_t NS = (int64_t)P->n_groups * 64;
+    BA_TRY(keep.alloc(&P->v_mu, 3 * CP));
+    BA_TRY(keep.alloc(&P->v_S, 6 * CP));
+    BA_TRY(keep.alloc(&P->v_N, CP));
+    BA_TRY(keep.alloc(&P->v_pose, CP));
+    BA_TRY(keep.alloc(&P->groups, std::max<int64_t>(P->n_groups, 1)));
+    BA_TRY(keep.alloc(&P->slot_vox, std::max<int64_t>(NS, 1)));
+    BA_TRY(keep.alloc(&P->vstate, 2 * std::max<int64_t>(NS, 1) * VSTATE));
+    BA_TRY(keep.alloc(&P->wave_cost, std::max<int64_t>(P->n_groups, 1)));
+    BA_TRY(keep.alloc(&P->p_mu, 3 * C));
+    BA_TRY(keep.alloc(&P->p_S, 6 * C));
+    BA_TRY(keep.alloc(&P->p_N, C));
+    BA_TRY(keep.alloc(&P->p_slot, C));
+    BA_TRY(keep.alloc(&P->chunks, std::max<int64_t>(P->n_chunks, 1)));
+    BA_TRY(keep.alloc(&P->chunk_ptr, N + 1));
+    BA_TRY(keep.alloc(&P->partials, std::max<int64_t>(P->n_chunks, 1) * NPART));
+    BA_TRY(keep.alloc(&P->win_group_ptr, W + 1));
+    BA_TRY(keep.alloc(&P->win_pose_ptr, W + 1));
+    BA_TRY(keep.alloc(&P->pose_window, N));
+    BA_TRY(keep.alloc(&P->g, 6LL * N));
+    BA_TRY(keep.alloc(&P->H, 36LL * N));
+    BA_TRY(keep.alloc(&P->dx, 6LL * N));
+    BA_TRY(keep.alloc(&P->poses_trial, 12LL * N));
+    BA_TRY(keep.alloc(&P->pose_q, N));
+    BA_TRY(keep.alloc(&P->pose_info, N));
+    BA_TRY(keep.alloc(&P->lm, W));
+    P->h_win_pose_ptr = new int32_t[W + 1];
+    std::memcpy(P->h_win_pose_ptr, win_pose_ptr.data(), sizeof(int32_t) * (W + 1));
+
+    BA_HIP(hipMemsetAsync(P->v_mu, 0, sizeof(double) * 3 * CP, s));
+    BA_HIP(hipMemsetAsync(P->v_S, 0, sizeof(double) * 6 * CP, s));
+    BA_HIP(hipMemsetAsync(P->v_N, 0, sizeof(double) * CP, s));
+    BA_HIP(hipMemsetAsync(P->v_pose, 0, sizeof(int32_t) * CP, s));
+    BA_HIP(hipMemsetAsync(P->vstate, 0, sizeof(double) * 2 * std::max<int64_t>(NS, 1) * VSTATE, s));
+    BA_HIP(hipMemcpyAsync(P->groups, groups.data(), sizeof(GroupDesc) * groups.size(), hipMemcpyHostToDevice, s));
+    BA_HIP(hipMemcpyAsync(P->slot_vox, slot_vox.data(), sizeof(int32_t) * slot_vox.size(), hipMemcpyHostToDevice, s));
+    BA_HIP(hipMemcpyAsync(P->chunks, chunks.data(), sizeof(ChunkDesc) * chunks.size(), hipMemcpyHostToDevice, s));
+    BA_HIP(hipMemcpyAsync(P->chunk_ptr, chunk_ptr.data(), sizeof(int32_t) * (N + 1), hipMemcpyHostToDevice, s));
+    BA_HIP(hipMemcpyAsync(P->win_group_ptr, win_group_ptr.data(), sizeof(int32_t) * (W + 1), hipMemcpyHostToDevice, s));
+    BA_HIP(hipMemcpyAsync(P->win_pose_ptr, win_pose_ptr.data(), sizeof(int32_t) * (W + 1), hipMemcpyHostToDevice, s));
+    BA_HIP(hipMemcpyAsync(P->pose_window, pose_window.data(), sizeof(int32_t) * N, hipMemcpyHostToDevice, s));
+
+    // scatter / gather the cluster payload
+    DevArena tmp;
+    int64_t *d_dst;
+    int32_t *d_slot_of, *d_porder;
+    BA_TRY(tmp.alloc(&d_dst, C));
+    BA_TRY(tmp.alloc(&d_slot_of, C));
+    BA_TRY(tmp.alloc(&d_porder, C));
+    BA_HIP(hipMemcpyAsync(d_dst, dst.data(), sizeof(int64_t) * C, hipMemcpyHostToDevice, s));
+    BA_HIP(hipMemcpyAsync(d_slot_of, slot_of.data(), sizeof(int32_t) * C, hipMemcpyHostToDevice, s));
+    BA_HIP(hipMemcpyAsync(d_porder, porder.data(), sizeof(int32_t) * C, hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(k_scatter_vox, dim3(nblk(C)), dim3(256), 0, s, C, d_dst, CP, P->c_N, P->c_mu, P->c_S,
+                       P->c_scan, P->v_N, P->v_mu, P->v_S, P->v_pose);
+    hipLaunchKernelGGL(k_gather_pose, dim3(nblk(C)), dim3(256), 0, s, C, d_porder, d_slot_of, P->c_N, P->c_mu,
+                       P->c_S, P->p_N, P->p_mu, P->p_S, P->p_slot);
+    BA_HIP(hipGetLastError());
+    BA_HIP(hipStreamSynchronize(s));
+    return BA_OK;
+}
+
+static ba_status finish_build(Problem *P, DevArena &keep, const ba_build_options *opt, hipStream_t s) {
+    const int64_t C = P->n_clusters;
+    std::vector<int32_t> cvox(C), cscan(C);
+    BA_HIP(hipMemcpyAsync(cvox.data(), P->c_vox, sizeof(int32_t) * C, hipMemcpyDeviceToHost, s));
+    BA_HIP(hipMemcpyAsync(cscan.data(), P->c_scan, sizeof(int32_t) * C, hipMemcpyDeviceToHost, s));
+    BA_HIP(hipStreamSynchronize(s));
+    std::vector<int32_t> scan_window(P->n_poses, 0);
+    int32_t W = 1;
+    if (opt && opt->n_windows > 1) {
+        if (!opt->scan_window) {
+            set_error("n_windows > 1 needs scan_window");
+            return BA_E_ARG;
+        }
+        W = opt->n_windows;
+        for (int32_t j = 0; j < P->n_poses; j++) {
+            int32_t w = opt->scan_window[j];
+            if (w < 0 || w >= W || (j > 0 && w < scan_window[j - 1])) {
+                set_error("scan_window must be non-decreasing in [0, n_windows)");
+                return BA_E_ARG;
+            }
+            scan_window[j] = w;
+        }
+    }
+    P->n_windows = W;
+    return make_plan(P, cvox, cscan, scan_window, keep, s);
+}
+
+ba_status build_from_points(const ba_points *pts, const ba_build_options *opt, Problem *P, DevArena &keep,
+                            hipStream_t s) {
+    const int64_t n = pts->n;
+    if (n < 1 || n > (int64_t)0xFFFFFFFF) {
+        set_error("point count %lld out of range [1, 2^32)", (long long)n);
+        return BA_E_ARG;
+    }
+    if (!pts->x || !pts->y || !pts->z || !pts->scan || !pts->voxel || pts->n_scans < 1 || pts->n_voxels < 1) {
+        set_error("null point array or empty label range");
+        return BA_E_ARG;
+    }
+    P->n_poses = pts->n_scans;
+    P->n_voxels_in = pts->n_voxels;
+    P->chunk_len = (opt && opt->chunk_len > 0) ? opt->chunk_len : 1024;
+    DevArena tmp;
+    int32_t *err;
+    uint64_t *keys;
+    uint32_t *vals;
+    int64_t *flags, *total;
+    BA_TRY(tmp.alloc(&err, 1));
+    BA_TRY(tmp.alloc(&keys, n));
+    BA_TRY(tmp.alloc(&vals, n));
+    BA_TRY(tmp.alloc(&flags, n + 1));
+    BA_TRY(tmp.alloc(&total, 1));
+    size_t ws_bytes = std::max(radix_sort_workspace_bytes(n), scan_workspace_bytes(n));
+    char *ws;
+    BA_TRY(tmp.alloc(&ws, (int64_t)ws_bytes));
+    BA_HIP(hipMemsetAsync(err, 0, sizeof(int32_t), s));
+    hipLaunchKernelGGL(k_validate_points, dim3(nblk(n)), dim3(256), 0, s, n, pts->x, pts->y, pts->z, pts->scan,
+                       pts->voxel, pts->n_scans, pts->n_voxels, err);
+    hipLaunchKernelGGL(k_make_keys, dim3(nblk(n)), dim3(256), 0, s, n, pts->scan, pts->voxel, pts->n_scans, keys,
+                       vals);
+    BA_HIP(hipGetLastError());
+    int32_t herr = 0;
+    BA_HIP(hipMemcpyAsync(&herr, err, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    BA_HIP(hipStreamSynchronize(s));
+    if (herr) {
+        set_error("invalid points (flags 0x%x: 1 non-finite, 2 scan out of range, 4 voxel out of range)", herr);
+        return BA_E_ARG;
+    }
+    int bits = bit_length((uint64_t)pts->n_voxels * (uint64_t)pts->n_scans - 1);
+    BA_HIP(radix_sort_pairs(keys, vals, n, bits, ws, s));
+    hipLaunchKernelGGL(k_head_flags, dim3(nblk(n)), dim3(256), 0, s, n, keys, flags);
+    BA_HIP(exclusive_scan_i64(flags, flags, n, total, ws, s));
+    int64_t C = 0;
+    BA_HIP(hipMemcpyAsync(&C, total, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    BA_HIP(hipStreamSynchronize(s));
+    P->n_clusters = C;
+    int64_t *starts;
+    double *xs, *ys, *zs;
+    BA_TRY(tmp.alloc(&starts, C + 1));
+    BA_TRY(tmp.alloc(&xs, n));
+    BA_TRY(tmp.alloc(&ys, n));
+    BA_TRY(tmp.alloc(&zs, n));
+    hipLaunchKernelGGL(k_segment_starts, dim3(nblk(n)), dim3(256), 0, s, n, keys, flags, starts, C);
+    hipLaunchKernelGGL(k_gather_xyz, dim3(nblk(n)), dim3(256), 0, s, n, vals, pts->x, pts->y, pts->z, xs, ys, zs);
+    BA_TRY(keep.alloc(&P->c_N, C));
+    BA_TRY(keep.alloc(&P->c_mu, 3 * C));
+    BA_TRY(keep.alloc(&P->c_S, 6 * C));
+    BA_TRY(keep.alloc(&P->c_vox, C));
+    BA_TRY(keep.alloc(&P->c_scan, C));
+    hipLaunchKernelGGL(k_cluster_stats, dim3(nblk(C * 64)), dim3(256), 0, s, C, starts, xs, ys, zs, keys,
+                       pts->n_scans, P->c_N, P->c_mu, P->c_S, P->c_vox, P->c_scan);
+    BA_HIP(hipGetLastError());
+    return finish_build(P, keep, opt, s);
+}
+
+ba_status build_from_sums(const ba_cluster_sums *cs, const ba_build_options *opt, Problem *P, DevArena &keep,
+                          hipStream_t s) {
+    const int64_t n = cs->n;
+    if (n < 1 || n > (int64_t)0xFFFFFFFF) {
+        set_error("cluster count %lld out of range [1, 2^32)", (long long)n);
+        return BA_E_ARG;
+    }
+    if (!cs->voxel || !cs->scan || !cs->count || !cs->sum || !cs->sumsq || cs->n_scans < 1 || cs->n_voxels < 1) {
+        set_error("null cluster array or empty label range");
+        return BA_E_ARG;
+    }
+    P->n_poses = cs->n_scans;
+    P->n_voxels_in = cs->n_voxels;
+    P->chunk_len = (opt && opt->chunk_len > 0) ? opt->chunk_len : 1024;
+    DevArena tmp;
+    int32_t *err;
+    uint64_t *keys;
+    uint32_t *vals;
+    BA_TRY(tmp.alloc(&err, 1));
+    BA_TRY(tmp.alloc(&keys, n));
+    BA_TRY(tmp.alloc(&vals, n));
+    char *ws;
+    BA_TRY(tmp.alloc(&ws, (int64_t)radix_sort_workspace_bytes(n)));
+    BA_HIP(hipMemsetAsync(err, 0, sizeof(int32_t), s));
+    hipLaunchKernelGGL(k_validate_sums, dim3(nblk(n)), dim3(256), 0, s, n, cs->voxel, cs->scan, cs->count, cs->sum,
+                       cs->sumsq, cs->n_scans, cs->n_voxels, err);
+    hipLaunchKernelGGL(k_make_keys, dim3(nblk(n)), dim3(256), 0, s, n, cs->scan, cs->voxel, cs->n_scans, keys, vals);
+    int bits = bit_length((uint64_t)cs->n_voxels * (uint64_t)cs->n_scans - 1);
+    BA_HIP(radix_sort_pairs(keys, vals, n, bits, ws, s));
+    hipLaunchKernelGGL(k_dup_keys, dim3(nblk(n)), dim3(256), 0, s, n, keys, err);
+    BA_HIP(hipGetLastError());
+    int32_t herr = 0;
+    BA_HIP(hipMemcpyAsync(&herr, err, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    BA_HIP(hipStreamSynchronize(s));
+    if (herr) {
+        set_error("invalid clusters (flags 0x%x: 1 non-finite, 2 scan, 4 voxel, 8 count < 1, 16 duplicate pair)",
+                  herr);
+        return BA_E_ARG;
+    }
+    P->n_clusters = n;
+    BA_TRY(keep.alloc(&P->c_N, n));
+    BA_TRY(keep.alloc(&P->c_mu, 3 * n));
+    BA_TRY(keep.alloc(&P->c_S, 6 * n));
+    BA_TRY(keep.alloc(&P->c_vox, n));
+    BA_TRY(keep.alloc(&P->c_scan, n));
+    hipLaunchKernelGGL(k_center_sums, dim3(nblk(n)), dim3(256), 0, s, n, vals, keys, cs->count, cs->sum, cs->sumsq,
+                       cs->n_scans, P->c_N, P->c_mu, P->c_S, P->c_vox, P->c_scan);
+    BA_HIP(hipGetLastError());
+    return finish_build(P, keep, opt, s);
+}
+
+}  // namespace ba

@@ -1,0 +1,173 @@
+// Device-side helpers shared by the gfx950 kernels of libba.
+// Wave64 reductions, double-double error-free transforms, small 3x3 algebra.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#define BA_WAVE 64
+
+namespace ba {
+
+// ---------------------------------------------------------------- wave reductions
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, BA_WAVE);
+    return v;
+}
+
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, BA_WAVE));
+    return v;
+}
+
+__device__ __forceinline__ int wave_min_i(int v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o, BA_WAVE));
+    return v;
+}
+
+// ---------------------------------------------------------------- error-free transforms
+// Knuth TwoSum: s + e == a + b exactly.
+__device__ __forceinline__ void two_sum(double a, double b, double &s, double &e) {
+    s = a + b;
+    double bb = s - a;
+    e = (a - (s - bb)) + (b - bb);
+}
+
+// Double-double accumulator (hi, lo) += x.
+__device__ __forceinline__ void dd_add(double &hi, double &lo, double x) {
+    double s, e;
+    two_sum(hi, x, s, e);
+    e += lo;
+    two_sum(s, e, hi, lo);
+}
+
+// (hi, lo) += (bhi, blo)
+__device__ __forceinline__ void dd_add_dd(double &hi, double &lo, double bhi, double blo) {
+    double s, e;
+    two_sum(hi, bhi, s, e);
+    e += lo + blo;
+    two_sum(s, e, hi, lo);
+}
+
+__device__ __forceinline__ void wave_dd_sum(double &hi, double &lo) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        double h2 = __shfl_xor(hi, o, BA_WAVE), l2 = __shfl_xor(lo, o, BA_WAVE);
+        dd_add_dd(hi, lo, h2, l2);
+    }
+}
+
+// ---------------------------------------------------------------- 3x3 helpers
+struct Pose {
+    double r[9];
+    double t[3];
+};
+
+__device__ __forceinline__ void load_pose(const double *__restrict__ poses, int j, Pose &p) {
+    const double *q = poses + 12 * (int64_t)j;
+#pragma unroll
+    for (int k = 0; k < 9; k++) p.r[k] = q[k];
+#pragma unroll
+    for (int k = 0; k < 3; k++) p.t[k] = q[9 + k];
+}
+
+// y = R x
+__device__ __forceinline__ void rot(const double *r, const double *x, double *y) {
+    y[0] = fma(r[0], x[0], fma(r[1], x[1], r[2] * x[2]));
+    y[1] = fma(r[3], x[0], fma(r[4], x[1], r[5] * x[2]));
+    y[2] = fma(r[6], x[0], fma(r[7], x[1], r[8] * x[2]));
+}
+
+// St = R S R^T for symmetric S (6: xx xy xz yy yz zz); output 6 unique.
+__device__ __forceinline__ void rot_sym(const double *r, const double *s, double *o) {
+    // M = R S (3x3)
+    double m[9];
+#pragma unroll
+    for (int i = 0; i < 3; i++) {
+        m[3 * i + 0] = fma(r[3 * i], s[0], fma(r[3 * i + 1], s[1], r[3 * i + 2] * s[2]));
+        m[3 * i + 1] = fma(r[3 * i], s[1], fma(r[3 * i + 1], s[3], r[3 * i + 2] * s[4]));
+        m[3 * i + 2] = fma(r[3 * i], s[2], fma(r[3 * i + 1], s[4], r[3 * i + 2] * s[5]));
+    }
+    // O = M R^T : O_ij = sum_k M_ik R_jk
+    o[0] = fma(m[0], r[0], fma(m[1], r[1], m[2] * r[2]));
+    o[1] = fma(m[0], r[3], fma(m[1], r[4], m[2] * r[5]));
+    o[2] = fma(m[0], r[6], fma(m[1], r[7], m[2] * r[8]));
+    o[3] = fma(m[3], r[3], fma(m[4], r[4], m[5] * r[5]));
+    o[4] = fma(m[3], r[6], fma(m[4], r[7], m[5] * r[8]));
+    o[5] = fma(m[6], r[6], fma(m[7], r[7], m[8] * r[8]));
+}
+
+__device__ __forceinline__ void cross(const double *a, const double *b, double *c) {
+    c[0] = a[1] * b[2] - a[2] * b[1];
+    c[1] = a[2] * b[0] - a[0] * b[2];
+    c[2] = a[0] * b[1] - a[1] * b[0];
+}
+
+__device__ __forceinline__ double dot(const double *a, const double *b) {
+    return fma(a[0], b[0], fma(a[1], b[1], a[2] * b[2]));
+}
+
+// symmetric (6) times vector
+__device__ __forceinline__ void sym_mv(const double *s, const double *x, double *y) {
+    y[0] = fma(s[0], x[0], fma(s[1], x[1], s[2] * x[2]));
+    y[1] = fma(s[1], x[0], fma(s[3], x[1], s[4] * x[2]));
+    y[2] = fma(s[2], x[0], fma(s[4], x[1], s[5] * x[2]));
+}
+
+// ---------------------------------------------------------------- 3x3 symmetric eigen
+// Smallest eigenpair of a symmetric positive semi-definite 3x3 (6 unique).
+// Cyclic Jacobi rotations (Golub & Van Loan, Sec. 8.5) with a fixed sweep
+// budget and an early exit once every off-diagonal entry is negligible;
+// returns all three eigenvalues ascending in lam and the eigenvector of
+// lam[0] in u.
+__device__ __forceinline__ void jacobi_rot(double &app, double &aqq, double &apq, double &apr, double &aqr,
+                                           double *vp, double *vq) {
+    // annihilate apq; r is the remaining index.
+    if (apq == 0.0) return;
+    double theta = (aqq - app) / (2.0 * apq);
+    double t = (fabs(theta) > 1e150) ? 0.5 / theta
+                                     : copysign(1.0, theta) / (fabs(theta) + sqrt(fma(theta, theta, 1.0)));
+    double c = 1.0 / sqrt(fma(t, t, 1.0));
+    double s = t * c;
+    double tau = s / (1.0 + c);
+    double napp = app - t * apq;
+    double naqq = aqq + t * apq;
+    double r1 = apr - s * (aqr + tau * apr);
+    double r2 = aqr + s * (apr - tau * aqr);
+    app = napp; aqq = naqq; apq = 0.0; apr = r1; aqr = r2;
+#pragma unroll
+    for (int k = 0; k < 3; k++) {
+        double a = vp[k], b = vq[k];
+        vp[k] = a - s * (b + tau * a);
+        vq[k] = b + s * (a - tau * b);
+    }
+}
+
+__device__ __forceinline__ void eig_sym3(const double *A, double *lam, double *u) {
+    double a00 = A[0], a01 = A[1], a02 = A[2], a11 = A[3], a12 = A[4], a22 = A[5];
+    double v0[3] = {1, 0, 0}, v1[3] = {0, 1, 0}, v2[3] = {0, 0, 1};
+    for (int sweep = 0; sweep < 12; sweep++) {
+        double scale = fabs(a00) + fabs(a11) + fabs(a22);
+        double off = fabs(a01) + fabs(a02) + fabs(a12);
+        if (off <= 1e-22 * scale || off == 0.0) break;
+        // (0,1), remaining 2
+        jacobi_rot(a00, a11, a01, a02, a12, v0, v1);
+        // (0,2), remaining 1
+        jacobi_rot(a00, a22, a02, a01, a12, v0, v2);
+        // (1,2), remaining 0
+        jacobi_rot(a11, a22, a12, a01, a02, v1, v2);
+    }
+    // ascending order
+    double d[3] = {a00, a11, a22};
+    int i0 = 0, i1 = 1, i2 = 2;
+    if (d[i1] < d[i0]) { int t = i0; i0 = i1; i1 = t; }
+    if (d[i2] < d[i1]) { int t = i1; i1 = i2; i2 = t; }
+    if (d[i1] < d[i0]) { int t = i0; i0 = i1; i1 = t; }
+    lam[0] = d[i0]; lam[1] = d[i1]; lam[2] = d[i2];
+    const double *vs = (i0 == 0) ? v0 : (i0 == 1 ? v1 : v2);
+    u[0] = vs[0]; u[1] = vs[1]; u[2] = vs[2];
+}
+
+}  // namespace ba

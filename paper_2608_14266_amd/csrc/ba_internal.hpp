@@ -1,0 +1,117 @@
+// Internal (non-ABI) declarations of libba: the device-resident problem, the
+// build primitives and the kernel launchers.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stddef.h>
+
+#include "ba.h"
+#include "ba_host.hpp"
+
+namespace ba {
+
+static inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+// One K_vox wave group: up to 64 voxels with the same cluster count m, one
+// voxel per lane; cluster k of lane l lives at cbase + 64 k + l.
+struct GroupDesc {
+    int64_t cbase;
+    int32_t m;
+    int32_t nvox;
+    int32_t window;
+    int32_t pad;
+};
+
+// One pose chunk: `count` consecutive clusters of the pose-sorted layout,
+// all observed by `pose`.
+struct ChunkDesc {
+    int64_t start;
+    int32_t count;
+    int32_t pose;
+};
+
+// Device-side Levenberg-Marquardt state of one window.
+struct LMState {
+    double mu, nu;
+    double cost, cost_trial;
+    double q, rho;
+    double gnorm, maxdiag;
+    double cost0;
+    int32_t accepted, need_eval, info, done;
+    int32_t iters, n_accepted, cur, pad;
+};
+
+static constexpr int VSTATE = 8;    // doubles per voxel slot: u[3] mbar[3] 2/N lam0
+static constexpr int NPART = 27;    // g[6] + Hpp[6] + Hpt[9] + Htt[6]
+
+struct Problem {
+    int device = 0;
+    int32_t n_poses = 0, n_voxels_in = 0, n_windows = 1;
+    int64_t n_clusters = 0;
+    int32_t n_vox = 0;          // voxels with at least one cluster
+    int32_t n_groups = 0;
+    int64_t c_pad = 0;          // clusters incl. padding in the K_vox layout
+    int32_t n_chunks = 0;
+    int32_t chunk_len = 0;      // max clusters per pose chunk
+    int32_t max_m = 0;
+
+    // K_vox layout (component-major SoA, length c_pad per component)
+    double *v_mu = nullptr;     // [3][c_pad]
+    double *v_S = nullptr;      // [6][c_pad]
+    double *v_N = nullptr;      // [c_pad]
+    int32_t *v_pose = nullptr;  // [c_pad]
+    GroupDesc *groups = nullptr;
+    int32_t *slot_vox = nullptr; // slot -> input voxel id (-1 padding), n_groups*64
+    double *vstate = nullptr;   // [2][n_groups*64][VSTATE]
+    double *wave_cost = nullptr; // [n_groups]
+
+    // pose-sorted layout (length n_clusters per component)
+    double *p_mu = nullptr;     // [3][C]
+    double *p_S = nullptr;      // [6][C]
+    double *p_N = nullptr;      // [C]
+    int32_t *p_slot = nullptr;  // [C]
+    ChunkDesc *chunks = nullptr;
+    int32_t *chunk_ptr = nullptr; // [n_poses+1]
+    double *partials = nullptr; // [n_chunks][NPART]
+
+    // centred clusters in (voxel, scan) order, kept for export
+    double *c_mu = nullptr, *c_S = nullptr, *c_N = nullptr; // [C][3], [C][6], [C]
+    int32_t *c_vox = nullptr, *c_scan = nullptr;
+
+    // windows
+    int32_t *win_group_ptr = nullptr; // [n_windows+1]
+    int32_t *win_pose_ptr = nullptr;  // [n_windows+1]
+    int32_t *pose_window = nullptr;   // [n_poses]
+    int32_t *h_win_pose_ptr = nullptr; // host copy
+
+    // LM work buffers
+    double *g = nullptr, *H = nullptr;       // [N][6], [N][36]
+    double *dx = nullptr, *poses_trial = nullptr;
+    double *pose_q = nullptr;                 // [N]
+    int32_t *pose_info = nullptr;             // [N]
+    LMState *lm = nullptr;                    // [n_windows]
+    double *trace = nullptr;                  // [max_iters][n_windows][8]
+    int32_t trace_cap = 0;
+
+    // dense coupled path
+    int64_t *win_dense_off = nullptr;         // [n_windows+1] offsets (doubles) of each window's dense H
+    int64_t dense_total = 0;
+    double *dense = nullptr;                  // per-window dense (6Nw)^2 matrices
+
+    int64_t n_points = 0;
+    DevArena mem;                             // every device allocation above
+    ~Problem() { delete[] h_win_pose_ptr; }
+};
+
+ba_status build_from_points(const ba_points *pts, const ba_build_options *opt, Problem *P, DevArena &keep,
+                            hipStream_t s);
+ba_status build_from_sums(const ba_cluster_sums *cs, const ba_build_options *opt, Problem *P, DevArena &keep,
+                          hipStream_t s);
+
+// primitives
+size_t scan_workspace_bytes(int64_t n);
+hipError_t exclusive_scan_i64(const int64_t *in, int64_t *out, int64_t n, int64_t *total, void *ws, hipStream_t s);
+size_t radix_sort_workspace_bytes(int64_t n);
+hipError_t radix_sort_pairs(uint64_t *keys, uint32_t *vals, int64_t n, int bits, void *ws, hipStream_t s);
+
+}  // namespace ba

@@ -1,0 +1,26 @@
+// Host-side launchers of the iteration kernels (internal to libba).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "ba_internal.hpp"
+
+namespace ba {
+
+// evaluation (ba_eval.hip)
+void launch_vox(Problem *P, const double *poses, bool use_lm, bool trial, hipStream_t s);
+void launch_window_cost(Problem *P, double *out, hipStream_t s);
+void launch_pose_derivs(Problem *P, const double *poses, bool use_lm, double *g, double *H, hipStream_t s);
+void launch_voxel_eig(Problem *P, double *out, hipStream_t s);
+
+// LM (ba_lm.hip)
+size_t solve_mm_workspace(int32_t n);
+void launch_solve_mm_plain(int32_t n, const double *H, const double *g, double mu, double *dx, int32_t *info,
+                           void *ws, hipStream_t s);
+void launch_lm_reset(Problem *P, double mu0, double nu0, hipStream_t s);
+void launch_lm_cost(Problem *P, hipStream_t s);
+void launch_window_stats(Problem *P, double tol_g, hipStream_t s);
+void launch_solve_mm_lm(Problem *P, const double *poses, hipStream_t s);
+void launch_decide(Problem *P, double *trace, int it, hipStream_t s);
+void launch_commit(Problem *P, double *poses, hipStream_t s);
+
+}  // namespace ba

@@ -1,0 +1,377 @@
+// Increment solve, SE(3) update and Levenberg-Marquardt control, all on the
+// device so that an iteration needs no host round trip (the paper runs LM
+// sequentially on the CPU, Fig. 1; PredResReduction and Adjust of Alg. 2 are
+// declared there but not printed).
+//
+//  k_solve_mm   — Alg. 2 Solver: one thread per scan factors the 6x6
+//                 H_jj + mu D_jj by LDL^T, solves for dx_j, forms the trial
+//                 pose T_j (+) dx_j and its share of the predicted reduction.
+//  k_window_stats / k_decide / k_commit — per-window gradient norm and
+//                 damping floor, gain ratio and damping update, pose commit.
+#include <hip/hip_runtime.h>
+
+#include "ba.h"
+#include "ba_device.hpp"
+#include "ba_internal.hpp"
+#include "ba_kernels.hpp"
+
+namespace ba {
+
+// LDL^T solve of a 6x6 symmetric positive definite system held in registers.
+// Returns 0, or the 1-based index of the first non-positive pivot.
+__device__ __forceinline__ int ldlt6(double A[6][6], const double b[6], double x[6]) {
+    double d[6];
+#pragma unroll
+    for (int j = 0; j < 6; j++) {
+        double s = A[j][j];
+#pragma unroll
+        for (int k = 0; k < j; k++) s -= A[j][k] * A[j][k] * d[k];
+        if (!(s > 0.0)) return j + 1;
+        d[j] = s;
+        const double inv = 1.0 / s;
+#pragma unroll
+        for (int i = j + 1; i < 6; i++) {
+            double t = A[i][j];
+#pragma unroll
+            for (int k = 0; k < j; k++) t -= A[i][k] * A[j][k] * d[k];
+            A[i][j] = t * inv;  // L[i][j]
+        }
+    }
+    double y[6];
+#pragma unroll
+    for (int i = 0; i < 6; i++) {
+        double t = b[i];
+#pragma unroll
+        for (int k = 0; k < i; k++) t -= A[i][k] * y[k];
+        y[i] = t;
+    }
+#pragma unroll
+    for (int i = 0; i < 6; i++) y[i] /= d[i];
+#pragma unroll
+    for (int i = 5; i >= 0; i--) {
+        double t = y[i];
+#pragma unroll
+        for (int k = i + 1; k < 6; k++) t -= A[k][i] * x[k];
+        x[i] = t;
+    }
+    return 0;
+}
+
+// Exp(phi) as the rotation of the unit quaternion (cos(th/2), sin(th/2) phi/th);
+// the ratio sin(th/2)/th uses its Taylor series below 1e-4 rad.
+__device__ __forceinline__ void so3_exp(const double *phi, double *E) {
+    const double th2 = phi[0] * phi[0] + phi[1] * phi[1] + phi[2] * phi[2];
+    double w, k;
+    if (th2 < 1e-8) {
+        w = 1.0 - th2 * (1.0 / 8.0) + th2 * th2 * (1.0 / 384.0);
+        k = 0.5 - th2 * (1.0 / 48.0) + th2 * th2 * (1.0 / 3840.0);
+    } else {
+        const double th = sqrt(th2);
+        double sh, chh;
+        sincos(0.5 * th, &sh, &chh);
+        w = chh;
+        k = sh / th;
+    }
+    const double x = k * phi[0], y = k * phi[1], z = k * phi[2];
+    E[0] = 1.0 - 2.0 * (y * y + z * z);
+    E[1] = 2.0 * (x * y - z * w);
+    E[2] = 2.0 * (x * z + y * w);
+    E[3] = 2.0 * (x * y + z * w);
+    E[4] = 1.0 - 2.0 * (x * x + z * z);
+    E[5] = 2.0 * (y * z - x * w);
+    E[6] = 2.0 * (x * z - y * w);
+    E[7] = 2.0 * (y * z + x * w);
+    E[8] = 1.0 - 2.0 * (x * x + y * y);
+}
+
+// T (+) x = (Exp(phi) R, t + dt)
+__device__ __forceinline__ void pose_plus(const double *T, const double *x, double *out) {
+    double E[9];
+    so3_exp(x, E);
+#pragma unroll
+    for (int i = 0; i < 3; i++)
+#pragma unroll
+        for (int j = 0; j < 3; j++)
+            out[3 * i + j] = E[3 * i] * T[j] + E[3 * i + 1] * T[3 + j] + E[3 * i + 2] * T[6 + j];
+    out[9] = T[9] + x[3];
+    out[10] = T[10] + x[4];
+    out[11] = T[11] + x[5];
+}
+
+// Damped 6x6 solve of one scan; returns info (0 ok).  q_out = -(g dx + dx H dx / 2).
+__device__ __forceinline__ int solve_pose(const double *__restrict__ h, const double *__restrict__ gj, double mu,
+                                          double floor_, double *dxj, double &q_out) {
+    double A[6][6], b[6], x[6];
+#pragma unroll
+    for (int r = 0; r < 6; r++) {
+#pragma unroll
+        for (int c = 0; c < 6; c++) A[r][c] = h[6 * r + c];
+        const double hk = A[r][r];
+        A[r][r] += mu * (hk > floor_ ? hk : floor_);
+        b[r] = -gj[r];
+    }
+    const int info = ldlt6(A, b, x);
+    if (info) {
+#pragma unroll
+        for (int r = 0; r < 6; r++) dxj[r] = 0.0;
+        q_out = 0.0;
+        return info;
+    }
+    double gdx = 0.0, dhd = 0.0;
+#pragma unroll
+    for (int r = 0; r < 6; r++) {
+        gdx += gj[r] * x[r];
+        double hr = 0.0;
+#pragma unroll
+        for (int c = 0; c < 6; c++) hr += h[6 * r + c] * x[c];
+        dhd += x[r] * hr;
+        dxj[r] = x[r];
+    }
+    q_out = -(gdx + 0.5 * dhd);
+    return 0;
+}
+
+__global__ void k_lm_reset(int32_t W, LMState *__restrict__ lm, double mu0, double nu0) {
+    const int w = blockIdx.x * blockDim.x + threadIdx.x;
+    if (w >= W) return;
+    LMState s;
+    s.mu = mu0; s.nu = nu0; s.cost = 0.0; s.cost_trial = 0.0; s.q = 0.0; s.rho = 0.0;
+    s.gnorm = 0.0; s.maxdiag = 0.0; s.cost0 = 0.0;
+    s.accepted = 0; s.need_eval = 1; s.info = 0; s.done = 0;
+    s.iters = 0; s.n_accepted = 0; s.cur = 0; s.pad = 0;
+    lm[w] = s;
+}
+
+// block per window: cost at the current poses from the wave residuals
+__global__ __launch_bounds__(256) void k_lm_cost(int32_t W, const int32_t *__restrict__ win_group_ptr,
+                                                 const double *__restrict__ wave_cost, LMState *__restrict__ lm) {
+    __shared__ double red[256];
+    const int w = blockIdx.x;
+    if (w >= W) return;
+    double s = 0.0;
+    for (int i = win_group_ptr[w] + threadIdx.x; i < win_group_ptr[w + 1]; i += 256) s += wave_cost[i];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        lm[w].cost = red[0];
+        lm[w].cost0 = red[0];
+    }
+}
+
+// block per window: ||g|| and max diag(H) at freshly evaluated poses; convergence test.
+__global__ __launch_bounds__(256) void k_window_stats(int32_t W, const int32_t *__restrict__ win_pose_ptr,
+                                                      const double *__restrict__ g, const double *__restrict__ H,
+                                                      LMState *__restrict__ lm, double tol_g) {
+    __shared__ double rs[256], rm[256];
+    const int w = blockIdx.x;
+    if (w >= W) return;
+    LMState &st = lm[w];
+    if (st.done || !st.need_eval) return;
+    double s = 0.0, m = 0.0;
+    const int p0 = win_pose_ptr[w], p1 = win_pose_ptr[w + 1];
+    for (int i = 6 * p0 + threadIdx.x; i < 6 * p1; i += 256) {
+        s += g[i] * g[i];
+        const int j = i / 6, k = i % 6;
+        m = fmax(m, H[36LL * j + 7 * k]);
+    }
+    rs[threadIdx.x] = s;
+    rm[threadIdx.x] = m;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) {
+            rs[threadIdx.x] += rs[threadIdx.x + o];
+            rm[threadIdx.x] = fmax(rm[threadIdx.x], rm[threadIdx.x + o]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        st.gnorm = sqrt(rs[0]);
+        st.maxdiag = rm[0];
+        st.need_eval = 0;
+        if (tol_g > 0.0 && st.gnorm < tol_g) {
+            st.done = 1;
+            st.accepted = 0;
+        }
+    }
+}
+
+__global__ void k_solve_mm_lm(int32_t n_poses, const int32_t *__restrict__ pose_window,
+                              const int32_t *__restrict__ win_pose_ptr, const LMState *__restrict__ lm,
+                              const double *__restrict__ H, const double *__restrict__ g,
+                              const double *__restrict__ poses, double *__restrict__ dx, double *__restrict__ pose_q,
+                              int32_t *__restrict__ pose_info, double *__restrict__ poses_trial) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n_poses) return;
+    const int w = pose_window[j];
+    const LMState &st = lm[w];
+    if (st.done) return;
+    double q;
+    const int info = solve_pose(H + 36LL * j, g + 6LL * j, st.mu, 1e-12 * st.maxdiag, dx + 6LL * j, q);
+    pose_q[j] = q;
+    pose_info[j] = info ? 6 * (j - win_pose_ptr[w]) + info : 0;
+    pose_plus(poses + 12LL * j, dx + 6LL * j, poses_trial + 12LL * j);
+}
+
+// block per window: predicted reduction, trial cost, gain ratio, damping update.
+__global__ __launch_bounds__(256) void k_decide(int32_t W, const int32_t *__restrict__ win_pose_ptr,
+                                                const int32_t *__restrict__ win_group_ptr,
+                                                const double *__restrict__ pose_q,
+                                                const int32_t *__restrict__ pose_info,
+                                                const double *__restrict__ wave_cost, LMState *__restrict__ lm,
+                                                double *__restrict__ trace, int it) {
+    __shared__ double rq[256], rc[256];
+    __shared__ int ri[256];
+    const int w = blockIdx.x;
+    if (w >= W) return;
+    LMState &st = lm[w];
+    if (st.done) return;
+    double q = 0.0, c = 0.0;
+    int info = 0x7fffffff;
+    for (int j = win_pose_ptr[w] + threadIdx.x; j < win_pose_ptr[w + 1]; j += 256) {
+        q += pose_q[j];
+        if (pose_info[j]) info = min(info, pose_info[j]);
+    }
+    for (int i = win_group_ptr[w] + threadIdx.x; i < win_group_ptr[w + 1]; i += 256) c += wave_cost[i];
+    rq[threadIdx.x] = q;
+    rc[threadIdx.x] = c;
+    ri[threadIdx.x] = info;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) {
+            rq[threadIdx.x] += rq[threadIdx.x + o];
+            rc[threadIdx.x] += rc[threadIdx.x + o];
+            ri[threadIdx.x] = min(ri[threadIdx.x], ri[threadIdx.x + o]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const double qq = rq[0], ct = rc[0];
+        const int inf = (ri[0] == 0x7fffffff) ? 0 : ri[0];
+        const double rho = (inf == 0 && qq > 0.0) ? (st.cost - ct) / qq : -1.0;
+        const int acc = rho > 0.0;
+        if (trace) {
+            double *t = trace + ((int64_t)it * W + w) * 8;
+            t[0] = st.cost; t[1] = inf ? st.cost : ct; t[2] = rho; t[3] = st.mu;
+            t[4] = acc; t[5] = st.gnorm; t[6] = inf; t[7] = inf ? 0.0 : qq;
+        }
+        st.q = qq;
+        st.rho = rho;
+        st.info = inf;
+        st.cost_trial = ct;
+        st.accepted = acc;
+        st.iters += 1;
+        if (acc) {
+            st.cost = ct;
+            st.cur = 1 - st.cur;
+            st.need_eval = 1;
+            st.n_accepted += 1;
+            const double f = 2.0 * rho - 1.0;
+            const double fac = 1.0 - f * f * f;
+            st.mu *= (fac > 1.0 / 3.0 ? fac : 1.0 / 3.0);
+            st.nu = 2.0;
+        } else {
+            st.mu *= st.nu;
+            st.nu *= 2.0;
+        }
+    }
+}
+
+__global__ void k_commit(int32_t n_poses, const int32_t *__restrict__ pose_window, const LMState *__restrict__ lm,
+                         const double *__restrict__ poses_trial, double *__restrict__ poses) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= 12LL * n_poses) return;
+    const int j = (int)(i / 12);
+    const LMState &st = lm[pose_window[j]];
+    if (!st.done && st.accepted) poses[i] = poses_trial[i];
+}
+
+// ---------------------------------------------------------------- standalone MM solve
+__global__ __launch_bounds__(256) void k_maxdiag_mm(int32_t n, const double *__restrict__ H,
+                                                    double *__restrict__ out) {
+    __shared__ double rm[256];
+    double m = 0.0;
+    for (int i = threadIdx.x; i < 6 * n; i += 256) m = fmax(m, H[36LL * (i / 6) + 7 * (i % 6)]);
+    rm[threadIdx.x] = m;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) rm[threadIdx.x] = fmax(rm[threadIdx.x], rm[threadIdx.x + o]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[0] = rm[0];
+}
+
+__global__ void k_solve_mm_plain(int32_t n, const double *__restrict__ H, const double *__restrict__ g, double mu,
+                                 const double *__restrict__ maxdiag, double *__restrict__ dx,
+                                 int32_t *__restrict__ infos) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    double q;
+    const int info = solve_pose(H + 36LL * j, g + 6LL * j, mu, 1e-12 * maxdiag[0], dx + 6LL * j, q);
+    infos[j] = info ? 6 * j + info : 0;
+}
+
+__global__ __launch_bounds__(256) void k_solve_finish(int32_t n, const int32_t *__restrict__ infos,
+                                                      double *__restrict__ dx, int32_t *__restrict__ info) {
+    __shared__ int ri[256];
+    int m = 0x7fffffff;
+    for (int j = threadIdx.x; j < n; j += 256)
+        if (infos[j]) m = min(m, infos[j]);
+    ri[threadIdx.x] = m;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) ri[threadIdx.x] = min(ri[threadIdx.x], ri[threadIdx.x + o]);
+        __syncthreads();
+    }
+    const int r = (ri[0] == 0x7fffffff) ? 0 : ri[0];
+    if (r)
+        for (int i = threadIdx.x; i < 6 * n; i += 256) dx[i] = 0.0;
+    if (threadIdx.x == 0) *info = r;
+}
+
+static inline unsigned nblk(int64_t n, int t = 256) { return (unsigned)((n + t - 1) / t); }
+
+size_t solve_mm_workspace(int32_t n) { return align_up(sizeof(double), 256) + sizeof(int32_t) * (size_t)n + 256; }
+
+void launch_solve_mm_plain(int32_t n, const double *H, const double *g, double mu, double *dx, int32_t *info,
+                           void *ws, hipStream_t s) {
+    double *md = (double *)ws;
+    int32_t *infos = (int32_t *)((char *)ws + align_up(sizeof(double), 256));
+    hipLaunchKernelGGL(k_maxdiag_mm, dim3(1), dim3(256), 0, s, n, H, md);
+    hipLaunchKernelGGL(k_solve_mm_plain, dim3(nblk(n)), dim3(256), 0, s, n, H, g, mu, md, dx, infos);
+    hipLaunchKernelGGL(k_solve_finish, dim3(1), dim3(256), 0, s, n, infos, dx, info);
+}
+
+void launch_lm_reset(Problem *P, double mu0, double nu0, hipStream_t s) {
+    hipLaunchKernelGGL(k_lm_reset, dim3(nblk(P->n_windows)), dim3(256), 0, s, P->n_windows, P->lm, mu0, nu0);
+}
+
+void launch_lm_cost(Problem *P, hipStream_t s) {
+    hipLaunchKernelGGL(k_lm_cost, dim3(P->n_windows), dim3(256), 0, s, P->n_windows, P->win_group_ptr,
+                       P->wave_cost, P->lm);
+}
+
+void launch_window_stats(Problem *P, double tol_g, hipStream_t s) {
+    hipLaunchKernelGGL(k_window_stats, dim3(P->n_windows), dim3(256), 0, s, P->n_windows, P->win_pose_ptr, P->g,
+                       P->H, P->lm, tol_g);
+}
+
+void launch_solve_mm_lm(Problem *P, const double *poses, hipStream_t s) {
+    hipLaunchKernelGGL(k_solve_mm_lm, dim3(nblk(P->n_poses)), dim3(256), 0, s, P->n_poses, P->pose_window,
+                       P->win_pose_ptr, P->lm, P->H, P->g, poses, P->dx, P->pose_q, P->pose_info, P->poses_trial);
+}
+
+void launch_decide(Problem *P, double *trace, int it, hipStream_t s) {
+    hipLaunchKernelGGL(k_decide, dim3(P->n_windows), dim3(256), 0, s, P->n_windows, P->win_pose_ptr,
+                       P->win_group_ptr, P->pose_q, P->pose_info, P->wave_cost, P->lm, trace, it);
+}
+
+void launch_commit(Problem *P, double *poses, hipStream_t s) {
+    hipLaunchKernelGGL(k_commit, dim3(nblk(12LL * P->n_poses)), dim3(256), 0, s, P->n_poses, P->pose_window, P->lm,
+                       P->poses_trial, poses);
+}
+
+}  // namespace ba

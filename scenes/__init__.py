@@ -116,18 +116,25 @@ def _perturb(rng, r_true, t_true, rot_bound, trans_bound):
 
 
 def _emit_points(rng, centres, normals, obs_voxel, obs_scan, obs_npts, r_true, t_true,
-                 sigma, patch=1.0, chunk=200_000):
+                 sigma, patch=1.0, chunk=50_000):
     """Sample the raw points of every (voxel, scan) observation.
 
     Observations are emitted in the given order, each one's points contiguous.
+    A point is x = c + a e1 + b e2 + eps n in the world (a, b uniform on the
+    patch, eps ~ N(0, sigma^2)); its body-frame coordinates R^T (x - t) are
+    assembled from the observation's body-frame patch basis.
     """
     e1, e2 = _inplane_basis(normals)
+    rt = np.transpose(r_true, (0, 2, 1))            # R^T per scan
+    ro = rt[obs_scan]                               # (nobs, 3, 3)
+    o = np.einsum("nij,nj->ni", ro, centres[obs_voxel] - t_true[obs_scan])
+    f1 = np.einsum("nij,nj->ni", ro, e1[obs_voxel])
+    f2 = np.einsum("nij,nj->ni", ro, e2[obs_voxel])
+    f3 = np.einsum("nij,nj->ni", ro, normals[obs_voxel])
     total = int(obs_npts.sum())
-    x = np.empty(total)
-    y = np.empty(total)
-    z = np.empty(total)
-    scan = np.empty(total, np.int32)
-    voxel = np.empty(total, np.int32)
+    out = [np.empty(total), np.empty(total), np.empty(total)]
+    scan = np.repeat(obs_scan.astype(np.int32), obs_npts)
+    voxel = np.repeat(obs_voxel.astype(np.int32), obs_npts)
     offs = np.concatenate([[0], np.cumsum(obs_npts)])
     nobs = obs_voxel.shape[0]
     for a in range(0, nobs, chunk):
@@ -135,20 +142,21 @@ def _emit_points(rng, centres, normals, obs_voxel, obs_scan, obs_npts, r_true, t
         cnt = obs_npts[a:b]
         p0, p1 = int(offs[a]), int(offs[b])
         k = p1 - p0
-        ov = np.repeat(obs_voxel[a:b], cnt)
-        os_ = np.repeat(obs_scan[a:b], cnt)
-        u = rng.uniform(-0.5 * patch, 0.5 * patch, size=(k, 2))
-        eps = rng.standard_normal(k) * sigma
-        w = (centres[ov] + u[:, 0:1] * e1[ov] + u[:, 1:2] * e2[ov] + eps[:, None] * normals[ov])
-        d = w - t_true[os_]
-        rt = r_true[os_]
-        # p = R^T d
-        x[p0:p1] = rt[:, 0, 0] * d[:, 0] + rt[:, 1, 0] * d[:, 1] + rt[:, 2, 0] * d[:, 2]
-        y[p0:p1] = rt[:, 0, 1] * d[:, 0] + rt[:, 1, 1] * d[:, 1] + rt[:, 2, 1] * d[:, 2]
-        z[p0:p1] = rt[:, 0, 2] * d[:, 0] + rt[:, 1, 2] * d[:, 1] + rt[:, 2, 2] * d[:, 2]
-        scan[p0:p1] = os_
-        voxel[p0:p1] = ov
-    return x, y, z, scan, voxel
+        ua = rng.uniform(-0.5 * patch, 0.5 * patch, size=k)
+        ub = rng.uniform(-0.5 * patch, 0.5 * patch, size=k)
+        eps = rng.standard_normal(k)
+        eps *= sigma
+        tmp = np.empty(k)
+        for d in range(3):
+            dst = out[d][p0:p1]
+            dst[:] = np.repeat(o[a:b, d], cnt)
+            np.multiply(ua, np.repeat(f1[a:b, d], cnt), out=tmp)
+            dst += tmp
+            np.multiply(ub, np.repeat(f2[a:b, d], cnt), out=tmp)
+            dst += tmp
+            np.multiply(eps, np.repeat(f3[a:b, d], cnt), out=tmp)
+            dst += tmp
+    return out[0], out[1], out[2], scan, voxel
 
 
 def _shuffle_points(rng, sc_arrays):
@@ -249,23 +257,25 @@ def window_scene(seed: int = 2000, n_scans: int = 500, n_planes: int = 200_000, 
     pk = (1 - geom_p) ** (k - 1) * geom_p
     pk /= pk.sum()
     m = rng.choice(k, size=n_planes, p=pk)
-    obs_v, obs_s = [], []
-    # nearest poses: process planes in batches against all poses
-    for a in range(0, n_planes, 4096):
-        b = min(n_planes, a + 4096)
-        dist = np.linalg.norm(centres[a:b, None, :] - t_true[None, :, :], axis=2)
-        order = np.argsort(dist, axis=1, kind="stable")[:, :m_max]
-        dsort = np.take_along_axis(dist, order, axis=1)
-        for ii in range(b - a):
-            i = a + ii
-            ok = order[ii][dsort[ii] <= obs_radius][: int(m[i])]
-            if ok.shape[0] == 0:
-                ok = order[ii][:1]
-            sc = np.sort(ok)
-            obs_v.append(np.full(sc.shape[0], i, np.int32))
-            obs_s.append(sc.astype(np.int32))
-    obs_v = np.concatenate(obs_v)
-    obs_s = np.concatenate(obs_s)
+    # the m nearest poses within obs_radius (at least the nearest one)
+    from scipy.spatial import cKDTree
+    tree = cKDTree(t_true)
+    kq = min(m_max, n_scans)
+    dist, idx = tree.query(centres, k=kq, distance_upper_bound=obs_radius)
+    dist = dist.reshape(n_planes, kq)
+    idx = idx.reshape(n_planes, kq)
+    valid = np.isfinite(dist) & (np.arange(kq)[None, :] < m[:, None])
+    none = ~valid.any(axis=1)
+    if none.any():
+        _, nn = tree.query(centres[none], k=1)
+        idx[none, 0] = nn
+        valid[none, 0] = True
+    big = np.iinfo(np.int64).max
+    sidx = np.where(valid, idx, big)
+    sidx.sort(axis=1)
+    keep = sidx != big
+    obs_s = sidx[keep].astype(np.int32)
+    obs_v = np.repeat(np.arange(n_planes, dtype=np.int32), keep.sum(axis=1))
     lo, hi = pts_range
     npts = np.rint(np.exp(rng.uniform(math.log(lo), math.log(hi), size=obs_v.shape[0]))).astype(np.int64)
     npts = np.clip(npts, lo, hi)
