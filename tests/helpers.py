@@ -29,3 +29,33 @@ def grad_rel_err(g, g_ref, g_abs_scale):
     d = np.linalg.norm(np.asarray(g) - np.asarray(g_ref))
     nref = np.linalg.norm(g_ref)
     return d / max(nref, 1e-3 * g_abs_scale, 1e-300)
+
+
+def cost_floor(orc, cl, poses):
+    """Absolute rounding floor of the cost: each lambda_min is only defined to
+    about eps * ||A_i|| by any backward-stable eigen-solver, so a cost that is
+    zero in exact arithmetic is compared against 1e-14 * sum_i lambda_max(A_i)."""
+    st = orc.voxel_stats(cl, poses)
+    return 1e-14 * float(np.sum(st["lam"][:, 2]))
+
+
+def resolved_prefix(tr, rep_ref, rtol=1e-11, floor=None):
+    """Number of leading LM iterations whose accept / reject decision is
+    resolved on both sides: the actual and the predicted cost changes exceed
+    rtol of the cost.  Past that point the decision is set by rounding noise
+    (several outcomes are correct) and traces are compared only at the end."""
+    k = 0
+    if floor is None:
+        floor = 1e-12 * abs(rep_ref[0][0])
+    for a, b in zip(tr, rep_ref):
+        c = max(abs(b[0]), 1e-300)
+        ok = True
+        for r in (a, b):
+            if r[6] != 0:      # failed factorization: decision is exact
+                continue
+            if abs(r[0] - r[1]) < rtol * c + floor or abs(r[7]) < rtol * c + floor:
+                ok = False
+        if not ok:
+            break
+        k += 1
+    return k
