@@ -80,7 +80,7 @@ typedef struct ba_cluster_sums {
 } ba_cluster_sums;
 
 typedef struct ba_build_options {
-    int32_t chunk_len;          /* clusters per pose chunk of the derivative pass; 0 = default (1024) */
+    int32_t chunk_len;          /* clusters per pose chunk of the derivative pass; 0 = default (256) */
     int32_t n_windows;          /* 0 or 1 = one problem; > 1 = independent windows (batched form) */
     const int32_t *scan_window; /* host, n_scans entries, non-decreasing window id per scan; NULL if n_windows <= 1 */
 } ba_build_options;

@@ -15,9 +15,18 @@
 #include "ba_internal.hpp"
 #include "ba_kernels.hpp"
 
+namespace ba {
+void dense_release(Problem *P);
+}
+
 struct ba_problem {
     ba::Problem P;
 };
+
+ba::Problem::~Problem() {
+    dense_release(this);
+    delete[] h_win_pose_ptr;
+}
 
 namespace ba {
 
@@ -35,7 +44,8 @@ size_t dense_solve_workspace(int64_t n);
 ba_status dense_assemble(Problem *P, const double *poses, double *hess_out, bool use_lm, hipStream_t s);
 ba_status dense_solve(int64_t n, const double *A, const double *g, double mu, double *dx, int32_t *info, void *ws,
                       size_t ws_bytes, hipStream_t s);
-ba_status dense_lm_step(Problem *P, const double *poses, hipStream_t s);
+ba_status dense_lm_step(Problem *P, const double *poses, double tol_g, hipStream_t s);
+void dense_release(Problem *P);
 ba_status dense_prepare(Problem *P);
 
 // ---------------------------------------------------------------- profiling
@@ -336,12 +346,10 @@ ba_status ba_iterate(ba_problem *p, double *poses_inout, const ba_lm_options *op
             launch_solve_mm_lm(P, poses_inout, stream);
         } else {
             BA_TRY(dense_assemble(P, poses_inout, nullptr, true, stream));
-            launch_window_stats(P, opt->tol_g, stream);
-            BA_TRY(dense_lm_step(P, poses_inout, stream));
+            BA_TRY(dense_lm_step(P, poses_inout, opt->tol_g, stream));
         }
         launch_vox(P, P->poses_trial, true, true, stream);
-        launch_decide(P, dtrace, it, stream);
-        launch_commit(P, poses_inout, stream);
+        launch_decide(P, dtrace, it, poses_inout, stream);
     }
     // derivatives at the final poses (windows whose last step was accepted),
     // so that the reported gradient norm belongs to the returned poses

@@ -378,7 +378,8 @@ static ba_status make_plan(Problem *P, const std::vector<int32_t> &cvox, const s
     int64_t *d_dst;
     int32_t *d_slot_of, *d_porder;
     BA_TRY(tmp.alloc(&d_dst, C));
-    BA_TRY(tmp.alloc(&d_slot_of, C));
+    BA_TRY(keep.alloc(&P->c_slot, C));
+    d_slot_of = P->c_slot;
     BA_TRY(tmp.alloc(&d_porder, C));
     BA_HIP(hipMemcpyAsync(d_dst, dst.data(), sizeof(int64_t) * C, hipMemcpyHostToDevice, s));
     BA_HIP(hipMemcpyAsync(d_slot_of, slot_of.data(), sizeof(int32_t) * C, hipMemcpyHostToDevice, s));
@@ -432,7 +433,7 @@ ba_status build_from_points(const ba_points *pts, const ba_build_options *opt, P
     }
     P->n_poses = pts->n_scans;
     P->n_voxels_in = pts->n_voxels;
-    P->chunk_len = (opt && opt->chunk_len > 0) ? opt->chunk_len : 1024;
+    P->chunk_len = (opt && opt->chunk_len > 0) ? opt->chunk_len : 256;
     DevArena tmp;
     int32_t *err;
     uint64_t *keys;
@@ -499,7 +500,7 @@ ba_status build_from_sums(const ba_cluster_sums *cs, const ba_build_options *opt
     }
     P->n_poses = cs->n_scans;
     P->n_voxels_in = cs->n_voxels;
-    P->chunk_len = (opt && opt->chunk_len > 0) ? opt->chunk_len : 1024;
+    P->chunk_len = (opt && opt->chunk_len > 0) ? opt->chunk_len : 256;
     DevArena tmp;
     int32_t *err;
     uint64_t *keys;

@@ -1,32 +1,781 @@
-// Dense coupled path (pose-pair Hessian blocks and blocked Cholesky).
+// Coupled Hessian and its dense damped solve.
+//
+// The first-stage majorizer u^T A_i(T) u of Eq. 1 (u frozen at T_l) keeps the
+// poses coupled: its Hessian is the block diagonal of the Eq. 3 surrogate
+// minus 2 h_ij h_ik^T for every pair of scans (j, k) observing voxel i, with
+//     h_ij = (N_ij / N_i) [ (R_j mu_ij) x u ; u ].
+// Assembly is deterministic and atomic-free: the plan lists every (voxel,
+// j <= k) contribution sorted by the pose-pair key (j, k); one wavefront sums
+// each key's contributions in a fixed order and writes that 6x6 block (and
+// its transpose) of the dense per-window matrix.
+//
+// The damped system (H + mu D) dx = -g is solved by a right-looking blocked
+// Cholesky with 64-wide panels (Alg. 2's Solver replaced by a dense one in
+// this coupled form): the diagonal block is factored and inverted in LDS,
+// the panel solve (P L^-T) and the trailing update (C -= P_I P_J^T) run on
+// FP64 matrix cores (v_mfma_f64_16x16x4f64), the forward substitution rides
+// along the panel steps, and the backward substitution sweeps the block
+// rows.  Every kernel is batched over independent windows (blockIdx.y).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <cmath>
+#include <numeric>
+#include <vector>
+
 #include "ba.h"
+#include "ba_device.hpp"
 #include "ba_internal.hpp"
+#include "ba_kernels.hpp"
 
 namespace ba {
 
-size_t dense_solve_workspace(int64_t n) { return 256; }
+typedef double d4 __attribute__((ext_vector_type(4)));
 
-ba_status dense_prepare(Problem *P) {
-    set_error("coupled mode not built yet");
-    return BA_E_UNSUPPORTED;
+static constexpr int TB = 64;         // tile / panel width
+static constexpr int LDK = 33;        // LDS row stride of a 32-wide K chunk (padded)
+
+// One dense matrix of the batch.
+struct DenseDesc {
+    int64_t a_off;     // doubles: start of the n x n row-major matrix
+    int64_t linv_off;  // doubles: start of ceil(n/64) inverted 64x64 diagonal blocks
+    int64_t v_off;     // doubles: start of the n-vector (right-hand side / forward result)
+    int32_t n;
+    int32_t pose0;     // first scan of the window (LM use)
+};
+
+// Per-matrix solve parameters.
+struct DenseParam {
+    double mu;
+    double floor_;
+    int32_t active;
+    int32_t info;
+};
+
+// ---------------------------------------------------------------- assembly
+// h_c = (N_c / N_i) [ (R mu_c) x u ; u ] for every cluster (voxel-major order)
+__global__ void k_hvec(int64_t C, const double *__restrict__ cN, const double *__restrict__ cmu,
+                       const int32_t *__restrict__ cscan, const int32_t *__restrict__ cslot,
+                       const double *__restrict__ poses, const double *__restrict__ vstate, int64_t n_slots,
+                       const int32_t *__restrict__ pose_window, const LMState *__restrict__ lm,
+                       double *__restrict__ h) {
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= C) return;
+    const int j = cscan[c];
+    int buf = 0;
+    if (lm) {
+        const LMState &st = lm[pose_window[j]];
+        if (st.done || !st.need_eval) return;
+        buf = st.cur;
+    }
+    const double *st = vstate + ((int64_t)buf * n_slots + cslot[c]) * VSTATE;
+    const double u[3] = {st[0], st[1], st[2]};
+    const double f = cN[c] * (0.5 * st[6]);
+    Pose P;
+    load_pose(poses, j, P);
+    const double mu[3] = {cmu[3 * c], cmu[3 * c + 1], cmu[3 * c + 2]};
+    double y[3], a[3];
+    rot(P.r, mu, y);
+    cross(y, u, a);
+    double *o = h + 6 * c;
+    o[0] = f * a[0]; o[1] = f * a[1]; o[2] = f * a[2];
+    o[3] = f * u[0]; o[4] = f * u[1]; o[5] = f * u[2];
 }
 
+__global__ void k_fill(int64_t n, double *__restrict__ p, double v) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+struct PairSeg {
+    int64_t start;
+    int32_t count;
+    int32_t ja, jb;   // scans, ja <= jb
+    int32_t pad;
+};
+
+// One wavefront per pose-pair key: block(ja, jb) = [H_MM(ja) if ja == jb] - 2 sum h_a h_b^T
+__global__ __launch_bounds__(256) void k_pairs(int32_t n_seg, const PairSeg *__restrict__ segs,
+                                               const int32_t *__restrict__ pa, const int32_t *__restrict__ pb,
+                                               const double *__restrict__ h, const double *__restrict__ Hmm,
+                                               const int32_t *__restrict__ pose_window,
+                                               const int32_t *__restrict__ win_pose_ptr,
+                                               const int64_t *__restrict__ win_off, const LMState *__restrict__ lm,
+                                               double *__restrict__ dense) {
+    const int wave = (int)(((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6);
+    const int lane = threadIdx.x & 63;
+    if (wave >= n_seg) return;
+    const PairSeg sg = segs[wave];
+    const int w = pose_window[sg.ja];
+    if (lm) {
+        const LMState &st = lm[w];
+        if (st.done || !st.need_eval) return;
+    }
+    double acc[36];
+#pragma unroll
+    for (int q = 0; q < 36; q++) acc[q] = 0.0;
+    for (int i = lane; i < sg.count; i += 64) {
+        const int64_t a = pa[sg.start + i], b = pb[sg.start + i];
+        double ha[6], hb[6];
+#pragma unroll
+        for (int q = 0; q < 6; q++) {
+            ha[q] = h[6 * a + q];
+            hb[q] = h[6 * b + q];
+        }
+#pragma unroll
+        for (int r = 0; r < 6; r++)
+#pragma unroll
+            for (int s = 0; s < 6; s++) acc[6 * r + s] = fma(ha[r], hb[s], acc[6 * r + s]);
+    }
+#pragma unroll
+    for (int q = 0; q < 36; q++) acc[q] = wave_sum(acc[q]);
+    if (lane < 36) {
+        const int r = lane / 6, s = lane % 6;
+        double v = 0.0;
+#pragma unroll
+        for (int q = 0; q < 36; q++)
+            if (q == lane) v = acc[q];
+        const int p0 = win_pose_ptr[w];
+        const int64_t nw = 6LL * (win_pose_ptr[w + 1] - p0);
+        const int la = sg.ja - p0, lb = sg.jb - p0;
+        double *D = dense + win_off[w];
+        double out = -2.0 * v;
+        if (sg.ja == sg.jb) out += Hmm[36LL * sg.ja + 6 * r + s];
+        D[(6LL * la + r) * nw + 6 * lb + s] = out;
+        if (sg.ja != sg.jb) D[(6LL * lb + s) * nw + 6 * la + r] = out;
+    }
+}
+
+// ---------------------------------------------------------------- MFMA tile helpers
+// Stage a 64 x 32 chunk (rows r0.., columns k0..k0+31) of a row-major matrix
+// (leading dimension ld, valid rows < nr, valid columns < nc) into LDS.
+__device__ __forceinline__ void stage_chunk(double *__restrict__ lds, const double *__restrict__ M, int64_t ld,
+                                            int64_t r0, int64_t k0, int64_t nr, int64_t nc) {
+#pragma unroll
+    for (int e = 0; e < 8; e++) {
+        const int idx = threadIdx.x + 256 * e;
+        const int row = idx >> 5, col = idx & 31;
+        const int64_t gr = r0 + row, gc = k0 + col;
+        lds[row * LDK + col] = (gr < nr && gc < nc) ? M[gr * ld + gc] : 0.0;
+    }
+}
+
+// acc += A_chunk (64x32) * B_chunk (64x32)^T for this wave's 32x32 quadrant.
+// v_mfma_f64_16x16x4f64 operand layout on gfx950 (lane l): A[l%16][l/16],
+// B[l/16][l%16]; accumulator register r holds D[l/16 + 4r][l%16].
+__device__ __forceinline__ void mma_chunk(const double *__restrict__ As, const double *__restrict__ Bs,
+                                          d4 acc[2][2]) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int r0 = 32 * (w >> 1), c0 = 32 * (w & 1);
+    const int li = lane & 15, lk = lane >> 4;
+#pragma unroll
+    for (int kk = 0; kk < 32; kk += 4) {
+        const double a0 = As[(r0 + li) * LDK + kk + lk];
+        const double a1 = As[(r0 + 16 + li) * LDK + kk + lk];
+        const double b0 = Bs[(c0 + li) * LDK + kk + lk];
+        const double b1 = Bs[(c0 + 16 + li) * LDK + kk + lk];
+        acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
+        acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
+        acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
+        acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
+    }
+}
+
+// tile(64x64) = A(rows ra.., cols ka..ka+63) * B(rows rb.., cols kb..kb+63)^T, result in acc
+__device__ __forceinline__ void tile_gemm_nt(double *__restrict__ As, double *__restrict__ Bs,
+                                             const double *__restrict__ A, int64_t lda, int64_t ra, int64_t ka,
+                                             int64_t nra, int64_t nca, const double *__restrict__ B, int64_t ldb,
+                                             int64_t rb, int64_t kb, int64_t nrb, int64_t ncb, d4 acc[2][2]) {
+#pragma unroll
+    for (int i = 0; i < 2; i++)
+#pragma unroll
+        for (int j = 0; j < 2; j++) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+    for (int kc = 0; kc < 64; kc += 32) {
+        stage_chunk(As, A, lda, ra, ka + kc, nra, nca);
+        stage_chunk(Bs, B, ldb, rb, kb + kc, nrb, ncb);
+        __syncthreads();
+        mma_chunk(As, Bs, acc);
+        __syncthreads();
+    }
+}
+
+// element (row, col) of the 64x64 tile held in acc[rb][cb][r] by this lane
+#define ACC_ROW(rb, r) (32 * ((threadIdx.x >> 6) >> 1) + 16 * (rb) + ((threadIdx.x & 63) >> 4) + 4 * (r))
+#define ACC_COL(cb) (32 * ((threadIdx.x >> 6) & 1) + 16 * (cb) + (threadIdx.x & 15))
+
+// ---------------------------------------------------------------- factorization
+// A = H + mu max(diag H, floor) ; v = -g
+__global__ void k_damp_copy(const DenseDesc *__restrict__ desc, const DenseParam *__restrict__ prm,
+                            const double *__restrict__ H, const int64_t *__restrict__ h_off,
+                            const double *__restrict__ g, double *__restrict__ work) {
+    const int m = blockIdx.y;
+    const DenseDesc d = desc[m];
+    const DenseParam p = prm[m];
+    if (!p.active) return;
+    const int64_t nn = (int64_t)d.n * d.n;
+    const double *Hm = H + h_off[m];
+    double *A = work + d.a_off;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nn; i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t r = i / d.n, c = i % d.n;
+        double v = Hm[i];
+        if (r == c) v += p.mu * (v > p.floor_ ? v : p.floor_);
+        A[i] = v;
+    }
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < d.n) work[d.v_off + t] = -g[6LL * d.pose0 + t];
+}
+
+// Factor diagonal block `step` in LDS, invert it in place, forward-substitute
+// its slice of the right-hand side.  LDS: one padded 64x64 tile + two vectors.
+__global__ __launch_bounds__(256) void k_potf2(const DenseDesc *__restrict__ desc, DenseParam *__restrict__ prm,
+                                               double *__restrict__ work, int step) {
+    __shared__ double L[TB][TB + 1];
+    __shared__ double col[TB];
+    __shared__ double bv[TB];
+    __shared__ int fail;
+    const int m = blockIdx.y;
+    const DenseDesc d = desc[m];
+    if (!prm[m].active || prm[m].info) return;
+    const int64_t k0 = (int64_t)TB * step;
+    if (k0 >= d.n) return;
+    const int nb = (int)std::min<int64_t>(TB, d.n - k0);
+    double *A = work + d.a_off;
+    const int t = threadIdx.x;
+    for (int e = t; e < TB * TB; e += 256) {
+        const int i = e / TB, j = e % TB;
+        L[i][j] = (i < nb && j < nb) ? A[(k0 + i) * d.n + k0 + j] : (i == j ? 1.0 : 0.0);
+    }
+    if (t < TB) bv[t] = (t < nb) ? work[d.v_off + k0 + t] : 0.0;
+    if (t == 0) fail = 0;
+    __syncthreads();
+    // right-looking unblocked Cholesky of the (padded) tile
+    for (int j = 0; j < nb; j++) {
+        if (t == 0) {
+            const double p = L[j][j];
+            if (!(p > 0.0)) fail = (int)(k0 + j + 1);
+            else L[j][j] = sqrt(p);
+        }
+        __syncthreads();
+        if (fail) break;
+        const double dj = L[j][j];
+        for (int i = j + 1 + t; i < TB; i += 256) L[i][j] = (i < nb) ? L[i][j] / dj : 0.0;
+        __syncthreads();
+        const int rem = nb - j - 1;
+        for (int e = t; e < rem * rem; e += 256) {
+            const int i = j + 1 + e / rem, c = j + 1 + e % rem;
+            if (c <= i) L[i][c] -= L[i][j] * L[c][j];
+        }
+        __syncthreads();
+    }
+    if (fail) {
+        if (t == 0) prm[m].info = fail;
+        return;
+    }
+    for (int e = t; e < TB * TB; e += 256) {
+        const int i = e / TB, j = e % TB;
+        if (i < nb && j < nb && j <= i) A[(k0 + i) * d.n + k0 + j] = L[i][j];
+    }
+    __syncthreads();
+    // in-place inverse of the lower factor, columns right to left:
+    // X_jj = 1 / L_jj,  X_ij = -(sum_{k=j+1..i} X_ik L_kj) / L_jj  (i > j)
+    for (int j = TB - 1; j >= 0; j--) {
+        if (t < TB) col[t] = (t >= j) ? L[t][j] : 0.0;
+        __syncthreads();
+        if (t > j && t < TB) {
+            double s = 0.0;
+            for (int k = j + 1; k <= t; k++) s += L[t][k] * col[k];
+            L[t][j] = -s / col[j];
+        }
+        if (t == j) L[j][j] = 1.0 / col[j];
+        __syncthreads();
+    }
+    double *linv = work + d.linv_off + (int64_t)step * TB * TB;
+    for (int e = t; e < TB * TB; e += 256) {
+        const int i = e / TB, j = e % TB;
+        linv[e] = (j <= i) ? L[i][j] : 0.0;
+    }
+    // y_k = L_kk^-1 b_k
+    if (t < nb) {
+        double s = 0.0;
+        for (int c = 0; c <= t; c++) s += L[t][c] * bv[c];
+        work[d.v_off + k0 + t] = s;
+    }
+}
+
+// Panel solve on matrix cores: rows below block `step`:  P <- P L_kk^-T,
+// then b_rows -= P y_k (forward substitution).
+__global__ __launch_bounds__(256) void k_trsm(const DenseDesc *__restrict__ desc, const DenseParam *__restrict__ prm,
+                                              double *__restrict__ work, int step) {
+    // one staging buffer: the two K chunks during the product, then the result tile
+    __shared__ double sm[2 * TB * LDK];
+    __shared__ double yk[TB];
+    double *As = sm, *Bs = sm + TB * LDK;
+    double(*Ts)[TB + 1] = (double(*)[TB + 1])sm;
+    const int m = blockIdx.y;
+    const DenseDesc d = desc[m];
+    if (!prm[m].active || prm[m].info) return;
+    const int64_t k0 = (int64_t)TB * step;
+    const int64_t R0 = k0 + TB + (int64_t)TB * blockIdx.x;
+    if (R0 >= d.n) return;
+    double *A = work + d.a_off;
+    const double *linv = work + d.linv_off + (int64_t)step * TB * TB;
+    d4 acc[2][2];
+    tile_gemm_nt(As, Bs, A, d.n, R0, k0, d.n, k0 + TB, linv, TB, 0, 0, TB, TB, acc);
+    const int64_t nrow = std::min<int64_t>(TB, d.n - R0);
+#pragma unroll
+    for (int rb = 0; rb < 2; rb++)
+#pragma unroll
+        for (int cb = 0; cb < 2; cb++)
+#pragma unroll
+            for (int r = 0; r < 4; r++) {
+                const int row = ACC_ROW(rb, r), col = ACC_COL(cb);
+                Ts[row][col] = acc[rb][cb][r];
+                if (row < nrow) A[(R0 + row) * d.n + k0 + col] = acc[rb][cb][r];
+            }
+    if (threadIdx.x < TB) yk[threadIdx.x] = work[d.v_off + k0 + threadIdx.x];
+    __syncthreads();
+    if (threadIdx.x < nrow) {
+        double s = 0.0;
+        for (int c = 0; c < TB; c++) s += Ts[threadIdx.x][c] * yk[c];
+        work[d.v_off + R0 + threadIdx.x] -= s;
+    }
+}
+
+// Trailing update on matrix cores: C_IJ -= P_I P_J^T for tiles I >= J.
+__global__ __launch_bounds__(256) void k_syrk(const DenseDesc *__restrict__ desc, const DenseParam *__restrict__ prm,
+                                              double *__restrict__ work, int step) {
+    __shared__ double sm[2 * TB * LDK];
+    double *As = sm, *Bs = sm + TB * LDK;
+    const int m = blockIdx.y;
+    const DenseDesc d = desc[m];
+    if (!prm[m].active || prm[m].info) return;
+    const int64_t k0 = (int64_t)TB * step;
+    const int64_t T0 = k0 + TB;
+    if (T0 >= d.n) return;
+    const int64_t nt = (d.n - T0 + TB - 1) / TB;
+    const int64_t idx = blockIdx.x;
+    if (idx >= nt * (nt + 1) / 2) return;
+    int64_t I = (int64_t)((sqrt(8.0 * (double)idx + 1.0) - 1.0) * 0.5);
+    while (I * (I + 1) / 2 > idx) I--;
+    while ((I + 1) * (I + 2) / 2 <= idx) I++;
+    const int64_t J = idx - I * (I + 1) / 2;
+    const int64_t ri = T0 + TB * I, rj = T0 + TB * J;
+    double *A = work + d.a_off;
+    d4 acc[2][2];
+    tile_gemm_nt(As, Bs, A, d.n, ri, k0, d.n, k0 + TB, A, d.n, rj, k0, d.n, k0 + TB, acc);
+#pragma unroll
+    for (int rb = 0; rb < 2; rb++)
+#pragma unroll
+        for (int cb = 0; cb < 2; cb++)
+#pragma unroll
+            for (int r = 0; r < 4; r++) {
+                const int64_t row = ri + ACC_ROW(rb, r), col = rj + ACC_COL(cb);
+                if (row < d.n && col < d.n) A[row * d.n + col] -= acc[rb][cb][r];
+            }
+}
+
+// Backward substitution, block row `step` (descending): x_k = L_kk^-T y_k and
+// y_J -= L_kJ^T x_k for the column tiles J < k (one tile per workgroup).
+__global__ __launch_bounds__(256) void k_backsub(const DenseDesc *__restrict__ desc,
+                                                 const DenseParam *__restrict__ prm, double *__restrict__ work,
+                                                 double *__restrict__ x, const int64_t *__restrict__ x_off, int step) {
+    __shared__ double xk[TB];
+    __shared__ double yk[TB];
+    const int m = blockIdx.y;
+    const DenseDesc d = desc[m];
+    if (!prm[m].active || prm[m].info) return;
+    const int64_t k0 = (int64_t)TB * step;
+    if (k0 >= d.n) return;
+    const int64_t J = blockIdx.x;
+    if (J > 0 && J >= step) return;
+    const int nb = (int)std::min<int64_t>(TB, d.n - k0);
+    const double *linv = work + d.linv_off + (int64_t)step * TB * TB;
+    const int t = threadIdx.x;
+    if (t < TB) yk[t] = (t < nb) ? work[d.v_off + k0 + t] : 0.0;
+    __syncthreads();
+    if (t < TB) {
+        double s = 0.0;
+        for (int c = t; c < TB; c++) s += linv[c * TB + t] * yk[c];
+        xk[t] = s;
+    }
+    __syncthreads();
+    if (J == 0 && t < nb) x[x_off[m] + k0 + t] = xk[t];
+    if (J >= step) return;
+    const double *A = work + d.a_off;
+    // y_J[c] -= sum_r L[k0 + r][64 J + c] x_k[r]
+    if (t < TB) {
+        double s = 0.0;
+        for (int r = 0; r < nb; r++) s += A[(k0 + r) * d.n + TB * J + t] * xk[r];
+        work[d.v_off + TB * J + t] -= s;
+    }
+}
+
+// ---------------------------------------------------------------- LM glue
+// Per-window damping parameters from the LM state and the dense diagonal.
+__global__ __launch_bounds__(256) void k_dense_params(int32_t W, const DenseDesc *__restrict__ desc,
+                                                      const double *__restrict__ H, const int64_t *__restrict__ h_off,
+                                                      LMState *__restrict__ lm, DenseParam *__restrict__ prm,
+                                                      double tol_g, const double *__restrict__ g) {
+    __shared__ double rm[256], rs[256];
+    const int w = blockIdx.x;
+    if (w >= W) return;
+    LMState &st = lm[w];
+    const DenseDesc d = desc[w];
+    if (st.done) {
+        if (threadIdx.x == 0) prm[w].active = 0;
+        return;
+    }
+    const bool fresh = st.need_eval;
+    double mx = 0.0, s = 0.0;
+    if (fresh) {
+        const double *Hm = H + h_off[w];
+        for (int i = threadIdx.x; i < d.n; i += 256) {
+            mx = fmax(mx, Hm[(int64_t)i * d.n + i]);
+            const double gi = g[6LL * d.pose0 + i];
+            s += gi * gi;
+        }
+    }
+    rm[threadIdx.x] = mx;
+    rs[threadIdx.x] = s;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) {
+            rm[threadIdx.x] = fmax(rm[threadIdx.x], rm[threadIdx.x + o]);
+            rs[threadIdx.x] += rs[threadIdx.x + o];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        if (fresh) {
+            st.maxdiag = rm[0];
+            st.gnorm = sqrt(rs[0]);
+            st.need_eval = 0;
+            if (tol_g > 0.0 && st.gnorm < tol_g) {
+                st.done = 1;
+                st.accepted = 0;
+            }
+        }
+        DenseParam p;
+        p.mu = st.mu;
+        p.floor_ = 1e-12 * st.maxdiag;
+        p.active = st.done ? 0 : 1;
+        p.info = 0;
+        prm[w] = p;
+    }
+}
+
+// (H dx) per row, one wavefront per row; then per scan: q_j, trial pose, info.
+__global__ __launch_bounds__(256) void k_dense_hdx(int32_t W, const DenseDesc *__restrict__ desc,
+                                                   const DenseParam *__restrict__ prm, const double *__restrict__ H,
+                                                   const int64_t *__restrict__ h_off, const double *__restrict__ dx,
+                                                   double *__restrict__ hdx) {
+    const int m = blockIdx.y;
+    const DenseDesc d = desc[m];
+    if (!prm[m].active) return;
+    const int64_t row = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int lane = threadIdx.x & 63;
+    if (row >= d.n) return;
+    const double *Hr = H + h_off[m] + row * d.n;
+    const double *xv = dx + 6LL * d.pose0;
+    double s = 0.0;
+    for (int64_t c = lane; c < d.n; c += 64) s = fma(Hr[c], xv[c], s);
+    s = wave_sum(s);
+    if (lane == 0) hdx[6LL * d.pose0 + row] = s;
+}
+
+__global__ void k_dense_finish(int32_t n_poses, const int32_t *__restrict__ pose_window,
+                               const int32_t *__restrict__ win_pose_ptr, const DenseParam *__restrict__ prm,
+                               const double *__restrict__ g, const double *__restrict__ hdx,
+                               const double *__restrict__ poses, double *__restrict__ dx,
+                               double *__restrict__ pose_q, int32_t *__restrict__ pose_info,
+                               double *__restrict__ poses_trial) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n_poses) return;
+    const int w = pose_window[j];
+    const DenseParam p = prm[w];
+    if (!p.active) return;
+    double *xj = dx + 6LL * j;
+    if (p.info) {
+#pragma unroll
+        for (int k = 0; k < 6; k++) xj[k] = 0.0;
+        pose_q[j] = 0.0;
+        pose_info[j] = (j == win_pose_ptr[w]) ? p.info : 0;
+    } else {
+        double gdx = 0.0, dhd = 0.0;
+#pragma unroll
+        for (int k = 0; k < 6; k++) {
+            gdx += g[6LL * j + k] * xj[k];
+            dhd += xj[k] * hdx[6LL * j + k];
+        }
+        pose_q[j] = -(gdx + 0.5 * dhd);
+        pose_info[j] = 0;
+    }
+    pose_plus(poses + 12LL * j, xj, poses_trial + 12LL * j);
+}
+
+// Zero the dense matrices of windows whose derivatives are being re-evaluated.
+__global__ void k_dense_zero_stale(int32_t W, const DenseDesc *__restrict__ desc, const int64_t *__restrict__ h_off,
+                                   const LMState *__restrict__ lm, double *__restrict__ dense) {
+    for (int w = 0; w < W; w++) {
+        const LMState &st = lm[w];
+        if (st.done || !st.need_eval) continue;
+        const int64_t a = h_off[w], b = h_off[w + 1];
+        for (int64_t i = a + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < b;
+             i += (int64_t)gridDim.x * blockDim.x)
+            dense[i] = 0.0;
+    }
+}
+
+// ---------------------------------------------------------------- host side
+static inline unsigned nblk(int64_t n, int t = 256) { return (unsigned)((n + t - 1) / t); }
+
+struct DenseState {
+    DevArena mem;
+    bool ready = false;
+    // pairs
+    int32_t n_seg = 0;
+    PairSeg *segs = nullptr;
+    int32_t *pa = nullptr, *pb = nullptr;
+    double *h = nullptr;
+    // matrices
+    DenseDesc *desc = nullptr;
+    DenseParam *prm = nullptr;
+    int64_t *h_off = nullptr;    // offsets of each window's undamped H in P->dense
+    int64_t *x_off = nullptr;    // offsets of each window's solution in P->dx
+    double *work = nullptr;
+    double *hdx = nullptr;
+    int32_t max_n = 0;
+};
+
+static DenseState *dense_state(Problem *P) { return (DenseState *)P->dense_state; }
+
+void dense_release(Problem *P) {
+    delete dense_state(P);
+    P->dense_state = nullptr;
+}
+
+static int64_t linv_doubles(int64_t n) { return ((n + TB - 1) / TB) * (int64_t)TB * TB; }
+
+ba_status dense_prepare(Problem *P) {
+    if (P->dense_state) return BA_OK;
+    hipStream_t s = 0;
+    DenseState *D = new DenseState();
+    P->dense_state = D;
+    const int64_t C = P->n_clusters;
+    const int32_t W = P->n_windows;
+    std::vector<int32_t> cvox(C), cscan(C);
+    BA_HIP(hipMemcpy(cvox.data(), P->c_vox, sizeof(int32_t) * C, hipMemcpyDeviceToHost));
+    BA_HIP(hipMemcpy(cscan.data(), P->c_scan, sizeof(int32_t) * C, hipMemcpyDeviceToHost));
+    // every (voxel, j <= k) pair, keyed by (j, k)
+    std::vector<int32_t> pa, pb;
+    std::vector<uint64_t> key;
+    for (int64_t a = 0; a < C;) {
+        int64_t b = a;
+        while (b < C && cvox[b] == cvox[a]) b++;
+        for (int64_t i = a; i < b; i++)
+            for (int64_t j = i; j < b; j++) {
+                pa.push_back((int32_t)i);
+                pb.push_back((int32_t)j);
+                key.push_back(((uint64_t)(uint32_t)cscan[i] << 32) | (uint32_t)cscan[j]);
+            }
+        a = b;
+    }
+    const int64_t E = (int64_t)pa.size();
+    std::vector<int64_t> ord(E);
+    std::iota(ord.begin(), ord.end(), 0);
+    std::stable_sort(ord.begin(), ord.end(), [&](int64_t x, int64_t y) { return key[x] < key[y]; });
+    std::vector<int32_t> spa(E), spb(E);
+    std::vector<PairSeg> segs;
+    for (int64_t q = 0; q < E; q++) {
+        spa[q] = pa[ord[q]];
+        spb[q] = pb[ord[q]];
+        if (q == 0 || key[ord[q]] != key[ord[q - 1]]) {
+            PairSeg sg;
+            sg.start = q;
+            sg.count = 0;
+            sg.ja = (int32_t)(key[ord[q]] >> 32);
+            sg.jb = (int32_t)(key[ord[q]] & 0xffffffffu);
+            sg.pad = 0;
+            segs.push_back(sg);
+        }
+        segs.back().count++;
+    }
+    D->n_seg = (int32_t)segs.size();
+    BA_TRY(D->mem.alloc(&D->segs, std::max<int64_t>(D->n_seg, 1)));
+    BA_TRY(D->mem.alloc(&D->pa, std::max<int64_t>(E, 1)));
+    BA_TRY(D->mem.alloc(&D->pb, std::max<int64_t>(E, 1)));
+    BA_TRY(D->mem.alloc(&D->h, 6 * std::max<int64_t>(C, 1)));
+    if (D->n_seg) BA_HIP(hipMemcpy(D->segs, segs.data(), sizeof(PairSeg) * segs.size(), hipMemcpyHostToDevice));
+    if (E) {
+        BA_HIP(hipMemcpy(D->pa, spa.data(), sizeof(int32_t) * E, hipMemcpyHostToDevice));
+        BA_HIP(hipMemcpy(D->pb, spb.data(), sizeof(int32_t) * E, hipMemcpyHostToDevice));
+    }
+    // per-window dense matrices
+    std::vector<DenseDesc> desc(W);
+    std::vector<int64_t> hoff(W + 1), xoff(W);
+    int64_t a_tot = 0, l_tot = 0, v_tot = 0, h_tot = 0;
+    for (int32_t w = 0; w < W; w++) {
+        const int32_t p0 = P->h_win_pose_ptr[w], p1 = P->h_win_pose_ptr[w + 1];
+        const int64_t n = 6LL * (p1 - p0);
+        desc[w].a_off = a_tot;
+        desc[w].linv_off = l_tot;
+        desc[w].v_off = v_tot;
+        desc[w].n = (int32_t)n;
+        desc[w].pose0 = p0;
+        hoff[w] = h_tot;
+        xoff[w] = 6LL * p0;
+        a_tot += n * n;
+        l_tot += linv_doubles(n);
+        v_tot += n;
+        h_tot += n * n;
+        D->max_n = std::max<int32_t>(D->max_n, (int32_t)n);
+    }
+    hoff[W] = h_tot;
+    BA_TRY(D->mem.alloc(&D->desc, W));
+    BA_TRY(D->mem.alloc(&D->prm, W));
+    BA_TRY(D->mem.alloc(&D->h_off, W + 1));
+    BA_TRY(D->mem.alloc(&D->x_off, W));
+    BA_TRY(D->mem.alloc(&D->work, a_tot + l_tot + v_tot));
+    BA_TRY(D->mem.alloc(&D->hdx, 6LL * P->n_poses));
+    BA_TRY(D->mem.alloc(&P->dense, std::max<int64_t>(h_tot, 1)));
+    P->dense_total = h_tot;
+    for (int32_t w = 0; w < W; w++) {
+        desc[w].linv_off += a_tot;
+        desc[w].v_off += a_tot + l_tot;
+    }
+    BA_HIP(hipMemcpy(D->desc, desc.data(), sizeof(DenseDesc) * W, hipMemcpyHostToDevice));
+    BA_HIP(hipMemcpy(D->h_off, hoff.data(), sizeof(int64_t) * (W + 1), hipMemcpyHostToDevice));
+    BA_HIP(hipMemcpy(D->x_off, xoff.data(), sizeof(int64_t) * W, hipMemcpyHostToDevice));
+    BA_HIP(hipMemset(P->dense, 0, sizeof(double) * std::max<int64_t>(h_tot, 1)));
+    D->ready = true;
+    return BA_OK;
+}
+
+// Coupled Hessian at `poses` into hess_out (one window, standalone) or into
+// the problem's per-window dense buffers (LM).
 ba_status dense_assemble(Problem *P, const double *poses, double *hess_out, bool use_lm, hipStream_t s) {
-    set_error("coupled mode not built yet");
-    return BA_E_UNSUPPORTED;
+    BA_TRY(dense_prepare(P));
+    DenseState *D = dense_state(P);
+    double *dst = hess_out ? hess_out : P->dense;
+    const LMState *lm = use_lm ? P->lm : nullptr;
+    const int64_t C = P->n_clusters;
+    hipLaunchKernelGGL(k_hvec, dim3(nblk(C)), dim3(256), 0, s, C, P->c_N, P->c_mu, P->c_scan, P->c_slot, poses,
+                       P->vstate, (int64_t)P->n_groups * 64, P->pose_window, lm, D->h);
+    // windows whose derivatives are stale are rebuilt whole; the others keep their matrix
+    if (!use_lm) {
+        const int64_t tot = P->dense_total;
+        hipLaunchKernelGGL(k_fill, dim3(nblk(tot)), dim3(256), 0, s, tot, dst, 0.0);
+    } else {
+        hipLaunchKernelGGL(k_dense_zero_stale, dim3(2048), dim3(256), 0, s, P->n_windows, D->desc, D->h_off, lm,
+                           dst);
+    }
+    if (D->n_seg)
+        hipLaunchKernelGGL(k_pairs, dim3(nblk((int64_t)D->n_seg * 64)), dim3(256), 0, s, D->n_seg, D->segs, D->pa,
+                           D->pb, D->h, P->H, P->pose_window, P->win_pose_ptr, D->h_off, lm, dst);
+    BA_HIP(hipGetLastError());
+    return BA_OK;
+}
+
+static void launch_factor_solve(DenseState *D, int32_t nmat, int32_t max_n, const double *H, const int64_t *h_off,
+                                const double *g, double *x, const int64_t *x_off, hipStream_t s) {
+    const int nsteps = (max_n + TB - 1) / TB;
+    const int64_t nn = (int64_t)max_n * max_n;
+    hipLaunchKernelGGL(k_damp_copy, dim3((unsigned)std::min<int64_t>(nblk(nn), 4096), nmat), dim3(256), 0, s,
+                       D->desc, D->prm, H, h_off, g, D->work);
+    for (int st = 0; st < nsteps; st++) {
+        hipLaunchKernelGGL(k_potf2, dim3(1, nmat), dim3(256), 0, s, D->desc, D->prm, D->work, st);
+        const int64_t below = nsteps - st - 1;
+        if (below > 0) {
+            {
+                ProfScope prof("k_trsm", s);
+                hipLaunchKernelGGL(k_trsm, dim3((unsigned)below, nmat), dim3(256), 0, s, D->desc, D->prm, D->work,
+                                   st);
+            }
+            ProfScope prof("k_syrk", s);
+            hipLaunchKernelGGL(k_syrk, dim3((unsigned)(below * (below + 1) / 2), nmat), dim3(256), 0, s, D->desc,
+                               D->prm, D->work, st);
+        }
+    }
+    for (int st = nsteps - 1; st >= 0; st--)
+        hipLaunchKernelGGL(k_backsub, dim3((unsigned)std::max(st, 1), nmat), dim3(256), 0, s, D->desc, D->prm,
+                           D->work, x, x_off, st);
+}
+
+ba_status dense_lm_step(Problem *P, const double *poses, double tol_g, hipStream_t s) {
+    DenseState *D = dense_state(P);
+    const int32_t W = P->n_windows;
+    hipLaunchKernelGGL(k_dense_params, dim3(W), dim3(256), 0, s, W, D->desc, P->dense, D->h_off, P->lm, D->prm, tol_g,
+                       P->g);
+    launch_factor_solve(D, W, D->max_n, P->dense, D->h_off, P->g, P->dx, D->x_off, s);
+    hipLaunchKernelGGL(k_dense_hdx, dim3(nblk((int64_t)D->max_n * 64), W), dim3(256), 0, s, W, D->desc, D->prm,
+                       P->dense, D->h_off, P->dx, D->hdx);
+    hipLaunchKernelGGL(k_dense_finish, dim3(nblk(P->n_poses)), dim3(256), 0, s, P->n_poses, P->pose_window,
+                       P->win_pose_ptr, D->prm, P->g, D->hdx, poses, P->dx, P->pose_q, P->pose_info,
+                       P->poses_trial);
+    BA_HIP(hipGetLastError());
+    return BA_OK;
+}
+
+// ---------------------------------------------------------------- standalone solve
+size_t dense_solve_workspace(int64_t n) {
+    return align_up(sizeof(DenseDesc) + sizeof(DenseParam) + 4 * sizeof(int64_t), 256) +
+           sizeof(double) * (size_t)(n * n + linv_doubles(n) + n) + 256;
+}
+
+__global__ void k_solve_setup(int64_t n, const double *__restrict__ H, double mu, DenseDesc *__restrict__ desc,
+                              DenseParam *__restrict__ prm, int64_t *__restrict__ offs) {
+    __shared__ double rm[256];
+    double mx = 0.0;
+    for (int64_t i = threadIdx.x; i < n; i += 256) mx = fmax(mx, H[i * n + i]);
+    rm[threadIdx.x] = mx;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) rm[threadIdx.x] = fmax(rm[threadIdx.x], rm[threadIdx.x + o]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        DenseDesc d;
+        d.a_off = 0;
+        d.linv_off = n * n;
+        d.v_off = n * n + ((n + TB - 1) / TB) * (int64_t)TB * TB;
+        d.n = (int32_t)n;
+        d.pose0 = 0;
+        desc[0] = d;
+        DenseParam p;
+        p.mu = mu;
+        p.floor_ = 1e-12 * rm[0];
+        p.active = 1;
+        p.info = 0;
+        prm[0] = p;
+        offs[0] = 0;  // h_off
+        offs[1] = 0;  // x_off
+    }
+}
+
+__global__ void k_solve_final(int64_t n, const DenseParam *__restrict__ prm, double *__restrict__ dx,
+                              int32_t *__restrict__ info) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int inf = prm[0].info;
+    if (i == 0) *info = inf;
+    if (inf && i < n) dx[i] = 0.0;
 }
 
 ba_status dense_solve(int64_t n, const double *A, const double *g, double mu, double *dx, int32_t *info, void *ws,
                       size_t ws_bytes, hipStream_t s) {
-    set_error("coupled mode not built yet");
-    return BA_E_UNSUPPORTED;
-}
-
-ba_status dense_lm_step(Problem *P, const double *poses, hipStream_t s) {
-    set_error("coupled mode not built yet");
-    return BA_E_UNSUPPORTED;
+    char *p = (char *)ws;
+    DenseDesc *desc = (DenseDesc *)p;
+    DenseParam *prm = (DenseParam *)(p + sizeof(DenseDesc));
+    int64_t *offs = (int64_t *)(p + sizeof(DenseDesc) + sizeof(DenseParam));
+    double *work = (double *)(p + align_up(sizeof(DenseDesc) + sizeof(DenseParam) + 4 * sizeof(int64_t), 256));
+    hipLaunchKernelGGL(k_solve_setup, dim3(1), dim3(256), 0, s, n, A, mu, desc, prm, offs);
+    DenseState tmp;
+    tmp.desc = desc;
+    tmp.prm = prm;
+    tmp.work = work;
+    launch_factor_solve(&tmp, 1, (int32_t)n, A, offs, g, dx, offs + 1, s);
+    hipLaunchKernelGGL(k_solve_final, dim3(nblk(n)), dim3(256), 0, s, n, prm, dx, info);
+    BA_HIP(hipGetLastError());
+    return BA_OK;
 }
 
 }  // namespace ba

@@ -170,4 +170,45 @@ __device__ __forceinline__ void eig_sym3(const double *A, double *lam, double *u
     u[0] = vs[0]; u[1] = vs[1]; u[2] = vs[2];
 }
 
+// Exp(phi) as the rotation of the unit quaternion (cos(th/2), sin(th/2) phi/th);
+// the ratio sin(th/2)/th uses its Taylor series below 1e-4 rad.
+__device__ __forceinline__ void so3_exp(const double *phi, double *E) {
+    const double th2 = phi[0] * phi[0] + phi[1] * phi[1] + phi[2] * phi[2];
+    double w, k;
+    if (th2 < 1e-8) {
+        w = 1.0 - th2 * (1.0 / 8.0) + th2 * th2 * (1.0 / 384.0);
+        k = 0.5 - th2 * (1.0 / 48.0) + th2 * th2 * (1.0 / 3840.0);
+    } else {
+        const double th = sqrt(th2);
+        double sh, chh;
+        sincos(0.5 * th, &sh, &chh);
+        w = chh;
+        k = sh / th;
+    }
+    const double x = k * phi[0], y = k * phi[1], z = k * phi[2];
+    E[0] = 1.0 - 2.0 * (y * y + z * z);
+    E[1] = 2.0 * (x * y - z * w);
+    E[2] = 2.0 * (x * z + y * w);
+    E[3] = 2.0 * (x * y + z * w);
+    E[4] = 1.0 - 2.0 * (x * x + z * z);
+    E[5] = 2.0 * (y * z - x * w);
+    E[6] = 2.0 * (x * z - y * w);
+    E[7] = 2.0 * (y * z + x * w);
+    E[8] = 1.0 - 2.0 * (x * x + y * y);
+}
+
+// T (+) x = (Exp(phi) R, t + dt)
+__device__ __forceinline__ void pose_plus(const double *T, const double *x, double *out) {
+    double E[9];
+    so3_exp(x, E);
+#pragma unroll
+    for (int i = 0; i < 3; i++)
+#pragma unroll
+        for (int j = 0; j < 3; j++)
+            out[3 * i + j] = E[3 * i] * T[j] + E[3 * i + 1] * T[3 + j] + E[3 * i + 2] * T[6 + j];
+    out[9] = T[9] + x[3];
+    out[10] = T[10] + x[4];
+    out[11] = T[11] + x[5];
+}
+
 }  // namespace ba

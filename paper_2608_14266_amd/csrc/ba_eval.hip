@@ -1,12 +1,13 @@
 // Evaluation kernels of one iteration (paper Alg. 2, CalRes and CalJH).
 //
-//  k_vox   — residual pass, one lane per voxel, one wavefront per group of
-//            64 voxels with equal cluster count.  Each lane transforms its
-//            voxel's clusters by the current poses (Eq. 2), forms the voxel
-//            covariance A_i (Eq. 1) in two passes (centroid, then scatter about
-//            it), takes the smallest eigenpair with register-resident Jacobi
+//  k_vox   — residual pass, one lane per voxel, one block per group of 64
+//            voxels with equal cluster count (their clusters split over the
+//            block's four waves).  Each lane transforms its voxel's clusters by
+//            the current poses (Eq. 2), forms the voxel covariance A_i (Eq. 1)
+//            by the parallel-axis theorem about a per-voxel reference point,
+//            takes the smallest eigenpair with register-resident Jacobi
 //            rotations, and stores (u, mbar, 2/N_i, lambda_min) for the
-//            derivative pass.  The residual of a wave is reduced in-wave.
+//            derivative pass.  The residual of a group is reduced in-wave.
 //  k_pose  — derivative pass, one wavefront per pose chunk (clusters of one
 //            scan, pose-major copy).  Each lane evaluates the per-cluster
 //            gradient and Hessian of the Eq. 3 surrogate from its cluster and
@@ -33,16 +34,26 @@
 
 namespace ba {
 
+// One block (4 waves) per group of 64 voxels with equal cluster count m.
+// Lane l of every wave serves voxel l; wave w visits the voxel's clusters
+// k = w, w + 4, ... so a voxel seen by many scans is summed by four waves at
+// once.  Each wave accumulates, relative to the voxel's first cluster
+// centroid r (which keeps the sums well conditioned at large coordinates),
+//   n = sum N_k,  s = sum N_k d_k,  M = sum [St_k + N_k d_k d_k^T],  d_k = m_k - r,
+// and wave 0 adds the four partial sums in a fixed order:
+//   mbar = r + s / n,  A = (M - s s^T / n) / n.
 __global__ __launch_bounds__(256) void k_vox(const GroupDesc *__restrict__ groups, int32_t n_groups, int64_t c_pad,
                                              const double *__restrict__ vN, const double *__restrict__ vmu,
                                              const double *__restrict__ vS, const int32_t *__restrict__ vpose,
                                              const double *__restrict__ poses, double *__restrict__ vstate,
                                              int64_t n_slots, const LMState *__restrict__ lm, int trial,
                                              double *__restrict__ wave_cost) {
-    const int wave = (int)(((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6);
+    __shared__ double part[3][10][64];
+    const int gi = blockIdx.x;
+    const int w = threadIdx.x >> 6;
     const int lane = threadIdx.x & 63;
-    if (wave >= n_groups) return;
-    const GroupDesc g = groups[wave];
+    if (gi >= n_groups) return;
+    const GroupDesc g = groups[gi];
     int buf = 0;
     if (lm) {
         const LMState &st = lm[g.window];
@@ -50,29 +61,22 @@ __global__ __launch_bounds__(256) void k_vox(const GroupDesc *__restrict__ group
         buf = trial ? 1 - st.cur : st.cur;
     }
     const bool active = lane < g.nvox;
-    double Ni = 0.0, s0 = 0.0, s1 = 0.0, s2 = 0.0;
-    double lam0 = 0.0;
-    if (active) {
-        // pass 1: N_i and sum_j N_ij m_ij
-        for (int k = 0; k < g.m; k++) {
-            const int64_t idx = g.cbase + 64LL * k + lane;
-            const double n = vN[idx];
+    double n = 0.0, s0 = 0.0, s1 = 0.0, s2 = 0.0;
+    double M[6] = {0, 0, 0, 0, 0, 0};
+    double r[3] = {0, 0, 0};
+    if (active && w < g.m) {
+        {   // reference: centroid of the voxel's first cluster
+            const int64_t idx = g.cbase + lane;
             const double mu[3] = {vmu[idx], vmu[c_pad + idx], vmu[2 * c_pad + idx]};
             Pose P;
             load_pose(poses, vpose[idx], P);
-            double y[3];
-            rot(P.r, mu, y);
-            Ni += n;
-            s0 = fma(n, y[0] + P.t[0], s0);
-            s1 = fma(n, y[1] + P.t[1], s1);
-            s2 = fma(n, y[2] + P.t[2], s2);
+            rot(P.r, mu, r);
+            r[0] += P.t[0]; r[1] += P.t[1]; r[2] += P.t[2];
         }
-        const double mb[3] = {s0 / Ni, s1 / Ni, s2 / Ni};
-        // pass 2: sum_j [ St_ij + N_ij (m_ij - mbar)(m_ij - mbar)^T ]
-        double A[6] = {0, 0, 0, 0, 0, 0};
-        for (int k = 0; k < g.m; k++) {
+#pragma unroll 2
+        for (int k = w; k < g.m; k += 4) {
             const int64_t idx = g.cbase + 64LL * k + lane;
-            const double n = vN[idx];
+            const double nk = vN[idx];
             const double mu[3] = {vmu[idx], vmu[c_pad + idx], vmu[2 * c_pad + idx]};
             double S[6];
 #pragma unroll
@@ -82,29 +86,56 @@ __global__ __launch_bounds__(256) void k_vox(const GroupDesc *__restrict__ group
             double y[3], St[6];
             rot(P.r, mu, y);
             rot_sym(P.r, S, St);
-            const double d0 = y[0] + P.t[0] - mb[0], d1 = y[1] + P.t[1] - mb[1], d2 = y[2] + P.t[2] - mb[2];
-            const double nd0 = n * d0, nd1 = n * d1, nd2 = n * d2;
-            A[0] += fma(nd0, d0, St[0]);
-            A[1] += fma(nd0, d1, St[1]);
-            A[2] += fma(nd0, d2, St[2]);
-            A[3] += fma(nd1, d1, St[3]);
-            A[4] += fma(nd1, d2, St[4]);
-            A[5] += fma(nd2, d2, St[5]);
+            const double d0 = (y[0] + P.t[0]) - r[0], d1 = (y[1] + P.t[1]) - r[1], d2 = (y[2] + P.t[2]) - r[2];
+            const double nd0 = nk * d0, nd1 = nk * d1, nd2 = nk * d2;
+            n += nk;
+            s0 += nd0; s1 += nd1; s2 += nd2;
+            M[0] += fma(nd0, d0, St[0]);
+            M[1] += fma(nd0, d1, St[1]);
+            M[2] += fma(nd0, d2, St[2]);
+            M[3] += fma(nd1, d1, St[3]);
+            M[4] += fma(nd1, d2, St[4]);
+            M[5] += fma(nd2, d2, St[5]);
         }
-        const double inv = 1.0 / Ni;
+    }
+    if (w > 0) {
+        double *pp = &part[w - 1][0][0];
+        pp[0 * 64 + lane] = n;
+        pp[1 * 64 + lane] = s0; pp[2 * 64 + lane] = s1; pp[3 * 64 + lane] = s2;
 #pragma unroll
-        for (int q = 0; q < 6; q++) A[q] *= inv;
+        for (int q = 0; q < 6; q++) pp[(4 + q) * 64 + lane] = M[q];
+    }
+    __syncthreads();
+    if (w != 0) return;
+    double lam0 = 0.0;
+    if (active) {
+        for (int v = 0; v < 3; v++) {
+            const double *pp = &part[v][0][0];
+            n += pp[lane];
+            s0 += pp[64 + lane]; s1 += pp[128 + lane]; s2 += pp[192 + lane];
+#pragma unroll
+            for (int q = 0; q < 6; q++) M[q] += pp[(4 + q) * 64 + lane];
+        }
+        const double inv = 1.0 / n;
+        const double b0 = s0 * inv, b1 = s1 * inv, b2 = s2 * inv;   // mbar - r
+        double A[6];
+        A[0] = (M[0] - s0 * b0) * inv;
+        A[1] = (M[1] - s0 * b1) * inv;
+        A[2] = (M[2] - s0 * b2) * inv;
+        A[3] = (M[3] - s1 * b1) * inv;
+        A[4] = (M[4] - s1 * b2) * inv;
+        A[5] = (M[5] - s2 * b2) * inv;
         double lam[3], u[3];
         eig_sym3(A, lam, u);
         lam0 = lam[0];
-        double *st = vstate + ((int64_t)buf * n_slots + (int64_t)wave * 64 + lane) * VSTATE;
+        double *st = vstate + ((int64_t)buf * n_slots + (int64_t)gi * 64 + lane) * VSTATE;
         st[0] = u[0]; st[1] = u[1]; st[2] = u[2];
-        st[3] = mb[0]; st[4] = mb[1]; st[5] = mb[2];
+        st[3] = r[0] + b0; st[4] = r[1] + b1; st[5] = r[2] + b2;
         st[6] = 2.0 * inv;
         st[7] = lam0;
     }
     const double c = wave_sum(lam0);
-    if (lane == 0) wave_cost[wave] = c;
+    if (lane == 0) wave_cost[gi] = c;
 }
 
 struct Acc27 {
@@ -274,7 +305,7 @@ static inline unsigned nblk(int64_t n, int t = 256) { return (unsigned)((n + t -
 void launch_vox(Problem *P, const double *poses, bool use_lm, bool trial, hipStream_t s) {
     if (P->n_groups == 0) return;
     ProfScope prof("k_vox", s);
-    hipLaunchKernelGGL(k_vox, dim3(nblk((int64_t)P->n_groups * 64)), dim3(256), 0, s, P->groups, P->n_groups,
+    hipLaunchKernelGGL(k_vox, dim3((unsigned)P->n_groups), dim3(256), 0, s, P->groups, P->n_groups,
                        P->c_pad, P->v_N, P->v_mu, P->v_S, P->v_pose, poses, P->vstate, (int64_t)P->n_groups * 64,
                        use_lm ? P->lm : nullptr, trial ? 1 : 0, P->wave_cost);
 }

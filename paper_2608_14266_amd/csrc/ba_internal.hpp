@@ -77,6 +77,7 @@ struct Problem {
     // centred clusters in (voxel, scan) order, kept for export
     double *c_mu = nullptr, *c_S = nullptr, *c_N = nullptr; // [C][3], [C][6], [C]
     int32_t *c_vox = nullptr, *c_scan = nullptr;
+    int32_t *c_slot = nullptr;                 // residual-pass slot of each cluster
 
     // windows
     int32_t *win_group_ptr = nullptr; // [n_windows+1]
@@ -97,10 +98,11 @@ struct Problem {
     int64_t *win_dense_off = nullptr;         // [n_windows+1] offsets (doubles) of each window's dense H
     int64_t dense_total = 0;
     double *dense = nullptr;                  // per-window dense (6Nw)^2 matrices
+    void *dense_state = nullptr;              // coupled-path plan and buffers
 
     int64_t n_points = 0;
     DevArena mem;                             // every device allocation above
-    ~Problem() { delete[] h_win_pose_ptr; }
+    ~Problem();
 };
 
 ba_status build_from_points(const ba_points *pts, const ba_build_options *opt, Problem *P, DevArena &keep,

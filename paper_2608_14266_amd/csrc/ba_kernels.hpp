@@ -20,7 +20,7 @@ void launch_lm_reset(Problem *P, double mu0, double nu0, hipStream_t s);
 void launch_lm_cost(Problem *P, hipStream_t s);
 void launch_window_stats(Problem *P, double tol_g, hipStream_t s);
 void launch_solve_mm_lm(Problem *P, const double *poses, hipStream_t s);
-void launch_decide(Problem *P, double *trace, int it, hipStream_t s);
+void launch_decide(Problem *P, double *trace, int it, double *poses, hipStream_t s);
 void launch_commit(Problem *P, double *poses, hipStream_t s);
 
 }  // namespace ba

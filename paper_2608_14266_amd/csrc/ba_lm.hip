@@ -6,8 +6,8 @@
 //  k_solve_mm   — Alg. 2 Solver: one thread per scan factors the 6x6
 //                 H_jj + mu D_jj by LDL^T, solves for dx_j, forms the trial
 //                 pose T_j (+) dx_j and its share of the predicted reduction.
-//  k_window_stats / k_decide / k_commit — per-window gradient norm and
-//                 damping floor, gain ratio and damping update, pose commit.
+//  k_window_stats / k_decide — per-window gradient norm and damping floor;
+//                 gain ratio, damping update and commit of accepted poses.
 #include <hip/hip_runtime.h>
 
 #include "ba.h"
@@ -55,47 +55,6 @@ __device__ __forceinline__ int ldlt6(double A[6][6], const double b[6], double x
         x[i] = t;
     }
     return 0;
-}
-
-// Exp(phi) as the rotation of the unit quaternion (cos(th/2), sin(th/2) phi/th);
-// the ratio sin(th/2)/th uses its Taylor series below 1e-4 rad.
-__device__ __forceinline__ void so3_exp(const double *phi, double *E) {
-    const double th2 = phi[0] * phi[0] + phi[1] * phi[1] + phi[2] * phi[2];
-    double w, k;
-    if (th2 < 1e-8) {
-        w = 1.0 - th2 * (1.0 / 8.0) + th2 * th2 * (1.0 / 384.0);
-        k = 0.5 - th2 * (1.0 / 48.0) + th2 * th2 * (1.0 / 3840.0);
-    } else {
-        const double th = sqrt(th2);
-        double sh, chh;
-        sincos(0.5 * th, &sh, &chh);
-        w = chh;
-        k = sh / th;
-    }
-    const double x = k * phi[0], y = k * phi[1], z = k * phi[2];
-    E[0] = 1.0 - 2.0 * (y * y + z * z);
-    E[1] = 2.0 * (x * y - z * w);
-    E[2] = 2.0 * (x * z + y * w);
-    E[3] = 2.0 * (x * y + z * w);
-    E[4] = 1.0 - 2.0 * (x * x + z * z);
-    E[5] = 2.0 * (y * z - x * w);
-    E[6] = 2.0 * (x * z - y * w);
-    E[7] = 2.0 * (y * z + x * w);
-    E[8] = 1.0 - 2.0 * (x * x + y * y);
-}
-
-// T (+) x = (Exp(phi) R, t + dt)
-__device__ __forceinline__ void pose_plus(const double *T, const double *x, double *out) {
-    double E[9];
-    so3_exp(x, E);
-#pragma unroll
-    for (int i = 0; i < 3; i++)
-#pragma unroll
-        for (int j = 0; j < 3; j++)
-            out[3 * i + j] = E[3 * i] * T[j] + E[3 * i + 1] * T[3 + j] + E[3 * i + 2] * T[6 + j];
-    out[9] = T[9] + x[3];
-    out[10] = T[10] + x[4];
-    out[11] = T[11] + x[5];
 }
 
 // Damped 6x6 solve of one scan; returns info (0 ok).  q_out = -(g dx + dx H dx / 2).
@@ -222,9 +181,11 @@ __global__ __launch_bounds__(256) void k_decide(int32_t W, const int32_t *__rest
                                                 const double *__restrict__ pose_q,
                                                 const int32_t *__restrict__ pose_info,
                                                 const double *__restrict__ wave_cost, LMState *__restrict__ lm,
-                                                double *__restrict__ trace, int it) {
+                                                double *__restrict__ trace, int it,
+                                                const double *__restrict__ poses_trial, double *__restrict__ poses) {
     __shared__ double rq[256], rc[256];
     __shared__ int ri[256];
+    __shared__ int s_acc;
     const int w = blockIdx.x;
     if (w >= W) return;
     LMState &st = lm[w];
@@ -258,6 +219,7 @@ __global__ __launch_bounds__(256) void k_decide(int32_t W, const int32_t *__rest
             t[0] = st.cost; t[1] = inf ? st.cost : ct; t[2] = rho; t[3] = st.mu;
             t[4] = acc; t[5] = st.gnorm; t[6] = inf; t[7] = inf ? 0.0 : qq;
         }
+        s_acc = acc;
         st.q = qq;
         st.rho = rho;
         st.info = inf;
@@ -277,6 +239,12 @@ __global__ __launch_bounds__(256) void k_decide(int32_t W, const int32_t *__rest
             st.mu *= st.nu;
             st.nu *= 2.0;
         }
+    }
+    __syncthreads();
+    // commit the window's trial poses on acceptance
+    if (s_acc) {
+        const int64_t a = 12LL * win_pose_ptr[w], b = 12LL * win_pose_ptr[w + 1];
+        for (int64_t i = a + threadIdx.x; i < b; i += 256) poses[i] = poses_trial[i];
     }
 }
 
@@ -364,9 +332,10 @@ void launch_solve_mm_lm(Problem *P, const double *poses, hipStream_t s) {
                        P->win_pose_ptr, P->lm, P->H, P->g, poses, P->dx, P->pose_q, P->pose_info, P->poses_trial);
 }
 
-void launch_decide(Problem *P, double *trace, int it, hipStream_t s) {
+void launch_decide(Problem *P, double *trace, int it, double *poses, hipStream_t s) {
     hipLaunchKernelGGL(k_decide, dim3(P->n_windows), dim3(256), 0, s, P->n_windows, P->win_pose_ptr,
-                       P->win_group_ptr, P->pose_q, P->pose_info, P->wave_cost, P->lm, trace, it);
+                       P->win_group_ptr, P->pose_q, P->pose_info, P->wave_cost, P->lm, trace, it,
+                       P->poses_trial, poses);
 }
 
 void launch_commit(Problem *P, double *poses, hipStream_t s) {
