@@ -24,6 +24,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0           # MI355X HBM3E, 8 TB/s
+FP64_MFMA_PEAK_TFS = 78.6       # MI355X dense FP64 matrix
 CLUSTER_BYTES = 8 + 24 + 48 + 4  # N (f64), mu (3 f64), S (6 f64), scan or slot id (i32)
 
 
@@ -61,9 +62,12 @@ def main():
     ap.add_argument("--iters", type=int, default=20, help="LM iterations per solve")
     ap.add_argument("--mode", choices=["mm", "coupled"], default="mm")
     ap.add_argument("--workload", choices=["window", "tiny"], default="window")
-    ap.add_argument("--cpu-iters", type=int, default=2, help="oracle LM iterations timed for cpu_baseline")
+    ap.add_argument("--cpu-iters", type=int, default=None,
+                    help="oracle LM iterations timed for cpu_baseline (default: 20 mm, 1 coupled)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
+    if args.cpu_iters is None:
+        args.cpu_iters = 20 if args.mode == "mm" else 1
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(see the sharding design notes); run with --gpus 1", file=sys.stderr)
@@ -115,18 +119,29 @@ def main():
     for w in range(args.warmup):
         step()
         log(f"warmup {w + 1}/{args.warmup}")
+    # timed region: each solve replays the captured iteration graph
     torch.cuda.synchronize()
-    ba.profile_reset()
-    ba.profile_enable(True)
     t0 = time.perf_counter()
     reps = None
     for k in range(args.steps):
         reps = step()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    # kernel timing: the same K solves launched eagerly with HIP events around
+    # every launch of the eval and factorization kernels
+    ba.profile_reset()
+    ba.profile_enable(True)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    for k in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    t3 = time.perf_counter()
     ba.profile_enable(False)
     vox_ms, vox_n = ba.profile_query("k_vox")
     pose_ms, pose_n = ba.profile_query("k_pose")
+    syrk_ms, syrk_n = ba.profile_query("k_syrk")
+    trsm_ms, trsm_n = ba.profile_query("k_trsm")
     ba.profile_reset()
     elapsed = t1 - t0
     ms_per_step = 1e3 * elapsed / args.steps
@@ -153,6 +168,26 @@ def main():
     roof = {"kernel": dom, "bound": "hbm", "achieved": round(kern[dom]["gbs"], 2), "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": round(kern[dom]["gbs"] / HBM_PEAK_GBS, 4), "traffic": None,
             "bytes_per_launch": kern[dom]["bytes"], "avg_launch_us": round(kern[dom]["avg_us"], 3)}
+    if args.mode == "coupled" and syrk_n > 0:
+        # dense factorization on FP64 matrix cores: algorithmic flops of the
+        # panel solves (rows below x 64 x 64 x 2) and trailing updates
+        # (rows below^2 x 64, lower half) of one 6N x 6N factorization
+        n = 6 * N
+        fl_trsm = fl_syrk = 0
+        for st in range((n + 63) // 64):
+            below = n - 64 * (st + 1)
+            if below > 0:
+                fl_trsm += below * 64 * 64 * 2
+                fl_syrk += below * below * 64
+        n_fact = syrk_n / max(1, sum(1 for st in range((n + 63) // 64) if n - 64 * (st + 1) > 0))
+        tfs = (fl_trsm + fl_syrk) * n_fact / ((syrk_ms + trsm_ms) * 1e-3) / 1e12
+        kern["k_syrk"] = dict(avg_us=1e3 * syrk_ms / max(syrk_n, 1), launches=syrk_n)
+        kern["k_trsm"] = dict(avg_us=1e3 * trsm_ms / max(trsm_n, 1), launches=trsm_n)
+        kern["factorization"] = dict(count=n_fact, flops=fl_trsm + fl_syrk)
+        roof = {"kernel": "k_syrk+k_trsm", "bound": "mfma", "achieved": round(tfs, 3),
+                "peak": FP64_MFMA_PEAK_TFS, "unit": "TFLOP/s", "frac": round(tfs / FP64_MFMA_PEAK_TFS, 4),
+                "traffic": None, "flops_per_factorization": fl_trsm + fl_syrk,
+                "avg_launch_us": round(1e3 * syrk_ms / max(syrk_n, 1), 3)}
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -181,6 +216,7 @@ def main():
                    "poses": N, "voxels": V, "clusters": C, "points": sc.n_points, "lm_iters": args.iters,
                    "mode": args.mode},
         "lm_iters_per_s": lm_iters_s,
+        "ms_per_step_eager_profiled": round(1e3 * (t3 - t2) / args.steps, 4),
         "build_ms": round(min(build_ms), 3),
         "kernels": {k: {kk: (round(vv, 3) if isinstance(vv, float) else vv) for kk, vv in d.items()}
                     for k, d in kern.items()},

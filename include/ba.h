@@ -203,6 +203,9 @@ ba_status ba_solve_increment(int32_t mode, int32_t n_scans, const double *hess, 
  * poses_inout: device [n_scans][12], updated in place.  rep: host array of
  * n_windows reports (may be NULL).  trace: host [max_iters][n_windows][8]
  * (cost, cost_trial, rho, mu, accepted, gnorm, info, q) or NULL.
+ * The launches of a call are captured once into a HIP graph and replayed
+ * by later calls with the same problem, poses pointer and options (set
+ * BA_NO_GRAPH=1 in the environment to launch eagerly).
  * Synchronous (returns after the stream has drained).
  */
 ba_status ba_iterate(ba_problem *p, double *poses_inout, const ba_lm_options *opt, ba_lm_report *rep,
@@ -211,7 +214,9 @@ ba_status ba_iterate(ba_problem *p, double *poses_inout, const ba_lm_options *op
 /*
  * Kernel timing (instrumentation, not part of the method): when enabled,
  * later calls record a pair of HIP events on their stream around each launch
- * of the residual kernel ("k_vox") and of the derivative kernel ("k_pose").
+ * of the residual kernel ("k_vox"), the derivative kernel ("k_pose") and the
+ * matrix-core factorization kernels ("k_trsm", "k_syrk"); ba_iterate then
+ * runs its launches eagerly instead of replaying a captured graph.
  * ba_profile_query waits for the recorded events and returns the summed
  * elapsed time and the launch count of one kernel; ba_profile_reset drops
  * the records.  Process-wide, guarded by a mutex.

@@ -2,6 +2,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <cstdlib>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -17,6 +18,8 @@
 
 namespace ba {
 void dense_release(Problem *P);
+void graph_release(Problem *P);
+bool prof_enabled();
 }
 
 struct ba_problem {
@@ -24,6 +27,7 @@ struct ba_problem {
 };
 
 ba::Problem::~Problem() {
+    graph_release(this);
     dense_release(this);
     delete[] h_win_pose_ptr;
 }
@@ -49,13 +53,17 @@ void dense_release(Problem *P);
 ba_status dense_prepare(Problem *P);
 
 // ---------------------------------------------------------------- profiling
+// Event pairs recorded around kernel launches (eager launches only: a call
+// made while profiling is enabled is not captured into a graph).  Elapsed
+// times are summed per kernel name when queried.
 struct ProfRec {
     const char *name;
     hipEvent_t a, b;
 };
 static bool g_prof_on = false;
-static std::vector<ProfRec> g_prof;
+static std::vector<ProfRec> g_pending;
 static std::vector<hipEvent_t> g_prof_pool;
+static std::map<std::string, std::pair<double, int64_t>> g_prof_tot;
 static std::mutex g_prof_mu;
 
 static hipEvent_t prof_event() {
@@ -69,6 +77,8 @@ static hipEvent_t prof_event() {
     return e;
 }
 
+bool prof_enabled() { return g_prof_on; }
+
 void prof_begin(const char *name, hipStream_t s) {
     if (!g_prof_on) return;
     std::lock_guard<std::mutex> lk(g_prof_mu);
@@ -78,18 +88,96 @@ void prof_begin(const char *name, hipStream_t s) {
     r.b = prof_event();
     if (!r.a || !r.b) return;
     (void)hipEventRecord(r.a, s);
-    g_prof.push_back(r);
+    g_pending.push_back(r);
 }
 
 void prof_end(hipStream_t s) {
     if (!g_prof_on) return;
     std::lock_guard<std::mutex> lk(g_prof_mu);
-    if (!g_prof.empty()) (void)hipEventRecord(g_prof.back().b, s);
+    if (!g_pending.empty()) (void)hipEventRecord(g_pending.back().b, s);
 }
+
+static void prof_add(const std::vector<ProfRec> &l) {
+    for (const ProfRec &r : l) {
+        if (hipEventSynchronize(r.b) != hipSuccess) continue;
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, r.a, r.b) != hipSuccess) continue;
+        auto &t = g_prof_tot[r.name];
+        t.first += ms;
+        t.second += 1;
+    }
+    (void)hipGetLastError();
+}
+
+// fold the eager records into the totals and recycle their events
+static void prof_collect_pending() {
+    prof_add(g_pending);
+    for (auto &r : g_pending) {
+        g_prof_pool.push_back(r.a);
+        g_prof_pool.push_back(r.b);
+    }
+    g_pending.clear();
+}
+
 
 }  // namespace ba
 
 using namespace ba;
+
+namespace ba {
+
+// Enqueue every launch of one ba_iterate call (stream-ordered, no host sync).
+static ba_status enqueue_lm(Problem *P, double *poses, const ba_lm_options *opt, double *dtrace, double mu0, double nu0,
+                            hipStream_t s) {
+    const int iters = opt->max_iters;
+    launch_lm_reset(P, mu0, nu0, s);
+    launch_vox(P, poses, true, false, s);
+    launch_lm_cost(P, s);
+    for (int it = 0; it < iters; it++) {
+        if (opt->mode == BA_MODE_MM) {
+            launch_pose_chunks(P, poses, true, s);
+            launch_window_solve_mm(P, poses, opt->tol_g, s);
+        } else {
+            launch_pose_derivs(P, poses, true, P->g, P->H, s);
+            BA_TRY(dense_assemble(P, poses, nullptr, true, s));
+            BA_TRY(dense_lm_step(P, poses, opt->tol_g, s));
+        }
+        // trial residual, then the per-window decision and commit
+        launch_vox(P, P->poses_trial, true, true, s);
+        launch_decide(P, dtrace, it, poses, s);
+    }
+    // derivatives at the final poses (windows whose last step was accepted),
+    // so that the reported gradient norm belongs to the returned poses
+    launch_pose_derivs(P, poses, true, P->g, P->H, s);
+    launch_window_stats(P, opt->tol_g, s);
+    BA_HIP(hipGetLastError());
+    return BA_OK;
+}
+
+struct IterGraph {
+    hipStream_t cap = nullptr;
+    hipGraphExec_t exec = nullptr;
+    // key
+    double *poses = nullptr, *trace = nullptr;
+    int32_t mode = -1, iters = -1;
+    double mu0 = 0, nu0 = 0, tol_g = 0;
+    ~IterGraph() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (cap) (void)hipStreamDestroy(cap);
+    }
+};
+
+void graph_release(Problem *P) {
+    delete (IterGraph *)P->iter_graph;
+    P->iter_graph = nullptr;
+}
+
+static bool g_graphs_enabled() {
+    const char *e = getenv("BA_NO_GRAPH");
+    return !(e && e[0] == '1');
+}
+
+}  // namespace ba
 
 extern "C" {
 
@@ -116,11 +204,8 @@ ba_status ba_profile_enable(int32_t on) {
 
 ba_status ba_profile_reset(void) {
     std::lock_guard<std::mutex> lk(g_prof_mu);
-    for (auto &r : g_prof) {
-        g_prof_pool.push_back(r.a);
-        g_prof_pool.push_back(r.b);
-    }
-    g_prof.clear();
+    prof_collect_pending();
+    g_prof_tot.clear();
     return BA_OK;
 }
 
@@ -130,18 +215,10 @@ ba_status ba_profile_query(const char *kernel, double *total_ms, int64_t *launch
         return BA_E_ARG;
     }
     std::lock_guard<std::mutex> lk(g_prof_mu);
-    double tot = 0.0;
-    int64_t cnt = 0;
-    for (auto &r : g_prof) {
-        if (std::strcmp(r.name, kernel) != 0) continue;
-        BA_HIP(hipEventSynchronize(r.b));
-        float ms = 0.f;
-        BA_HIP(hipEventElapsedTime(&ms, r.a, r.b));
-        tot += ms;
-        cnt++;
-    }
-    *total_ms = tot;
-    *launches = cnt;
+    prof_collect_pending();
+    auto it = g_prof_tot.find(kernel);
+    *total_ms = (it == g_prof_tot.end()) ? 0.0 : it->second.first;
+    *launches = (it == g_prof_tot.end()) ? 0 : it->second.second;
     return BA_OK;
 }
 
@@ -333,29 +410,48 @@ ba_status ba_iterate(ba_problem *p, double *poses_inout, const ba_lm_options *op
             P->trace_cap = iters;
         }
         dtrace = P->trace;
-        BA_HIP(hipMemsetAsync(dtrace, 0, sizeof(double) * (size_t)iters * W * 8, stream));
     }
-    launch_lm_reset(P, mu0, nu0, stream);
-    launch_vox(P, poses_inout, true, false, stream);
-    launch_lm_cost(P, stream);
-    std::vector<LMState> st0(W);
-    for (int it = 0; it < iters; it++) {
-        launch_pose_derivs(P, poses_inout, true, P->g, P->H, stream);
-        if (opt->mode == BA_MODE_MM) {
-            launch_window_stats(P, opt->tol_g, stream);
-            launch_solve_mm_lm(P, poses_inout, stream);
-        } else {
-            BA_TRY(dense_assemble(P, poses_inout, nullptr, true, stream));
-            BA_TRY(dense_lm_step(P, poses_inout, opt->tol_g, stream));
+    // The whole call is captured once into a HIP graph and replayed while its
+    // arguments stay the same (profiling records events, so it runs eagerly).
+    bool done = false;
+    if (g_graphs_enabled() && !prof_enabled()) {   // event records cannot be captured: profile eagerly
+        IterGraph *G = (IterGraph *)P->iter_graph;
+        const bool same = G && G->exec && G->poses == poses_inout && G->trace == dtrace && G->mode == opt->mode &&
+                          G->iters == iters && G->mu0 == mu0 && G->nu0 == nu0 && G->tol_g == opt->tol_g;
+        if (!same) {
+            graph_release(P);
+            G = new IterGraph();
+            P->iter_graph = G;
+            hipGraph_t graph = nullptr;
+            bool ok = hipStreamCreateWithFlags(&G->cap, hipStreamNonBlocking) == hipSuccess &&
+                      hipStreamBeginCapture(G->cap, hipStreamCaptureModeThreadLocal) == hipSuccess;
+            if (ok) {
+                ba_status st = enqueue_lm(P, poses_inout, opt, dtrace, mu0, nu0, G->cap);
+                hipError_t e = hipStreamEndCapture(G->cap, &graph);
+                ok = (st == BA_OK) && e == hipSuccess && graph &&
+                     hipGraphInstantiate(&G->exec, graph, nullptr, nullptr, 0) == hipSuccess;
+            }
+            if (graph) (void)hipGraphDestroy(graph);
+            (void)hipGetLastError();
+            if (ok) {
+                G->poses = poses_inout;
+                G->trace = dtrace;
+                G->mode = opt->mode;
+                G->iters = iters;
+                G->mu0 = mu0;
+                G->nu0 = nu0;
+                G->tol_g = opt->tol_g;
+            } else {
+                graph_release(P);
+                G = nullptr;
+            }
         }
-        launch_vox(P, P->poses_trial, true, true, stream);
-        launch_decide(P, dtrace, it, poses_inout, stream);
+        if (G && G->exec) {
+            BA_HIP(hipGraphLaunch(G->exec, stream));
+            done = true;
+        }
     }
-    // derivatives at the final poses (windows whose last step was accepted),
-    // so that the reported gradient norm belongs to the returned poses
-    launch_pose_derivs(P, poses_inout, true, P->g, P->H, stream);
-    launch_window_stats(P, opt->tol_g, stream);
-    BA_HIP(hipGetLastError());
+    if (!done) BA_TRY(enqueue_lm(P, poses_inout, opt, dtrace, mu0, nu0, stream));
     std::vector<LMState> st(W);
     BA_HIP(hipMemcpyAsync(st.data(), P->lm, sizeof(LMState) * W, hipMemcpyDeviceToHost, stream));
     if (dtrace) BA_HIP(hipMemcpyAsync(trace, dtrace, sizeof(double) * (size_t)iters * W * 8, hipMemcpyDeviceToHost, stream));

@@ -296,6 +296,13 @@ static ba_status make_plan(Problem *P, const std::vector<int32_t> &cvox, const s
     for (int32_t w = 0; w < W; w++) win_group_ptr[w + 1] = std::max(win_group_ptr[w + 1], win_group_ptr[w]);
     P->n_groups = (int32_t)groups.size();
     P->c_pad = cbase;
+    // residual-pass blocks, one per group, the largest cluster counts first so
+    // that the longest blocks start earliest
+    std::vector<VoxBlock> vblocks;
+    for (int32_t w = 0; w < W; w++)
+        for (int32_t gi = win_group_ptr[w + 1] - 1; gi >= win_group_ptr[w]; gi--)
+            vblocks.push_back(VoxBlock{gi, 1, 4, w});
+    P->n_vblocks = (int32_t)vblocks.size();
     // pose-major order: (scan, slot)
     std::vector<int32_t> porder(C);
     std::iota(porder.begin(), porder.end(), 0);
@@ -337,6 +344,7 @@ static ba_status make_plan(Problem *P, const std::vector<int32_t> &cvox, const s
     BA_TRY(keep.alloc(&P->v_N, CP));
     BA_TRY(keep.alloc(&P->v_pose, CP));
     BA_TRY(keep.alloc(&P->groups, std::max<int64_t>(P->n_groups, 1)));
+    BA_TRY(keep.alloc(&P->vblocks, std::max<int64_t>(P->n_vblocks, 1)));
     BA_TRY(keep.alloc(&P->slot_vox, std::max<int64_t>(NS, 1)));
     BA_TRY(keep.alloc(&P->vstate, 2 * std::max<int64_t>(NS, 1) * VSTATE));
     BA_TRY(keep.alloc(&P->wave_cost, std::max<int64_t>(P->n_groups, 1)));
@@ -366,6 +374,7 @@ static ba_status make_plan(Problem *P, const std::vector<int32_t> &cvox, const s
     BA_HIP(hipMemsetAsync(P->v_pose, 0, sizeof(int32_t) * CP, s));
     BA_HIP(hipMemsetAsync(P->vstate, 0, sizeof(double) * 2 * std::max<int64_t>(NS, 1) * VSTATE, s));
     BA_HIP(hipMemcpyAsync(P->groups, groups.data(), sizeof(GroupDesc) * groups.size(), hipMemcpyHostToDevice, s));
+    BA_HIP(hipMemcpyAsync(P->vblocks, vblocks.data(), sizeof(VoxBlock) * vblocks.size(), hipMemcpyHostToDevice, s));
     BA_HIP(hipMemcpyAsync(P->slot_vox, slot_vox.data(), sizeof(int32_t) * slot_vox.size(), hipMemcpyHostToDevice, s));
     BA_HIP(hipMemcpyAsync(P->chunks, chunks.data(), sizeof(ChunkDesc) * chunks.size(), hipMemcpyHostToDevice, s));
     BA_HIP(hipMemcpyAsync(P->chunk_ptr, chunk_ptr.data(), sizeof(int32_t) * (N + 1), hipMemcpyHostToDevice, s));

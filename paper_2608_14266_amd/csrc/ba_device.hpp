@@ -27,6 +27,42 @@ __device__ __forceinline__ int wave_min_i(int v) {
     return v;
 }
 
+// Reduce-scatter of 32 per-lane values over a wave64: after five halving
+// exchanges and one final one, lane l holds the sum over all 64 lanes of
+// value l / 2 (fixed exchange order, so the result is deterministic).
+__device__ __forceinline__ double wave_reduce_scatter32(double (&a)[32], int lane) {
+#pragma unroll
+    for (int i = 0; i < 16; i++) {
+        const bool hi = lane & 32;
+        const double mine = hi ? a[16 + i] : a[i], other = hi ? a[i] : a[16 + i];
+        a[i] = mine + __shfl_xor(other, 32, BA_WAVE);
+    }
+#pragma unroll
+    for (int i = 0; i < 8; i++) {
+        const bool hi = lane & 16;
+        const double mine = hi ? a[8 + i] : a[i], other = hi ? a[i] : a[8 + i];
+        a[i] = mine + __shfl_xor(other, 16, BA_WAVE);
+    }
+#pragma unroll
+    for (int i = 0; i < 4; i++) {
+        const bool hi = lane & 8;
+        const double mine = hi ? a[4 + i] : a[i], other = hi ? a[i] : a[4 + i];
+        a[i] = mine + __shfl_xor(other, 8, BA_WAVE);
+    }
+#pragma unroll
+    for (int i = 0; i < 2; i++) {
+        const bool hi = lane & 4;
+        const double mine = hi ? a[2 + i] : a[i], other = hi ? a[i] : a[2 + i];
+        a[i] = mine + __shfl_xor(other, 4, BA_WAVE);
+    }
+    {
+        const bool hi = lane & 2;
+        const double mine = hi ? a[1] : a[0], other = hi ? a[0] : a[1];
+        a[0] = mine + __shfl_xor(other, 2, BA_WAVE);
+    }
+    return a[0] + __shfl_xor(a[0], 1, BA_WAVE);
+}
+
 // ---------------------------------------------------------------- error-free transforms
 // Knuth TwoSum: s + e == a + b exactly.
 __device__ __forceinline__ void two_sum(double a, double b, double &s, double &e) {

@@ -34,113 +34,131 @@
 
 namespace ba {
 
-// One block (4 waves) per group of 64 voxels with equal cluster count m.
-// Lane l of every wave serves voxel l; wave w visits the voxel's clusters
-// k = w, w + 4, ... so a voxel seen by many scans is summed by four waves at
-// once.  Each wave accumulates, relative to the voxel's first cluster
-// centroid r (which keeps the sums well conditioned at large coordinates),
-//   n = sum N_k,  s = sum N_k d_k,  M = sum [St_k + N_k d_k d_k^T],  d_k = m_k - r,
-// and wave 0 adds the four partial sums in a fixed order:
-//   mbar = r + s / n,  A = (M - s s^T / n) / n.
-__global__ __launch_bounds__(256) void k_vox(const GroupDesc *__restrict__ groups, int32_t n_groups, int64_t c_pad,
-                                             const double *__restrict__ vN, const double *__restrict__ vmu,
-                                             const double *__restrict__ vS, const int32_t *__restrict__ vpose,
-                                             const double *__restrict__ poses, double *__restrict__ vstate,
-                                             int64_t n_slots, const LMState *__restrict__ lm, int trial,
-                                             double *__restrict__ wave_cost) {
+// Accumulates the clusters k = k0, k0 + kstep, ... of the voxel in `lane` of
+// group g relative to the centroid r of the voxel's first cluster (which keeps
+// the sums well conditioned at large coordinates):
+//   n = sum N_k,  s = sum N_k d_k,  M = sum [St_k + N_k d_k d_k^T],  d_k = m_k - r.
+struct VoxSums {
+    double n, s0, s1, s2;
+    double M[6];
+    double r[3];
+};
+
+__device__ __forceinline__ void vox_accumulate(const GroupDesc &g, int lane, int k0, int kstep, int64_t c_pad,
+                                               const double *__restrict__ vN, const double *__restrict__ vmu,
+                                               const double *__restrict__ vS, const int32_t *__restrict__ vpose,
+                                               const double *__restrict__ poses, VoxSums &a) {
+    a.n = a.s0 = a.s1 = a.s2 = 0.0;
+#pragma unroll
+    for (int q = 0; q < 6; q++) a.M[q] = 0.0;
+    {
+        const int64_t idx = g.cbase + lane;
+        const double mu[3] = {vmu[idx], vmu[c_pad + idx], vmu[2 * c_pad + idx]};
+        Pose P;
+        load_pose(poses, vpose[idx], P);
+        rot(P.r, mu, a.r);
+        a.r[0] += P.t[0]; a.r[1] += P.t[1]; a.r[2] += P.t[2];
+    }
+#pragma unroll 2
+    for (int k = k0; k < g.m; k += kstep) {
+        const int64_t idx = g.cbase + 64LL * k + lane;
+        const double nk = vN[idx];
+        const double mu[3] = {vmu[idx], vmu[c_pad + idx], vmu[2 * c_pad + idx]};
+        double S[6];
+#pragma unroll
+        for (int q = 0; q < 6; q++) S[q] = vS[q * c_pad + idx];
+        Pose P;
+        load_pose(poses, vpose[idx], P);
+        double y[3], St[6];
+        rot(P.r, mu, y);
+        rot_sym(P.r, S, St);
+        const double d0 = (y[0] + P.t[0]) - a.r[0], d1 = (y[1] + P.t[1]) - a.r[1], d2 = (y[2] + P.t[2]) - a.r[2];
+        const double nd0 = nk * d0, nd1 = nk * d1, nd2 = nk * d2;
+        a.n += nk;
+        a.s0 += nd0; a.s1 += nd1; a.s2 += nd2;
+        a.M[0] += fma(nd0, d0, St[0]);
+        a.M[1] += fma(nd0, d1, St[1]);
+        a.M[2] += fma(nd0, d2, St[2]);
+        a.M[3] += fma(nd1, d1, St[3]);
+        a.M[4] += fma(nd1, d2, St[4]);
+        a.M[5] += fma(nd2, d2, St[5]);
+    }
+}
+
+// mbar = r + s / n,  A = (M - s s^T / n) / n;  smallest eigenpair; voxel state.
+__device__ __forceinline__ double vox_finish(const VoxSums &a, double *__restrict__ st) {
+    const double inv = 1.0 / a.n;
+    const double b0 = a.s0 * inv, b1 = a.s1 * inv, b2 = a.s2 * inv;
+    double A[6];
+    A[0] = (a.M[0] - a.s0 * b0) * inv;
+    A[1] = (a.M[1] - a.s0 * b1) * inv;
+    A[2] = (a.M[2] - a.s0 * b2) * inv;
+    A[3] = (a.M[3] - a.s1 * b1) * inv;
+    A[4] = (a.M[4] - a.s1 * b2) * inv;
+    A[5] = (a.M[5] - a.s2 * b2) * inv;
+    double lam[3], u[3];
+    eig_sym3(A, lam, u);
+    st[0] = u[0]; st[1] = u[1]; st[2] = u[2];
+    st[3] = a.r[0] + b0; st[4] = a.r[1] + b1; st[5] = a.r[2] + b2;
+    st[6] = 2.0 * inv;
+    st[7] = lam[0];
+    return lam[0];
+}
+
+// Residual pass.  One block per group of 64 voxels with equal cluster count
+// (blocks ordered largest count first); the four waves split the group's
+// clusters (k = w, w + 4, ...) and wave 0 adds the partial sums in wave order.
+// (The LM decision runs as its own kernel: a last-block-done ticket would need
+// a device-scope fence per block, which writes back the XCD-private L2.)
+__global__ __launch_bounds__(256) void k_vox(const VoxBlock *__restrict__ blocks, const GroupDesc *__restrict__ groups,
+                                             int64_t c_pad, const double *__restrict__ vN,
+                                             const double *__restrict__ vmu, const double *__restrict__ vS,
+                                             const int32_t *__restrict__ vpose, const double *__restrict__ poses,
+                                             double *__restrict__ vstate, int64_t n_slots,
+                                             const LMState *__restrict__ lm, int trial,
+                                             double *__restrict__ group_cost) {
     __shared__ double part[3][10][64];
-    const int gi = blockIdx.x;
+    const VoxBlock b = blocks[blockIdx.x];
     const int w = threadIdx.x >> 6;
     const int lane = threadIdx.x & 63;
-    if (gi >= n_groups) return;
-    const GroupDesc g = groups[gi];
     int buf = 0;
     if (lm) {
-        const LMState &st = lm[g.window];
+        const LMState &st = lm[b.window];
         if (st.done) return;
         buf = trial ? 1 - st.cur : st.cur;
     }
+    double *vs = vstate + (int64_t)buf * n_slots * VSTATE;
+    const int gi = b.g0;
+    const GroupDesc g = groups[gi];
     const bool active = lane < g.nvox;
-    double n = 0.0, s0 = 0.0, s1 = 0.0, s2 = 0.0;
-    double M[6] = {0, 0, 0, 0, 0, 0};
-    double r[3] = {0, 0, 0};
-    if (active && w < g.m) {
-        {   // reference: centroid of the voxel's first cluster
-            const int64_t idx = g.cbase + lane;
-            const double mu[3] = {vmu[idx], vmu[c_pad + idx], vmu[2 * c_pad + idx]};
-            Pose P;
-            load_pose(poses, vpose[idx], P);
-            rot(P.r, mu, r);
-            r[0] += P.t[0]; r[1] += P.t[1]; r[2] += P.t[2];
-        }
-#pragma unroll 2
-        for (int k = w; k < g.m; k += 4) {
-            const int64_t idx = g.cbase + 64LL * k + lane;
-            const double nk = vN[idx];
-            const double mu[3] = {vmu[idx], vmu[c_pad + idx], vmu[2 * c_pad + idx]};
-            double S[6];
-#pragma unroll
-            for (int q = 0; q < 6; q++) S[q] = vS[q * c_pad + idx];
-            Pose P;
-            load_pose(poses, vpose[idx], P);
-            double y[3], St[6];
-            rot(P.r, mu, y);
-            rot_sym(P.r, S, St);
-            const double d0 = (y[0] + P.t[0]) - r[0], d1 = (y[1] + P.t[1]) - r[1], d2 = (y[2] + P.t[2]) - r[2];
-            const double nd0 = nk * d0, nd1 = nk * d1, nd2 = nk * d2;
-            n += nk;
-            s0 += nd0; s1 += nd1; s2 += nd2;
-            M[0] += fma(nd0, d0, St[0]);
-            M[1] += fma(nd0, d1, St[1]);
-            M[2] += fma(nd0, d2, St[2]);
-            M[3] += fma(nd1, d1, St[3]);
-            M[4] += fma(nd1, d2, St[4]);
-            M[5] += fma(nd2, d2, St[5]);
-        }
-    }
+    VoxSums a;
+    a.n = a.s0 = a.s1 = a.s2 = 0.0;
+    for (int q = 0; q < 6; q++) a.M[q] = 0.0;
+    if (active && w < g.m) vox_accumulate(g, lane, w, 4, c_pad, vN, vmu, vS, vpose, poses, a);
     if (w > 0) {
         double *pp = &part[w - 1][0][0];
-        pp[0 * 64 + lane] = n;
-        pp[1 * 64 + lane] = s0; pp[2 * 64 + lane] = s1; pp[3 * 64 + lane] = s2;
+        pp[lane] = a.n;
+        pp[64 + lane] = a.s0; pp[128 + lane] = a.s1; pp[192 + lane] = a.s2;
 #pragma unroll
-        for (int q = 0; q < 6; q++) pp[(4 + q) * 64 + lane] = M[q];
+        for (int q = 0; q < 6; q++) pp[(4 + q) * 64 + lane] = a.M[q];
     }
     __syncthreads();
-    if (w != 0) return;
-    double lam0 = 0.0;
-    if (active) {
-        for (int v = 0; v < 3; v++) {
-            const double *pp = &part[v][0][0];
-            n += pp[lane];
-            s0 += pp[64 + lane]; s1 += pp[128 + lane]; s2 += pp[192 + lane];
+    if (w == 0) {
+        double lam0 = 0.0;
+        if (active) {
+            for (int v = 0; v < 3; v++) {
+                const double *pp = &part[v][0][0];
+                a.n += pp[lane];
+                a.s0 += pp[64 + lane]; a.s1 += pp[128 + lane]; a.s2 += pp[192 + lane];
 #pragma unroll
-            for (int q = 0; q < 6; q++) M[q] += pp[(4 + q) * 64 + lane];
+                for (int q = 0; q < 6; q++) a.M[q] += pp[(4 + q) * 64 + lane];
+            }
+            lam0 = vox_finish(a, vs + ((int64_t)gi * 64 + lane) * VSTATE);
         }
-        const double inv = 1.0 / n;
-        const double b0 = s0 * inv, b1 = s1 * inv, b2 = s2 * inv;   // mbar - r
-        double A[6];
-        A[0] = (M[0] - s0 * b0) * inv;
-        A[1] = (M[1] - s0 * b1) * inv;
-        A[2] = (M[2] - s0 * b2) * inv;
-        A[3] = (M[3] - s1 * b1) * inv;
-        A[4] = (M[4] - s1 * b2) * inv;
-        A[5] = (M[5] - s2 * b2) * inv;
-        double lam[3], u[3];
-        eig_sym3(A, lam, u);
-        lam0 = lam[0];
-        double *st = vstate + ((int64_t)buf * n_slots + (int64_t)gi * 64 + lane) * VSTATE;
-        st[0] = u[0]; st[1] = u[1]; st[2] = u[2];
-        st[3] = r[0] + b0; st[4] = r[1] + b1; st[5] = r[2] + b2;
-        st[6] = 2.0 * inv;
-        st[7] = lam0;
+        const double c = wave_sum(lam0);
+        if (lane == 0) group_cost[gi] = c;
     }
-    const double c = wave_sum(lam0);
-    if (lane == 0) wave_cost[gi] = c;
 }
-
-struct Acc27 {
-    double v[NPART];
-};
 
 __global__ __launch_bounds__(256) void k_pose(const ChunkDesc *__restrict__ chunks, int32_t n_chunks, int64_t C,
                                               const double *__restrict__ pN, const double *__restrict__ pmu,
@@ -227,13 +245,12 @@ __global__ __launch_bounds__(256) void k_pose(const ChunkDesc *__restrict__ chun
 #pragma unroll
         for (int k = 0; k < 6; k++) acc[21 + k] = fma(sn * u[ii[k]], u[jj[k]], acc[21 + k]);
     }
+    // reduce-scatter over the wave: lane l ends with the sum of value l / 2
+    double red[32];
 #pragma unroll
-    for (int q = 0; q < NPART; q++) acc[q] = wave_sum(acc[q]);
-    if (lane == 0) {
-        double *o = partials + (int64_t)wave * NPART;
-#pragma unroll
-        for (int q = 0; q < NPART; q++) o[q] = acc[q];
-    }
+    for (int q = 0; q < 32; q++) red[q] = (q < NPART) ? acc[q] : 0.0;
+    const double v = wave_reduce_scatter32(red, lane);
+    if ((lane & 1) == 0 && (lane >> 1) < NPART) partials[(int64_t)wave * NPART + (lane >> 1)] = v;
 }
 
 // One thread per (pose, component): fixed-order sum over the pose's chunks.
@@ -303,16 +320,25 @@ __global__ void k_voxel_eig(int64_t n_slots, const int32_t *__restrict__ slot_vo
 static inline unsigned nblk(int64_t n, int t = 256) { return (unsigned)((n + t - 1) / t); }
 
 void launch_vox(Problem *P, const double *poses, bool use_lm, bool trial, hipStream_t s) {
-    if (P->n_groups == 0) return;
+    if (P->n_vblocks == 0) return;
     ProfScope prof("k_vox", s);
-    hipLaunchKernelGGL(k_vox, dim3((unsigned)P->n_groups), dim3(256), 0, s, P->groups, P->n_groups,
-                       P->c_pad, P->v_N, P->v_mu, P->v_S, P->v_pose, poses, P->vstate, (int64_t)P->n_groups * 64,
+    hipLaunchKernelGGL(k_vox, dim3((unsigned)P->n_vblocks), dim3(256), 0, s, P->vblocks, P->groups, P->c_pad, P->v_N,
+                       P->v_mu, P->v_S, P->v_pose, poses, P->vstate, (int64_t)P->n_groups * 64,
                        use_lm ? P->lm : nullptr, trial ? 1 : 0, P->wave_cost);
 }
 
 void launch_window_cost(Problem *P, double *out, hipStream_t s) {
     hipLaunchKernelGGL(k_window_cost, dim3(P->n_windows), dim3(256), 0, s, P->n_windows, P->win_group_ptr,
                        P->wave_cost, out);
+}
+
+void launch_pose_chunks(Problem *P, const double *poses, bool use_lm, hipStream_t s) {
+    if (P->n_chunks > 0) {
+        ProfScope prof("k_pose", s);
+        hipLaunchKernelGGL(k_pose, dim3(nblk((int64_t)P->n_chunks * 64)), dim3(256), 0, s, P->chunks, P->n_chunks,
+                           P->n_clusters, P->p_N, P->p_mu, P->p_S, P->p_slot, poses, P->vstate,
+                           (int64_t)P->n_groups * 64, P->pose_window, use_lm ? P->lm : nullptr, P->partials);
+    }
 }
 
 void launch_pose_derivs(Problem *P, const double *poses, bool use_lm, double *g, double *H, hipStream_t s) {

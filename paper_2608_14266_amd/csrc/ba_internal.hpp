@@ -22,14 +22,6 @@ struct GroupDesc {
     int32_t pad;
 };
 
-// One pose chunk: `count` consecutive clusters of the pose-sorted layout,
-// all observed by `pose`.
-struct ChunkDesc {
-    int64_t start;
-    int32_t count;
-    int32_t pose;
-};
-
 // Device-side Levenberg-Marquardt state of one window.
 struct LMState {
     double mu, nu;
@@ -39,6 +31,35 @@ struct LMState {
     double cost0;
     int32_t accepted, need_eval, info, done;
     int32_t iters, n_accepted, cur, pad;
+};
+
+// One residual-pass block: `ng` consecutive groups served one wave each
+// (split == 1), or one group whose clusters four waves share (split == 4).
+struct VoxBlock {
+    int32_t g0, ng, split, window;
+};
+
+// One pose chunk: `count` consecutive clusters of the pose-sorted layout,
+// all observed by `pose`.
+struct ChunkDesc {
+    int64_t start;
+    int32_t count;
+    int32_t pose;
+};
+
+
+// Arguments of the per-window LM decision kernel.
+struct DecideArgs {
+    int32_t W;
+    const int32_t *win_pose_ptr, *win_group_ptr;
+    const double *pose_q;
+    const int32_t *pose_info;
+    const double *group_cost;
+    LMState *lm;
+    double *trace;
+    int32_t it;
+    const double *poses_trial;
+    double *poses;
 };
 
 static constexpr int VSTATE = 8;    // doubles per voxel slot: u[3] mbar[3] 2/N lam0
@@ -61,6 +82,8 @@ struct Problem {
     double *v_N = nullptr;      // [c_pad]
     int32_t *v_pose = nullptr;  // [c_pad]
     GroupDesc *groups = nullptr;
+    VoxBlock *vblocks = nullptr;
+    int32_t n_vblocks = 0;
     int32_t *slot_vox = nullptr; // slot -> input voxel id (-1 padding), n_groups*64
     double *vstate = nullptr;   // [2][n_groups*64][VSTATE]
     double *wave_cost = nullptr; // [n_groups]
@@ -99,6 +122,7 @@ struct Problem {
     int64_t dense_total = 0;
     double *dense = nullptr;                  // per-window dense (6Nw)^2 matrices
     void *dense_state = nullptr;              // coupled-path plan and buffers
+    void *iter_graph = nullptr;               // captured ba_iterate graph
 
     int64_t n_points = 0;
     DevArena mem;                             // every device allocation above

@@ -9,6 +9,7 @@ namespace ba {
 // evaluation (ba_eval.hip)
 void launch_vox(Problem *P, const double *poses, bool use_lm, bool trial, hipStream_t s);
 void launch_window_cost(Problem *P, double *out, hipStream_t s);
+void launch_pose_chunks(Problem *P, const double *poses, bool use_lm, hipStream_t s);
 void launch_pose_derivs(Problem *P, const double *poses, bool use_lm, double *g, double *H, hipStream_t s);
 void launch_voxel_eig(Problem *P, double *out, hipStream_t s);
 
@@ -20,6 +21,8 @@ void launch_lm_reset(Problem *P, double mu0, double nu0, hipStream_t s);
 void launch_lm_cost(Problem *P, hipStream_t s);
 void launch_window_stats(Problem *P, double tol_g, hipStream_t s);
 void launch_solve_mm_lm(Problem *P, const double *poses, hipStream_t s);
+void launch_window_solve_mm(Problem *P, const double *poses, double tol_g, hipStream_t s);
+DecideArgs decide_args(Problem *P, double *trace, int it, double *poses);
 void launch_decide(Problem *P, double *trace, int it, double *poses, hipStream_t s);
 void launch_commit(Problem *P, double *poses, hipStream_t s);
 

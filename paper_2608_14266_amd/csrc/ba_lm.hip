@@ -14,6 +14,7 @@
 #include "ba_device.hpp"
 #include "ba_internal.hpp"
 #include "ba_kernels.hpp"
+#include "ba_decide.hpp"
 
 namespace ba {
 
@@ -90,13 +91,15 @@ __device__ __forceinline__ int solve_pose(const double *__restrict__ h, const do
     return 0;
 }
 
-__global__ void k_lm_reset(int32_t W, LMState *__restrict__ lm, double mu0, double nu0) {
+__global__ void k_lm_reset(int32_t W, LMState *__restrict__ lm, double mu0, double nu0,
+                           const int32_t *__restrict__ win_group_ptr) {
     const int w = blockIdx.x * blockDim.x + threadIdx.x;
     if (w >= W) return;
     LMState s;
     s.mu = mu0; s.nu = nu0; s.cost = 0.0; s.cost_trial = 0.0; s.q = 0.0; s.rho = 0.0;
     s.gnorm = 0.0; s.maxdiag = 0.0; s.cost0 = 0.0;
-    s.accepted = 0; s.need_eval = 1; s.info = 0; s.done = 0;
+    s.accepted = 0; s.need_eval = 1; s.info = 0;
+    s.done = (win_group_ptr[w + 1] == win_group_ptr[w]) ? 1 : 0;   // a window without voxels has nothing to do
     s.iters = 0; s.n_accepted = 0; s.cur = 0; s.pad = 0;
     lm[w] = s;
 }
@@ -176,76 +179,9 @@ __global__ void k_solve_mm_lm(int32_t n_poses, const int32_t *__restrict__ pose_
 }
 
 // block per window: predicted reduction, trial cost, gain ratio, damping update.
-__global__ __launch_bounds__(256) void k_decide(int32_t W, const int32_t *__restrict__ win_pose_ptr,
-                                                const int32_t *__restrict__ win_group_ptr,
-                                                const double *__restrict__ pose_q,
-                                                const int32_t *__restrict__ pose_info,
-                                                const double *__restrict__ wave_cost, LMState *__restrict__ lm,
-                                                double *__restrict__ trace, int it,
-                                                const double *__restrict__ poses_trial, double *__restrict__ poses) {
-    __shared__ double rq[256], rc[256];
-    __shared__ int ri[256];
-    __shared__ int s_acc;
-    const int w = blockIdx.x;
-    if (w >= W) return;
-    LMState &st = lm[w];
-    if (st.done) return;
-    double q = 0.0, c = 0.0;
-    int info = 0x7fffffff;
-    for (int j = win_pose_ptr[w] + threadIdx.x; j < win_pose_ptr[w + 1]; j += 256) {
-        q += pose_q[j];
-        if (pose_info[j]) info = min(info, pose_info[j]);
-    }
-    for (int i = win_group_ptr[w] + threadIdx.x; i < win_group_ptr[w + 1]; i += 256) c += wave_cost[i];
-    rq[threadIdx.x] = q;
-    rc[threadIdx.x] = c;
-    ri[threadIdx.x] = info;
-    __syncthreads();
-    for (int o = 128; o > 0; o >>= 1) {
-        if ((int)threadIdx.x < o) {
-            rq[threadIdx.x] += rq[threadIdx.x + o];
-            rc[threadIdx.x] += rc[threadIdx.x + o];
-            ri[threadIdx.x] = min(ri[threadIdx.x], ri[threadIdx.x + o]);
-        }
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) {
-        const double qq = rq[0], ct = rc[0];
-        const int inf = (ri[0] == 0x7fffffff) ? 0 : ri[0];
-        const double rho = (inf == 0 && qq > 0.0) ? (st.cost - ct) / qq : -1.0;
-        const int acc = rho > 0.0;
-        if (trace) {
-            double *t = trace + ((int64_t)it * W + w) * 8;
-            t[0] = st.cost; t[1] = inf ? st.cost : ct; t[2] = rho; t[3] = st.mu;
-            t[4] = acc; t[5] = st.gnorm; t[6] = inf; t[7] = inf ? 0.0 : qq;
-        }
-        s_acc = acc;
-        st.q = qq;
-        st.rho = rho;
-        st.info = inf;
-        st.cost_trial = ct;
-        st.accepted = acc;
-        st.iters += 1;
-        if (acc) {
-            st.cost = ct;
-            st.cur = 1 - st.cur;
-            st.need_eval = 1;
-            st.n_accepted += 1;
-            const double f = 2.0 * rho - 1.0;
-            const double fac = 1.0 - f * f * f;
-            st.mu *= (fac > 1.0 / 3.0 ? fac : 1.0 / 3.0);
-            st.nu = 2.0;
-        } else {
-            st.mu *= st.nu;
-            st.nu *= 2.0;
-        }
-    }
-    __syncthreads();
-    // commit the window's trial poses on acceptance
-    if (s_acc) {
-        const int64_t a = 12LL * win_pose_ptr[w], b = 12LL * win_pose_ptr[w + 1];
-        for (int64_t i = a + threadIdx.x; i < b; i += 256) poses[i] = poses_trial[i];
-    }
+__global__ __launch_bounds__(256) void k_decide(DecideArgs da) {
+    if ((int)blockIdx.x >= da.W) return;
+    decide_window(blockIdx.x, da);
 }
 
 __global__ void k_commit(int32_t n_poses, const int32_t *__restrict__ pose_window, const LMState *__restrict__ lm,
@@ -255,6 +191,100 @@ __global__ void k_commit(int32_t n_poses, const int32_t *__restrict__ pose_windo
     const int j = (int)(i / 12);
     const LMState &st = lm[pose_window[j]];
     if (!st.done && st.accepted) poses[i] = poses_trial[i];
+}
+
+// Expand the 27 per-pose sums (g 6, H_phiphi upper 6, H_phit 9, H_tt upper 6).
+__device__ __forceinline__ void expand_gH(const double *a, double *g6, double *h) {
+#pragma unroll
+    for (int k = 0; k < 6; k++) g6[k] = a[k];
+    const int ii[6] = {0, 0, 0, 1, 1, 2}, jj[6] = {0, 1, 2, 1, 2, 2};
+#pragma unroll
+    for (int k = 0; k < 6; k++) {
+        h[6 * ii[k] + jj[k]] = a[6 + k];
+        h[6 * jj[k] + ii[k]] = a[6 + k];
+        h[6 * (3 + ii[k]) + 3 + jj[k]] = a[21 + k];
+        h[6 * (3 + jj[k]) + 3 + ii[k]] = a[21 + k];
+    }
+#pragma unroll
+    for (int r = 0; r < 3; r++)
+#pragma unroll
+        for (int c = 0; c < 3; c++) {
+            h[6 * r + 3 + c] = a[12 + 3 * r + c];
+            h[6 * (3 + c) + r] = a[12 + 3 * r + c];
+        }
+}
+
+// One block per window: (when the poses moved) sum each pose's chunk partials
+// in a fixed order into g and H, the window's gradient norm and damping floor
+// and the convergence test; then every pose's damped 6x6 solve, predicted
+// reduction share and trial pose.
+__global__ __launch_bounds__(256) void k_window_solve_mm(int32_t W, const int32_t *__restrict__ win_pose_ptr,
+                                                         const int32_t *__restrict__ chunk_ptr,
+                                                         const double *__restrict__ partials, LMState *__restrict__ lm,
+                                                         double *__restrict__ g, double *__restrict__ H,
+                                                         const double *__restrict__ poses, double *__restrict__ dx,
+                                                         double *__restrict__ pose_q, int32_t *__restrict__ pose_info,
+                                                         double *__restrict__ poses_trial, double tol_g) {
+    __shared__ double rs[256], rm[256];
+    __shared__ int s_done;
+    const int w = blockIdx.x;
+    if (w >= W) return;
+    LMState &st = lm[w];
+    if (st.done) return;
+    const int p0 = win_pose_ptr[w], p1 = win_pose_ptr[w + 1];
+    if (st.need_eval) {
+        double gs = 0.0, mx = 0.0;
+        for (int j = p0 + threadIdx.x; j < p1; j += 256) {
+            double a[NPART];
+#pragma unroll
+            for (int k = 0; k < NPART; k++) a[k] = 0.0;
+            for (int c = chunk_ptr[j]; c < chunk_ptr[j + 1]; c++) {
+                const double *pp = partials + (int64_t)c * NPART;
+#pragma unroll
+                for (int k = 0; k < NPART; k++) a[k] += pp[k];
+            }
+            expand_gH(a, g + 6LL * j, H + 36LL * j);
+#pragma unroll
+            for (int k = 0; k < 6; k++) gs += a[k] * a[k];
+            mx = fmax(mx, fmax(fmax(a[6], a[9]), fmax(a[11], fmax(a[21], fmax(a[24], a[26])))));
+        }
+        rs[threadIdx.x] = gs;
+        rm[threadIdx.x] = mx;
+        __syncthreads();
+        for (int o = 128; o > 0; o >>= 1) {
+            if ((int)threadIdx.x < o) {
+                rs[threadIdx.x] += rs[threadIdx.x + o];
+                rm[threadIdx.x] = fmax(rm[threadIdx.x], rm[threadIdx.x + o]);
+            }
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) {
+            st.gnorm = sqrt(rs[0]);
+            st.maxdiag = rm[0];
+            st.need_eval = 0;
+            if (tol_g > 0.0 && st.gnorm < tol_g) {
+                st.done = 1;
+                st.accepted = 0;
+            }
+            s_done = st.done;
+        }
+        __syncthreads();
+        if (s_done) return;
+    }
+    const double mu = st.mu, fl = 1e-12 * st.maxdiag;
+    for (int j = p0 + threadIdx.x; j < p1; j += 256) {
+        double q;
+        const int info = solve_pose(H + 36LL * j, g + 6LL * j, mu, fl, dx + 6LL * j, q);
+        pose_q[j] = q;
+        pose_info[j] = info ? 6 * (j - p0) + info : 0;
+        pose_plus(poses + 12LL * j, dx + 6LL * j, poses_trial + 12LL * j);
+    }
+}
+
+void launch_window_solve_mm(Problem *P, const double *poses, double tol_g, hipStream_t s) {
+    hipLaunchKernelGGL(k_window_solve_mm, dim3(P->n_windows), dim3(256), 0, s, P->n_windows, P->win_pose_ptr,
+                       P->chunk_ptr, P->partials, P->lm, P->g, P->H, poses, P->dx, P->pose_q, P->pose_info,
+                       P->poses_trial, tol_g);
 }
 
 // ---------------------------------------------------------------- standalone MM solve
@@ -314,7 +344,8 @@ void launch_solve_mm_plain(int32_t n, const double *H, const double *g, double m
 }
 
 void launch_lm_reset(Problem *P, double mu0, double nu0, hipStream_t s) {
-    hipLaunchKernelGGL(k_lm_reset, dim3(nblk(P->n_windows)), dim3(256), 0, s, P->n_windows, P->lm, mu0, nu0);
+    hipLaunchKernelGGL(k_lm_reset, dim3(nblk(P->n_windows)), dim3(256), 0, s, P->n_windows, P->lm, mu0, nu0,
+                       P->win_group_ptr);
 }
 
 void launch_lm_cost(Problem *P, hipStream_t s) {
@@ -332,10 +363,25 @@ void launch_solve_mm_lm(Problem *P, const double *poses, hipStream_t s) {
                        P->win_pose_ptr, P->lm, P->H, P->g, poses, P->dx, P->pose_q, P->pose_info, P->poses_trial);
 }
 
+DecideArgs decide_args(Problem *P, double *trace, int it, double *poses) {
+    DecideArgs da;
+    da.W = P->n_windows;
+    da.win_pose_ptr = P->win_pose_ptr;
+    da.win_group_ptr = P->win_group_ptr;
+    da.pose_q = P->pose_q;
+    da.pose_info = P->pose_info;
+    da.group_cost = P->wave_cost;
+    da.lm = P->lm;
+    da.trace = trace;
+    da.it = it;
+    da.poses_trial = P->poses_trial;
+    da.poses = poses;
+    return da;
+}
+
 void launch_decide(Problem *P, double *trace, int it, double *poses, hipStream_t s) {
-    hipLaunchKernelGGL(k_decide, dim3(P->n_windows), dim3(256), 0, s, P->n_windows, P->win_pose_ptr,
-                       P->win_group_ptr, P->pose_q, P->pose_info, P->wave_cost, P->lm, trace, it,
-                       P->poses_trial, poses);
+    DecideArgs da = decide_args(P, trace, it, poses);
+    hipLaunchKernelGGL(k_decide, dim3(P->n_windows), dim3(256), 0, s, da);
 }
 
 void launch_commit(Problem *P, double *poses, hipStream_t s) {
