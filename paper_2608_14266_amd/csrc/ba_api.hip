@@ -135,7 +135,7 @@ static ba_status enqueue_lm(Problem *P, double *poses, const ba_lm_options *opt,
     launch_lm_cost(P, s);
     for (int it = 0; it < iters; it++) {
         if (opt->mode == BA_MODE_MM) {
-            launch_pose_chunks(P, poses, true, s);
+            launch_pose_derivs(P, poses, true, P->g, P->H, s);
             launch_window_solve_mm(P, poses, opt->tol_g, s);
         } else {
             launch_pose_derivs(P, poses, true, P->g, P->H, s);

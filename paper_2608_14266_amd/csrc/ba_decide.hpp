@@ -16,13 +16,16 @@ __device__ __forceinline__ void decide_window(int w, const DecideArgs &da) {
     if (st.done) return;
     double q = 0.0, c = 0.0;
     int info = 0x7fffffff;
+    const int p0 = da.win_pose_ptr[w], p1 = da.win_pose_ptr[w + 1];
+    const int g0 = da.win_group_ptr[w], g1 = da.win_group_ptr[w + 1];
 #pragma unroll 4
-    for (int j = da.win_pose_ptr[w] + threadIdx.x; j < da.win_pose_ptr[w + 1]; j += 256) {
+    for (int j = p0 + threadIdx.x; j < p1; j += 256) {
         q += da.pose_q[j];
-        if (da.pose_info[j]) info = min(info, da.pose_info[j]);
+        const int inf = da.pose_info[j];
+        if (inf) info = min(info, inf);
     }
 #pragma unroll 8
-    for (int i = da.win_group_ptr[w] + threadIdx.x; i < da.win_group_ptr[w + 1]; i += 256) c += da.group_cost[i];
+    for (int i = g0 + threadIdx.x; i < g1; i += 256) c += da.group_cost[i];
     rq[threadIdx.x] = q;
     rc[threadIdx.x] = c;
     ri[threadIdx.x] = info;
@@ -68,7 +71,8 @@ __device__ __forceinline__ void decide_window(int w, const DecideArgs &da) {
     }
     __syncthreads();
     if (s_acc) {
-        const int64_t a = 12LL * da.win_pose_ptr[w], b = 12LL * da.win_pose_ptr[w + 1];
+        const int64_t a = 12LL * p0, b = 12LL * p1;
+#pragma unroll 4
         for (int64_t i = a + threadIdx.x; i < b; i += 256) da.poses[i] = da.poses_trial[i];
     }
 }

@@ -225,14 +225,19 @@ __global__ void k_damp_copy(const DenseDesc *__restrict__ desc, const DenseParam
     if (t < d.n) work[d.v_off + t] = -g[6LL * d.pose0 + t];
 }
 
-// Factor diagonal block `step` in LDS, invert it in place, forward-substitute
-// its slice of the right-hand side.  LDS: one padded 64x64 tile + two vectors.
-__global__ __launch_bounds__(256) void k_potf2(const DenseDesc *__restrict__ desc, DenseParam *__restrict__ prm,
-                                               double *__restrict__ work, int step) {
-    __shared__ double L[TB][TB + 1];
-    __shared__ double col[TB];
-    __shared__ double bv[TB];
-    __shared__ int fail;
+// Broadcast lane `src` (compile-time) of a wave-wide double to every lane.
+__device__ __forceinline__ double bcast(double v, int src) {
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), src);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), src);
+    return __hiloint2double(hi, lo);
+}
+
+// Factor diagonal block `step`, invert it, forward-substitute its slice of
+// the right-hand side, all in the registers of one wavefront: lane i holds
+// row i of the 64x64 tile; the entries of column j that other lanes need are
+// broadcast as scalars (fully unrolled right-looking sweeps).
+__global__ __launch_bounds__(64) void k_potf2(const DenseDesc *__restrict__ desc, DenseParam *__restrict__ prm,
+                                              double *__restrict__ work, int step) {
     const int m = blockIdx.y;
     const DenseDesc d = desc[m];
     if (!prm[m].active || prm[m].info) return;
@@ -240,66 +245,70 @@ __global__ __launch_bounds__(256) void k_potf2(const DenseDesc *__restrict__ des
     if (k0 >= d.n) return;
     const int nb = (int)std::min<int64_t>(TB, d.n - k0);
     double *A = work + d.a_off;
-    const int t = threadIdx.x;
-    for (int e = t; e < TB * TB; e += 256) {
-        const int i = e / TB, j = e % TB;
-        L[i][j] = (i < nb && j < nb) ? A[(k0 + i) * d.n + k0 + j] : (i == j ? 1.0 : 0.0);
-    }
-    if (t < TB) bv[t] = (t < nb) ? work[d.v_off + k0 + t] : 0.0;
-    if (t == 0) fail = 0;
-    __syncthreads();
-    // right-looking unblocked Cholesky of the (padded) tile
-    for (int j = 0; j < nb; j++) {
-        if (t == 0) {
-            const double p = L[j][j];
-            if (!(p > 0.0)) fail = (int)(k0 + j + 1);
-            else L[j][j] = sqrt(p);
+    const int i = threadIdx.x;
+    double a[TB];
+#pragma unroll
+    for (int c = 0; c < TB; c++)
+        a[c] = (i < nb && c < nb) ? A[(k0 + i) * d.n + k0 + c] : (i == c ? 1.0 : 0.0);
+    // Cholesky: a[c] of lane i becomes L_ic (c <= i)
+    int fail = 0;
+#pragma unroll
+    for (int j = 0; j < TB; j++) {
+        const double p = bcast(a[j], j);
+        if (!(p > 0.0)) {
+            fail = (int)(k0 + j + 1);
+            break;
         }
-        __syncthreads();
-        if (fail) break;
-        const double dj = L[j][j];
-        for (int i = j + 1 + t; i < TB; i += 256) L[i][j] = (i < nb) ? L[i][j] / dj : 0.0;
-        __syncthreads();
-        const int rem = nb - j - 1;
-        for (int e = t; e < rem * rem; e += 256) {
-            const int i = j + 1 + e / rem, c = j + 1 + e % rem;
-            if (c <= i) L[i][c] -= L[i][j] * L[c][j];
+        const double dj = sqrt(p);
+        if (i == j) a[j] = dj;
+        if (i > j) a[j] = a[j] / dj;
+#pragma unroll
+        for (int c = j + 1; c < TB; c++) {
+            const double lcj = bcast(a[j], c);
+            if (c <= i) a[c] = fma(-a[j], lcj, a[c]);
         }
-        __syncthreads();
     }
-    if (fail) {
-        if (t == 0) prm[m].info = fail;
+    if (fail) {   // fail is wave-uniform (the pivot is a broadcast)
+        if (i == 0 && fail <= d.n) prm[m].info = fail;
         return;
     }
-    for (int e = t; e < TB * TB; e += 256) {
-        const int i = e / TB, j = e % TB;
-        if (i < nb && j < nb && j <= i) A[(k0 + i) * d.n + k0 + j] = L[i][j];
+    if (i < nb) {
+#pragma unroll
+        for (int c = 0; c < TB; c++)
+            if (c <= i && c < nb) A[(k0 + i) * d.n + k0 + c] = a[c];
     }
-    __syncthreads();
-    // in-place inverse of the lower factor, columns right to left:
-    // X_jj = 1 / L_jj,  X_ij = -(sum_{k=j+1..i} X_ik L_kj) / L_jj  (i > j)
-    for (int j = TB - 1; j >= 0; j--) {
-        if (t < TB) col[t] = (t >= j) ? L[t][j] : 0.0;
-        __syncthreads();
-        if (t > j && t < TB) {
-            double s = 0.0;
-            for (int k = j + 1; k <= t; k++) s += L[t][k] * col[k];
-            L[t][j] = -s / col[j];
+    // Inverse X = L^-1, right-looking: step k finishes row k of X
+    // (X_k. = T_k. / L_kk), then rows i > k subtract L_ik X_k..  Lane i keeps
+    // L_ik in a[k] until step k, after which a[k] accumulates T_ik.
+#pragma unroll
+    for (int k = 0; k < TB; k++) {
+        const double lkk = bcast(a[k], k);
+        const double rk = 1.0 / lkk;
+        const double lik = (i > k) ? a[k] : 0.0;
+        if (i > k) a[k] = 0.0;
+        if (i == k) {
+#pragma unroll
+            for (int c = 0; c < k; c++) a[c] *= rk;
+            a[k] = rk;
         }
-        if (t == j) L[j][j] = 1.0 / col[j];
-        __syncthreads();
+#pragma unroll
+        for (int c = 0; c <= k; c++) {
+            const double xkc = bcast(a[c], k);
+            if (i > k) a[c] = fma(-lik, xkc, a[c]);
+        }
     }
     double *linv = work + d.linv_off + (int64_t)step * TB * TB;
-    for (int e = t; e < TB * TB; e += 256) {
-        const int i = e / TB, j = e % TB;
-        linv[e] = (j <= i) ? L[i][j] : 0.0;
-    }
+#pragma unroll
+    for (int c = 0; c < TB; c++) linv[i * TB + c] = (c <= i) ? a[c] : 0.0;
     // y_k = L_kk^-1 b_k
-    if (t < nb) {
-        double s = 0.0;
-        for (int c = 0; c <= t; c++) s += L[t][c] * bv[c];
-        work[d.v_off + k0 + t] = s;
+    const double bi = (i < nb) ? work[d.v_off + k0 + i] : 0.0;
+    double y = 0.0;
+#pragma unroll
+    for (int c = 0; c < TB; c++) {
+        const double bc = bcast(bi, c);
+        if (c <= i) y = fma(a[c], bc, y);
     }
+    if (i < nb) work[d.v_off + k0 + i] = y;
 }
 
 // Panel solve on matrix cores: rows below block `step`:  P <- P L_kk^-T,
@@ -376,6 +385,7 @@ __global__ __launch_bounds__(256) void k_syrk(const DenseDesc *__restrict__ desc
 
 // Backward substitution, block row `step` (descending): x_k = L_kk^-T y_k and
 // y_J -= L_kJ^T x_k for the column tiles J < k (one tile per workgroup).
+// Four threads share each 64-term dot product.
 __global__ __launch_bounds__(256) void k_backsub(const DenseDesc *__restrict__ desc,
                                                  const DenseParam *__restrict__ prm, double *__restrict__ work,
                                                  double *__restrict__ x, const int64_t *__restrict__ x_off, int step) {
@@ -390,23 +400,34 @@ __global__ __launch_bounds__(256) void k_backsub(const DenseDesc *__restrict__ d
     if (J > 0 && J >= step) return;
     const int nb = (int)std::min<int64_t>(TB, d.n - k0);
     const double *linv = work + d.linv_off + (int64_t)step * TB * TB;
-    const int t = threadIdx.x;
+    const int t = threadIdx.x, o = t >> 2, part = t & 3;
     if (t < TB) yk[t] = (t < nb) ? work[d.v_off + k0 + t] : 0.0;
     __syncthreads();
-    if (t < TB) {
+    {   // x_k[o] = sum_c Linv[c][o] y[c]
         double s = 0.0;
-        for (int c = t; c < TB; c++) s += linv[c * TB + t] * yk[c];
-        xk[t] = s;
+#pragma unroll
+        for (int q = 0; q < 16; q++) {
+            const int c = part + 4 * q;
+            s += linv[c * TB + o] * yk[c];
+        }
+        s += __shfl_xor(s, 1, 64);
+        s += __shfl_xor(s, 2, 64);
+        if (part == 0) xk[o] = s;
     }
     __syncthreads();
     if (J == 0 && t < nb) x[x_off[m] + k0 + t] = xk[t];
     if (J >= step) return;
     const double *A = work + d.a_off;
-    // y_J[c] -= sum_r L[k0 + r][64 J + c] x_k[r]
-    if (t < TB) {
+    {   // y_J[o] -= sum_r L[k0 + r][64 J + o] x_k[r]
         double s = 0.0;
-        for (int r = 0; r < nb; r++) s += A[(k0 + r) * d.n + TB * J + t] * xk[r];
-        work[d.v_off + TB * J + t] -= s;
+#pragma unroll
+        for (int q = 0; q < 16; q++) {
+            const int r = part + 4 * q;
+            if (r < nb) s += A[(k0 + r) * d.n + TB * J + o] * xk[r];
+        }
+        s += __shfl_xor(s, 1, 64);
+        s += __shfl_xor(s, 2, 64);
+        if (part == 0) work[d.v_off + TB * J + o] -= s;
     }
 }
 
@@ -683,7 +704,7 @@ static void launch_factor_solve(DenseState *D, int32_t nmat, int32_t max_n, cons
     hipLaunchKernelGGL(k_damp_copy, dim3((unsigned)std::min<int64_t>(nblk(nn), 4096), nmat), dim3(256), 0, s,
                        D->desc, D->prm, H, h_off, g, D->work);
     for (int st = 0; st < nsteps; st++) {
-        hipLaunchKernelGGL(k_potf2, dim3(1, nmat), dim3(256), 0, s, D->desc, D->prm, D->work, st);
+        hipLaunchKernelGGL(k_potf2, dim3(1, nmat), dim3(64), 0, s, D->desc, D->prm, D->work, st);
         const int64_t below = nsteps - st - 1;
         if (below > 0) {
             {

@@ -265,7 +265,9 @@ __global__ void k_reduce_partials(int32_t n_poses, const int32_t *__restrict__ c
         if (st.done || !st.need_eval) return;
     }
     double s = 0.0;
-    for (int c = chunk_ptr[j]; c < chunk_ptr[j + 1]; c++) s += partials[(int64_t)c * NPART + k];
+    const int c0 = chunk_ptr[j], c1 = chunk_ptr[j + 1];
+#pragma unroll 4
+    for (int c = c0; c < c1; c++) s += partials[(int64_t)c * NPART + k];
     double *h = H + 36LL * j;
     if (k < 6) {
         g[6LL * j + k] = s;

@@ -193,35 +193,12 @@ __global__ void k_commit(int32_t n_poses, const int32_t *__restrict__ pose_windo
     if (!st.done && st.accepted) poses[i] = poses_trial[i];
 }
 
-// Expand the 27 per-pose sums (g 6, H_phiphi upper 6, H_phit 9, H_tt upper 6).
-__device__ __forceinline__ void expand_gH(const double *a, double *g6, double *h) {
-#pragma unroll
-    for (int k = 0; k < 6; k++) g6[k] = a[k];
-    const int ii[6] = {0, 0, 0, 1, 1, 2}, jj[6] = {0, 1, 2, 1, 2, 2};
-#pragma unroll
-    for (int k = 0; k < 6; k++) {
-        h[6 * ii[k] + jj[k]] = a[6 + k];
-        h[6 * jj[k] + ii[k]] = a[6 + k];
-        h[6 * (3 + ii[k]) + 3 + jj[k]] = a[21 + k];
-        h[6 * (3 + jj[k]) + 3 + ii[k]] = a[21 + k];
-    }
-#pragma unroll
-    for (int r = 0; r < 3; r++)
-#pragma unroll
-        for (int c = 0; c < 3; c++) {
-            h[6 * r + 3 + c] = a[12 + 3 * r + c];
-            h[6 * (3 + c) + r] = a[12 + 3 * r + c];
-        }
-}
-
-// One block per window: (when the poses moved) sum each pose's chunk partials
-// in a fixed order into g and H, the window's gradient norm and damping floor
-// and the convergence test; then every pose's damped 6x6 solve, predicted
-// reduction share and trial pose.
+// One block per window: (when the poses moved, after the per-pose partial
+// reduction) the window's gradient norm, damping floor and convergence test;
+// then every pose's damped 6x6 solve, predicted-reduction share and trial pose.
 __global__ __launch_bounds__(256) void k_window_solve_mm(int32_t W, const int32_t *__restrict__ win_pose_ptr,
-                                                         const int32_t *__restrict__ chunk_ptr,
-                                                         const double *__restrict__ partials, LMState *__restrict__ lm,
-                                                         double *__restrict__ g, double *__restrict__ H,
+                                                         LMState *__restrict__ lm, const double *__restrict__ g,
+                                                         const double *__restrict__ H,
                                                          const double *__restrict__ poses, double *__restrict__ dx,
                                                          double *__restrict__ pose_q, int32_t *__restrict__ pose_info,
                                                          double *__restrict__ poses_trial, double tol_g) {
@@ -234,19 +211,10 @@ __global__ __launch_bounds__(256) void k_window_solve_mm(int32_t W, const int32_
     const int p0 = win_pose_ptr[w], p1 = win_pose_ptr[w + 1];
     if (st.need_eval) {
         double gs = 0.0, mx = 0.0;
-        for (int j = p0 + threadIdx.x; j < p1; j += 256) {
-            double a[NPART];
-#pragma unroll
-            for (int k = 0; k < NPART; k++) a[k] = 0.0;
-            for (int c = chunk_ptr[j]; c < chunk_ptr[j + 1]; c++) {
-                const double *pp = partials + (int64_t)c * NPART;
-#pragma unroll
-                for (int k = 0; k < NPART; k++) a[k] += pp[k];
-            }
-            expand_gH(a, g + 6LL * j, H + 36LL * j);
-#pragma unroll
-            for (int k = 0; k < 6; k++) gs += a[k] * a[k];
-            mx = fmax(mx, fmax(fmax(a[6], a[9]), fmax(a[11], fmax(a[21], fmax(a[24], a[26])))));
+        for (int i = 6 * p0 + threadIdx.x; i < 6 * p1; i += 256) {
+            const double gi = g[i];
+            gs += gi * gi;
+            mx = fmax(mx, H[36LL * (i / 6) + 7 * (i % 6)]);
         }
         rs[threadIdx.x] = gs;
         rm[threadIdx.x] = mx;
@@ -282,9 +250,8 @@ __global__ __launch_bounds__(256) void k_window_solve_mm(int32_t W, const int32_
 }
 
 void launch_window_solve_mm(Problem *P, const double *poses, double tol_g, hipStream_t s) {
-    hipLaunchKernelGGL(k_window_solve_mm, dim3(P->n_windows), dim3(256), 0, s, P->n_windows, P->win_pose_ptr,
-                       P->chunk_ptr, P->partials, P->lm, P->g, P->H, poses, P->dx, P->pose_q, P->pose_info,
-                       P->poses_trial, tol_g);
+    hipLaunchKernelGGL(k_window_solve_mm, dim3(P->n_windows), dim3(256), 0, s, P->n_windows, P->win_pose_ptr, P->lm,
+                       P->g, P->H, poses, P->dx, P->pose_q, P->pose_info, P->poses_trial, tol_g);
 }
 
 // ---------------------------------------------------------------- standalone MM solve
