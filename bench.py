@@ -54,6 +54,21 @@ def cpu_baseline(sc, mode_name: str, iters: int):
     return dt, rep, t_build
 
 
+def _pose_diff_aligned(Pa, Pb):
+    """Max rotation angle (rad) and translation difference (m) between two
+    pose sets after removing the gauge: Pa moved by the rigid motion that maps
+    its pose 0 onto Pb's pose 0."""
+    import numpy as np
+    Ra = Pa[:, :9].reshape(-1, 3, 3); ta = Pa[:, 9:]
+    Rb = Pb[:, :9].reshape(-1, 3, 3); tb = Pb[:, 9:]
+    Rg = Rb[0] @ Ra[0].T
+    tg = tb[0] - Rg @ ta[0]
+    Ra2 = np.einsum("ij,njk->nik", Rg, Ra)
+    ta2 = ta @ Rg.T + tg
+    c = (np.einsum("nij,nij->n", Ra2, Rb) - 1.0) / 2.0
+    return float(np.arccos(np.clip(c, -1.0, 1.0)).max()), float(np.abs(ta2 - tb).max())
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -61,10 +76,18 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--iters", type=int, default=20, help="LM iterations per solve")
     ap.add_argument("--mode", choices=["mm", "coupled"], default="mm")
-    ap.add_argument("--workload", choices=["window", "tiny"], default="window")
+    ap.add_argument("--workload", choices=["window", "tiny", "city", "batch", "served"], default="window",
+                    help="window: 500-pose single window (the headline); city: 2000-pose 5 km precision-form "
+                         "map; batch: 256 uneven windows; served: Poisson request stream")
+    ap.add_argument("--rate", type=float, default=20.0, help="served: request arrival rate (req/s)")
+    ap.add_argument("--requests", type=int, default=24, help="served: number of requests")
+    ap.add_argument("--slots", type=int, default=4, help="served: concurrent requests")
+    ap.add_argument("--windows", type=int, default=256, help="batch: number of windows")
     ap.add_argument("--cpu-iters", type=int, default=None,
                     help="oracle LM iterations timed for cpu_baseline (default: 20 mm, 1 coupled)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-precision-leg", action="store_true",
+                    help="skip the FP32 precision-form run on the same workload")
     args = ap.parse_args()
     if args.cpu_iters is None:
         args.cpu_iters = 20 if args.mode == "mm" else 1
@@ -83,6 +106,11 @@ def main():
         hb.build()
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.workload in ("city", "batch", "served"):
+        import bench_legs
+        out = {"city": bench_legs.city, "batch": bench_legs.batch, "served": bench_legs.served}[args.workload](args)
+        print(json.dumps(out), flush=True)
+        return
 
     t0 = time.perf_counter()
     sc = make_scene(args.workload)
@@ -189,6 +217,52 @@ def main():
                 "traffic": None, "flops_per_factorization": fl_trsm + fl_syrk,
                 "avg_launch_us": round(1e3 * syrk_ms / max(syrk_n, 1), 3)}
 
+    # precision form on the same workload: FP32 voxel-centred clusters, same
+    # LM, same number of solves; final poses compared with the FP64 run
+    prec = None
+    if not args.no_precision_leg:
+        P64_final = P.clone()
+        prob32 = ba.build_clusters(xs, ys, zs, scan, vox, sc.n_scans, sc.n_voxels, precision=ba.PREC_F32,
+                                   ref_poses=P0)
+        P32 = P0.clone().contiguous()
+
+        def step32():
+            P32.copy_(P0)
+            return ba.iterate(prob32, P32, mode, max_iters=args.iters, trace=False)[0]
+
+        for _ in range(args.warmup):
+            step32()
+        torch.cuda.synchronize()
+        t4 = time.perf_counter()
+        for _ in range(args.steps):
+            reps32 = step32()
+        torch.cuda.synchronize()
+        t5 = time.perf_counter()
+        ba.profile_reset()
+        ba.profile_enable(True)
+        step32()
+        torch.cuda.synchronize()
+        ba.profile_enable(False)
+        v32_ms, v32_n = ba.profile_query("k_vox")
+        p32_ms, p32_n = ba.profile_query("k_pose")
+        ba.profile_reset()
+        inf32 = prob32.info()
+        vox32_bytes = C * inf32["cluster_bytes"] + V * (64 + 32) + N * 2 * 96 + n_groups * 8
+        vox32_us = 1e3 * v32_ms / max(v32_n, 1)
+        ang, dt = _pose_diff_aligned(P32.cpu().numpy(), P64_final.cpu().numpy())
+        prec = {"value": V * args.iters * args.steps / (t5 - t4),
+                "ms_per_step": 1e3 * (t5 - t4) / args.steps,
+                "cluster_bytes": inf32["cluster_bytes"], "device_bytes": inf32["device_bytes"],
+                "k_vox_avg_us": round(vox32_us, 3), "k_pose_avg_us": round(1e3 * p32_ms / max(p32_n, 1), 3),
+                "k_vox_gbs": round(vox32_bytes / (vox32_us * 1e-6) / 1e9, 2) if vox32_us > 0 else 0.0,
+                "final_cost": reps32[0]["cost_final"],
+                "final_cost_rel_diff_vs_f64": abs(reps32[0]["cost_final"] - reps[0]["cost_final"])
+                / reps[0]["cost_final"],
+                "pose_diff_vs_f64_gauge_aligned": {"rad": ang, "m": dt}}
+        log(f"precision form: {prec['ms_per_step']:.3f} ms/solve, k_vox {vox32_us:.2f} us, "
+            f"pose diff {ang:.2e} rad {dt:.2e} m")
+        prob32.close()
+
     cpu = None
     if not args.no_cpu_baseline:
         log(f"cpu baseline: oracle, {args.cpu_iters} LM iterations")
@@ -223,6 +297,7 @@ def main():
         "roofline": roof,
         "cpu_baseline": cpu,
         "final_cost": reps[0]["cost_final"],
+        "precision_form": prec,
     }
     print(json.dumps(out), flush=True)
 

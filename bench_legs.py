@@ -1,0 +1,336 @@
+"""Measurement legs of bench.py beyond the headline single-window workload.
+
+  city    — 2000 poses on a 5 km x 1 km loop, 1M planes (raw-sum clusters):
+            the precision form (FP32 voxel-centred clusters) against the
+            all-FP64 GPU path on the same problem, with the FP64 oracle's
+            evaluation at the initial poses as the accuracy reference.
+  batch   — 256 uneven windows (20..400 poses each) in one problem: the
+            batched precision form, autotuned, against the plain per-problem
+            FP64 GPU path (every window its own problem, solved one after
+            another), at equal final pose accuracy.
+  served  — Poisson arrivals of window requests (20..1000 poses, ~400 planes
+            per pose) into the request server (precision form, concurrent
+            slots, device-memory budget), against serial plain FP64 solves of
+            the same requests under the same arrivals: p50/p99 latency and
+            solves/s.
+
+Inputs are seeded synthetic raw-sum clusters (scenes.sums); every leg
+returns one JSON-ready dict.
+"""
+from __future__ import annotations
+
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def _dev_sums(sc, dev):
+    import torch
+    t = lambda a, dt: torch.as_tensor(np.ascontiguousarray(a), dtype=dt, device=dev)
+    return (t(sc.voxel, torch.int32), t(sc.scan, torch.int32), t(sc.count, torch.int64), t(sc.sum, torch.float64),
+            t(sc.sumsq, torch.float64))
+
+
+def _build(ba, sc, arrs, prec, P0, **kw):
+    if sc.n_windows > 1:
+        kw = dict(kw, n_windows=sc.n_windows, scan_window=sc.scan_window)
+    if prec == "f32":
+        kw = dict(kw, precision=ba.PREC_F32, ref_poses=P0)
+    return ba.build_clusters_from_sums(*arrs, sc.n_scans, sc.n_voxels, **kw)
+
+
+def _pose_diff_aligned(Pa, Pb):
+    Ra = Pa[:, :9].reshape(-1, 3, 3); ta = Pa[:, 9:]
+    Rb = Pb[:, :9].reshape(-1, 3, 3); tb = Pb[:, 9:]
+    Rg = Rb[0] @ Ra[0].T
+    tg = tb[0] - Rg @ ta[0]
+    Ra2 = np.einsum("ij,njk->nik", Rg, Ra)
+    ta2 = ta @ Rg.T + tg
+    c = (np.einsum("nij,nij->n", Ra2, Rb) - 1.0) / 2.0
+    return float(np.arccos(np.clip(c, -1.0, 1.0)).max()), float(np.abs(ta2 - tb).max())
+
+
+def _ape(P, Ptrue):
+    """Gauge-aligned absolute position error (RMS, m) against the truth."""
+    Pa = P.copy()
+    Ra = Pa[:, :9].reshape(-1, 3, 3); ta = Pa[:, 9:]
+    Rb = Ptrue[:, :9].reshape(-1, 3, 3); tb = Ptrue[:, 9:]
+    Rg = Rb[0] @ Ra[0].T
+    tg = tb[0] - Rg @ ta[0]
+    ta2 = ta @ Rg.T + tg
+    return float(np.sqrt(np.mean(np.sum((ta2 - tb) ** 2, axis=1))))
+
+
+def _timed_solves(ba, prob, P0, mode, iters, steps, warmup, tol_g=0.0):
+    import torch
+    P = P0.clone().contiguous()
+    reps = None
+    for _ in range(warmup):
+        P.copy_(P0)
+        reps, _ = ba.iterate(prob, P, mode, max_iters=iters, tol_g=tol_g, trace=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        P.copy_(P0)
+        reps, _ = ba.iterate(prob, P, mode, max_iters=iters, tol_g=tol_g, trace=False)
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps, reps, P
+
+
+def _kernel_times(ba, prob, P0, mode, iters):
+    import torch
+    ba.profile_reset()
+    ba.profile_enable(True)
+    P = P0.clone().contiguous()
+    ba.iterate(prob, P, mode, max_iters=iters, trace=False)
+    torch.cuda.synchronize()
+    ba.profile_enable(False)
+    out = {}
+    for k in ("k_vox", "k_pose", "k_syrk", "k_trsm"):
+        ms, n = ba.profile_query(k)
+        if n:
+            out[k] = {"avg_us": round(1e3 * ms / n, 3), "launches": n}
+    ba.profile_reset()
+    return out
+
+
+# ---------------------------------------------------------------- city
+def city(args):
+    import torch
+    import paper_2608_14266_amd as ba
+    import scenes.sums as ss
+    dev = torch.device("cuda:0")
+    t0 = time.perf_counter()
+    sc = ss.city_config(seed=3000)
+    log(f"city scene: {sc.n_clusters} clusters, {sc.n_points} virtual points, {sc.n_voxels} voxels, "
+        f"generated in {time.perf_counter() - t0:.1f}s")
+    arrs = _dev_sums(sc, dev)
+    P0 = torch.as_tensor(sc.poses_init, device=dev)
+    mode = ba.MODE_MM if args.mode == "mm" else ba.MODE_COUPLED
+    iters = args.iters if args.mode == "mm" else min(args.iters, 5)
+    res = {}
+    finals = {}
+    for prec in ("f64", "f32"):
+        t0 = time.perf_counter()
+        prob = _build(ba, sc, arrs, prec, P0)
+        torch.cuda.synchronize()
+        tb = time.perf_counter() - t0
+        inf = prob.info()
+        dt, reps, P = _timed_solves(ba, prob, P0, mode, iters, args.steps, args.warmup)
+        kt = _kernel_times(ba, prob, P0, mode, iters)
+        cost0, g0, _, _ = ba.eval_residual_grad_hessian(prob, P0, ba.MODE_MM)
+        V, C, N = inf["n_voxels"], inf["n_clusters"], inf["n_scans"]
+        vb = C * inf["cluster_bytes"] + V * (64 + (32 if prec == "f32" else 0)) + N * 96 * (2 if prec == "f32" else 1)
+        kv = kt.get("k_vox", {}).get("avg_us", 0.0)
+        res[prec] = {"ms_per_solve": 1e3 * dt, "evals_per_s": V * iters / dt, "build_s": round(tb, 3),
+                     "device_bytes": inf["device_bytes"], "cluster_bytes": inf["cluster_bytes"], "kernels": kt,
+                     "k_vox_algorithmic_gbs": round(vb / (kv * 1e-6) / 1e9, 1) if kv else None,
+                     "k_vox_hbm_frac": round(vb / (kv * 1e-6) / 1e9 / HBM_PEAK_GBS, 4) if kv else None,
+                     "cost_initial": float(cost0.cpu().numpy()[0]), "cost_final": reps[0]["cost_final"],
+                     "grad_initial": g0.cpu().numpy().ravel()}
+        finals[prec] = P.cpu().numpy()
+        log(f"city {prec}: {1e3 * dt:.2f} ms/solve, k_vox {kv} us, build {tb:.2f}s")
+        prob.close()
+    # accuracy: FP32 against the FP64 GPU path and the FP64 oracle at the initial poses
+    acc = {}
+    if not args.no_cpu_baseline:
+        import oracle
+        log("oracle evaluation at the initial poses")
+        order = np.lexsort((sc.scan, sc.voxel))
+        mu, S = oracle.center_raw_sums(sc.count[order], sc.sum[order], sc.sumsq[order])
+        cl = oracle.Clusters(sc.voxel[order].astype(np.int32), sc.scan[order].astype(np.int32),
+                             sc.count[order].astype(np.int64), mu, S, sc.n_voxels, sc.n_scans)
+        t0 = time.perf_counter()
+        c_ref, g_ref, _, _ = oracle.evaluate(oracle.MM, cl, sc.poses_init)
+        t_eval = time.perf_counter() - t0
+        for prec in ("f64", "f32"):
+            acc[prec] = {"residual_rel_err": abs(res[prec]["cost_initial"] - c_ref) / c_ref,
+                         "gradient_rel_err": float(np.linalg.norm(res[prec]["grad_initial"] - g_ref)
+                                                   / np.linalg.norm(g_ref))}
+        acc["oracle_eval_s"] = round(t_eval, 3)
+    for prec in res:
+        res[prec].pop("grad_initial")
+    ang, dtr = _pose_diff_aligned(finals["f32"], finals["f64"])
+    acc["f32_vs_f64_pose_diff"] = {"rad": ang, "m": dtr}
+    acc["f32_vs_f64_final_cost_rel"] = abs(res["f32"]["cost_final"] - res["f64"]["cost_final"]) / res["f64"]["cost_final"]
+    V = sc.n_voxels
+    return {"metric": "plane-voxel evals/s", "value": res["f32"]["evals_per_s"], "unit": "plane-voxel evals/s",
+            "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "higher_is_better": True,
+            "dtype": "f32 clusters / f64 solve", "data": "synthetic",
+            "config": {"workload": f"city-2000pose-1Mvox ({args.mode}, {iters} LM iterations per solve)",
+                       "poses": sc.n_scans, "voxels": V, "clusters": sc.n_clusters, "virtual_points": sc.n_points},
+            "speedup_f32_vs_f64": res["f64"]["ms_per_solve"] / res["f32"]["ms_per_solve"],
+            "f32": res["f32"], "f64": res["f64"], "accuracy": acc}
+
+
+# ---------------------------------------------------------------- batch
+def batch(args):
+    import torch
+    import paper_2608_14266_amd as ba
+    import scenes.sums as ss
+    dev = torch.device("cuda:0")
+    t0 = time.perf_counter()
+    sc = ss.batch_windows(seed=4000, n_windows=args.windows)
+    log(f"batch: {sc.n_windows} windows, {sc.n_scans} poses, {sc.n_clusters} clusters, generated in "
+        f"{time.perf_counter() - t0:.1f}s")
+    mode = ba.MODE_MM if args.mode == "mm" else ba.MODE_COUPLED
+    iters = 10
+    arrs = _dev_sums(sc, dev)
+    P0 = torch.as_tensor(sc.poses_init, device=dev)
+    out = {}
+    finals = {}
+    for prec in ("f32", "f64"):
+        prob = _build(ba, sc, arrs, prec, P0)
+        tune = None
+        if prec == "f32":
+            t0 = time.perf_counter()
+            tune = ba.tuned(prob, P0, cache_path=None, reps=3)
+            log(f"autotuned in {time.perf_counter() - t0:.1f}s: {tune}")
+        dt, reps, P = _timed_solves(ba, prob, P0, mode, iters, args.steps, args.warmup)
+        kt = _kernel_times(ba, prob, P0, mode, iters)
+        out[f"batched_{prec}"] = {"ms_per_batch": 1e3 * dt, "solves_per_s": sc.n_windows / dt,
+                                  "tuning": tune, "kernels": kt, "device_bytes": prob.info()["device_bytes"]}
+        finals[prec] = P.cpu().numpy()
+        log(f"batched {prec}: {1e3 * dt:.2f} ms per {sc.n_windows} windows")
+        prob.close()
+    del arrs
+    torch.cuda.empty_cache()
+    # plain per-problem FP64: every window its own problem, one after another
+    probs, p0s = [], []
+    for w in range(sc.n_windows):
+        sw = ss.window_of(sc, w)
+        a = _dev_sums(sw, dev)
+        probs.append((sw, ba.build_clusters_from_sums(*a, sw.n_scans, sw.n_voxels)))
+        p0s.append(torch.as_tensor(sw.poses_init, device=dev))
+    Ps = [p.clone().contiguous() for p in p0s]
+    for (sw, pr), p0, P in zip(probs, p0s, Ps):      # warm-up: capture every window's graph
+        P.copy_(p0)
+        ba.iterate(pr, P, mode, max_iters=iters, trace=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        for (sw, pr), p0, P in zip(probs, p0s, Ps):
+            P.copy_(p0)
+            ba.iterate(pr, P, mode, max_iters=iters, trace=False)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    out["plain_per_problem_f64"] = {"ms_per_batch": 1e3 * dt, "solves_per_s": sc.n_windows / dt}
+    # accuracy per window: batched FP32 vs per-problem FP64, gauge-aligned; APE vs truth
+    worst_rad = worst_m = 0.0
+    ape32, ape64 = [], []
+    s0 = 0
+    for (sw, pr), P in zip(probs, Ps):
+        n = sw.n_scans
+        a = finals["f32"][s0:s0 + n]
+        b = P.cpu().numpy()
+        r, m = _pose_diff_aligned(a, b)
+        worst_rad, worst_m = max(worst_rad, r), max(worst_m, m)
+        ape32.append(_ape(a, sw.poses_true)); ape64.append(_ape(b, sw.poses_true))
+        s0 += n
+        pr.close()
+    rel_ape = float(np.max(np.abs(np.array(ape32) - np.array(ape64)) / np.array(ape64)))
+    acc = {"batched_f32_vs_plain_f64_pose_diff": {"rad": worst_rad, "m": worst_m},
+           "ape_f32_mean_m": float(np.mean(ape32)), "ape_f64_mean_m": float(np.mean(ape64)),
+           "ape_rel_diff_max": rel_ape}
+    bf = out["batched_f32"]["solves_per_s"]
+    return {"metric": "window solves/s", "value": bf, "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
+            "warmup": args.warmup, "higher_is_better": True, "dtype": "f32 clusters / f64 solve",
+            "data": "synthetic",
+            "config": {"workload": f"batch-{sc.n_windows}win ({args.mode}, {iters} LM iterations per window)",
+                       "windows": sc.n_windows, "poses": sc.n_scans, "voxels": sc.n_voxels,
+                       "clusters": sc.n_clusters, "virtual_points": sc.n_points},
+            "speedup_vs_plain_per_problem_f64": bf / out["plain_per_problem_f64"]["solves_per_s"],
+            **out, "accuracy": acc}
+
+
+# ---------------------------------------------------------------- served
+def _gen_request(a):
+    import scenes.sums as ss
+    seed, n = a
+    return ss.request_scene(seed=seed, n_poses=n, vox_per_pose=400)
+
+
+def served(args):
+    import torch
+    import paper_2608_14266_amd as ba
+    rng = np.random.Generator(np.random.Philox(key=5000))
+    R = args.requests
+    sizes = np.clip(np.rint(np.exp(rng.uniform(math.log(20), math.log(1000), size=R))), 20, 1000).astype(int)
+    gaps = rng.exponential(1.0 / args.rate, size=R)
+    arrivals = np.cumsum(gaps) - gaps[0]
+    t0 = time.perf_counter()
+    from concurrent.futures import ProcessPoolExecutor
+    import multiprocessing as mp
+    with ProcessPoolExecutor(max_workers=min(16, os.cpu_count() or 1), mp_context=mp.get_context("fork")) as ex:
+        reqs = list(ex.map(_gen_request, [(6000 + i, int(n)) for i, n in enumerate(sizes)]))
+    log(f"served: {R} requests ({sizes.min()}..{sizes.max()} poses, {sum(r.n_clusters for r in reqs)} clusters), "
+        f"generated in {time.perf_counter() - t0:.1f}s")
+    mode = ba.MODE_MM if args.mode == "mm" else ba.MODE_COUPLED
+    opts = dict(mode=mode, max_iters=50, tol_g=1e-6)
+    budget = 200 << 30
+
+    def serve(prec, slots, arr):
+        res = [None] * R
+        with ba.Server(budget, slots=slots, precision=prec, **opts) as srv:
+            # warm-up request (first kernels loaded, first allocation pools)
+            srv.wait(srv.submit_scene(reqs[0]))
+            base = time.perf_counter()
+            ids = []
+            for i, r in enumerate(reqs):
+                now = time.perf_counter() - base
+                if arr is not None and arr[i] > now:
+                    time.sleep(arr[i] - now)
+                ids.append(srv.submit_scene(r))
+            for i, rid in enumerate(ids):
+                res[i] = srv.wait(rid)
+        return res
+
+    served32 = serve(ba.PREC_F32, args.slots, arrivals)
+    lat = np.array([s["t_done"] - s["t_submit"] for _, s in served32])
+    first = min(s["t_submit"] for _, s in served32)
+    last = max(s["t_done"] for _, s in served32)
+    # serial plain FP64: one request at a time (service times measured
+    # back-to-back), latencies under the same arrivals by FIFO replay
+    serial = serve(ba.PREC_F64, 1, None)
+    service = np.array([s["t_done"] - s["t_admit"] for _, s in serial])
+    finish = np.zeros(R)
+    for i in range(R):
+        start = max(arrivals[i], finish[i - 1] if i else 0.0)
+        finish[i] = start + service[i]
+    lat64 = finish - arrivals
+    worst_rad = worst_m = 0.0
+    ape_rel = 0.0
+    for r, (p32, s32), (p64, s64) in zip(reqs, served32, serial):
+        a, m = _pose_diff_aligned(p32, p64)
+        worst_rad, worst_m = max(worst_rad, a), max(worst_m, m)
+        e32, e64 = _ape(p32, r.poses_true), _ape(p64, r.poses_true)
+        ape_rel = max(ape_rel, abs(e32 - e64) / e64)
+    sps = R / (last - first)
+    sps64 = R / (finish[-1] - arrivals[0])
+    conv = sum(1 for _, s in served32 if s["report"]["converged"])
+    return {"metric": "window-BA solve latency p50/p99 (served)", "value": float(np.percentile(lat, 99) * 1e3),
+            "unit": "ms (p99)", "n_gpus": 1, "higher_is_better": False, "dtype": "f32 clusters / f64 solve",
+            "data": "synthetic",
+            "config": {"workload": f"served Poisson {args.rate:g} req/s, {R} requests of 20..1000 poses "
+                                   f"(~400 planes per pose), solve to ||g|| < 1e-6 or 50 iterations ({args.mode})",
+                       "slots": args.slots, "hbm_budget_bytes": budget},
+            "served_f32": {"p50_ms": float(np.percentile(lat, 50) * 1e3), "p99_ms": float(np.percentile(lat, 99) * 1e3),
+                           "solves_per_s": sps, "converged": conv},
+            "serial_plain_f64": {"p50_ms": float(np.percentile(lat64, 50) * 1e3),
+                                 "p99_ms": float(np.percentile(lat64, 99) * 1e3), "solves_per_s": sps64,
+                                 "mean_service_ms": float(service.mean() * 1e3)},
+            "accuracy": {"served_f32_vs_serial_f64_pose_diff": {"rad": worst_rad, "m": worst_m},
+                         "ape_rel_diff_max": ape_rel}}

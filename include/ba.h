@@ -49,6 +49,12 @@ typedef int32_t ba_status;
 #define BA_E_NOT_SPD (-4)      /* a factorization met a non-positive pivot */
 #define BA_E_UNSUPPORTED (-5)  /* mode or size not supported */
 #define BA_E_NOMEM (-6)        /* device allocation failed */
+#define BA_E_BUDGET (-7)       /* a served request can never fit the server's device-memory budget */
+#define BA_E_NOT_FOUND (-8)    /* unknown or already collected request id */
+
+/* Cluster storage precision of a problem (ba_build_options.precision). */
+#define BA_PREC_F64 0      /* clusters stored and evaluated in FP64 */
+#define BA_PREC_F32 1      /* FP32 clusters centred on a per-voxel FP64 reference point (see ba_build_clusters) */
 
 /* Hessian forms (mode arguments). */
 #define BA_MODE_MM 0       /* Eq. 3 surrogate: block-diagonal, [N][6][6] full symmetric */
@@ -80,9 +86,11 @@ typedef struct ba_cluster_sums {
 } ba_cluster_sums;
 
 typedef struct ba_build_options {
-    int32_t chunk_len;          /* clusters per pose chunk of the derivative pass; 0 = default (256) */
+    int32_t chunk_len;          /* clusters per pose chunk of the derivative pass: 0 = default (256), else 32..2^20 */
     int32_t n_windows;          /* 0 or 1 = one problem; > 1 = independent windows (batched form) */
     const int32_t *scan_window; /* host, n_scans entries, non-decreasing window id per scan; NULL if n_windows <= 1 */
+    int32_t precision;          /* BA_PREC_F64 (default) or BA_PREC_F32 */
+    const double *ref_poses;    /* device [n_scans][12]; BA_PREC_F32 only: poses that place the voxel references */
 } ba_build_options;
 
 typedef struct ba_problem_info {
@@ -96,6 +104,8 @@ typedef struct ba_problem_info {
     int32_t n_wave_groups;  /* residual-pass wave groups (64 voxels of equal cluster count each) */
     int32_t n_pose_chunks;  /* derivative-pass chunks (clusters of one scan each) */
     int64_t padded_clusters; /* cluster slots of the wave-interleaved layout, incl. padding */
+    int32_t precision;      /* BA_PREC_F64 or BA_PREC_F32 */
+    int32_t cluster_bytes;  /* bytes of one stored cluster in each iteration copy (84 FP64, 44 FP32) */
 } ba_problem_info;
 
 typedef struct ba_lm_options {
@@ -117,6 +127,17 @@ typedef struct ba_lm_report {  /* one per window */
     double mu_final;
 } ba_lm_report;
 
+/* Launch choices of the two evaluation passes.  They change the order in
+ * which floating-point partial sums are combined (so results move at the
+ * rounding level between settings), never what is computed; for one setting
+ * results stay bitwise reproducible. */
+typedef struct ba_tuning {
+    int32_t vox_split;  /* waves sharing one 64-voxel group in the residual pass: 1, 2 or 4 */
+    int32_t vox_grid;   /* residual pass: 0 = one block per group; 1..64 = persistent grid of that many blocks per CU */
+    int32_t pose_grid;  /* derivative pass: 0 = one wavefront per chunk; 1..64 = persistent, blocks of 4 waves per CU */
+    int32_t chunk_len;  /* clusters per derivative-pass chunk, 32..2^20 */
+} ba_tuning;
+
 /* ---------------------------------------------------------------------- */
 
 /* Text of a status code (static storage). */
@@ -134,8 +155,17 @@ const char *ba_last_error(void);
  * pass (the paper's mappers M_v, M_s, built once).
  * pts: host struct of device arrays (not retained).  opt: may be NULL.
  * *out receives a new problem owned by the caller.  Synchronous.
+ * Precision form (opt->precision == BA_PREC_F32): the iteration copies hold
+ * each cluster as FP32 (N, mu - o, S), where o = R0_j^T (c_i - t0_j) is the
+ * voxel's reference point c_i (its FP64 centroid at opt->ref_poses) seen
+ * from scan j at its reference pose T0_j; the residual and derivative passes
+ * then run their per-cluster arithmetic in FP32 on these voxel-centred
+ * coordinates, accumulate in FP64, and keep the 3x3 eigensolve, the solves
+ * and the SE(3) update in FP64.  The FP64 clusters stay available to
+ * ba_problem_export_clusters.  Needs N_ij < 2^24 (BA_E_UNSUPPORTED).
  * Errors: BA_E_ARG for null pointers, n < 1, labels out of range, non-finite
- * coordinates or windows that a voxel straddles; BA_E_NOMEM; BA_E_HIP.
+ * coordinates or windows that a voxel straddles, an unknown precision or a
+ * missing/non-finite ref_poses in the precision form; BA_E_NOMEM; BA_E_HIP.
  */
 ba_status ba_build_clusters(const ba_points *pts, const ba_build_options *opt, ba_problem **out,
                             hipStream_t stream);
@@ -210,6 +240,93 @@ ba_status ba_solve_increment(int32_t mode, int32_t n_scans, const double *hess, 
  */
 ba_status ba_iterate(ba_problem *p, double *poses_inout, const ba_lm_options *opt, ba_lm_report *rep,
                      double *trace, hipStream_t stream);
+
+/* Current launch choices of a problem (host output). */
+ba_status ba_problem_get_tuning(const ba_problem *p, ba_tuning *t);
+
+/* Set the launch choices (host input; BA_E_ARG outside the ranges above).
+ * Re-cuts the derivative-pass chunks when chunk_len changes and drops the
+ * problem's captured ba_iterate graph.  Synchronous. */
+ba_status ba_problem_set_tuning(ba_problem *p, const ba_tuning *t);
+
+/*
+ * ba_autotune — grid search over the launch choices on this problem: every
+ * (vox_split, vox_grid) pair of the residual pass and every (chunk_len,
+ * pose_grid) pair of the derivative pass is timed with HIP events over
+ * `reps` evaluations at `poses` (device [n_scans][12]); the fastest of each
+ * pass is applied to the problem and returned in *best (host, may be NULL).
+ * Overwrites the problem's voxel state (as an evaluation does).  Synchronous.
+ */
+ba_status ba_autotune(ba_problem *p, const double *poses, int32_t reps, ba_tuning *best, hipStream_t stream);
+
+/* ---------------------------------------------------------------------- */
+/*
+ * Served form: a request server that keeps window problems resident on the
+ * device while they iterate.  Requests are queued in arrival order; the head
+ * of the queue is admitted as soon as a slot is free and its device footprint
+ * (ba_request_footprint) fits, together with the requests already admitted,
+ * in the budget.  Each slot owns a host thread and a HIP stream: it uploads
+ * the request's clusters, builds its problem (ba_build_clusters_from_sums),
+ * runs ba_iterate to the options' gradient tolerance or iteration cap, copies
+ * the poses back and releases the device memory.  Requests that arrive while
+ * others iterate are admitted as slots and memory free up, and their device
+ * work overlaps with the running ones.  A request's result does not depend on
+ * what else is served (every pass reduces in a fixed order per problem).
+ */
+typedef struct ba_server ba_server;
+
+typedef struct ba_server_options {
+    int64_t hbm_budget;    /* device bytes the admitted requests may reserve together (> 0) */
+    int32_t slots;         /* requests on the device at once, 1..64 */
+    int32_t precision;     /* BA_PREC_F64 or BA_PREC_F32 (references placed by each request's initial poses) */
+    ba_lm_options lm;      /* LM options of every request (mode, max_iters, mu0, nu0, tol_g) */
+} ba_server_options;
+
+typedef struct ba_request {  /* raw-sum clusters of one window (Eq. 2); host arrays, copied on submit */
+    int64_t n;
+    const int32_t *voxel, *scan;
+    const int64_t *count;
+    const double *sum, *sumsq;     /* n x 3, n x 6 */
+    int32_t n_scans, n_voxels;
+    const double *poses_init;      /* n_scans x 12 */
+} ba_request;
+
+#define BA_REQ_QUEUED 0
+#define BA_REQ_RUNNING 1
+#define BA_REQ_DONE 2
+#define BA_REQ_FAILED 3
+
+typedef struct ba_request_status {
+    int32_t state;         /* BA_REQ_* */
+    ba_status status;      /* BA_OK, or the error of a failed request */
+    double t_submit, t_admit, t_done;   /* seconds since the server was created (steady clock) */
+    int64_t footprint;     /* device bytes reserved for the request */
+    ba_lm_report report;
+} ba_request_status;
+
+/* Device bytes a request may hold at its peak (build temporaries, the
+ * problem, the LM buffers and, in BA_MODE_COUPLED, the dense matrices);
+ * an upper bound used for admission.  Host inputs. */
+ba_status ba_request_footprint(const ba_request *req, int32_t mode, int32_t precision, int64_t *bytes);
+
+/* Start a server on the current device.  *out receives the handle. */
+ba_status ba_server_create(const ba_server_options *opt, ba_server **out);
+
+/* Queue a request (inputs copied; the caller may free them on return).
+ * *id receives its id.  BA_E_BUDGET if its footprint exceeds the budget;
+ * BA_E_ARG for invalid sizes or labels. */
+ba_status ba_server_submit(ba_server *s, const ba_request *req, int64_t *id);
+
+/* Current status of a request (non-blocking; host output). */
+ba_status ba_server_query(ba_server *s, int64_t id, ba_request_status *st);
+
+/* Wait until request `id` has finished, copy its poses (host [n_scans][12],
+ * may be NULL) and status, and forget the request.  BA_E_NOT_FOUND for an
+ * unknown id. */
+ba_status ba_server_wait(ba_server *s, int64_t id, double *poses_out, ba_request_status *st);
+
+/* Finish the running requests, drop the queued ones, stop the slots. */
+ba_status ba_server_destroy(ba_server *s);
 
 /*
  * Kernel timing (instrumentation, not part of the method): when enabled,

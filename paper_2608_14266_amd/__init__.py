@@ -11,8 +11,12 @@ from __future__ import annotations
 from ._lib import (  # noqa: F401
     MODE_COUPLED,
     MODE_MM,
+    PREC_F32,
+    PREC_F64,
     BAError,
     Problem,
+    Server,
+    autotune,
     build_clusters,
     build_clusters_from_sums,
     eval_residual_grad_hessian,
@@ -22,6 +26,10 @@ from ._lib import (  # noqa: F401
     profile_enable,
     profile_query,
     profile_reset,
+    problem_get_tuning,
+    problem_set_tuning,
+    request_footprint,
     solve_increment,
     solve_increment_workspace,
 )
+from .tuning import tuned  # noqa: F401,E402

@@ -14,9 +14,11 @@ _LIB_PATH = os.path.join(_HERE, "libba.so")
 
 MODE_MM = 0
 MODE_COUPLED = 1
+PREC_F64 = 0
+PREC_F32 = 1
 
 _STATUS = {0: "BA_OK", -1: "BA_E_ARG", -2: "BA_E_WORKSPACE", -3: "BA_E_HIP", -4: "BA_E_NOT_SPD",
-           -5: "BA_E_UNSUPPORTED", -6: "BA_E_NOMEM"}
+           -5: "BA_E_UNSUPPORTED", -6: "BA_E_NOMEM", -7: "BA_E_BUDGET", -8: "BA_E_NOT_FOUND"}
 
 
 class BAError(RuntimeError):
@@ -36,14 +38,15 @@ class _Sums(ct.Structure):
 
 
 class _BuildOpts(ct.Structure):
-    _fields_ = [("chunk_len", ct.c_int32), ("n_windows", ct.c_int32), ("scan_window", ct.c_void_p)]
+    _fields_ = [("chunk_len", ct.c_int32), ("n_windows", ct.c_int32), ("scan_window", ct.c_void_p),
+                ("precision", ct.c_int32), ("ref_poses", ct.c_void_p)]
 
 
 class _Info(ct.Structure):
     _fields_ = [("n_points", ct.c_int64), ("n_clusters", ct.c_int64), ("n_voxels", ct.c_int32),
                 ("n_scans", ct.c_int32), ("n_windows", ct.c_int32), ("max_m", ct.c_int32),
                 ("device_bytes", ct.c_int64), ("n_wave_groups", ct.c_int32), ("n_pose_chunks", ct.c_int32),
-                ("padded_clusters", ct.c_int64)]
+                ("padded_clusters", ct.c_int64), ("precision", ct.c_int32), ("cluster_bytes", ct.c_int32)]
 
 
 class _LMOpts(ct.Structure):
@@ -51,10 +54,31 @@ class _LMOpts(ct.Structure):
                 ("tol_g", ct.c_double)]
 
 
+class _Tuning(ct.Structure):
+    _fields_ = [("vox_split", ct.c_int32), ("vox_grid", ct.c_int32), ("pose_grid", ct.c_int32),
+                ("chunk_len", ct.c_int32)]
+
+
+class _ServerOpts(ct.Structure):
+    _fields_ = [("hbm_budget", ct.c_int64), ("slots", ct.c_int32), ("precision", ct.c_int32),
+                ("lm", _LMOpts)]
+
+
+class _Request(ct.Structure):
+    _fields_ = [("n", ct.c_int64), ("voxel", ct.c_void_p), ("scan", ct.c_void_p), ("count", ct.c_void_p),
+                ("sum", ct.c_void_p), ("sumsq", ct.c_void_p), ("n_scans", ct.c_int32), ("n_voxels", ct.c_int32),
+                ("poses_init", ct.c_void_p)]
+
+
 class _LMReport(ct.Structure):
     _fields_ = [("iters", ct.c_int32), ("n_accepted", ct.c_int32), ("converged", ct.c_int32),
                 ("last_info", ct.c_int32), ("cost_initial", ct.c_double), ("cost_final", ct.c_double),
                 ("gnorm_final", ct.c_double), ("mu_final", ct.c_double)]
+
+
+class _ReqStatus(ct.Structure):
+    _fields_ = [("state", ct.c_int32), ("status", ct.c_int32), ("t_submit", ct.c_double), ("t_admit", ct.c_double),
+                ("t_done", ct.c_double), ("footprint", ct.c_int64), ("report", _LMReport)]
 
 
 _lib = None
@@ -102,6 +126,24 @@ def load():
     L.ba_profile_query.argtypes = [ct.c_char_p, ct.POINTER(ct.c_double), ct.POINTER(ct.c_int64)]
     L.ba_iterate.restype = i32
     L.ba_iterate.argtypes = [P, P, ct.POINTER(_LMOpts), ct.POINTER(_LMReport), P, P]
+    L.ba_problem_get_tuning.restype = i32
+    L.ba_problem_get_tuning.argtypes = [P, ct.POINTER(_Tuning)]
+    L.ba_problem_set_tuning.restype = i32
+    L.ba_problem_set_tuning.argtypes = [P, ct.POINTER(_Tuning)]
+    L.ba_autotune.restype = i32
+    L.ba_autotune.argtypes = [P, P, i32, ct.POINTER(_Tuning), P]
+    L.ba_request_footprint.restype = i32
+    L.ba_request_footprint.argtypes = [ct.POINTER(_Request), i32, i32, ct.POINTER(ct.c_int64)]
+    L.ba_server_create.restype = i32
+    L.ba_server_create.argtypes = [ct.POINTER(_ServerOpts), ct.POINTER(P)]
+    L.ba_server_submit.restype = i32
+    L.ba_server_submit.argtypes = [P, ct.POINTER(_Request), ct.POINTER(ct.c_int64)]
+    L.ba_server_query.restype = i32
+    L.ba_server_query.argtypes = [P, ct.c_int64, ct.POINTER(_ReqStatus)]
+    L.ba_server_wait.restype = i32
+    L.ba_server_wait.argtypes = [P, ct.c_int64, P, ct.POINTER(_ReqStatus)]
+    L.ba_server_destroy.restype = i32
+    L.ba_server_destroy.argtypes = [P]
     _lib = L
     return L
 
@@ -168,22 +210,32 @@ class Problem:
             pass
 
 
-def _opts(chunk_len, n_windows, scan_window):
+def _opts(chunk_len, n_windows, scan_window, precision=PREC_F64, ref_poses=None):
     o = _BuildOpts()
     o.chunk_len = int(chunk_len)
     o.n_windows = int(n_windows)
-    keep = None
+    keep = []
     if scan_window is not None:
-        keep = np.ascontiguousarray(np.asarray(scan_window, dtype=np.int32))
-        o.scan_window = keep.ctypes.data_as(ct.c_void_p)
+        sw = np.ascontiguousarray(np.asarray(scan_window, dtype=np.int32))
+        keep.append(sw)
+        o.scan_window = sw.ctypes.data_as(ct.c_void_p)
     else:
         o.scan_window = None
+    o.precision = int(precision)
+    if ref_poses is not None:
+        rp = _dev(ref_poses, torch.float64, "ref_poses")
+        keep.append(rp)
+        o.ref_poses = rp.data_ptr()
+    else:
+        o.ref_poses = None
     return o, keep
 
 
 def build_clusters(x, y, z, scan, voxel, n_scans: int, n_voxels: int, chunk_len: int = 0, n_windows: int = 1,
-                   scan_window=None) -> Problem:
-    """ba_build_clusters: points (device tensors) -> problem.  Synchronous."""
+                   scan_window=None, precision: int = PREC_F64, ref_poses=None) -> Problem:
+    """ba_build_clusters: points (device tensors) -> problem.  Synchronous.
+    precision=PREC_F32 builds the precision form; ref_poses (device [n_scans, 12])
+    then place the per-voxel reference points."""
     x = _dev(x, torch.float64, "x"); y = _dev(y, torch.float64, "y"); z = _dev(z, torch.float64, "z")
     scan = _dev(scan, torch.int32, "scan"); voxel = _dev(voxel, torch.int32, "voxel")
     n = x.numel()
@@ -191,14 +243,15 @@ def build_clusters(x, y, z, scan, voxel, n_scans: int, n_voxels: int, chunk_len:
         raise ValueError("point arrays must have equal length")
     p = _Points(n, x.data_ptr(), y.data_ptr(), z.data_ptr(), scan.data_ptr(), voxel.data_ptr(), int(n_scans),
                 int(n_voxels))
-    o, keep = _opts(chunk_len, n_windows, scan_window)
+    o, keep = _opts(chunk_len, n_windows, scan_window, precision, ref_poses)
     h = ct.c_void_p()
     _check(load().ba_build_clusters(ct.byref(p), ct.byref(o), ct.byref(h), _stream()))
     return Problem(h, n_voxels)
 
 
 def build_clusters_from_sums(voxel, scan, count, sums, sumsq, n_scans: int, n_voxels: int, chunk_len: int = 0,
-                             n_windows: int = 1, scan_window=None) -> Problem:
+                             n_windows: int = 1, scan_window=None, precision: int = PREC_F64,
+                             ref_poses=None) -> Problem:
     """ba_build_clusters_from_sums: raw-sum clusters (device tensors) -> problem.  Synchronous."""
     voxel = _dev(voxel, torch.int32, "voxel"); scan = _dev(scan, torch.int32, "scan")
     count = _dev(count, torch.int64, "count")
@@ -208,7 +261,7 @@ def build_clusters_from_sums(voxel, scan, count, sums, sumsq, n_scans: int, n_vo
         raise ValueError("cluster arrays have inconsistent sizes")
     s = _Sums(n, voxel.data_ptr(), scan.data_ptr(), count.data_ptr(), sums.data_ptr(), sumsq.data_ptr(),
               int(n_scans), int(n_voxels))
-    o, keep = _opts(chunk_len, n_windows, scan_window)
+    o, keep = _opts(chunk_len, n_windows, scan_window, precision, ref_poses)
     h = ct.c_void_p()
     _check(load().ba_build_clusters_from_sums(ct.byref(s), ct.byref(o), ct.byref(h), _stream()))
     return Problem(h, n_voxels)
@@ -290,3 +343,113 @@ def profile_query(kernel: str):
     n = ct.c_int64(0)
     _check(load().ba_profile_query(kernel.encode(), ct.byref(ms), ct.byref(n)))
     return ms.value, n.value
+
+
+def problem_get_tuning(problem) -> dict:
+    """ba_problem_get_tuning: the problem's launch choices."""
+    t = _Tuning()
+    _check(load().ba_problem_get_tuning(problem.handle, ct.byref(t)))
+    return {k: getattr(t, k) for k, _ in _Tuning._fields_}
+
+
+def problem_set_tuning(problem, tuning: dict):
+    """ba_problem_set_tuning (synchronous)."""
+    cur = problem_get_tuning(problem)
+    cur.update({k: int(v) for k, v in tuning.items()})
+    t = _Tuning(**cur)
+    _check(load().ba_problem_set_tuning(problem.handle, ct.byref(t)))
+
+
+def autotune(problem, poses, reps: int = 5) -> dict:
+    """ba_autotune: time every launch choice at `poses`, apply and return the best."""
+    poses = _dev(poses, torch.float64, "poses")
+    t = _Tuning()
+    _check(load().ba_autotune(problem.handle, _ptr(poses), int(reps), ct.byref(t), _stream()))
+    return {k: getattr(t, k) for k, _ in _Tuning._fields_}
+
+
+REQ_QUEUED, REQ_RUNNING, REQ_DONE, REQ_FAILED = 0, 1, 2, 3
+
+
+def _request(voxel, scan, count, sums, sumsq, n_scans, n_voxels, poses_init):
+    keep = [np.ascontiguousarray(voxel, dtype=np.int32), np.ascontiguousarray(scan, dtype=np.int32),
+            np.ascontiguousarray(count, dtype=np.int64), np.ascontiguousarray(sums, dtype=np.float64),
+            np.ascontiguousarray(sumsq, dtype=np.float64), np.ascontiguousarray(poses_init, dtype=np.float64)]
+    n = keep[0].shape[0]
+    if not (keep[1].shape[0] == n and keep[2].shape[0] == n and keep[3].size == 3 * n and keep[4].size == 6 * n
+            and keep[5].size == 12 * int(n_scans)):
+        raise ValueError("request arrays have inconsistent sizes")
+    r = _Request(n, *[k.ctypes.data for k in keep[:5]], int(n_scans), int(n_voxels), keep[5].ctypes.data)
+    return r, keep
+
+
+def _status_dict(st: "_ReqStatus") -> dict:
+    d = {k: getattr(st, k) for k, _ in _ReqStatus._fields_ if k != "report"}
+    d["report"] = {k: getattr(st.report, k) for k, _ in _LMReport._fields_}
+    return d
+
+
+def request_footprint(voxel, scan, count, sums, sumsq, n_scans, n_voxels, poses_init, mode=MODE_MM,
+                      precision=PREC_F64) -> int:
+    """ba_request_footprint: device bytes reserved for a request (host arrays)."""
+    r, keep = _request(voxel, scan, count, sums, sumsq, n_scans, n_voxels, poses_init)
+    b = ct.c_int64(0)
+    _check(load().ba_request_footprint(ct.byref(r), int(mode), int(precision), ct.byref(b)))
+    return b.value
+
+
+class Server:
+    """ba_server_*: the served form.  Requests are host arrays of raw-sum
+    clusters; results are host poses and an LM report."""
+
+    def __init__(self, hbm_budget: int, slots: int = 4, precision: int = PREC_F64, mode: int = MODE_MM,
+                 max_iters: int = 50, tol_g: float = 1e-6, mu0: float = 0.0, nu0: float = 0.0):
+        o = _ServerOpts()
+        o.hbm_budget = int(hbm_budget)
+        o.slots = int(slots)
+        o.precision = int(precision)
+        o.lm = _LMOpts(int(mode), int(max_iters), float(mu0), float(nu0), float(tol_g))
+        h = ct.c_void_p()
+        _check(load().ba_server_create(ct.byref(o), ct.byref(h)))
+        self._h = h
+        self._n_scans = {}
+
+    def submit(self, voxel, scan, count, sums, sumsq, n_scans, n_voxels, poses_init) -> int:
+        r, keep = _request(voxel, scan, count, sums, sumsq, n_scans, n_voxels, poses_init)
+        rid = ct.c_int64(0)
+        _check(load().ba_server_submit(self._h, ct.byref(r), ct.byref(rid)))
+        self._n_scans[rid.value] = int(n_scans)
+        return rid.value
+
+    def submit_scene(self, sc) -> int:
+        return self.submit(sc.voxel, sc.scan, sc.count, sc.sum, sc.sumsq, sc.n_scans, sc.n_voxels, sc.poses_init)
+
+    def query(self, rid: int) -> dict:
+        st = _ReqStatus()
+        _check(load().ba_server_query(self._h, int(rid), ct.byref(st)))
+        return _status_dict(st)
+
+    def wait(self, rid: int):
+        """Block until request `rid` is done: (poses (n_scans, 12), status dict)."""
+        poses = np.empty((self._n_scans[rid], 12))
+        st = _ReqStatus()
+        _check(load().ba_server_wait(self._h, int(rid), poses.ctypes.data_as(ct.c_void_p), ct.byref(st)))
+        del self._n_scans[rid]
+        return poses, _status_dict(st)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _check(load().ba_server_destroy(self._h))
+            self._h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,6 +1,7 @@
 // C-ABI entry points of libba (declared in include/ba.h).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdlib>
 #include <cstdarg>
@@ -22,9 +23,6 @@ void graph_release(Problem *P);
 bool prof_enabled();
 }
 
-struct ba_problem {
-    ba::Problem P;
-};
 
 ba::Problem::~Problem() {
     graph_release(this);
@@ -159,7 +157,7 @@ struct IterGraph {
     hipGraphExec_t exec = nullptr;
     // key
     double *poses = nullptr, *trace = nullptr;
-    int32_t mode = -1, iters = -1;
+    int32_t mode = -1, iters = -1, tune_gen = -1;
     double mu0 = 0, nu0 = 0, tol_g = 0;
     ~IterGraph() {
         if (exec) (void)hipGraphExecDestroy(exec);
@@ -190,6 +188,8 @@ const char *ba_status_str(ba_status s) {
         case BA_E_NOT_SPD: return "matrix not positive definite";
         case BA_E_UNSUPPORTED: return "unsupported";
         case BA_E_NOMEM: return "out of device memory";
+        case BA_E_BUDGET: return "request exceeds the device-memory budget";
+        case BA_E_NOT_FOUND: return "unknown request";
         default: return "unknown status";
     }
 }
@@ -247,6 +247,9 @@ static ba_status build_common(ba_problem **out, hipStream_t stream,
         return BA_E_HIP;
     }
     p->P.device = dev;
+    int ncu = 0;
+    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && ncu > 0)
+        p->P.n_cu = ncu;
     ba_status st = fn(src, opt, &p->P, p->P.mem, stream);
     if (st != BA_OK) {
         (void)hipStreamSynchronize(stream);
@@ -303,10 +306,12 @@ ba_status ba_problem_get_info(const ba_problem *p, ba_problem_info *info) {
     info->n_scans = P.n_poses;
     info->n_windows = P.n_windows;
     info->max_m = P.max_m;
-    info->device_bytes = (int64_t)P.mem.bytes;
+    info->device_bytes = (int64_t)P.mem.bytes + dense_device_bytes(&P);
     info->n_wave_groups = P.n_groups;
     info->n_pose_chunks = P.n_chunks;
     info->padded_clusters = P.c_pad;
+    info->precision = P.prec;
+    info->cluster_bytes = P.prec == BA_PREC_F32 ? 4 + 12 + 24 + 4 : 8 + 24 + 48 + 4;
     return BA_OK;
 }
 
@@ -414,10 +419,11 @@ ba_status ba_iterate(ba_problem *p, double *poses_inout, const ba_lm_options *op
     // The whole call is captured once into a HIP graph and replayed while its
     // arguments stay the same (profiling records events, so it runs eagerly).
     bool done = false;
-    if (g_graphs_enabled() && !prof_enabled()) {   // event records cannot be captured: profile eagerly
+    if (g_graphs_enabled() && !prof_enabled() && !P->no_graph) {   // event records cannot be captured: profile eagerly
         IterGraph *G = (IterGraph *)P->iter_graph;
         const bool same = G && G->exec && G->poses == poses_inout && G->trace == dtrace && G->mode == opt->mode &&
-                          G->iters == iters && G->mu0 == mu0 && G->nu0 == nu0 && G->tol_g == opt->tol_g;
+                          G->iters == iters && G->mu0 == mu0 && G->nu0 == nu0 && G->tol_g == opt->tol_g &&
+                          G->tune_gen == P->tune_gen;
         if (!same) {
             graph_release(P);
             G = new IterGraph();
@@ -441,6 +447,7 @@ ba_status ba_iterate(ba_problem *p, double *poses_inout, const ba_lm_options *op
                 G->mu0 = mu0;
                 G->nu0 = nu0;
                 G->tol_g = opt->tol_g;
+                G->tune_gen = P->tune_gen;
             } else {
                 graph_release(P);
                 G = nullptr;
@@ -468,6 +475,142 @@ ba_status ba_iterate(ba_problem *p, double *poses_inout, const ba_lm_options *op
             rep[w].cost_initial = st[w].cost0;
         }
     }
+    return BA_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------- tuning
+namespace ba {
+
+static ba_status check_tuning(const ba_tuning *t) {
+    if (!(t->vox_split == 1 || t->vox_split == 2 || t->vox_split == 4) || t->vox_grid < 0 || t->vox_grid > 64 ||
+        t->pose_grid < 0 || t->pose_grid > 64 || t->chunk_len < MIN_CHUNK || t->chunk_len > (1 << 20)) {
+        set_error("tuning out of range (vox_split %d, vox_grid %d, pose_grid %d, chunk_len %d)", t->vox_split,
+                  t->vox_grid, t->pose_grid, t->chunk_len);
+        return BA_E_ARG;
+    }
+    return BA_OK;
+}
+
+static ba_status apply_tuning(Problem *P, const ba_tuning *t, hipStream_t s) {
+    BA_TRY(check_tuning(t));
+    if (t->chunk_len != P->tune.chunk_len) BA_TRY(replan_chunks(P, t->chunk_len, s));
+    P->tune.vox_split = t->vox_split;
+    P->tune.vox_grid = t->vox_grid;
+    P->tune.pose_grid = t->pose_grid;
+    P->tune_gen++;
+    graph_release(P);
+    return BA_OK;
+}
+
+static ba_tuning export_tuning(const Problem *P) {
+    ba_tuning t;
+    t.vox_split = P->tune.vox_split;
+    t.vox_grid = P->tune.vox_grid;
+    t.pose_grid = P->tune.pose_grid;
+    t.chunk_len = P->tune.chunk_len;
+    return t;
+}
+
+// Mean time of `reps` launches of one pass (after one untimed launch).
+static ba_status time_pass(Problem *P, const double *poses, bool vox, int reps, hipStream_t s, float *ms) {
+    hipEvent_t a, b;
+    BA_HIP(hipEventCreate(&a));
+    BA_HIP(hipEventCreate(&b));
+    auto launch = [&]() {
+        if (vox)
+            launch_vox(P, poses, false, false, s);
+        else
+            launch_pose_chunks(P, poses, false, s);
+    };
+    launch();
+    hipError_t e = hipEventRecord(a, s);
+    for (int r = 0; r < reps && e == hipSuccess; r++) launch();
+    if (e == hipSuccess) e = hipEventRecord(b, s);
+    if (e == hipSuccess) e = hipEventSynchronize(b);
+    if (e == hipSuccess) e = hipGetLastError();
+    float t = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&t, a, b);
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    if (e != hipSuccess) {
+        set_error("autotune timing failed: %s", hipGetErrorString(e));
+        return BA_E_HIP;
+    }
+    *ms = t / (float)std::max(reps, 1);
+    return BA_OK;
+}
+
+}  // namespace ba
+
+extern "C" {
+
+ba_status ba_problem_get_tuning(const ba_problem *p, ba_tuning *t) {
+    if (!p || !t) {
+        ba::set_error("null argument");
+        return BA_E_ARG;
+    }
+    *t = ba::export_tuning(&p->P);
+    return BA_OK;
+}
+
+ba_status ba_problem_set_tuning(ba_problem *p, const ba_tuning *t) {
+    if (!p || !t) {
+        ba::set_error("null argument");
+        return BA_E_ARG;
+    }
+    return ba::apply_tuning(&p->P, t, 0);
+}
+
+ba_status ba_autotune(ba_problem *p, const double *poses, int32_t reps, ba_tuning *best, hipStream_t stream) {
+    using namespace ba;
+    if (!p || !poses || reps < 1) {
+        set_error("null problem or poses, or reps < 1");
+        return BA_E_ARG;
+    }
+    Problem *P = &p->P;
+    ba_tuning cur = export_tuning(P);
+    // residual pass: cluster split x grid
+    const int splits[3] = {4, 2, 1};
+    const int vgrids[5] = {0, 1, 2, 4, 8};
+    float best_ms = 1e30f;
+    ba_tuning t = cur, win = cur;
+    for (int sp : splits)
+        for (int gr : vgrids) {
+            t.vox_split = sp;
+            t.vox_grid = gr;
+            BA_TRY(apply_tuning(P, &t, stream));
+            float ms = 0.f;
+            BA_TRY(time_pass(P, poses, true, reps, stream, &ms));
+            if (ms < best_ms) {
+                best_ms = ms;
+                win.vox_split = sp;
+                win.vox_grid = gr;
+            }
+        }
+    t = win;
+    BA_TRY(apply_tuning(P, &t, stream));
+    // the derivative pass reads the voxel state of the residual pass
+    launch_vox(P, poses, false, false, stream);
+    const int chunks[5] = {256, 64, 128, 512, 1024};
+    const int pgrids[4] = {0, 2, 4, 8};
+    best_ms = 1e30f;
+    for (int cl : chunks)
+        for (int gr : pgrids) {
+            t.chunk_len = cl;
+            t.pose_grid = gr;
+            BA_TRY(apply_tuning(P, &t, stream));
+            float ms = 0.f;
+            BA_TRY(time_pass(P, poses, false, reps, stream, &ms));
+            if (ms < best_ms) {
+                best_ms = ms;
+                win.chunk_len = cl;
+                win.pose_grid = gr;
+            }
+        }
+    BA_TRY(apply_tuning(P, &win, stream));
+    if (best) *best = win;
     return BA_OK;
 }
 

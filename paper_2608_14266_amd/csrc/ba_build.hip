@@ -219,10 +219,154 @@ __global__ void k_gather_pose(int64_t C, const int32_t *__restrict__ order, cons
 
 static inline unsigned nblk(int64_t n, int t = 256) { return (unsigned)((n + t - 1) / t); }
 
+// ---------------------------------------------------------------- precision form
+// Reference point of each voxel slot: the FP64 centroid c_i of the voxel's
+// clusters placed by the reference poses T0.  Each cluster is then stored in
+// FP32 in the world frame of its scan's reference pose, relative to c_i:
+//   mu' = R0 mu + t0 - c_i,   S' = R0 S R0^T,
+// so that at poses T the iteration only applies the pose change
+// G = R R0^T = I + E (small) to small, voxel-centred quantities.
+__device__ __forceinline__ void ref_frame_f32(const Pose &P0, const double *c, const double *mu, const double *S,
+                                              float *mu32, float *S32) {
+    double y[3], St[6];
+    rot(P0.r, mu, y);
+#pragma unroll
+    for (int k = 0; k < 3; k++) mu32[k] = (float)((y[k] + P0.t[k]) - c[k]);
+    rot_sym(P0.r, S, St);
+#pragma unroll
+    for (int k = 0; k < 6; k++) S32[k] = (float)St[k];
+}
+
+// One thread per slot; padding slots get a zero reference (their clusters are
+// never read).  err: 1 = non-finite reference, 2 = a count >= 2^24.
+__global__ void k_vox_ref_f32(int64_t n_slots, const GroupDesc *__restrict__ groups, int64_t c_pad,
+                              const double *__restrict__ vN, const double *__restrict__ vmu,
+                              const double *__restrict__ vS, const int32_t *__restrict__ vpose,
+                              const double *__restrict__ ref_poses, double *__restrict__ vref,
+                              float *__restrict__ vN32, float *__restrict__ vmu32, float *__restrict__ vS32,
+                              int32_t *__restrict__ err) {
+    const int64_t sl = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (sl >= n_slots) return;
+    const GroupDesc g = groups[sl >> 6];
+    const int lane = (int)(sl & 63);
+    double *ref = vref + 4 * sl;
+    if (lane >= g.nvox) {
+        ref[0] = ref[1] = ref[2] = ref[3] = 0.0;
+        return;
+    }
+    double n = 0.0, c[3] = {0.0, 0.0, 0.0};
+    for (int k = 0; k < g.m; k++) {
+        const int64_t idx = g.cbase + 64LL * k + lane;
+        Pose P0;
+        load_pose(ref_poses, vpose[idx], P0);
+        const double mu[3] = {vmu[idx], vmu[c_pad + idx], vmu[2 * c_pad + idx]};
+        double y[3];
+        rot(P0.r, mu, y);
+        const double nk = vN[idx];
+        n += nk;
+#pragma unroll
+        for (int q = 0; q < 3; q++) c[q] = fma(nk, y[q] + P0.t[q], c[q]);
+    }
+#pragma unroll
+    for (int q = 0; q < 3; q++) c[q] /= n;
+    int bad = 0;
+    if (!(isfinite(c[0]) && isfinite(c[1]) && isfinite(c[2]))) bad |= 1;
+    ref[0] = c[0]; ref[1] = c[1]; ref[2] = c[2]; ref[3] = 0.0;
+    for (int k = 0; k < g.m; k++) {
+        const int64_t idx = g.cbase + 64LL * k + lane;
+        Pose P0;
+        load_pose(ref_poses, vpose[idx], P0);
+        const double mu[3] = {vmu[idx], vmu[c_pad + idx], vmu[2 * c_pad + idx]};
+        double S[6];
+#pragma unroll
+        for (int e = 0; e < 6; e++) S[e] = vS[e * c_pad + idx];
+        float m32[3], S32[6];
+        ref_frame_f32(P0, c, mu, S, m32, S32);
+#pragma unroll
+        for (int e = 0; e < 3; e++) vmu32[e * c_pad + idx] = m32[e];
+#pragma unroll
+        for (int e = 0; e < 6; e++) vS32[e * c_pad + idx] = S32[e];
+        const double nk = vN[idx];
+        if (nk >= 16777216.0) bad |= 2;
+        vN32[idx] = (float)nk;
+    }
+    if (bad) atomicOr(err, bad);
+}
+
+// Pose-major FP32 copy in the same reference frames.
+__global__ void k_gather_pose_f32(int64_t C, const int32_t *__restrict__ order, const int32_t *__restrict__ slot_of,
+                                  const int32_t *__restrict__ cscan, const double *__restrict__ cN,
+                                  const double *__restrict__ cmu, const double *__restrict__ cS,
+                                  const double *__restrict__ vref, const double *__restrict__ ref_poses,
+                                  float *__restrict__ pN, float *__restrict__ pmu, float *__restrict__ pS,
+                                  int32_t *__restrict__ pslot) {
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= C) return;
+    const int64_t c = order[q];
+    const int32_t sl = slot_of[c];
+    Pose P0;
+    load_pose(ref_poses, cscan[c], P0);
+    const double mu[3] = {cmu[3 * c], cmu[3 * c + 1], cmu[3 * c + 2]};
+    double S[6];
+#pragma unroll
+    for (int k = 0; k < 6; k++) S[k] = cS[6 * c + k];
+    float m32[3], S32[6];
+    ref_frame_f32(P0, vref + 4LL * sl, mu, S, m32, S32);
+#pragma unroll
+    for (int k = 0; k < 3; k++) pmu[k * C + q] = m32[k];
+#pragma unroll
+    for (int k = 0; k < 6; k++) pS[k * C + q] = S32[k];
+    pN[q] = (float)cN[c];
+    pslot[q] = sl;
+}
+
+__global__ void k_validate_poses(int64_t n, const double *__restrict__ poses, int32_t *__restrict__ err) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n && !isfinite(poses[i])) atomicOr(err, 1);
+}
+
+
 static int bit_length(uint64_t v) {
     int b = 0;
     while (v) { b++; v >>= 1; }
     return b;
+}
+
+// ---------------------------------------------------------------- pose chunks
+// Cuts every pose's range of the pose-major layout into chunks of at most
+// chunk_len clusters and uploads the chunk tables (synchronous).
+ba_status replan_chunks(Problem *P, int32_t chunk_len, hipStream_t s) {
+    if (chunk_len < MIN_CHUNK || chunk_len > (1 << 20)) {
+        set_error("chunk_len %d out of range [%d, 2^20]", chunk_len, MIN_CHUNK);
+        return BA_E_ARG;
+    }
+    const int32_t N = P->n_poses;
+    std::vector<ChunkDesc> chunks;
+    std::vector<int32_t> chunk_ptr(N + 1, 0);
+    for (int32_t j = 0; j < N; j++) {
+        chunk_ptr[j] = (int32_t)chunks.size();
+        const int64_t a = P->h_pose_start[j], b = P->h_pose_start[j + 1];
+        for (int64_t s0 = a; s0 < b; s0 += chunk_len) {
+            ChunkDesc ch;
+            ch.start = s0;
+            ch.count = (int32_t)std::min<int64_t>(chunk_len, b - s0);
+            ch.pose = j;
+            chunks.push_back(ch);
+        }
+    }
+    chunk_ptr[N] = (int32_t)chunks.size();
+    if ((int64_t)chunks.size() > P->chunk_cap) {
+        set_error("internal: %zu chunks exceed the table capacity %lld", chunks.size(), (long long)P->chunk_cap);
+        return BA_E_ARG;
+    }
+    if (!chunks.empty())
+        BA_HIP(hipMemcpyAsync(P->chunks, chunks.data(), sizeof(ChunkDesc) * chunks.size(), hipMemcpyHostToDevice, s));
+    BA_HIP(hipMemcpyAsync(P->chunk_ptr, chunk_ptr.data(), sizeof(int32_t) * (N + 1), hipMemcpyHostToDevice, s));
+    BA_HIP(hipStreamSynchronize(s));
+    P->n_chunks = (int32_t)chunks.size();
+    P->chunk_len = chunk_len;
+    P->tune.chunk_len = chunk_len;
+    return BA_OK;
 }
 
 // ---------------------------------------------------------------- host plan
@@ -310,25 +454,16 @@ static ba_status make_plan(Problem *P, const std::vector<int32_t> &cvox, const s
         if (cscan[a] != cscan[b]) return cscan[a] < cscan[b];
         return slot_of[a] < slot_of[b];
     });
-    std::vector<ChunkDesc> chunks;
-    std::vector<int32_t> chunk_ptr(N + 1, 0);
+    P->h_pose_start.assign(N + 1, 0);
     {
         int64_t q = 0;
         for (int32_t j = 0; j < N; j++) {
-            chunk_ptr[j] = (int32_t)chunks.size();
-            int64_t a = q;
+            P->h_pose_start[j] = q;
             while (q < C && cscan[porder[q]] == j) q++;
-            for (int64_t s0 = a; s0 < q; s0 += P->chunk_len) {
-                ChunkDesc ch;
-                ch.start = s0;
-                ch.count = (int32_t)std::min<int64_t>(P->chunk_len, q - s0);
-                ch.pose = j;
-                chunks.push_back(ch);
-            }
         }
-        chunk_ptr[N] = (int32_t)chunks.size();
+        P->h_pose_start[N] = q;
     }
-    P->n_chunks = (int32_t)chunks.size();
+    P->chunk_cap = C / MIN_CHUNK + N + 1;
     std::vector<int32_t> win_pose_ptr(W + 1, 0), pose_window(N);
     for (int32_t j = 0; j < N; j++) {
         pose_window[j] = scan_window[j];
@@ -339,22 +474,37 @@ static ba_status make_plan(Problem *P, const std::vector<int32_t> &cvox, const s
     // device allocations owned by the problem
     const int64_t CP = P->c_pad;
     const int64_t NS = (int64_t)P->n_groups * 64;
-    BA_TRY(keep.alloc(&P->v_mu, 3 * CP));
-    BA_TRY(keep.alloc(&P->v_S, 6 * CP));
-    BA_TRY(keep.alloc(&P->v_N, CP));
+    // a precision-form problem keeps only FP32 iteration copies: the FP64
+    // voxel-major copy is a build temporary and no FP64 pose-major copy exists
+    const bool f32 = P->prec == BA_PREC_F32;
+    DevArena f64tmp;
+    DevArena &iter = f32 ? f64tmp : keep;
+    BA_TRY(iter.alloc(&P->v_mu, 3 * CP));
+    BA_TRY(iter.alloc(&P->v_S, 6 * CP));
+    BA_TRY(iter.alloc(&P->v_N, CP));
     BA_TRY(keep.alloc(&P->v_pose, CP));
     BA_TRY(keep.alloc(&P->groups, std::max<int64_t>(P->n_groups, 1)));
     BA_TRY(keep.alloc(&P->vblocks, std::max<int64_t>(P->n_vblocks, 1)));
     BA_TRY(keep.alloc(&P->slot_vox, std::max<int64_t>(NS, 1)));
     BA_TRY(keep.alloc(&P->vstate, 2 * std::max<int64_t>(NS, 1) * VSTATE));
     BA_TRY(keep.alloc(&P->wave_cost, std::max<int64_t>(P->n_groups, 1)));
-    BA_TRY(keep.alloc(&P->p_mu, 3 * C));
-    BA_TRY(keep.alloc(&P->p_S, 6 * C));
-    BA_TRY(keep.alloc(&P->p_N, C));
+    if (f32) {
+        BA_TRY(keep.alloc(&P->v_mu32, 3 * CP));
+        BA_TRY(keep.alloc(&P->v_S32, 6 * CP));
+        BA_TRY(keep.alloc(&P->v_N32, CP));
+        BA_TRY(keep.alloc(&P->p_mu32, 3 * C));
+        BA_TRY(keep.alloc(&P->p_S32, 6 * C));
+        BA_TRY(keep.alloc(&P->p_N32, C));
+        BA_TRY(keep.alloc(&P->v_ref, 4 * std::max<int64_t>(NS, 1)));
+    } else {
+        BA_TRY(keep.alloc(&P->p_mu, 3 * C));
+        BA_TRY(keep.alloc(&P->p_S, 6 * C));
+        BA_TRY(keep.alloc(&P->p_N, C));
+    }
     BA_TRY(keep.alloc(&P->p_slot, C));
-    BA_TRY(keep.alloc(&P->chunks, std::max<int64_t>(P->n_chunks, 1)));
+    BA_TRY(keep.alloc(&P->chunks, P->chunk_cap));
     BA_TRY(keep.alloc(&P->chunk_ptr, N + 1));
-    BA_TRY(keep.alloc(&P->partials, std::max<int64_t>(P->n_chunks, 1) * NPART));
+    BA_TRY(keep.alloc(&P->partials, P->chunk_cap * NPART));
     BA_TRY(keep.alloc(&P->win_group_ptr, W + 1));
     BA_TRY(keep.alloc(&P->win_pose_ptr, W + 1));
     BA_TRY(keep.alloc(&P->pose_window, N));
@@ -376,8 +526,7 @@ static ba_status make_plan(Problem *P, const std::vector<int32_t> &cvox, const s
     BA_HIP(hipMemcpyAsync(P->groups, groups.data(), sizeof(GroupDesc) * groups.size(), hipMemcpyHostToDevice, s));
     BA_HIP(hipMemcpyAsync(P->vblocks, vblocks.data(), sizeof(VoxBlock) * vblocks.size(), hipMemcpyHostToDevice, s));
     BA_HIP(hipMemcpyAsync(P->slot_vox, slot_vox.data(), sizeof(int32_t) * slot_vox.size(), hipMemcpyHostToDevice, s));
-    BA_HIP(hipMemcpyAsync(P->chunks, chunks.data(), sizeof(ChunkDesc) * chunks.size(), hipMemcpyHostToDevice, s));
-    BA_HIP(hipMemcpyAsync(P->chunk_ptr, chunk_ptr.data(), sizeof(int32_t) * (N + 1), hipMemcpyHostToDevice, s));
+    BA_TRY(replan_chunks(P, P->chunk_len, s));
     BA_HIP(hipMemcpyAsync(P->win_group_ptr, win_group_ptr.data(), sizeof(int32_t) * (W + 1), hipMemcpyHostToDevice, s));
     BA_HIP(hipMemcpyAsync(P->win_pose_ptr, win_pose_ptr.data(), sizeof(int32_t) * (W + 1), hipMemcpyHostToDevice, s));
     BA_HIP(hipMemcpyAsync(P->pose_window, pose_window.data(), sizeof(int32_t) * N, hipMemcpyHostToDevice, s));
@@ -390,15 +539,42 @@ static ba_status make_plan(Problem *P, const std::vector<int32_t> &cvox, const s
     BA_TRY(keep.alloc(&P->c_slot, C));
     d_slot_of = P->c_slot;
     BA_TRY(tmp.alloc(&d_porder, C));
+    int32_t *d_err;
+    BA_TRY(tmp.alloc(&d_err, 1));
     BA_HIP(hipMemcpyAsync(d_dst, dst.data(), sizeof(int64_t) * C, hipMemcpyHostToDevice, s));
     BA_HIP(hipMemcpyAsync(d_slot_of, slot_of.data(), sizeof(int32_t) * C, hipMemcpyHostToDevice, s));
     BA_HIP(hipMemcpyAsync(d_porder, porder.data(), sizeof(int32_t) * C, hipMemcpyHostToDevice, s));
     hipLaunchKernelGGL(k_scatter_vox, dim3(nblk(C)), dim3(256), 0, s, C, d_dst, CP, P->c_N, P->c_mu, P->c_S,
                        P->c_scan, P->v_N, P->v_mu, P->v_S, P->v_pose);
-    hipLaunchKernelGGL(k_gather_pose, dim3(nblk(C)), dim3(256), 0, s, C, d_porder, d_slot_of, P->c_N, P->c_mu,
-                       P->c_S, P->p_N, P->p_mu, P->p_S, P->p_slot);
+    if (!f32) {
+        hipLaunchKernelGGL(k_gather_pose, dim3(nblk(C)), dim3(256), 0, s, C, d_porder, d_slot_of, P->c_N, P->c_mu,
+                           P->c_S, P->p_N, P->p_mu, P->p_S, P->p_slot);
+        BA_HIP(hipGetLastError());
+        BA_HIP(hipStreamSynchronize(s));
+        return BA_OK;
+    }
+    BA_HIP(hipMemsetAsync(d_err, 0, sizeof(int32_t), s));
+    BA_HIP(hipMemsetAsync(P->v_mu32, 0, sizeof(float) * 3 * CP, s));
+    BA_HIP(hipMemsetAsync(P->v_S32, 0, sizeof(float) * 6 * CP, s));
+    BA_HIP(hipMemsetAsync(P->v_N32, 0, sizeof(float) * CP, s));
+    if (NS > 0)
+        hipLaunchKernelGGL(k_vox_ref_f32, dim3(nblk(NS)), dim3(256), 0, s, NS, P->groups, CP, P->v_N, P->v_mu, P->v_S,
+                           P->v_pose, P->ref_poses, P->v_ref, P->v_N32, P->v_mu32, P->v_S32, d_err);
+    hipLaunchKernelGGL(k_gather_pose_f32, dim3(nblk(C)), dim3(256), 0, s, C, d_porder, d_slot_of, P->c_scan,
+                       P->c_N, P->c_mu, P->c_S, P->v_ref, P->ref_poses, P->p_N32, P->p_mu32, P->p_S32, P->p_slot);
     BA_HIP(hipGetLastError());
+    int32_t herr = 0;
+    BA_HIP(hipMemcpyAsync(&herr, d_err, sizeof(int32_t), hipMemcpyDeviceToHost, s));
     BA_HIP(hipStreamSynchronize(s));
+    P->v_mu = P->v_S = P->v_N = nullptr;   // released with f64tmp
+    if (herr & 2) {
+        set_error("precision form: a cluster holds 2^24 points or more (its count is not exact in FP32)");
+        return BA_E_UNSUPPORTED;
+    }
+    if (herr & 1) {
+        set_error("precision form: non-finite voxel reference point (check ref_poses)");
+        return BA_E_ARG;
+    }
     return BA_OK;
 }
 
@@ -426,6 +602,33 @@ static ba_status finish_build(Problem *P, DevArena &keep, const ba_build_options
         }
     }
     P->n_windows = W;
+    P->prec = opt ? opt->precision : BA_PREC_F64;
+    if (P->prec != BA_PREC_F64 && P->prec != BA_PREC_F32) {
+        set_error("unknown precision %d", P->prec);
+        return BA_E_ARG;
+    }
+    if (P->prec == BA_PREC_F32) {
+        if (!opt->ref_poses) {
+            set_error("the precision form needs ref_poses");
+            return BA_E_ARG;
+        }
+        const int64_t np = 12LL * P->n_poses;
+        BA_TRY(keep.alloc(&P->ref_poses, np));
+        BA_HIP(hipMemcpyAsync(P->ref_poses, opt->ref_poses, sizeof(double) * np, hipMemcpyDeviceToDevice, s));
+        DevArena tmp;
+        int32_t *d_err;
+        BA_TRY(tmp.alloc(&d_err, 1));
+        BA_HIP(hipMemsetAsync(d_err, 0, sizeof(int32_t), s));
+        hipLaunchKernelGGL(k_validate_poses, dim3(nblk(np)), dim3(256), 0, s, np, P->ref_poses, d_err);
+        BA_HIP(hipGetLastError());
+        int32_t herr = 0;
+        BA_HIP(hipMemcpyAsync(&herr, d_err, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        BA_HIP(hipStreamSynchronize(s));
+        if (herr) {
+            set_error("ref_poses holds non-finite values");
+            return BA_E_ARG;
+        }
+    }
     return make_plan(P, cvox, cscan, scan_window, keep, s);
 }
 

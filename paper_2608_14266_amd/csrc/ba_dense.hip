@@ -577,6 +577,11 @@ void dense_release(Problem *P) {
 
 static int64_t linv_doubles(int64_t n) { return ((n + TB - 1) / TB) * (int64_t)TB * TB; }
 
+int64_t dense_device_bytes(const Problem *P) {
+    const DenseState *D = (const DenseState *)P->dense_state;
+    return D ? (int64_t)D->mem.bytes : 0;
+}
+
 ba_status dense_prepare(Problem *P) {
     if (P->dense_state) return BA_OK;
     hipStream_t s = 0;

@@ -96,6 +96,9 @@ __device__ __forceinline__ void wave_dd_sum(double &hi, double &lo) {
 }
 
 // ---------------------------------------------------------------- 3x3 helpers
+__device__ __forceinline__ double fmaT(double a, double b, double c) { return fma(a, b, c); }
+__device__ __forceinline__ float fmaT(float a, float b, float c) { return fmaf(a, b, c); }
+
 struct Pose {
     double r[9];
     double t[3];
@@ -109,47 +112,89 @@ __device__ __forceinline__ void load_pose(const double *__restrict__ poses, int 
     for (int k = 0; k < 3; k++) p.t[k] = q[9 + k];
 }
 
+// Pose change from a reference pose: E = R R0^T - I and dt = t - t0, so a
+// world point x placed by T0 moves to x + E (x - t0) + dt under T.
+struct PoseDelta {
+    double E[9];
+    double dt[3];
+};
+
+__device__ __forceinline__ void pose_delta(const Pose &P, const Pose &P0, PoseDelta &D) {
+#pragma unroll
+    for (int i = 0; i < 3; i++)
+#pragma unroll
+        for (int k = 0; k < 3; k++)
+            D.E[3 * i + k] = fma(P.r[3 * i], P0.r[3 * k], fma(P.r[3 * i + 1], P0.r[3 * k + 1],
+                                 P.r[3 * i + 2] * P0.r[3 * k + 2])) - (i == k ? 1.0 : 0.0);
+#pragma unroll
+    for (int k = 0; k < 3; k++) D.dt[k] = P.t[k] - P0.t[k];
+}
+
+// D = E S + S E^T + E S E^T for symmetric S (6 unique), so that
+// (I + E) S (I + E)^T = S + D with D of the size of E.
+template <typename T>
+__device__ __forceinline__ void delta_sym(const T *E, const T *S, T *D) {
+    const T Sf[3][3] = {{S[0], S[1], S[2]}, {S[1], S[3], S[4]}, {S[2], S[4], S[5]}};
+    T A[3][3];
+#pragma unroll
+    for (int i = 0; i < 3; i++)
+#pragma unroll
+        for (int j = 0; j < 3; j++)
+            A[i][j] = fmaT(E[3 * i], Sf[0][j], fmaT(E[3 * i + 1], Sf[1][j], E[3 * i + 2] * Sf[2][j]));
+    const int ii[6] = {0, 0, 0, 1, 1, 2}, jj[6] = {0, 1, 2, 1, 2, 2};
+#pragma unroll
+    for (int q = 0; q < 6; q++) {
+        const int i = ii[q], j = jj[q];
+        D[q] = A[i][j] + A[j][i] + fmaT(A[i][0], E[3 * j], fmaT(A[i][1], E[3 * j + 1], A[i][2] * E[3 * j + 2]));
+    }
+}
+
 // y = R x
-__device__ __forceinline__ void rot(const double *r, const double *x, double *y) {
-    y[0] = fma(r[0], x[0], fma(r[1], x[1], r[2] * x[2]));
-    y[1] = fma(r[3], x[0], fma(r[4], x[1], r[5] * x[2]));
-    y[2] = fma(r[6], x[0], fma(r[7], x[1], r[8] * x[2]));
+template <typename T>
+__device__ __forceinline__ void rot(const T *r, const T *x, T *y) {
+    y[0] = fmaT(r[0], x[0], fmaT(r[1], x[1], r[2] * x[2]));
+    y[1] = fmaT(r[3], x[0], fmaT(r[4], x[1], r[5] * x[2]));
+    y[2] = fmaT(r[6], x[0], fmaT(r[7], x[1], r[8] * x[2]));
 }
 
 // St = R S R^T for symmetric S (6: xx xy xz yy yz zz); output 6 unique.
-__device__ __forceinline__ void rot_sym(const double *r, const double *s, double *o) {
+template <typename T>
+__device__ __forceinline__ void rot_sym(const T *r, const T *s, T *o) {
     // M = R S (3x3)
-    double m[9];
+    T m[9];
 #pragma unroll
     for (int i = 0; i < 3; i++) {
-        m[3 * i + 0] = fma(r[3 * i], s[0], fma(r[3 * i + 1], s[1], r[3 * i + 2] * s[2]));
-        m[3 * i + 1] = fma(r[3 * i], s[1], fma(r[3 * i + 1], s[3], r[3 * i + 2] * s[4]));
-        m[3 * i + 2] = fma(r[3 * i], s[2], fma(r[3 * i + 1], s[4], r[3 * i + 2] * s[5]));
+        m[3 * i + 0] = fmaT(r[3 * i], s[0], fmaT(r[3 * i + 1], s[1], r[3 * i + 2] * s[2]));
+        m[3 * i + 1] = fmaT(r[3 * i], s[1], fmaT(r[3 * i + 1], s[3], r[3 * i + 2] * s[4]));
+        m[3 * i + 2] = fmaT(r[3 * i], s[2], fmaT(r[3 * i + 1], s[4], r[3 * i + 2] * s[5]));
     }
     // O = M R^T : O_ij = sum_k M_ik R_jk
-    o[0] = fma(m[0], r[0], fma(m[1], r[1], m[2] * r[2]));
-    o[1] = fma(m[0], r[3], fma(m[1], r[4], m[2] * r[5]));
-    o[2] = fma(m[0], r[6], fma(m[1], r[7], m[2] * r[8]));
-    o[3] = fma(m[3], r[3], fma(m[4], r[4], m[5] * r[5]));
-    o[4] = fma(m[3], r[6], fma(m[4], r[7], m[5] * r[8]));
-    o[5] = fma(m[6], r[6], fma(m[7], r[7], m[8] * r[8]));
+    o[0] = fmaT(m[0], r[0], fmaT(m[1], r[1], m[2] * r[2]));
+    o[1] = fmaT(m[0], r[3], fmaT(m[1], r[4], m[2] * r[5]));
+    o[2] = fmaT(m[0], r[6], fmaT(m[1], r[7], m[2] * r[8]));
+    o[3] = fmaT(m[3], r[3], fmaT(m[4], r[4], m[5] * r[5]));
+    o[4] = fmaT(m[3], r[6], fmaT(m[4], r[7], m[5] * r[8]));
+    o[5] = fmaT(m[6], r[6], fmaT(m[7], r[7], m[8] * r[8]));
 }
 
-__device__ __forceinline__ void cross(const double *a, const double *b, double *c) {
+template <typename T>
+__device__ __forceinline__ void cross(const T *a, const T *b, T *c) {
     c[0] = a[1] * b[2] - a[2] * b[1];
     c[1] = a[2] * b[0] - a[0] * b[2];
     c[2] = a[0] * b[1] - a[1] * b[0];
 }
 
-__device__ __forceinline__ double dot(const double *a, const double *b) {
-    return fma(a[0], b[0], fma(a[1], b[1], a[2] * b[2]));
+template <typename T>
+__device__ __forceinline__ T dot(const T *a, const T *b) {
+    return fmaT(a[0], b[0], fmaT(a[1], b[1], a[2] * b[2]));
 }
 
 // symmetric (6) times vector
-__device__ __forceinline__ void sym_mv(const double *s, const double *x, double *y) {
-    y[0] = fma(s[0], x[0], fma(s[1], x[1], s[2] * x[2]));
-    y[1] = fma(s[1], x[0], fma(s[3], x[1], s[4] * x[2]));
-    y[2] = fma(s[2], x[0], fma(s[4], x[1], s[5] * x[2]));
+template <typename T>
+__device__ __forceinline__ void sym_mv(const T *s, const T *x, T *y) {
+    y[0] = fmaT(s[0], x[0], fmaT(s[1], x[1], s[2] * x[2]));
+    y[1] = fmaT(s[1], x[0], fmaT(s[3], x[1], s[4] * x[2]));
+    y[2] = fmaT(s[2], x[0], fmaT(s[4], x[1], s[5] * x[2]));
 }
 
 // ---------------------------------------------------------------- 3x3 symmetric eigen

@@ -27,6 +27,8 @@
 // these derivatives to BALM3, they are derived from Eq. 3 directly).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "ba.h"
 #include "ba_device.hpp"
 #include "ba_internal.hpp"
@@ -35,8 +37,8 @@
 namespace ba {
 
 // Accumulates the clusters k = k0, k0 + kstep, ... of the voxel in `lane` of
-// group g relative to the centroid r of the voxel's first cluster (which keeps
-// the sums well conditioned at large coordinates):
+// group g relative to a reference point r of the voxel (which keeps the sums
+// well conditioned at large coordinates):
 //   n = sum N_k,  s = sum N_k d_k,  M = sum [St_k + N_k d_k d_k^T],  d_k = m_k - r.
 struct VoxSums {
     double n, s0, s1, s2;
@@ -44,16 +46,46 @@ struct VoxSums {
     double r[3];
 };
 
-__device__ __forceinline__ void vox_accumulate(const GroupDesc &g, int lane, int k0, int kstep, int64_t c_pad,
-                                               const double *__restrict__ vN, const double *__restrict__ vmu,
-                                               const double *__restrict__ vS, const int32_t *__restrict__ vpose,
-                                               const double *__restrict__ poses, VoxSums &a) {
+// Cluster sources of the two precisions.  FP64: (N, mu, S) as built.  FP32
+// (precision form): (N, mu', S') with mu' = R0 mu + t0 - c_i and
+// S' = R0 S R0^T, in the world frame of the scan's reference pose T0 and
+// relative to the voxel's reference point c_i (`ref`, per slot).
+struct SrcF64 {
+    const double *N, *mu, *S;
+};
+struct SrcF32 {
+    const float *N, *mu, *S;
+    const double *ref_poses;   // [n_poses][12]
+    const double *ref;         // [slots][4]
+};
+
+template <typename T>
+__device__ __forceinline__ void vox_add(VoxSums &a, T nk, const T *d, const T *St) {
+    const T nd0 = nk * d[0], nd1 = nk * d[1], nd2 = nk * d[2];
+    a.n += (double)nk;
+    a.s0 += (double)nd0; a.s1 += (double)nd1; a.s2 += (double)nd2;
+    a.M[0] += (double)fmaT(nd0, d[0], St[0]);
+    a.M[1] += (double)fmaT(nd0, d[1], St[1]);
+    a.M[2] += (double)fmaT(nd0, d[2], St[2]);
+    a.M[3] += (double)fmaT(nd1, d[1], St[3]);
+    a.M[4] += (double)fmaT(nd1, d[2], St[4]);
+    a.M[5] += (double)fmaT(nd2, d[2], St[5]);
+}
+
+__device__ __forceinline__ void vox_zero(VoxSums &a) {
     a.n = a.s0 = a.s1 = a.s2 = 0.0;
 #pragma unroll
     for (int q = 0; q < 6; q++) a.M[q] = 0.0;
+}
+
+// FP64: the reference is the centroid of the lane's first cluster.
+__device__ __forceinline__ void vox_accumulate(const GroupDesc &g, int64_t slot, int lane, int k0, int kstep,
+                                               int64_t c_pad, const SrcF64 &src, const int32_t *__restrict__ vpose,
+                                               const double *__restrict__ poses, VoxSums &a) {
+    vox_zero(a);
     {
         const int64_t idx = g.cbase + lane;
-        const double mu[3] = {vmu[idx], vmu[c_pad + idx], vmu[2 * c_pad + idx]};
+        const double mu[3] = {src.mu[idx], src.mu[c_pad + idx], src.mu[2 * c_pad + idx]};
         Pose P;
         load_pose(poses, vpose[idx], P);
         rot(P.r, mu, a.r);
@@ -62,26 +94,57 @@ __device__ __forceinline__ void vox_accumulate(const GroupDesc &g, int lane, int
 #pragma unroll 2
     for (int k = k0; k < g.m; k += kstep) {
         const int64_t idx = g.cbase + 64LL * k + lane;
-        const double nk = vN[idx];
-        const double mu[3] = {vmu[idx], vmu[c_pad + idx], vmu[2 * c_pad + idx]};
+        const double nk = src.N[idx];
+        const double mu[3] = {src.mu[idx], src.mu[c_pad + idx], src.mu[2 * c_pad + idx]};
         double S[6];
 #pragma unroll
-        for (int q = 0; q < 6; q++) S[q] = vS[q * c_pad + idx];
+        for (int q = 0; q < 6; q++) S[q] = src.S[q * c_pad + idx];
         Pose P;
         load_pose(poses, vpose[idx], P);
         double y[3], St[6];
         rot(P.r, mu, y);
         rot_sym(P.r, S, St);
-        const double d0 = (y[0] + P.t[0]) - a.r[0], d1 = (y[1] + P.t[1]) - a.r[1], d2 = (y[2] + P.t[2]) - a.r[2];
-        const double nd0 = nk * d0, nd1 = nk * d1, nd2 = nk * d2;
-        a.n += nk;
-        a.s0 += nd0; a.s1 += nd1; a.s2 += nd2;
-        a.M[0] += fma(nd0, d0, St[0]);
-        a.M[1] += fma(nd0, d1, St[1]);
-        a.M[2] += fma(nd0, d2, St[2]);
-        a.M[3] += fma(nd1, d1, St[3]);
-        a.M[4] += fma(nd1, d2, St[4]);
-        a.M[5] += fma(nd2, d2, St[5]);
+        const double d[3] = {(y[0] + P.t[0]) - a.r[0], (y[1] + P.t[1]) - a.r[1], (y[2] + P.t[2]) - a.r[2]};
+        vox_add(a, nk, d, St);
+    }
+}
+
+// FP32 storage: the reference is the voxel's reference point c.  With the
+// pose change (E, dt) of the cluster's scan, d = m - c = mu' + E mu' + b where
+// b = E (c - t0) + dt, and St = S' + D(E, S').  The arithmetic stays FP64:
+// the residual feeds the LM gain ratio, whose cost differences reach 1e-12
+// relative near convergence, below the noise of any FP32 product here.
+__device__ __forceinline__ void vox_accumulate(const GroupDesc &g, int64_t slot, int lane, int k0, int kstep,
+                                               int64_t c_pad, const SrcF32 &src, const int32_t *__restrict__ vpose,
+                                               const double *__restrict__ poses, VoxSums &a) {
+    vox_zero(a);
+    const double *c = src.ref + 4 * slot;
+    a.r[0] = c[0]; a.r[1] = c[1]; a.r[2] = c[2];
+#pragma unroll 2
+    for (int k = k0; k < g.m; k += kstep) {
+        const int64_t idx = g.cbase + 64LL * k + lane;
+        const double nk = (double)src.N[idx];
+        const double mu[3] = {(double)src.mu[idx], (double)src.mu[c_pad + idx], (double)src.mu[2 * c_pad + idx]};
+        double S[6];
+#pragma unroll
+        for (int q = 0; q < 6; q++) S[q] = (double)src.S[q * c_pad + idx];
+        const int j = vpose[idx];
+        Pose P, P0;
+        load_pose(poses, j, P);
+        load_pose(src.ref_poses, j, P0);
+        PoseDelta D;
+        pose_delta(P, P0, D);
+        const double q[3] = {a.r[0] - P0.t[0], a.r[1] - P0.t[1], a.r[2] - P0.t[2]};
+        double Em[3], Eq[3], Dl[6];
+        rot(D.E, mu, Em);
+        rot(D.E, q, Eq);
+        delta_sym(D.E, S, Dl);
+        const double d[3] = {mu[0] + (Em[0] + (Eq[0] + D.dt[0])), mu[1] + (Em[1] + (Eq[1] + D.dt[1])),
+                             mu[2] + (Em[2] + (Eq[2] + D.dt[2]))};
+        double St[6];
+#pragma unroll
+        for (int e = 0; e < 6; e++) St[e] = S[e] + Dl[e];
+        vox_add(a, nk, d, St);
     }
 }
 
@@ -105,152 +168,224 @@ __device__ __forceinline__ double vox_finish(const VoxSums &a, double *__restric
     return lam[0];
 }
 
-// Residual pass.  One block per group of 64 voxels with equal cluster count
-// (blocks ordered largest count first); the four waves split the group's
-// clusters (k = w, w + 4, ...) and wave 0 adds the partial sums in wave order.
-// (The LM decision runs as its own kernel: a last-block-done ticket would need
-// a device-scope fence per block, which writes back the XCD-private L2.)
-__global__ __launch_bounds__(256) void k_vox(const VoxBlock *__restrict__ blocks, const GroupDesc *__restrict__ groups,
-                                             int64_t c_pad, const double *__restrict__ vN,
-                                             const double *__restrict__ vmu, const double *__restrict__ vS,
+// Residual pass.  One work item per group of 64 voxels with equal cluster
+// count (items ordered largest count first); the block's `split` waves
+// (blockDim = 64 split) share the group's clusters (k = w, w + split, ...)
+// and wave 0 adds the partial sums in wave order.  With a persistent grid
+// (fewer blocks than items) each block walks the item list with a stride of
+// the grid size.  (The LM decision runs as its own kernel: a last-block-done
+// ticket would need a device-scope fence per block, which writes back the
+// XCD-private L2.)
+template <class Src>
+__global__ __launch_bounds__(256) void k_vox(const VoxBlock *__restrict__ blocks, int32_t n_blocks,
+                                             const GroupDesc *__restrict__ groups, int64_t c_pad, Src src,
                                              const int32_t *__restrict__ vpose, const double *__restrict__ poses,
                                              double *__restrict__ vstate, int64_t n_slots,
                                              const LMState *__restrict__ lm, int trial,
                                              double *__restrict__ group_cost) {
     __shared__ double part[3][10][64];
-    const VoxBlock b = blocks[blockIdx.x];
+    const int split = (int)(blockDim.x >> 6);
     const int w = threadIdx.x >> 6;
     const int lane = threadIdx.x & 63;
-    int buf = 0;
-    if (lm) {
-        const LMState &st = lm[b.window];
-        if (st.done) return;
-        buf = trial ? 1 - st.cur : st.cur;
-    }
-    double *vs = vstate + (int64_t)buf * n_slots * VSTATE;
-    const int gi = b.g0;
-    const GroupDesc g = groups[gi];
-    const bool active = lane < g.nvox;
-    VoxSums a;
-    a.n = a.s0 = a.s1 = a.s2 = 0.0;
-    for (int q = 0; q < 6; q++) a.M[q] = 0.0;
-    if (active && w < g.m) vox_accumulate(g, lane, w, 4, c_pad, vN, vmu, vS, vpose, poses, a);
-    if (w > 0) {
-        double *pp = &part[w - 1][0][0];
-        pp[lane] = a.n;
-        pp[64 + lane] = a.s0; pp[128 + lane] = a.s1; pp[192 + lane] = a.s2;
-#pragma unroll
-        for (int q = 0; q < 6; q++) pp[(4 + q) * 64 + lane] = a.M[q];
-    }
-    __syncthreads();
-    if (w == 0) {
-        double lam0 = 0.0;
-        if (active) {
-            for (int v = 0; v < 3; v++) {
-                const double *pp = &part[v][0][0];
-                a.n += pp[lane];
-                a.s0 += pp[64 + lane]; a.s1 += pp[128 + lane]; a.s2 += pp[192 + lane];
-#pragma unroll
-                for (int q = 0; q < 6; q++) a.M[q] += pp[(4 + q) * 64 + lane];
-            }
-            lam0 = vox_finish(a, vs + ((int64_t)gi * 64 + lane) * VSTATE);
+    for (int bi = blockIdx.x; bi < n_blocks; bi += gridDim.x) {
+        const VoxBlock b = blocks[bi];
+        int buf = 0;
+        if (lm) {
+            const LMState &st = lm[b.window];
+            if (st.done) continue;       // uniform over the block
+            buf = trial ? 1 - st.cur : st.cur;
         }
-        const double c = wave_sum(lam0);
-        if (lane == 0) group_cost[gi] = c;
+        double *vs = vstate + (int64_t)buf * n_slots * VSTATE;
+        const int gi = b.g0;
+        const GroupDesc g = groups[gi];
+        const bool active = lane < g.nvox;
+        VoxSums a;
+        vox_zero(a);
+        if (active && w < g.m) vox_accumulate(g, (int64_t)gi * 64 + lane, lane, w, split, c_pad, src, vpose, poses, a);
+        if (w > 0) {
+            double *pp = &part[w - 1][0][0];
+            pp[lane] = a.n;
+            pp[64 + lane] = a.s0; pp[128 + lane] = a.s1; pp[192 + lane] = a.s2;
+#pragma unroll
+            for (int q = 0; q < 6; q++) pp[(4 + q) * 64 + lane] = a.M[q];
+        }
+        __syncthreads();
+        if (w == 0) {
+            double lam0 = 0.0;
+            if (active) {
+                for (int v = 0; v < split - 1; v++) {
+                    const double *pp = &part[v][0][0];
+                    a.n += pp[lane];
+                    a.s0 += pp[64 + lane]; a.s1 += pp[128 + lane]; a.s2 += pp[192 + lane];
+#pragma unroll
+                    for (int q = 0; q < 6; q++) a.M[q] += pp[(4 + q) * 64 + lane];
+                }
+                lam0 = vox_finish(a, vs + ((int64_t)gi * 64 + lane) * VSTATE);
+            }
+            const double c = wave_sum(lam0);
+            if (lane == 0) group_cost[gi] = c;
+        }
+        __syncthreads();   // part[] is reused by the block's next item
     }
 }
 
+// Per-cluster surrogate gradient and Hessian terms (formulas in the header of
+// this file) in arithmetic T from y = R mu (lever arm), e = u^T (m - mbar)
+// (FP64), St and u, added into the FP64 accumulators with the voxel scale
+// sc = 2 / N_i.
+template <typename T>
+__device__ __forceinline__ void pose_terms(T n, const T *y, double e64, const T *St, const T *u, double sc,
+                                           double *acc) {
+    const T e = (T)e64;
+    T su[3];
+    sym_mv(St, u, su);
+    const T ne = n * e;
+    const T w[3] = {fmaT(ne, y[0], su[0]), fmaT(ne, y[1], su[1]), fmaT(ne, y[2], su[2])};
+    T wxu[3], a[3];
+    cross(w, u, wxu);
+    cross(y, u, a);
+    // gradient
+    acc[0] = fma(sc, (double)wxu[0], acc[0]);
+    acc[1] = fma(sc, (double)wxu[1], acc[1]);
+    acc[2] = fma(sc, (double)wxu[2], acc[2]);
+    const double sne = sc * ((double)n * e64);
+    acc[3] = fma(sne, (double)u[0], acc[3]);
+    acc[4] = fma(sne, (double)u[1], acc[4]);
+    acc[5] = fma(sne, (double)u[2], acc[5]);
+    // [u]x St [u]x^T : B = [u]x St, C = B [u]x^T
+    const T Sf[3][3] = {{St[0], St[1], St[2]}, {St[1], St[3], St[4]}, {St[2], St[4], St[5]}};
+    const T K[3][3] = {{T(0), -u[2], u[1]}, {u[2], T(0), -u[0]}, {-u[1], u[0], T(0)}};
+    T B[3][3];
+#pragma unroll
+    for (int r = 0; r < 3; r++)
+#pragma unroll
+        for (int c = 0; c < 3; c++) B[r][c] = K[r][0] * Sf[0][c] + K[r][1] * Sf[1][c] + K[r][2] * Sf[2][c];
+    T Cu[6];
+    Cu[0] = B[0][0] * K[0][0] + B[0][1] * K[0][1] + B[0][2] * K[0][2];
+    Cu[1] = B[0][0] * K[1][0] + B[0][1] * K[1][1] + B[0][2] * K[1][2];
+    Cu[2] = B[0][0] * K[2][0] + B[0][1] * K[2][1] + B[0][2] * K[2][2];
+    Cu[3] = B[1][0] * K[1][0] + B[1][1] * K[1][1] + B[1][2] * K[1][2];
+    Cu[4] = B[1][0] * K[2][0] + B[1][1] * K[2][1] + B[1][2] * K[2][2];
+    Cu[5] = B[2][0] * K[2][0] + B[2][1] * K[2][1] + B[2][2] * K[2][2];
+    const T uw = dot(u, w);
+    const int ii[6] = {0, 0, 0, 1, 1, 2}, jj[6] = {0, 1, 2, 1, 2, 2};
+#pragma unroll
+    for (int k = 0; k < 6; k++) {
+        const int r = ii[k], c = jj[k];
+        T h = n * a[r] * a[c] + Cu[k] + T(0.5) * (u[r] * w[c] + w[r] * u[c]);
+        if (r == c) h -= uw;
+        acc[6 + k] = fma(sc, (double)h, acc[6 + k]);
+    }
+    const double sn = sc * (double)n;
+#pragma unroll
+    for (int r = 0; r < 3; r++)
+#pragma unroll
+        for (int c = 0; c < 3; c++)
+            acc[12 + 3 * r + c] = fma(sn * (double)a[r], (double)u[c], acc[12 + 3 * r + c]);
+#pragma unroll
+    for (int k = 0; k < 6; k++) acc[21 + k] = fma(sn * (double)u[ii[k]], (double)u[jj[k]], acc[21 + k]);
+}
+
+// Pose context of a chunk: the pose, and for the FP32 form its reference
+// pose, the pose change (E, dt) and E rounded to FP32.
+struct PoseCtx {
+    Pose P, P0;
+    PoseDelta D;
+    float E[9];
+};
+
+__device__ __forceinline__ void pose_cluster(const SrcF64 &src, const PoseCtx &cx, int64_t q, int64_t C,
+                                             const double *st, int32_t slot, double *acc) {
+    const double n = src.N[q];
+    const double mu[3] = {src.mu[q], src.mu[C + q], src.mu[2 * C + q]};
+    double S[6];
+#pragma unroll
+    for (int k = 0; k < 6; k++) S[k] = src.S[k * C + q];
+    const double u[3] = {st[0], st[1], st[2]};
+    double y[3], St[6];
+    rot(cx.P.r, mu, y);
+    rot_sym(cx.P.r, S, St);
+    const double d[3] = {y[0] + cx.P.t[0] - st[3], y[1] + cx.P.t[1] - st[4], y[2] + cx.P.t[2] - st[5]};
+    pose_terms(n, y, dot(u, d), St, u, st[6], acc);
+}
+
+// FP32 form: with q = c - t0 and G = I + E the pose change,
+//   y = R mu = G mu' + G q,   d = m - mbar = G mu' + (E q + dt + c - mbar);
+// E mu' and St = S' + D(E, S') in FP32; y is rounded to FP32 once, and the
+// plane offset e = u^T d is formed in FP64.
+__device__ __forceinline__ void pose_cluster(const SrcF32 &src, const PoseCtx &cx, int64_t q, int64_t C,
+                                             const double *st, int32_t slot, double *acc) {
+    const float n = src.N[q];
+    const float mu[3] = {src.mu[q], src.mu[C + q], src.mu[2 * C + q]};
+    float S[6];
+#pragma unroll
+    for (int k = 0; k < 6; k++) S[k] = src.S[k * C + q];
+    const double *c = src.ref + 4LL * slot;
+    const double q0 = c[0] - cx.P0.t[0], q1 = c[1] - cx.P0.t[1], q2 = c[2] - cx.P0.t[2];
+    float Em[3], Dl[6];
+    rot(cx.E, mu, Em);
+    delta_sym(cx.E, S, Dl);
+    float y[3];
+    double e = 0.0;
+#pragma unroll
+    for (int i = 0; i < 3; i++) {
+        const double eq = fma(cx.D.E[3 * i], q0, fma(cx.D.E[3 * i + 1], q1, cx.D.E[3 * i + 2] * q2));
+        const double qi = i == 0 ? q0 : (i == 1 ? q1 : q2);
+        const double gm = (double)mu[i] + (double)Em[i];
+        y[i] = (float)(gm + (qi + eq));
+        // d_i in FP64: its normal component e is centimetres out of metres
+        e = fma(st[i], gm + ((eq + cx.D.dt[i]) + (c[i] - st[3 + i])), e);
+    }
+    const float u[3] = {(float)st[0], (float)st[1], (float)st[2]};
+    float St[6];
+#pragma unroll
+    for (int k = 0; k < 6; k++) St[k] = S[k] + Dl[k];
+    pose_terms(n, y, e, St, u, st[6], acc);
+}
+
+// Derivative pass: one wavefront per pose chunk.  With a persistent grid
+// each wave walks the chunk list with a stride of the number of waves.
+template <class Src>
 __global__ __launch_bounds__(256) void k_pose(const ChunkDesc *__restrict__ chunks, int32_t n_chunks, int64_t C,
-                                              const double *__restrict__ pN, const double *__restrict__ pmu,
-                                              const double *__restrict__ pS, const int32_t *__restrict__ pslot,
+                                              Src src, const int32_t *__restrict__ pslot,
                                               const double *__restrict__ poses, const double *__restrict__ vstate,
                                               int64_t n_slots, const int32_t *__restrict__ pose_window,
                                               const LMState *__restrict__ lm, double *__restrict__ partials) {
-    const int wave = (int)(((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6);
     const int lane = threadIdx.x & 63;
-    if (wave >= n_chunks) return;
-    const ChunkDesc ch = chunks[wave];
-    int buf = 0;
-    if (lm) {
-        const LMState &st = lm[pose_window[ch.pose]];
-        if (st.done || !st.need_eval) return;
-        buf = st.cur;
-    }
-    Pose P;
-    load_pose(poses, ch.pose, P);
-    const double *vs = vstate + (int64_t)buf * n_slots * VSTATE;
-    double acc[NPART];
-#pragma unroll
-    for (int q = 0; q < NPART; q++) acc[q] = 0.0;
-    for (int i = lane; i < ch.count; i += 64) {
-        const int64_t q = ch.start + i;
-        const double n = pN[q];
-        const double mu[3] = {pmu[q], pmu[C + q], pmu[2 * C + q]};
-        double S[6];
-#pragma unroll
-        for (int k = 0; k < 6; k++) S[k] = pS[k * C + q];
-        const double *st = vs + (int64_t)pslot[q] * VSTATE;
-        const double u[3] = {st[0], st[1], st[2]};
-        const double mb[3] = {st[3], st[4], st[5]};
-        const double sc = st[6];
-        double y[3], St[6];
-        rot(P.r, mu, y);
-        rot_sym(P.r, S, St);
-        const double d[3] = {y[0] + P.t[0] - mb[0], y[1] + P.t[1] - mb[1], y[2] + P.t[2] - mb[2]};
-        const double e = dot(u, d);
-        double su[3];
-        sym_mv(St, u, su);
-        const double ne = n * e;
-        const double w[3] = {fma(ne, y[0], su[0]), fma(ne, y[1], su[1]), fma(ne, y[2], su[2])};
-        double wxu[3], a[3];
-        cross(w, u, wxu);
-        cross(y, u, a);
-        // gradient
-        acc[0] = fma(sc, wxu[0], acc[0]);
-        acc[1] = fma(sc, wxu[1], acc[1]);
-        acc[2] = fma(sc, wxu[2], acc[2]);
-        const double sne = sc * ne;
-        acc[3] = fma(sne, u[0], acc[3]);
-        acc[4] = fma(sne, u[1], acc[4]);
-        acc[5] = fma(sne, u[2], acc[5]);
-        // [u]x St [u]x^T : B = [u]x St, C = B [u]x^T
-        const double Sf[3][3] = {{St[0], St[1], St[2]}, {St[1], St[3], St[4]}, {St[2], St[4], St[5]}};
-        const double K[3][3] = {{0.0, -u[2], u[1]}, {u[2], 0.0, -u[0]}, {-u[1], u[0], 0.0}};
-        double B[3][3];
-#pragma unroll
-        for (int r = 0; r < 3; r++)
-#pragma unroll
-            for (int c = 0; c < 3; c++) B[r][c] = K[r][0] * Sf[0][c] + K[r][1] * Sf[1][c] + K[r][2] * Sf[2][c];
-        double Cu[6];
-        Cu[0] = B[0][0] * K[0][0] + B[0][1] * K[0][1] + B[0][2] * K[0][2];
-        Cu[1] = B[0][0] * K[1][0] + B[0][1] * K[1][1] + B[0][2] * K[1][2];
-        Cu[2] = B[0][0] * K[2][0] + B[0][1] * K[2][1] + B[0][2] * K[2][2];
-        Cu[3] = B[1][0] * K[1][0] + B[1][1] * K[1][1] + B[1][2] * K[1][2];
-        Cu[4] = B[1][0] * K[2][0] + B[1][1] * K[2][1] + B[1][2] * K[2][2];
-        Cu[5] = B[2][0] * K[2][0] + B[2][1] * K[2][1] + B[2][2] * K[2][2];
-        const double uw = dot(u, w);
-        const int ii[6] = {0, 0, 0, 1, 1, 2}, jj[6] = {0, 1, 2, 1, 2, 2};
-#pragma unroll
-        for (int k = 0; k < 6; k++) {
-            const int r = ii[k], c = jj[k];
-            double h = n * a[r] * a[c] + Cu[k] + 0.5 * (u[r] * w[c] + w[r] * u[c]);
-            if (r == c) h -= uw;
-            acc[6 + k] = fma(sc, h, acc[6 + k]);
+    const int n_waves = (int)((gridDim.x * blockDim.x) >> 6);
+    for (int wave = (int)(((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6); wave < n_chunks;
+         wave += n_waves) {
+        const ChunkDesc ch = chunks[wave];
+        int buf = 0;
+        if (lm) {
+            const LMState &st = lm[pose_window[ch.pose]];
+            if (st.done || !st.need_eval) continue;   // uniform over the wave
+            buf = st.cur;
         }
-        const double sn = sc * n;
+        PoseCtx cx;
+        load_pose(poses, ch.pose, cx.P);
+        if constexpr (sizeof(*src.N) == 4) {
+            load_pose(src.ref_poses, ch.pose, cx.P0);
+            pose_delta(cx.P, cx.P0, cx.D);
 #pragma unroll
-        for (int r = 0; r < 3; r++)
+            for (int k = 0; k < 9; k++) cx.E[k] = (float)cx.D.E[k];
+        }
+        const double *vs = vstate + (int64_t)buf * n_slots * VSTATE;
+        double acc[NPART];
 #pragma unroll
-            for (int c = 0; c < 3; c++) acc[12 + 3 * r + c] = fma(sn * a[r], u[c], acc[12 + 3 * r + c]);
+        for (int q = 0; q < NPART; q++) acc[q] = 0.0;
+        for (int i = lane; i < ch.count; i += 64) {
+            const int64_t q = ch.start + i;
+            const int32_t slot = pslot[q];
+            pose_cluster(src, cx, q, C, vs + (int64_t)slot * VSTATE, slot, acc);
+        }
+        // reduce-scatter over the wave: lane l ends with the sum of value l / 2
+        double red[32];
 #pragma unroll
-        for (int k = 0; k < 6; k++) acc[21 + k] = fma(sn * u[ii[k]], u[jj[k]], acc[21 + k]);
+        for (int q = 0; q < 32; q++) red[q] = (q < NPART) ? acc[q] : 0.0;
+        const double v = wave_reduce_scatter32(red, lane);
+        if ((lane & 1) == 0 && (lane >> 1) < NPART) partials[(int64_t)wave * NPART + (lane >> 1)] = v;
     }
-    // reduce-scatter over the wave: lane l ends with the sum of value l / 2
-    double red[32];
-#pragma unroll
-    for (int q = 0; q < 32; q++) red[q] = (q < NPART) ? acc[q] : 0.0;
-    const double v = wave_reduce_scatter32(red, lane);
-    if ((lane & 1) == 0 && (lane >> 1) < NPART) partials[(int64_t)wave * NPART + (lane >> 1)] = v;
 }
 
 // One thread per (pose, component): fixed-order sum over the pose's chunks.
@@ -321,12 +456,34 @@ __global__ void k_voxel_eig(int64_t n_slots, const int32_t *__restrict__ slot_vo
 
 static inline unsigned nblk(int64_t n, int t = 256) { return (unsigned)((n + t - 1) / t); }
 
+static SrcF64 src64(const Problem *P, bool vox) {
+    return vox ? SrcF64{P->v_N, P->v_mu, P->v_S} : SrcF64{P->p_N, P->p_mu, P->p_S};
+}
+static SrcF32 src32(const Problem *P, bool vox) {
+    return vox ? SrcF32{P->v_N32, P->v_mu32, P->v_S32, P->ref_poses, P->v_ref}
+               : SrcF32{P->p_N32, P->p_mu32, P->p_S32, P->ref_poses, P->v_ref};
+}
+
+// Grid of a pass with `items` work items: one block per item, or a
+// persistent grid of `per_cu` blocks per compute unit.
+static unsigned pass_grid(int64_t items, int per_item_blocks_div, int per_cu, int n_cu) {
+    const int64_t full = (items + per_item_blocks_div - 1) / per_item_blocks_div;
+    if (per_cu <= 0) return (unsigned)std::max<int64_t>(full, 1);
+    return (unsigned)std::max<int64_t>(1, std::min<int64_t>(full, (int64_t)per_cu * n_cu));
+}
+
 void launch_vox(Problem *P, const double *poses, bool use_lm, bool trial, hipStream_t s) {
     if (P->n_vblocks == 0) return;
     ProfScope prof("k_vox", s);
-    hipLaunchKernelGGL(k_vox, dim3((unsigned)P->n_vblocks), dim3(256), 0, s, P->vblocks, P->groups, P->c_pad, P->v_N,
-                       P->v_mu, P->v_S, P->v_pose, poses, P->vstate, (int64_t)P->n_groups * 64,
-                       use_lm ? P->lm : nullptr, trial ? 1 : 0, P->wave_cost);
+    const int64_t ns = (int64_t)P->n_groups * 64;
+    const LMState *lm = use_lm ? P->lm : nullptr;
+    const dim3 grid(pass_grid(P->n_vblocks, 1, P->tune.vox_grid, P->n_cu)), block(64 * P->tune.vox_split);
+    if (P->prec == BA_PREC_F32)
+        hipLaunchKernelGGL(k_vox<SrcF32>, grid, block, 0, s, P->vblocks, P->n_vblocks, P->groups, P->c_pad,
+                           src32(P, true), P->v_pose, poses, P->vstate, ns, lm, trial ? 1 : 0, P->wave_cost);
+    else
+        hipLaunchKernelGGL(k_vox<SrcF64>, grid, block, 0, s, P->vblocks, P->n_vblocks, P->groups, P->c_pad,
+                           src64(P, true), P->v_pose, poses, P->vstate, ns, lm, trial ? 1 : 0, P->wave_cost);
 }
 
 void launch_window_cost(Problem *P, double *out, hipStream_t s) {
@@ -335,21 +492,21 @@ void launch_window_cost(Problem *P, double *out, hipStream_t s) {
 }
 
 void launch_pose_chunks(Problem *P, const double *poses, bool use_lm, hipStream_t s) {
-    if (P->n_chunks > 0) {
-        ProfScope prof("k_pose", s);
-        hipLaunchKernelGGL(k_pose, dim3(nblk((int64_t)P->n_chunks * 64)), dim3(256), 0, s, P->chunks, P->n_chunks,
-                           P->n_clusters, P->p_N, P->p_mu, P->p_S, P->p_slot, poses, P->vstate,
-                           (int64_t)P->n_groups * 64, P->pose_window, use_lm ? P->lm : nullptr, P->partials);
-    }
+    if (P->n_chunks == 0) return;
+    ProfScope prof("k_pose", s);
+    const int64_t ns = (int64_t)P->n_groups * 64;
+    const LMState *lm = use_lm ? P->lm : nullptr;
+    const dim3 grid(pass_grid(P->n_chunks, 4, P->tune.pose_grid, P->n_cu));
+    if (P->prec == BA_PREC_F32)
+        hipLaunchKernelGGL(k_pose<SrcF32>, grid, dim3(256), 0, s, P->chunks, P->n_chunks, P->n_clusters,
+                           src32(P, false), P->p_slot, poses, P->vstate, ns, P->pose_window, lm, P->partials);
+    else
+        hipLaunchKernelGGL(k_pose<SrcF64>, grid, dim3(256), 0, s, P->chunks, P->n_chunks, P->n_clusters,
+                           src64(P, false), P->p_slot, poses, P->vstate, ns, P->pose_window, lm, P->partials);
 }
 
 void launch_pose_derivs(Problem *P, const double *poses, bool use_lm, double *g, double *H, hipStream_t s) {
-    if (P->n_chunks > 0) {
-        ProfScope prof("k_pose", s);
-        hipLaunchKernelGGL(k_pose, dim3(nblk((int64_t)P->n_chunks * 64)), dim3(256), 0, s, P->chunks, P->n_chunks,
-                           P->n_clusters, P->p_N, P->p_mu, P->p_S, P->p_slot, poses, P->vstate,
-                           (int64_t)P->n_groups * 64, P->pose_window, use_lm ? P->lm : nullptr, P->partials);
-    }
+    launch_pose_chunks(P, poses, use_lm, s);
     hipLaunchKernelGGL(k_reduce_partials, dim3(nblk((int64_t)P->n_poses * NPART)), dim3(256), 0, s, P->n_poses,
                        P->chunk_ptr, P->partials, P->pose_window, use_lm ? P->lm : nullptr, g, H);
 }

@@ -5,6 +5,8 @@
 #include <stdint.h>
 #include <stddef.h>
 
+#include <vector>
+
 #include "ba.h"
 #include "ba_host.hpp"
 
@@ -65,8 +67,24 @@ struct DecideArgs {
 static constexpr int VSTATE = 8;    // doubles per voxel slot: u[3] mbar[3] 2/N lam0
 static constexpr int NPART = 27;    // g[6] + Hpp[6] + Hpt[9] + Htt[6]
 
+// Launch choices of the two evaluation passes (ba_tuning).
+struct Tuning {
+    int32_t vox_split = 4;   // waves sharing one 64-voxel group in the residual pass
+    int32_t vox_grid = 0;    // 0: one block per group; k > 0: persistent grid of k blocks per CU
+    int32_t pose_grid = 0;   // 0: one wave per chunk; k > 0: persistent grid of k blocks per CU
+    int32_t chunk_len = 256; // clusters per derivative-pass chunk
+};
+
+static constexpr int32_t MIN_CHUNK = 32;   // smallest chunk length the chunk tables are sized for
+
 struct Problem {
     int device = 0;
+    int n_cu = 256;              // compute units of the device
+    Tuning tune;
+    int32_t tune_gen = 0;        // bumped on every tuning change (captured graphs depend on it)
+    bool no_graph = false;       // ba_iterate launches eagerly (one-shot problems of the request server)
+    std::vector<int64_t> h_pose_start;   // [n_poses+1] pose ranges of the pose-major layout
+    int64_t chunk_cap = 0;       // capacity of chunks / partials (chunk descriptors)
     int32_t n_poses = 0, n_voxels_in = 0, n_windows = 1;
     int64_t n_clusters = 0;
     int32_t n_vox = 0;          // voxels with at least one cluster
@@ -75,6 +93,7 @@ struct Problem {
     int32_t n_chunks = 0;
     int32_t chunk_len = 0;      // max clusters per pose chunk
     int32_t max_m = 0;
+    int32_t prec = BA_PREC_F64;   // storage of the two iteration copies
 
     // K_vox layout (component-major SoA, length c_pad per component)
     double *v_mu = nullptr;     // [3][c_pad]
@@ -87,6 +106,12 @@ struct Problem {
     int32_t *slot_vox = nullptr; // slot -> input voxel id (-1 padding), n_groups*64
     double *vstate = nullptr;   // [2][n_groups*64][VSTATE]
     double *wave_cost = nullptr; // [n_groups]
+
+    // precision form: the same two layouts in FP32, voxel-centred
+    float *v_mu32 = nullptr, *v_S32 = nullptr, *v_N32 = nullptr;  // [3][c_pad], [6][c_pad], [c_pad]
+    float *p_mu32 = nullptr, *p_S32 = nullptr, *p_N32 = nullptr;  // [3][C], [6][C], [C]
+    double *v_ref = nullptr;      // [n_groups*64][4] reference point c_i of each voxel slot (xyz, pad)
+    double *ref_poses = nullptr;  // [n_poses][12] poses that placed the references
 
     // pose-sorted layout (length n_clusters per component)
     double *p_mu = nullptr;     // [3][C]
@@ -129,6 +154,8 @@ struct Problem {
     ~Problem();
 };
 
+ba_status replan_chunks(Problem *P, int32_t chunk_len, hipStream_t s);
+int64_t dense_device_bytes(const Problem *P);
 ba_status build_from_points(const ba_points *pts, const ba_build_options *opt, Problem *P, DevArena &keep,
                             hipStream_t s);
 ba_status build_from_sums(const ba_cluster_sums *cs, const ba_build_options *opt, Problem *P, DevArena &keep,
@@ -141,3 +168,8 @@ size_t radix_sort_workspace_bytes(int64_t n);
 hipError_t radix_sort_pairs(uint64_t *keys, uint32_t *vals, int64_t n, int bits, void *ws, hipStream_t s);
 
 }  // namespace ba
+
+// The opaque handle of the C-ABI.
+struct ba_problem {
+    ba::Problem P;
+};

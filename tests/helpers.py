@@ -59,3 +59,62 @@ def resolved_prefix(tr, rep_ref, rtol=1e-11, floor=None):
             break
         k += 1
     return k
+
+
+def grad_abs_scale(orc, cl, poses):
+    """G = || sum_i |g_i| ||_2: the summed absolute per-voxel gradient
+    contributions (the oracle evaluated one voxel at a time).  Relative
+    gradient errors are taken against G where the gradient itself cancels."""
+    ends = np.flatnonzero(np.diff(cl.vox)) + 1
+    starts = np.concatenate(([0], ends))
+    stops = np.concatenate((ends, [cl.C]))
+    acc = np.zeros(6 * cl.n_scans)
+    for a, b in zip(starts, stops):
+        sub = type(cl)(cl.vox[a:b].copy(), cl.scan[a:b].copy(), cl.n[a:b].copy(), cl.mu[a:b].copy(),
+                       cl.S[a:b].copy(), cl.n_voxels, cl.n_scans)
+        _, g, _, _ = orc.evaluate(orc.MM, sub, poses)
+        acc += np.abs(g)
+    return float(np.linalg.norm(acc))
+
+
+def pose_diff(Pa, Pb):
+    """(max rotation angle in rad, max translation difference) between pose sets."""
+    Ra = np.asarray(Pa)[:, :9].reshape(-1, 3, 3)
+    Rb = np.asarray(Pb)[:, :9].reshape(-1, 3, 3)
+    c = (np.einsum("nij,nij->n", Ra, Rb) - 1.0) / 2.0
+    ang = np.arccos(np.clip(c, -1.0, 1.0))
+    dt = np.abs(np.asarray(Pa)[:, 9:] - np.asarray(Pb)[:, 9:]).max()
+    return float(ang.max()), float(dt)
+
+
+def align_to(Pa, Pb):
+    """Pb moved by the one rigid motion G that maps its pose 0 onto Pa's pose 0
+    (G = T_a0 T_b0^-1): removes the 6-dimensional gauge freedom of the cost
+    before poses of two runs are compared."""
+    Pa = np.asarray(Pa); Pb = np.asarray(Pb)
+    Ra0 = Pa[0, :9].reshape(3, 3); ta0 = Pa[0, 9:]
+    Rb0 = Pb[0, :9].reshape(3, 3); tb0 = Pb[0, 9:]
+    Rg = Ra0 @ Rb0.T
+    tg = ta0 - Rg @ tb0
+    R = np.einsum("ij,njk->nik", Rg, Pb[:, :9].reshape(-1, 3, 3))
+    t = Pb[:, 9:] @ Rg.T + tg
+    return np.concatenate([R.reshape(-1, 9), t], axis=1)
+
+
+def build_gpu_sums(ba, sc, dev, **kw):
+    """Problem from a raw-sum scene (scenes.sums.SumsScene)."""
+    import torch
+    t = lambda a, dt: torch.as_tensor(np.ascontiguousarray(a), dtype=dt, device=dev)
+    if sc.n_windows > 1 and "scan_window" not in kw:
+        kw = dict(kw, n_windows=sc.n_windows, scan_window=sc.scan_window)
+    return ba.build_clusters_from_sums(t(sc.voxel, torch.int32), t(sc.scan, torch.int32),
+                                       t(sc.count, torch.int64), t(sc.sum, torch.float64),
+                                       t(sc.sumsq, torch.float64), sc.n_scans, sc.n_voxels, **kw)
+
+
+def oracle_clusters_from_sums(orc, sc):
+    """Oracle clusters of a raw-sum scene (the oracle centres the sums itself)."""
+    order = np.lexsort((sc.scan, sc.voxel))
+    mu, S = orc.center_raw_sums(sc.count[order], sc.sum[order], sc.sumsq[order])
+    return orc.Clusters(sc.voxel[order].astype(np.int32), sc.scan[order].astype(np.int32),
+                        sc.count[order].astype(np.int64), mu, S, sc.n_voxels, sc.n_scans)

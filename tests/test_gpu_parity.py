@@ -210,7 +210,17 @@ def test_iterate_mm_matches_oracle(ba, dev, orc, case, iters):
     # end state: the same minimum
     assert abs(reps[0]["cost_final"] - c_ref) <= TOL * max(c_ref, 1e-3 * rep_ref[0, 0])
     dP = np.abs(P.cpu().numpy() - P_ref)
-    ptol = 1e-11 if k == iters else 1e-8
+    if k == iters:
+        ptol = 1e-11
+    else:
+        # past the resolved prefix each side may accept or reject steps whose
+        # cost change is below the resolution c_res = 1e-11 c + 1e-12 c0, i.e.
+        # moves of up to sqrt(2 c_res / h_min) along the flattest direction
+        _, _, H_end, _ = orc.evaluate(orc.MM, cl, P_ref)
+        h_min = min(np.linalg.eigvalsh(Hj)[0] for Hj in H_end if np.any(Hj))
+        c_res = 1e-11 * c_ref + 1e-12 * rep_ref[0, 0]
+        ptol = 3.0 * np.sqrt(2.0 * c_res / h_min)
+        print(f"unresolved tail from iteration {k}: pose tolerance {ptol:.2e}, max difference {dP.max():.2e}")
     assert np.all(dP <= ptol * (1.0 + np.abs(P_ref)))
 
 

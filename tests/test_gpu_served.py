@@ -1,0 +1,133 @@
+"""GPU tests of the served form: the request server admits window problems
+by device-memory budget into concurrent slots and solves each to the
+gradient tolerance.
+
+Bar: every request's result (poses and LM report) is bitwise identical
+whether it is served alone or in a mix of concurrent requests; served
+results agree with the FP64 oracle at 1e-12 (cost at the returned poses);
+the footprint used for admission bounds the real device memory; a budget
+that fits one request at a time serialises the requests."""
+import numpy as np
+import pytest
+
+import scenes.sums as ss
+from helpers import build_gpu_sums, oracle_clusters_from_sums
+
+pytestmark = pytest.mark.gpu
+
+
+def say(msg):
+    print(f"[gpu-case] {msg}", flush=True)
+
+
+@pytest.fixture(scope="module")
+def dev():
+    import torch
+    d = torch.device("cuda:0")
+    torch.cuda.set_device(d)
+    return d
+
+
+@pytest.fixture(scope="module")
+def ba():
+    import os
+    from paper_2608_14266_amd import build as hb
+    if not os.path.exists(hb.LIB):
+        hb.build()
+    import paper_2608_14266_amd as m
+    m.load()
+    return m
+
+
+@pytest.fixture(scope="module")
+def requests():
+    sizes = [12, 30, 8, 45, 20, 16, 60, 10]
+    return [ss.request_scene(seed=5000 + i, n_poses=n, vox_per_pose=40) for i, n in enumerate(sizes)]
+
+
+GB = 1 << 30
+
+
+def _serve(ba, reqs, slots, budget, **kw):
+    with ba.Server(budget, slots=slots, **kw) as srv:
+        ids = [srv.submit_scene(r) for r in reqs]
+        return [srv.wait(i) for i in ids]
+
+
+@pytest.mark.parametrize("prec,mode", [("f64", "mm"), ("f32", "mm"), ("f64", "coupled")])
+def test_each_result_is_the_same_alone_and_in_the_mix(ba, dev, requests, prec, mode):
+    say(f"served alone vs mix {prec} {mode}")
+    kw = dict(precision=ba.PREC_F64 if prec == "f64" else ba.PREC_F32,
+              mode=ba.MODE_MM if mode == "mm" else ba.MODE_COUPLED,
+              max_iters=30 if mode == "mm" else 12, tol_g=1e-6)
+    alone = [_serve(ba, [r], 1, 8 * GB, **kw)[0] for r in requests]
+    mix = _serve(ba, requests, 4, 8 * GB, **kw)
+    overlap = 0
+    for (pa, sa), (pm, sm) in zip(alone, mix):
+        assert sa["state"] == sm["state"] == ba._lib.REQ_DONE
+        assert np.array_equal(pa, pm)
+        assert sa["report"] == sm["report"]
+    # the mix really ran requests side by side
+    iv = sorted((s["t_admit"], s["t_done"]) for _, s in mix)
+    overlap = sum(1 for a, b in zip(iv, iv[1:]) if b[0] < a[1])
+    print(f"  {prec}/{mode}: {overlap} overlapping admissions")
+    assert overlap >= 1
+
+
+def test_served_results_match_oracle(ba, dev, orc, requests):
+    say("served vs oracle")
+    res = _serve(ba, requests[:4], 4, 8 * GB, max_iters=40, tol_g=1e-6)
+    for r, (P, st) in zip(requests[:4], res):
+        cl = oracle_clusters_from_sums(orc, r)
+        c_ref = orc.cost(cl, P)
+        rep = st["report"]
+        assert abs(rep["cost_final"] - c_ref) <= 1e-12 * c_ref
+        assert rep["converged"] == 1 or rep["iters"] == 40
+        assert rep["cost_final"] < rep["cost_initial"]
+
+
+def test_budget_of_one_request_serialises(ba, dev, requests):
+    say("tiny budget")
+    fp = [ba.request_footprint(r.voxel, r.scan, r.count, r.sum, r.sumsq, r.n_scans, r.n_voxels, r.poses_init)
+          for r in requests]
+    budget = max(fp)            # fits any single request, never two of the largest
+    res = _serve(ba, requests, 4, budget, max_iters=10, tol_g=0.0)
+    iv = sorted((s["t_admit"], s["t_done"], s["footprint"]) for _, s in res)
+    # at every admission the reserved bytes stay within the budget
+    for a in iv:
+        live = sum(f for (s0, s1, f) in iv if s0 <= a[0] < s1)
+        assert live <= budget
+    alone = [_serve(ba, [r], 1, 8 * GB, max_iters=10, tol_g=0.0)[0] for r in requests]
+    for (pa, _), (pm, _) in zip(alone, res):
+        assert np.array_equal(pa, pm)
+
+
+def test_footprint_bounds_device_memory(ba, dev, requests):
+    import torch
+    say("footprint bound")
+    for r in requests[:3]:
+        for mode in (ba.MODE_MM, ba.MODE_COUPLED):
+            for prec in (ba.PREC_F64, ba.PREC_F32):
+                fp = ba.request_footprint(r.voxel, r.scan, r.count, r.sum, r.sumsq, r.n_scans, r.n_voxels,
+                                          r.poses_init, mode=mode, precision=prec)
+                kw = {} if prec == ba.PREC_F64 else dict(precision=prec,
+                                                          ref_poses=torch.as_tensor(r.poses_init, device=dev))
+                p = build_gpu_sums(ba, r, dev, **kw)
+                P = torch.as_tensor(r.poses_init, device=dev).contiguous()
+                ba.iterate(p, P, mode, max_iters=2)
+                used = p.info()["device_bytes"]
+                assert used <= fp, (mode, prec, used, fp)
+
+
+def test_over_budget_request_is_refused(ba, dev, requests):
+    with ba.Server(1 << 20, slots=2) as srv:
+        with pytest.raises(ba.BAError) as e:
+            srv.submit_scene(requests[0])
+        assert e.value.status == -7
+
+
+def test_unknown_request_id(ba, dev):
+    with ba.Server(GB, slots=1) as srv:
+        with pytest.raises(ba.BAError) as e:
+            srv.query(12345)
+        assert e.value.status == -8
