@@ -88,6 +88,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-precision-leg", action="store_true",
                     help="skip the FP32 precision-form run on the same workload")
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="after the run, copy a buffer of this many MiB device to device three times "
+                         "(a plain copy kernel of known size, to scale hardware byte counters)")
     args = ap.parse_args()
     if args.cpu_iters is None:
         args.cpu_iters = 20 if args.mode == "mm" else 1
@@ -300,6 +303,14 @@ def main():
         "precision_form": prec,
     }
     print(json.dumps(out), flush=True)
+    if args.calib_copy_mib > 0:
+        nb = args.calib_copy_mib << 20
+        src = torch.ones(nb // 4, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"calibration copy: 3 x {args.calib_copy_mib} MiB")
 
 
 if __name__ == "__main__":

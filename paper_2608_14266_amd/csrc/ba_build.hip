@@ -447,13 +447,25 @@ static ba_status make_plan(Problem *P, const std::vector<int32_t> &cvox, const s
         for (int32_t gi = win_group_ptr[w + 1] - 1; gi >= win_group_ptr[w]; gi--)
             vblocks.push_back(VoxBlock{gi, 1, 4, w});
     P->n_vblocks = (int32_t)vblocks.size();
-    // pose-major order: (scan, slot)
+    // pose-major order (scan, slot): a stable counting sort by scan of the
+    // clusters listed in slot order (a voxel's clusters have distinct scans)
     std::vector<int32_t> porder(C);
-    std::iota(porder.begin(), porder.end(), 0);
-    std::stable_sort(porder.begin(), porder.end(), [&](int32_t a, int32_t b) {
-        if (cscan[a] != cscan[b]) return cscan[a] < cscan[b];
-        return slot_of[a] < slot_of[b];
-    });
+    {
+        std::vector<int32_t> by_slot(C);
+        {
+            std::vector<int64_t> slot_first(P->n_groups * 64LL + 1, 0);
+            for (int64_t c = 0; c < C; c++) slot_first[slot_of[c] + 1]++;
+            for (size_t i = 1; i < slot_first.size(); i++) slot_first[i] += slot_first[i - 1];
+            for (int64_t c = 0; c < C; c++) by_slot[slot_first[slot_of[c]]++] = (int32_t)c;
+        }
+        std::vector<int64_t> scan_first(N + 1, 0);
+        for (int64_t c = 0; c < C; c++) scan_first[cscan[c] + 1]++;
+        for (int32_t j = 0; j < N; j++) scan_first[j + 1] += scan_first[j];
+        for (int64_t q = 0; q < C; q++) {
+            const int32_t c = by_slot[q];
+            porder[scan_first[cscan[c]]++] = c;
+        }
+    }
     P->h_pose_start.assign(N + 1, 0);
     {
         int64_t q = 0;

@@ -134,26 +134,23 @@ static constexpr int RS_BINS = 16;
 
 __device__ __forceinline__ int digit_of(uint64_t k, int shift) { return (int)((k >> shift) & (RS_BINS - 1)); }
 
-// per-thread digit counts into cnt[d][t]
-__device__ __forceinline__ void tile_counts(const uint64_t *__restrict__ keys, int64_t n, int shift,
-                                            uint32_t (*cnt)[RS_THREADS]) {
-    int t = threadIdx.x;
-#pragma unroll
-    for (int d = 0; d < RS_BINS; d++) cnt[d][t] = 0;
-    int64_t base = (int64_t)blockIdx.x * RS_TILE + (int64_t)t * RS_IPT;
-    for (int k = 0; k < RS_IPT; k++) {
-        int64_t i = base + k;
-        if (i < n) cnt[digit_of(keys[i], shift)][t]++;
-    }
-}
-
+// Tiles of RS_TILE keys; thread t of a block handles the items
+// tile + 256 k + t (k = 0..15), so every load and store row is coalesced.
 __global__ __launch_bounds__(RS_THREADS) void k_radix_hist(const uint64_t *__restrict__ keys, int64_t n, int shift,
                                                            int64_t *__restrict__ hist, int64_t nblocks) {
     __shared__ uint32_t cnt[RS_BINS][RS_THREADS];
-    tile_counts(keys, n, shift, cnt);
+    const int t = threadIdx.x;
+#pragma unroll
+    for (int d = 0; d < RS_BINS; d++) cnt[d][t] = 0;
+    const int64_t base = (int64_t)blockIdx.x * RS_TILE + t;
+#pragma unroll 4
+    for (int k = 0; k < RS_IPT; k++) {
+        const int64_t i = base + (int64_t)k * RS_THREADS;
+        if (i < n) cnt[digit_of(keys[i], shift)][t]++;
+    }
     __syncthreads();
     // 16 bins x 256 threads: wave w sums bins 4w..4w+3
-    int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int lane = t & 63, w = t >> 6;
     for (int d = 4 * w; d < 4 * w + 4; d++) {
         uint32_t s = cnt[d][lane] + cnt[d][lane + 64] + cnt[d][lane + 128] + cnt[d][lane + 192];
 #pragma unroll
@@ -162,49 +159,97 @@ __global__ __launch_bounds__(RS_THREADS) void k_radix_hist(const uint64_t *__res
     }
 }
 
+// Stable scatter of one tile: every item gets its rank among the tile's
+// items of the same digit (rows in order; within a row, wave ballots give
+// the rank among the wave's lanes and per-wave counts order the waves); the
+// tile is then laid out by digit in LDS and written to the output as
+// contiguous runs, one per digit.
 __global__ __launch_bounds__(RS_THREADS) void k_radix_scatter(const uint64_t *__restrict__ keys_in,
                                                               const uint32_t *__restrict__ vals_in, int64_t n,
                                                               int shift, const int64_t *__restrict__ gofs,
                                                               int64_t nblocks, uint64_t *__restrict__ keys_out,
                                                               uint32_t *__restrict__ vals_out) {
-    __shared__ uint32_t cnt[RS_BINS][RS_THREADS];
-    __shared__ int64_t lw[RS_THREADS / 64];
-    __shared__ uint32_t tstart[RS_BINS];
+    __shared__ uint64_t sk[RS_TILE];
+    __shared__ uint32_t sv[RS_TILE];
+    __shared__ uint32_t wcnt[RS_THREADS / 64][RS_BINS];
+    __shared__ uint32_t run[RS_BINS];
+    __shared__ uint32_t dstart[RS_BINS];
     __shared__ int64_t gbase[RS_BINS];
-    int t = threadIdx.x;
-    tile_counts(keys_in, n, shift, cnt);
-    if (t < RS_BINS) gbase[t] = gofs[(int64_t)t * nblocks + blockIdx.x];
-    __syncthreads();
-    // 2-D exclusive scan over flattened (d, t): thread k owns entries [16k, 16k+16)
-    uint32_t *flat = &cnt[0][0];
-    uint32_t loc[16];
-    uint32_t s = 0;
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    const int64_t tile0 = (int64_t)blockIdx.x * RS_TILE;
+    const int tile_n = (int)(n - tile0 < RS_TILE ? n - tile0 : RS_TILE);
+    const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    uint64_t key[RS_IPT];
+    uint32_t val[RS_IPT];
+    uint32_t rank[RS_IPT];
+    int dg[RS_IPT];
 #pragma unroll
-    for (int k = 0; k < 16; k++) {
-        loc[k] = flat[16 * t + k];
-        s += loc[k];
-    }
-    int64_t tot;
-    int64_t ex = block_excl_scan((int64_t)s, lw, tot);
-    uint32_t run = (uint32_t)ex;
-#pragma unroll
-    for (int k = 0; k < 16; k++) {
-        flat[16 * t + k] = run;
-        run += loc[k];
-    }
-    __syncthreads();
-    if (t < RS_BINS) tstart[t] = cnt[t][0];
-    __syncthreads();
-    int64_t base = (int64_t)blockIdx.x * RS_TILE + (int64_t)t * RS_IPT;
     for (int k = 0; k < RS_IPT; k++) {
-        int64_t i = base + k;
-        if (i < n) {
-            uint64_t key = keys_in[i];
-            int d = digit_of(key, shift);
-            uint32_t r = cnt[d][t]++;
-            int64_t pos = gbase[d] + (int64_t)(r - tstart[d]);
-            keys_out[pos] = key;
-            vals_out[pos] = vals_in[i];
+        const int64_t i = tile0 + (int64_t)k * RS_THREADS + t;
+        const bool ok = i < n;
+        key[k] = ok ? keys_in[i] : 0ull;
+        val[k] = ok ? vals_in[i] : 0u;
+        dg[k] = ok ? digit_of(key[k], shift) : RS_BINS;   // RS_BINS marks an empty slot
+        rank[k] = 0;
+    }
+    if (t < RS_BINS) {
+        run[t] = 0;
+        gbase[t] = gofs[(int64_t)t * nblocks + blockIdx.x];
+    }
+#pragma unroll
+    for (int k = 0; k < RS_IPT; k++) {
+        if (t < (RS_THREADS / 64) * RS_BINS) wcnt[t / RS_BINS][t % RS_BINS] = 0;
+        __syncthreads();
+        const int d = dg[k];
+        uint64_t same = ~0ull;
+#pragma unroll
+        for (int b = 0; b < 5; b++) {
+            const bool bit = (d >> b) & 1;
+            const uint64_t bal = __ballot(bit);
+            same &= bit ? bal : ~bal;
+        }
+        const uint32_t rw = (uint32_t)__popcll(same & lt_mask);
+        if (rw == 0 && d < RS_BINS) wcnt[w][d] = (uint32_t)__popcll(same);
+        __syncthreads();
+        if (d < RS_BINS) {
+            uint32_t off = run[d];
+            for (int v = 0; v < w; v++) off += wcnt[v][d];
+            rank[k] = off + rw;
+        }
+        __syncthreads();
+        if (t < RS_BINS) run[t] += wcnt[0][t] + wcnt[1][t] + wcnt[2][t] + wcnt[3][t];
+    }
+    __syncthreads();
+    if (t == 0) {
+        uint32_t a = 0;
+        for (int d = 0; d < RS_BINS; d++) {
+            dstart[d] = a;
+            a += run[d];
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < RS_IPT; k++) {
+        if (dg[k] < RS_BINS) {
+            const uint32_t p = dstart[dg[k]] + rank[k];
+            if (p < (uint32_t)RS_TILE) {
+                sk[p] = key[k];
+                sv[p] = val[k];
+            }
+        }
+    }
+    __syncthreads();
+#pragma unroll 4
+    for (int k = 0; k < RS_IPT; k++) {
+        const int j = k * RS_THREADS + t;
+        if (j < tile_n) {
+            const uint64_t kk = sk[j];
+            const int d = digit_of(kk, shift);
+            const int64_t pos = gbase[d] + (int64_t)(j - (int)dstart[d]);
+            if (pos >= 0 && pos < n) {
+                keys_out[pos] = kk;
+                vals_out[pos] = sv[j];
+            }
         }
     }
 }
