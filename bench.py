@@ -88,6 +88,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-precision-leg", action="store_true",
                     help="skip the FP32 precision-form run on the same workload")
+    ap.add_argument("--no-autotune", action="store_true", help="keep the default launch choices")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="after the run, copy a buffer of this many MiB device to device three times "
                          "(a plain copy kernel of known size, to scale hardware byte counters)")
@@ -141,6 +142,11 @@ def main():
     mode = ba.MODE_MM if args.mode == "mm" else ba.MODE_COUPLED
     P0 = f(sc.poses_init, torch.float64)
     P = P0.clone().contiguous()
+    tuning = None
+    if not args.no_autotune:
+        t0 = time.perf_counter()
+        tuning = ba.tuned(prob, P0, cache_path=None, reps=5)
+        log(f"autotuned in {time.perf_counter() - t0:.2f}s: {tuning}")
 
     def step():
         P.copy_(P0)
@@ -227,6 +233,7 @@ def main():
         P64_final = P.clone()
         prob32 = ba.build_clusters(xs, ys, zs, scan, vox, sc.n_scans, sc.n_voxels, precision=ba.PREC_F32,
                                    ref_poses=P0)
+        tuning32 = None if args.no_autotune else ba.tuned(prob32, P0, cache_path=None, reps=5)
         P32 = P0.clone().contiguous()
 
         def step32():
@@ -258,7 +265,7 @@ def main():
                 "cluster_bytes": inf32["cluster_bytes"], "device_bytes": inf32["device_bytes"],
                 "k_vox_avg_us": round(vox32_us, 3), "k_pose_avg_us": round(1e3 * p32_ms / max(p32_n, 1), 3),
                 "k_vox_gbs": round(vox32_bytes / (vox32_us * 1e-6) / 1e9, 2) if vox32_us > 0 else 0.0,
-                "final_cost": reps32[0]["cost_final"],
+                "final_cost": reps32[0]["cost_final"], "tuning": tuning32,
                 "final_cost_rel_diff_vs_f64": abs(reps32[0]["cost_final"] - reps[0]["cost_final"])
                 / reps[0]["cost_final"],
                 "pose_diff_vs_f64_gauge_aligned": {"rad": ang, "m": dt}}
@@ -295,6 +302,7 @@ def main():
         "lm_iters_per_s": lm_iters_s,
         "ms_per_step_eager_profiled": round(1e3 * (t3 - t2) / args.steps, 4),
         "build_ms": round(min(build_ms), 3),
+        "tuning": tuning,
         "kernels": {k: {kk: (round(vv, 3) if isinstance(vv, float) else vv) for kk, vv in d.items()}
                     for k, d in kern.items()},
         "roofline": roof,

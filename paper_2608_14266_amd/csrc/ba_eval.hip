@@ -120,7 +120,7 @@ __device__ __forceinline__ void vox_accumulate(const GroupDesc &g, int64_t slot,
     vox_zero(a);
     const double *c = src.ref + 4 * slot;
     a.r[0] = c[0]; a.r[1] = c[1]; a.r[2] = c[2];
-#pragma unroll 2
+#pragma unroll 1
     for (int k = k0; k < g.m; k += kstep) {
         const int64_t idx = g.cbase + 64LL * k + lane;
         const double nk = (double)src.N[idx];
@@ -168,64 +168,78 @@ __device__ __forceinline__ double vox_finish(const VoxSums &a, double *__restric
     return lam[0];
 }
 
-// Residual pass.  One work item per group of 64 voxels with equal cluster
-// count (items ordered largest count first); the block's `split` waves
-// (blockDim = 64 split) share the group's clusters (k = w, w + split, ...)
-// and wave 0 adds the partial sums in wave order.  With a persistent grid
-// (fewer blocks than items) each block walks the item list with a stride of
-// the grid size.  (The LM decision runs as its own kernel: a last-block-done
-// ticket would need a device-scope fence per block, which writes back the
-// XCD-private L2.)
-template <class Src>
-__global__ __launch_bounds__(256) void k_vox(const VoxBlock *__restrict__ blocks, int32_t n_blocks,
-                                             const GroupDesc *__restrict__ groups, int64_t c_pad, Src src,
-                                             const int32_t *__restrict__ vpose, const double *__restrict__ poses,
-                                             double *__restrict__ vstate, int64_t n_slots,
-                                             const LMState *__restrict__ lm, int trial,
-                                             double *__restrict__ group_cost) {
-    __shared__ double part[3][10][64];
-    const int split = (int)(blockDim.x >> 6);
+template <class Src, int SPLIT>
+__device__ __forceinline__ void vox_item(int bi, const VoxBlock *__restrict__ blocks,
+                                         const GroupDesc *__restrict__ groups, int64_t c_pad, const Src &src,
+                                         const int32_t *__restrict__ vpose, const double *__restrict__ poses,
+                                         double *__restrict__ vstate, int64_t n_slots,
+                                         const LMState *__restrict__ lm, int trial,
+                                         double *__restrict__ group_cost, double (*part)[10][64]) {
     const int w = threadIdx.x >> 6;
     const int lane = threadIdx.x & 63;
-    for (int bi = blockIdx.x; bi < n_blocks; bi += gridDim.x) {
-        const VoxBlock b = blocks[bi];
-        int buf = 0;
-        if (lm) {
-            const LMState &st = lm[b.window];
-            if (st.done) continue;       // uniform over the block
-            buf = trial ? 1 - st.cur : st.cur;
-        }
-        double *vs = vstate + (int64_t)buf * n_slots * VSTATE;
-        const int gi = b.g0;
-        const GroupDesc g = groups[gi];
-        const bool active = lane < g.nvox;
-        VoxSums a;
-        vox_zero(a);
-        if (active && w < g.m) vox_accumulate(g, (int64_t)gi * 64 + lane, lane, w, split, c_pad, src, vpose, poses, a);
-        if (w > 0) {
-            double *pp = &part[w - 1][0][0];
-            pp[lane] = a.n;
-            pp[64 + lane] = a.s0; pp[128 + lane] = a.s1; pp[192 + lane] = a.s2;
+    const VoxBlock b = blocks[bi];
+    int buf = 0;
+    if (lm) {
+        const LMState &st = lm[b.window];
+        if (st.done) return;       // uniform over the block
+        buf = trial ? 1 - st.cur : st.cur;
+    }
+    double *vs = vstate + (int64_t)buf * n_slots * VSTATE;
+    const int gi = b.g0;
+    const GroupDesc g = groups[gi];
+    const bool active = lane < g.nvox;
+    VoxSums a;
+    vox_zero(a);
+    if (active && w < g.m) vox_accumulate(g, (int64_t)gi * 64 + lane, lane, w, SPLIT, c_pad, src, vpose, poses, a);
+    if (SPLIT > 1 && w > 0) {
+        double *pp = &part[w - 1][0][0];
+        pp[lane] = a.n;
+        pp[64 + lane] = a.s0; pp[128 + lane] = a.s1; pp[192 + lane] = a.s2;
 #pragma unroll
-            for (int q = 0; q < 6; q++) pp[(4 + q) * 64 + lane] = a.M[q];
-        }
-        __syncthreads();
-        if (w == 0) {
-            double lam0 = 0.0;
-            if (active) {
-                for (int v = 0; v < split - 1; v++) {
-                    const double *pp = &part[v][0][0];
-                    a.n += pp[lane];
-                    a.s0 += pp[64 + lane]; a.s1 += pp[128 + lane]; a.s2 += pp[192 + lane];
+        for (int q = 0; q < 6; q++) pp[(4 + q) * 64 + lane] = a.M[q];
+    }
+    if (SPLIT > 1) __syncthreads();
+    if (w == 0) {
+        double lam0 = 0.0;
+        if (active) {
+            for (int v = 0; v < SPLIT - 1; v++) {
+                const double *pp = &part[v][0][0];
+                a.n += pp[lane];
+                a.s0 += pp[64 + lane]; a.s1 += pp[128 + lane]; a.s2 += pp[192 + lane];
 #pragma unroll
-                    for (int q = 0; q < 6; q++) a.M[q] += pp[(4 + q) * 64 + lane];
-                }
-                lam0 = vox_finish(a, vs + ((int64_t)gi * 64 + lane) * VSTATE);
+                for (int q = 0; q < 6; q++) a.M[q] += pp[(4 + q) * 64 + lane];
             }
-            const double c = wave_sum(lam0);
-            if (lane == 0) group_cost[gi] = c;
+            lam0 = vox_finish(a, vs + ((int64_t)gi * 64 + lane) * VSTATE);
         }
-        __syncthreads();   // part[] is reused by the block's next item
+        const double c = wave_sum(lam0);
+        if (lane == 0) group_cost[gi] = c;
+    }
+}
+
+// Residual pass.  One work item per group of 64 voxels with equal cluster
+// count (items ordered largest count first); the block's SPLIT waves share
+// the group's clusters (k = w, w + SPLIT, ...) and wave 0 adds the partial
+// sums in wave order.  With a persistent grid (PERSIST) each block walks the
+// item list with a stride of the grid size.  (The LM decision runs as its own
+// kernel: a last-block-done ticket would need a device-scope fence per block,
+// which writes back the XCD-private L2.)
+template <class Src, int SPLIT, bool PERSIST>
+__global__ __launch_bounds__(64 * SPLIT) void k_vox(const VoxBlock *__restrict__ blocks, int32_t n_blocks,
+                                                    const GroupDesc *__restrict__ groups, int64_t c_pad, Src src,
+                                                    const int32_t *__restrict__ vpose,
+                                                    const double *__restrict__ poses, double *__restrict__ vstate,
+                                                    int64_t n_slots, const LMState *__restrict__ lm, int trial,
+                                                    double *__restrict__ group_cost) {
+    __shared__ double part[SPLIT > 1 ? SPLIT - 1 : 1][10][64];
+    if constexpr (!PERSIST) {
+        vox_item<Src, SPLIT>((int)blockIdx.x, blocks, groups, c_pad, src, vpose, poses, vstate, n_slots, lm, trial,
+                             group_cost, part);
+    } else {
+        for (int bi = blockIdx.x; bi < n_blocks; bi += gridDim.x) {
+            vox_item<Src, SPLIT>(bi, blocks, groups, c_pad, src, vpose, poses, vstate, n_slots, lm, trial,
+                                 group_cost, part);
+            if (SPLIT > 1) __syncthreads();   // part[] is reused by the next item
+        }
     }
 }
 
@@ -343,9 +357,21 @@ __device__ __forceinline__ void pose_cluster(const SrcF32 &src, const PoseCtx &c
     pose_terms(n, y, e, St, u, st[6], acc);
 }
 
-// Derivative pass: one wavefront per pose chunk.  With a persistent grid
-// each wave walks the chunk list with a stride of the number of waves.
-template <class Src>
+// Block b of a launch runs on XCD b mod 8.  Renumbering the blocks so that
+// XCD x receives one contiguous range of the work list gives each XCD's L2
+// the chunks of neighbouring poses, which observe the same voxels: their
+// voxel-state lines are then fetched once per XCD instead of once per cluster.
+__device__ __forceinline__ int xcd_block(int b, int nb) {
+    constexpr int X = 8;
+    const int q = nb / X, r = nb % X;
+    const int x = b % X, i = b / X;
+    return x * q + min(x, r) + i;
+}
+
+// Derivative pass: one wavefront per pose chunk, blocks renumbered per XCD.
+// With a persistent grid each wave walks the chunk list with a stride of the
+// number of waves.
+template <class Src, bool PERSIST>
 __global__ __launch_bounds__(256) void k_pose(const ChunkDesc *__restrict__ chunks, int32_t n_chunks, int64_t C,
                                               Src src, const int32_t *__restrict__ pslot,
                                               const double *__restrict__ poses, const double *__restrict__ vstate,
@@ -353,8 +379,9 @@ __global__ __launch_bounds__(256) void k_pose(const ChunkDesc *__restrict__ chun
                                               const LMState *__restrict__ lm, double *__restrict__ partials) {
     const int lane = threadIdx.x & 63;
     const int n_waves = (int)((gridDim.x * blockDim.x) >> 6);
-    for (int wave = (int)(((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6); wave < n_chunks;
-         wave += n_waves) {
+    const int blk = xcd_block((int)blockIdx.x, (int)gridDim.x);
+    for (int wave = (int)(((int64_t)blk * blockDim.x + threadIdx.x) >> 6); wave < n_chunks;
+         wave += (PERSIST ? n_waves : n_chunks)) {
         const ChunkDesc ch = chunks[wave];
         int buf = 0;
         if (lm) {
@@ -374,6 +401,7 @@ __global__ __launch_bounds__(256) void k_pose(const ChunkDesc *__restrict__ chun
         double acc[NPART];
 #pragma unroll
         for (int q = 0; q < NPART; q++) acc[q] = 0.0;
+#pragma unroll 1
         for (int i = lane; i < ch.count; i += 64) {
             const int64_t q = ch.start + i;
             const int32_t slot = pslot[q];
@@ -477,13 +505,30 @@ void launch_vox(Problem *P, const double *poses, bool use_lm, bool trial, hipStr
     ProfScope prof("k_vox", s);
     const int64_t ns = (int64_t)P->n_groups * 64;
     const LMState *lm = use_lm ? P->lm : nullptr;
-    const dim3 grid(pass_grid(P->n_vblocks, 1, P->tune.vox_grid, P->n_cu)), block(64 * P->tune.vox_split);
-    if (P->prec == BA_PREC_F32)
-        hipLaunchKernelGGL(k_vox<SrcF32>, grid, block, 0, s, P->vblocks, P->n_vblocks, P->groups, P->c_pad,
-                           src32(P, true), P->v_pose, poses, P->vstate, ns, lm, trial ? 1 : 0, P->wave_cost);
-    else
-        hipLaunchKernelGGL(k_vox<SrcF64>, grid, block, 0, s, P->vblocks, P->n_vblocks, P->groups, P->c_pad,
-                           src64(P, true), P->v_pose, poses, P->vstate, ns, lm, trial ? 1 : 0, P->wave_cost);
+    const dim3 grid(pass_grid(P->n_vblocks, 1, P->tune.vox_grid, P->n_cu));
+    const int t = trial ? 1 : 0;
+    const bool pers = P->tune.vox_grid > 0;
+#define BA_VOX(SRC, SPL, MK)                                                                                       \
+    do {                                                                                                           \
+        if (pers)                                                                                                  \
+            hipLaunchKernelGGL((k_vox<SRC, SPL, true>), grid, dim3(64 * SPL), 0, s, P->vblocks, P->n_vblocks,      \
+                               P->groups, P->c_pad, MK(P, true), P->v_pose, poses, P->vstate, ns, lm, t,           \
+                               P->wave_cost);                                                                      \
+        else                                                                                                       \
+            hipLaunchKernelGGL((k_vox<SRC, SPL, false>), grid, dim3(64 * SPL), 0, s, P->vblocks, P->n_vblocks,     \
+                               P->groups, P->c_pad, MK(P, true), P->v_pose, poses, P->vstate, ns, lm, t,           \
+                               P->wave_cost);                                                                      \
+    } while (0)
+    if (P->prec == BA_PREC_F32) {
+        if (P->tune.vox_split == 1) BA_VOX(SrcF32, 1, src32);
+        else if (P->tune.vox_split == 2) BA_VOX(SrcF32, 2, src32);
+        else BA_VOX(SrcF32, 4, src32);
+    } else {
+        if (P->tune.vox_split == 1) BA_VOX(SrcF64, 1, src64);
+        else if (P->tune.vox_split == 2) BA_VOX(SrcF64, 2, src64);
+        else BA_VOX(SrcF64, 4, src64);
+    }
+#undef BA_VOX
 }
 
 void launch_window_cost(Problem *P, double *out, hipStream_t s) {
@@ -497,12 +542,18 @@ void launch_pose_chunks(Problem *P, const double *poses, bool use_lm, hipStream_
     const int64_t ns = (int64_t)P->n_groups * 64;
     const LMState *lm = use_lm ? P->lm : nullptr;
     const dim3 grid(pass_grid(P->n_chunks, 4, P->tune.pose_grid, P->n_cu));
-    if (P->prec == BA_PREC_F32)
-        hipLaunchKernelGGL(k_pose<SrcF32>, grid, dim3(256), 0, s, P->chunks, P->n_chunks, P->n_clusters,
-                           src32(P, false), P->p_slot, poses, P->vstate, ns, P->pose_window, lm, P->partials);
-    else
-        hipLaunchKernelGGL(k_pose<SrcF64>, grid, dim3(256), 0, s, P->chunks, P->n_chunks, P->n_clusters,
-                           src64(P, false), P->p_slot, poses, P->vstate, ns, P->pose_window, lm, P->partials);
+    const bool pers = P->tune.pose_grid > 0;
+#define BA_POSE(SRC, PER, MK)                                                                                      \
+    hipLaunchKernelGGL((k_pose<SRC, PER>), grid, dim3(256), 0, s, P->chunks, P->n_chunks, P->n_clusters,          \
+                       MK(P, false), P->p_slot, poses, P->vstate, ns, P->pose_window, lm, P->partials)
+    if (P->prec == BA_PREC_F32) {
+        if (pers) BA_POSE(SrcF32, true, src32);
+        else BA_POSE(SrcF32, false, src32);
+    } else {
+        if (pers) BA_POSE(SrcF64, true, src64);
+        else BA_POSE(SrcF64, false, src64);
+    }
+#undef BA_POSE
 }
 
 void launch_pose_derivs(Problem *P, const double *poses, bool use_lm, double *g, double *H, hipStream_t s) {
