@@ -1,6 +1,6 @@
 // Per-window Levenberg-Marquardt decision (reading of the unprinted
 // PredResReduction / Adjust of Alg. 2): gain ratio, damping update, commit of
-// accepted poses.  Executed by one 256-thread block per window.
+// accepted poses.  Executed by one 1024-thread block per window.
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -8,9 +8,12 @@
 
 namespace ba {
 
+static constexpr int DECIDE_THREADS = 1024;
+
 __device__ __forceinline__ void decide_window(int w, const DecideArgs &da) {
-    __shared__ double rq[256], rc[256];
-    __shared__ int ri[256];
+    constexpr int NW = DECIDE_THREADS / 64;
+    __shared__ double red[NW];
+    __shared__ int redi[NW];
     __shared__ int s_acc;
     LMState &st = da.lm[w];
     if (st.done) return;
@@ -18,29 +21,19 @@ __device__ __forceinline__ void decide_window(int w, const DecideArgs &da) {
     int info = 0x7fffffff;
     const int p0 = da.win_pose_ptr[w], p1 = da.win_pose_ptr[w + 1];
     const int g0 = da.win_group_ptr[w], g1 = da.win_group_ptr[w + 1];
-#pragma unroll 4
-    for (int j = p0 + threadIdx.x; j < p1; j += 256) {
+    for (int j = p0 + threadIdx.x; j < p1; j += DECIDE_THREADS) {
         q += da.pose_q[j];
         const int inf = da.pose_info[j];
         if (inf) info = min(info, inf);
     }
-#pragma unroll 8
-    for (int i = g0 + threadIdx.x; i < g1; i += 256) c += da.group_cost[i];
-    rq[threadIdx.x] = q;
-    rc[threadIdx.x] = c;
-    ri[threadIdx.x] = info;
-    __syncthreads();
-    for (int o = 128; o > 0; o >>= 1) {
-        if ((int)threadIdx.x < o) {
-            rq[threadIdx.x] += rq[threadIdx.x + o];
-            rc[threadIdx.x] += rc[threadIdx.x + o];
-            ri[threadIdx.x] = min(ri[threadIdx.x], ri[threadIdx.x + o]);
-        }
-        __syncthreads();
-    }
+#pragma unroll 4
+    for (int i = g0 + threadIdx.x; i < g1; i += DECIDE_THREADS) c += da.group_cost[i];
+    q = block_sum<NW>(q, red);
+    c = block_sum<NW>(c, red);
+    info = block_min_i<NW>(info, redi);
     if (threadIdx.x == 0) {
-        const double qq = rq[0], ct = rc[0];
-        const int inf = (ri[0] == 0x7fffffff) ? 0 : ri[0];
+        const double qq = q, ct = c;
+        const int inf = (info == 0x7fffffff) ? 0 : info;
         const double rho = (inf == 0 && qq > 0.0) ? (st.cost - ct) / qq : -1.0;
         const int acc = rho > 0.0;
         if (da.trace) {
@@ -72,8 +65,7 @@ __device__ __forceinline__ void decide_window(int w, const DecideArgs &da) {
     __syncthreads();
     if (s_acc) {
         const int64_t a = 12LL * p0, b = 12LL * p1;
-#pragma unroll 4
-        for (int64_t i = a + threadIdx.x; i < b; i += 256) da.poses[i] = da.poses_trial[i];
+        for (int64_t i = a + threadIdx.x; i < b; i += DECIDE_THREADS) da.poses[i] = da.poses_trial[i];
     }
 }
 

@@ -27,6 +27,45 @@ __device__ __forceinline__ int wave_min_i(int v) {
     return v;
 }
 
+// Block-wide reductions for blocks of 64 * NW threads: wave reductions, then
+// the wave results combined in wave order by every thread (fixed order, so
+// deterministic).  `lds` holds NW entries; the block synchronises twice.
+template <int NW>
+__device__ __forceinline__ double block_sum(double v, double *lds) {
+    v = wave_sum(v);
+    if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double s = 0.0;
+#pragma unroll
+    for (int i = 0; i < NW; i++) s += lds[i];
+    __syncthreads();
+    return s;
+}
+
+template <int NW>
+__device__ __forceinline__ double block_max(double v, double *lds) {
+    v = wave_max(v);
+    if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double s = lds[0];
+#pragma unroll
+    for (int i = 1; i < NW; i++) s = fmax(s, lds[i]);
+    __syncthreads();
+    return s;
+}
+
+template <int NW>
+__device__ __forceinline__ int block_min_i(int v, int *lds) {
+    v = wave_min_i(v);
+    if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = v;
+    __syncthreads();
+    int s = lds[0];
+#pragma unroll
+    for (int i = 1; i < NW; i++) s = min(s, lds[i]);
+    __syncthreads();
+    return s;
+}
+
 // Reduce-scatter of 32 per-lane values over a wave64: after five halving
 // exchanges and one final one, lane l holds the sum over all 64 lanes of
 // value l / 2 (fixed exchange order, so the result is deterministic).

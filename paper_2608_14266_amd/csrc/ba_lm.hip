@@ -125,34 +125,33 @@ __global__ __launch_bounds__(256) void k_lm_cost(int32_t W, const int32_t *__res
 }
 
 // block per window: ||g|| and max diag(H) at freshly evaluated poses; convergence test.
-__global__ __launch_bounds__(256) void k_window_stats(int32_t W, const int32_t *__restrict__ win_pose_ptr,
-                                                      const double *__restrict__ g, const double *__restrict__ H,
-                                                      LMState *__restrict__ lm, double tol_g) {
-    __shared__ double rs[256], rm[256];
+// Gradient norm and largest Hessian diagonal of every window whose
+// derivatives are fresh, in the order the fused MM solve forms them (per pose,
+// then the wave totals in wave order).
+__global__ __launch_bounds__(1024) void k_window_stats(int32_t W, const int32_t *__restrict__ win_pose_ptr,
+                                                       const double *__restrict__ g, const double *__restrict__ H,
+                                                       LMState *__restrict__ lm, double tol_g) {
+    constexpr int NW = 1024 / 64;
+    __shared__ double red[NW];
     const int w = blockIdx.x;
     if (w >= W) return;
     LMState &st = lm[w];
     if (st.done || !st.need_eval) return;
     double s = 0.0, m = 0.0;
     const int p0 = win_pose_ptr[w], p1 = win_pose_ptr[w + 1];
-    for (int i = 6 * p0 + threadIdx.x; i < 6 * p1; i += 256) {
-        s += g[i] * g[i];
-        const int j = i / 6, k = i % 6;
-        m = fmax(m, H[36LL * j + 7 * k]);
-    }
-    rs[threadIdx.x] = s;
-    rm[threadIdx.x] = m;
-    __syncthreads();
-    for (int o = 128; o > 0; o >>= 1) {
-        if ((int)threadIdx.x < o) {
-            rs[threadIdx.x] += rs[threadIdx.x + o];
-            rm[threadIdx.x] = fmax(rm[threadIdx.x], rm[threadIdx.x + o]);
+    for (int j = p0 + threadIdx.x; j < p1; j += 1024) {
+#pragma unroll
+        for (int k = 0; k < 6; k++) {
+            const double gk = g[6LL * j + k];
+            s = fma(gk, gk, s);
+            m = fmax(m, H[36LL * j + 7 * k]);
         }
-        __syncthreads();
     }
+    s = block_sum<NW>(s, red);
+    m = block_max<NW>(m, red);
     if (threadIdx.x == 0) {
-        st.gnorm = sqrt(rs[0]);
-        st.maxdiag = rm[0];
+        st.gnorm = sqrt(s);
+        st.maxdiag = m;
         st.need_eval = 0;
         if (tol_g > 0.0 && st.gnorm < tol_g) {
             st.done = 1;
@@ -179,7 +178,7 @@ __global__ void k_solve_mm_lm(int32_t n_poses, const int32_t *__restrict__ pose_
 }
 
 // block per window: predicted reduction, trial cost, gain ratio, damping update.
-__global__ __launch_bounds__(256) void k_decide(DecideArgs da) {
+__global__ __launch_bounds__(DECIDE_THREADS) void k_decide(DecideArgs da) {
     if ((int)blockIdx.x >= da.W) return;
     decide_window(blockIdx.x, da);
 }
@@ -196,13 +195,18 @@ __global__ void k_commit(int32_t n_poses, const int32_t *__restrict__ pose_windo
 // One block per window: (when the poses moved, after the per-pose partial
 // reduction) the window's gradient norm, damping floor and convergence test;
 // then every pose's damped 6x6 solve, predicted-reduction share and trial pose.
-__global__ __launch_bounds__(256) void k_window_solve_mm(int32_t W, const int32_t *__restrict__ win_pose_ptr,
-                                                         LMState *__restrict__ lm, const double *__restrict__ g,
-                                                         const double *__restrict__ H,
-                                                         const double *__restrict__ poses, double *__restrict__ dx,
-                                                         double *__restrict__ pose_q, int32_t *__restrict__ pose_info,
-                                                         double *__restrict__ poses_trial, double tol_g) {
-    __shared__ double rs[256], rm[256];
+// One 512-thread block per window: when the derivatives are fresh, the
+// window's gradient norm and largest Hessian diagonal (same order as
+// k_window_stats); then every pose's damped 6x6 system is solved and the
+// trial pose T (+) dx formed (one pose per thread for windows up to 512 poses).
+static constexpr int WSOLVE_THREADS = 512;
+
+__global__ __launch_bounds__(WSOLVE_THREADS) void k_window_solve_mm(
+    int32_t W, const int32_t *__restrict__ win_pose_ptr, LMState *__restrict__ lm, const double *__restrict__ g,
+    const double *__restrict__ H, const double *__restrict__ poses, double *__restrict__ dx,
+    double *__restrict__ pose_q, int32_t *__restrict__ pose_info, double *__restrict__ poses_trial, double tol_g) {
+    constexpr int NW = WSOLVE_THREADS / 64;
+    __shared__ double red[NW];
     __shared__ int s_done;
     const int w = blockIdx.x;
     if (w >= W) return;
@@ -211,24 +215,19 @@ __global__ __launch_bounds__(256) void k_window_solve_mm(int32_t W, const int32_
     const int p0 = win_pose_ptr[w], p1 = win_pose_ptr[w + 1];
     if (st.need_eval) {
         double gs = 0.0, mx = 0.0;
-        for (int i = 6 * p0 + threadIdx.x; i < 6 * p1; i += 256) {
-            const double gi = g[i];
-            gs += gi * gi;
-            mx = fmax(mx, H[36LL * (i / 6) + 7 * (i % 6)]);
-        }
-        rs[threadIdx.x] = gs;
-        rm[threadIdx.x] = mx;
-        __syncthreads();
-        for (int o = 128; o > 0; o >>= 1) {
-            if ((int)threadIdx.x < o) {
-                rs[threadIdx.x] += rs[threadIdx.x + o];
-                rm[threadIdx.x] = fmax(rm[threadIdx.x], rm[threadIdx.x + o]);
+        for (int j = p0 + threadIdx.x; j < p1; j += WSOLVE_THREADS) {
+#pragma unroll
+            for (int k = 0; k < 6; k++) {
+                const double gk = g[6LL * j + k];
+                gs = fma(gk, gk, gs);
+                mx = fmax(mx, H[36LL * j + 7 * k]);
             }
-            __syncthreads();
         }
+        gs = block_sum<NW>(gs, red);
+        mx = block_max<NW>(mx, red);
         if (threadIdx.x == 0) {
-            st.gnorm = sqrt(rs[0]);
-            st.maxdiag = rm[0];
+            st.gnorm = sqrt(gs);
+            st.maxdiag = mx;
             st.need_eval = 0;
             if (tol_g > 0.0 && st.gnorm < tol_g) {
                 st.done = 1;
@@ -240,7 +239,7 @@ __global__ __launch_bounds__(256) void k_window_solve_mm(int32_t W, const int32_
         if (s_done) return;
     }
     const double mu = st.mu, fl = 1e-12 * st.maxdiag;
-    for (int j = p0 + threadIdx.x; j < p1; j += 256) {
+    for (int j = p0 + threadIdx.x; j < p1; j += WSOLVE_THREADS) {
         double q;
         const int info = solve_pose(H + 36LL * j, g + 6LL * j, mu, fl, dx + 6LL * j, q);
         pose_q[j] = q;
@@ -250,8 +249,9 @@ __global__ __launch_bounds__(256) void k_window_solve_mm(int32_t W, const int32_
 }
 
 void launch_window_solve_mm(Problem *P, const double *poses, double tol_g, hipStream_t s) {
-    hipLaunchKernelGGL(k_window_solve_mm, dim3(P->n_windows), dim3(256), 0, s, P->n_windows, P->win_pose_ptr, P->lm,
-                       P->g, P->H, poses, P->dx, P->pose_q, P->pose_info, P->poses_trial, tol_g);
+    hipLaunchKernelGGL(k_window_solve_mm, dim3(P->n_windows), dim3(WSOLVE_THREADS), 0, s, P->n_windows,
+                       P->win_pose_ptr, P->lm, P->g, P->H, poses, P->dx, P->pose_q, P->pose_info, P->poses_trial,
+                       tol_g);
 }
 
 // ---------------------------------------------------------------- standalone MM solve
@@ -321,7 +321,7 @@ void launch_lm_cost(Problem *P, hipStream_t s) {
 }
 
 void launch_window_stats(Problem *P, double tol_g, hipStream_t s) {
-    hipLaunchKernelGGL(k_window_stats, dim3(P->n_windows), dim3(256), 0, s, P->n_windows, P->win_pose_ptr, P->g,
+    hipLaunchKernelGGL(k_window_stats, dim3(P->n_windows), dim3(1024), 0, s, P->n_windows, P->win_pose_ptr, P->g,
                        P->H, P->lm, tol_g);
 }
 
@@ -348,7 +348,7 @@ DecideArgs decide_args(Problem *P, double *trace, int it, double *poses) {
 
 void launch_decide(Problem *P, double *trace, int it, double *poses, hipStream_t s) {
     DecideArgs da = decide_args(P, trace, it, poses);
-    hipLaunchKernelGGL(k_decide, dim3(P->n_windows), dim3(256), 0, s, da);
+    hipLaunchKernelGGL(k_decide, dim3(P->n_windows), dim3(DECIDE_THREADS), 0, s, da);
 }
 
 void launch_commit(Problem *P, double *poses, hipStream_t s) {
