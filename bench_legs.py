@@ -321,16 +321,28 @@ def served(args):
     sps = R / (last - first)
     sps64 = R / (finish[-1] - arrivals[0])
     conv = sum(1 for _, s in served32 if s["report"]["converged"])
+    conv64 = sum(1 for _, s in serial if s["report"]["converged"])
+    stall = sum(1 for _, s in served32 if s["report"]["stalled"])
+    stall64 = sum(1 for _, s in serial if s["report"]["stalled"])
+    g32 = np.array([s["report"]["gnorm_final"] for _, s in served32])
+    g64 = np.array([s["report"]["gnorm_final"] for _, s in serial])
+    it32 = np.array([s["report"]["iters"] for _, s in served32])
+    it64 = np.array([s["report"]["iters"] for _, s in serial])
     return {"metric": "window-BA solve latency p50/p99 (served)", "value": float(np.percentile(lat, 99) * 1e3),
             "unit": "ms (p99)", "n_gpus": 1, "higher_is_better": False, "dtype": "f32 clusters / f64 solve",
             "data": "synthetic",
             "config": {"workload": f"served Poisson {args.rate:g} req/s, {R} requests of 20..1000 poses "
-                                   f"(~400 planes per pose), solve to ||g|| < 1e-6 or 50 iterations ({args.mode})",
+                                   f"(~400 planes per pose), solve to ||g|| < 1e-6, 10 rejections in a row "
+                                   f"or 50 iterations ({args.mode})",
                        "slots": args.slots, "hbm_budget_bytes": budget},
             "served_f32": {"p50_ms": float(np.percentile(lat, 50) * 1e3), "p99_ms": float(np.percentile(lat, 99) * 1e3),
-                           "solves_per_s": sps, "converged": conv},
+                           "solves_per_s": sps, "converged": conv, "stalled": stall, "iters_mean": float(it32.mean()),
+                           "gnorm_final_median": float(np.median(g32)), "gnorm_final_max": float(g32.max())},
             "serial_plain_f64": {"p50_ms": float(np.percentile(lat64, 50) * 1e3),
                                  "p99_ms": float(np.percentile(lat64, 99) * 1e3), "solves_per_s": sps64,
-                                 "mean_service_ms": float(service.mean() * 1e3)},
+                                 "mean_service_ms": float(service.mean() * 1e3), "converged": conv64,
+                                 "stalled": stall64,
+                                 "iters_mean": float(it64.mean()), "gnorm_final_median": float(np.median(g64)),
+                                 "gnorm_final_max": float(g64.max())},
             "accuracy": {"served_f32_vs_serial_f64_pose_diff": {"rad": worst_rad, "m": worst_m},
                          "ape_rel_diff_max": ape_rel}}

@@ -114,6 +114,8 @@ typedef struct ba_lm_options {
     double mu0;          /* initial damping (0 -> 1e-2) */
     double nu0;          /* initial damping growth (0 -> 2) */
     double tol_g;        /* stop a window once ||g||_2 < tol_g at its current poses (<= 0: never) */
+    int32_t max_rejects; /* stop a window after this many rejected steps in a row (<= 0: never) */
+    int32_t reserved;    /* 0 */
 } ba_lm_options;
 
 typedef struct ba_lm_report {  /* one per window */
@@ -125,6 +127,8 @@ typedef struct ba_lm_report {  /* one per window */
     double cost_final;
     double gnorm_final;   /* ||g|| at the last evaluated point */
     double mu_final;
+    int32_t stalled;      /* stopped after max_rejects rejections in a row */
+    int32_t reserved;
 } ba_lm_report;
 
 /* Launch choices of the two evaluation passes.  They change the order in

@@ -776,14 +776,16 @@ void orc_apply_increment(int32_t Np, const double *poses, const double *dx, doub
  *   otherwise (including a failed factorization): mu <- mu nu, nu <- 2 nu.
  * One iteration = one solve, accepted or not.  The loop stops after
  * max_iters iterations, or earlier when ||g||_2 < tol_g at an accepted point
- * (tol_g <= 0 disables that).
+ * (tol_g <= 0 disables that), or after max_rejects rejections in a row
+ * (max_rejects <= 0 disables that): near the optimum the predicted reduction
+ * falls below the resolution of the cost and no step can be confirmed.
  * report (may be NULL) holds 8 doubles per iteration:
  *   [cost, cost_trial, rho, mu_used, accepted, gnorm, info, q]
  * Returns the number of iterations run; final cost in *cost_final.
  */
 int orc_lm(int mode, int64_t C, const int32_t *vox, const int32_t *scan, const int64_t *n, const double *mu_c,
            const double *S, int32_t V, int32_t Np, double *poses, int max_iters, double mu0, double nu0,
-           double tol_g, double *report, double *cost_final) {
+           double tol_g, int max_rejects, double *report, double *cost_final) {
     int64_t D = 6 * (int64_t)Np;
     size_t hsz = (mode == ORC_MM) ? 36 * (size_t)Np : (size_t)(D * D);
     double *g = (double *)malloc(sizeof(double) * (size_t)D);
@@ -791,8 +793,9 @@ int orc_lm(int mode, int64_t C, const int32_t *vox, const int32_t *scan, const i
     double *dx = (double *)malloc(sizeof(double) * (size_t)D);
     double *trial = (double *)malloc(sizeof(double) * 12 * (size_t)Np);
     double lm_mu = mu0, nu = nu0, cost = 0.0;
-    int need_eval = 1, it;
+    int need_eval = 1, it, rejects = 0;
     for (it = 0; it < max_iters; it++) {
+        if (max_rejects > 0 && rejects >= max_rejects) break;
         if (need_eval) {
             if (orc_eval(mode, C, vox, scan, n, mu_c, S, V, Np, poses, &cost, g, H, NULL)) break;
             need_eval = 0;
@@ -831,9 +834,11 @@ int orc_lm(int mode, int64_t C, const int32_t *vox, const int32_t *scan, const i
             lm_mu *= (fac > 1.0 / 3.0 ? fac : 1.0 / 3.0);
             nu = 2.0;
             need_eval = 1;
+            rejects = 0;
         } else {
             lm_mu *= nu;
             nu *= 2.0;
+            rejects++;
         }
     }
     if (need_eval) cost = orc_cost(C, vox, scan, n, mu_c, S, V, Np, poses);

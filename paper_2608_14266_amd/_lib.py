@@ -51,7 +51,7 @@ class _Info(ct.Structure):
 
 class _LMOpts(ct.Structure):
     _fields_ = [("mode", ct.c_int32), ("max_iters", ct.c_int32), ("mu0", ct.c_double), ("nu0", ct.c_double),
-                ("tol_g", ct.c_double)]
+                ("tol_g", ct.c_double), ("max_rejects", ct.c_int32), ("reserved", ct.c_int32)]
 
 
 class _Tuning(ct.Structure):
@@ -73,7 +73,8 @@ class _Request(ct.Structure):
 class _LMReport(ct.Structure):
     _fields_ = [("iters", ct.c_int32), ("n_accepted", ct.c_int32), ("converged", ct.c_int32),
                 ("last_info", ct.c_int32), ("cost_initial", ct.c_double), ("cost_final", ct.c_double),
-                ("gnorm_final", ct.c_double), ("mu_final", ct.c_double)]
+                ("gnorm_final", ct.c_double), ("mu_final", ct.c_double), ("stalled", ct.c_int32),
+                ("reserved", ct.c_int32)]
 
 
 class _ReqStatus(ct.Structure):
@@ -313,13 +314,13 @@ def solve_increment(mode: int, hess, grad, mu: float):
 
 
 def iterate(problem: Problem, poses, mode: int = MODE_MM, max_iters: int = 10, mu0: float = 1e-2,
-            nu0: float = 2.0, tol_g: float = 0.0, trace: bool = True):
+            nu0: float = 2.0, tol_g: float = 0.0, trace: bool = True, max_rejects: int = 0):
     """ba_iterate: LM on the device, poses updated in place.  Synchronous.
     Returns (reports: list of dicts per window, trace ndarray (iters, W, 8) or None)."""
     if not (poses.is_cuda and poses.dtype == torch.float64 and poses.is_contiguous()):
         raise TypeError("poses must be a contiguous float64 device tensor (updated in place)")
     W = problem.info()["n_windows"]
-    o = _LMOpts(int(mode), int(max_iters), float(mu0), float(nu0), float(tol_g))
+    o = _LMOpts(int(mode), int(max_iters), float(mu0), float(nu0), float(tol_g), int(max_rejects), 0)
     reps = (_LMReport * W)()
     tr = np.zeros((max(int(max_iters), 1), W, 8)) if trace else None
     trp = tr.ctypes.data_as(ct.c_void_p) if trace else ct.c_void_p(0)
@@ -403,12 +404,13 @@ class Server:
     clusters; results are host poses and an LM report."""
 
     def __init__(self, hbm_budget: int, slots: int = 4, precision: int = PREC_F64, mode: int = MODE_MM,
-                 max_iters: int = 50, tol_g: float = 1e-6, mu0: float = 0.0, nu0: float = 0.0):
+                 max_iters: int = 50, tol_g: float = 1e-6, mu0: float = 0.0, nu0: float = 0.0,
+                 max_rejects: int = 10):
         o = _ServerOpts()
         o.hbm_budget = int(hbm_budget)
         o.slots = int(slots)
         o.precision = int(precision)
-        o.lm = _LMOpts(int(mode), int(max_iters), float(mu0), float(nu0), float(tol_g))
+        o.lm = _LMOpts(int(mode), int(max_iters), float(mu0), float(nu0), float(tol_g), int(max_rejects), 0)
         h = ct.c_void_p()
         _check(load().ba_server_create(ct.byref(o), ct.byref(h)))
         self._h = h

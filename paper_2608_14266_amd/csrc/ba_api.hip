@@ -136,17 +136,17 @@ static ba_status enqueue_lm(Problem *P, double *poses, const ba_lm_options *opt,
             launch_pose_derivs(P, poses, true, P->g, P->H, s);
             launch_window_solve_mm(P, poses, opt->tol_g, s);
         } else {
-            launch_pose_derivs(P, poses, true, P->g, P->H, s);
+            launch_pose_derivs(P, poses, true, P->g, P->H, s, true);
             BA_TRY(dense_assemble(P, poses, nullptr, true, s));
             BA_TRY(dense_lm_step(P, poses, opt->tol_g, s));
         }
         // trial residual, then the per-window decision and commit
         launch_vox(P, P->poses_trial, true, true, s);
-        launch_decide(P, dtrace, it, poses, s);
+        launch_decide(P, dtrace, it, poses, s, opt->max_rejects);
     }
     // derivatives at the final poses (windows whose last step was accepted),
     // so that the reported gradient norm belongs to the returned poses
-    launch_pose_derivs(P, poses, true, P->g, P->H, s);
+    launch_pose_derivs(P, poses, true, P->g, P->H, s, opt->mode == BA_MODE_COUPLED);
     launch_window_stats(P, opt->tol_g, s);
     BA_HIP(hipGetLastError());
     return BA_OK;
@@ -157,7 +157,7 @@ struct IterGraph {
     hipGraphExec_t exec = nullptr;
     // key
     double *poses = nullptr, *trace = nullptr;
-    int32_t mode = -1, iters = -1, tune_gen = -1;
+    int32_t mode = -1, iters = -1, tune_gen = -1, max_rejects = 0;
     double mu0 = 0, nu0 = 0, tol_g = 0;
     ~IterGraph() {
         if (exec) (void)hipGraphExecDestroy(exec);
@@ -351,7 +351,8 @@ ba_status ba_eval_residual_grad_hessian(ba_problem *p, const double *poses, int3
     if (voxel_eig) launch_voxel_eig(P, voxel_eig, stream);
     if (grad) {
         double *Hmm = (mode == BA_MODE_MM) ? hess : P->H;
-        launch_pose_derivs(P, poses, false, grad, Hmm, stream);
+        if (mode == BA_MODE_COUPLED) BA_TRY(dense_prepare(P));   // the derivative pass may fill its h vectors
+        launch_pose_derivs(P, poses, false, grad, Hmm, stream, mode == BA_MODE_COUPLED);
         if (mode == BA_MODE_COUPLED) BA_TRY(dense_assemble(P, poses, hess, false, stream));
     }
     BA_HIP(hipGetLastError());
@@ -423,7 +424,7 @@ ba_status ba_iterate(ba_problem *p, double *poses_inout, const ba_lm_options *op
         IterGraph *G = (IterGraph *)P->iter_graph;
         const bool same = G && G->exec && G->poses == poses_inout && G->trace == dtrace && G->mode == opt->mode &&
                           G->iters == iters && G->mu0 == mu0 && G->nu0 == nu0 && G->tol_g == opt->tol_g &&
-                          G->tune_gen == P->tune_gen;
+                          G->tune_gen == P->tune_gen && G->max_rejects == opt->max_rejects;
         if (!same) {
             graph_release(P);
             G = new IterGraph();
@@ -448,6 +449,7 @@ ba_status ba_iterate(ba_problem *p, double *poses_inout, const ba_lm_options *op
                 G->nu0 = nu0;
                 G->tol_g = opt->tol_g;
                 G->tune_gen = P->tune_gen;
+                G->max_rejects = opt->max_rejects;
             } else {
                 graph_release(P);
                 G = nullptr;
@@ -467,7 +469,9 @@ ba_status ba_iterate(ba_problem *p, double *poses_inout, const ba_lm_options *op
         for (int w = 0; w < W; w++) {
             rep[w].iters = st[w].iters;
             rep[w].n_accepted = st[w].n_accepted;
-            rep[w].converged = st[w].done;
+            rep[w].converged = st[w].done == 1;
+            rep[w].stalled = st[w].done == 2;
+            rep[w].reserved = 0;
             rep[w].last_info = st[w].info;
             rep[w].cost_final = st[w].cost;
             rep[w].gnorm_final = st[w].gnorm;

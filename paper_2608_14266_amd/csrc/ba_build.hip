@@ -514,6 +514,7 @@ static ba_status make_plan(Problem *P, const std::vector<int32_t> &cvox, const s
         BA_TRY(keep.alloc(&P->p_N, C));
     }
     BA_TRY(keep.alloc(&P->p_slot, C));
+    BA_TRY(keep.alloc(&P->p_cidx, C));
     BA_TRY(keep.alloc(&P->chunks, P->chunk_cap));
     BA_TRY(keep.alloc(&P->chunk_ptr, N + 1));
     BA_TRY(keep.alloc(&P->partials, P->chunk_cap * NPART));
@@ -556,6 +557,7 @@ static ba_status make_plan(Problem *P, const std::vector<int32_t> &cvox, const s
     BA_HIP(hipMemcpyAsync(d_dst, dst.data(), sizeof(int64_t) * C, hipMemcpyHostToDevice, s));
     BA_HIP(hipMemcpyAsync(d_slot_of, slot_of.data(), sizeof(int32_t) * C, hipMemcpyHostToDevice, s));
     BA_HIP(hipMemcpyAsync(d_porder, porder.data(), sizeof(int32_t) * C, hipMemcpyHostToDevice, s));
+    BA_HIP(hipMemcpyAsync(P->p_cidx, porder.data(), sizeof(int32_t) * C, hipMemcpyHostToDevice, s));
     hipLaunchKernelGGL(k_scatter_vox, dim3(nblk(C)), dim3(256), 0, s, C, d_dst, CP, P->c_N, P->c_mu, P->c_S,
                        P->c_scan, P->v_N, P->v_mu, P->v_S, P->v_pose);
     if (!f32) {

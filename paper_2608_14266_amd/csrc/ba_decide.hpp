@@ -10,6 +10,16 @@ namespace ba {
 
 static constexpr int DECIDE_THREADS = 1024;
 
+// Sum of a window's group residuals [g0, g1) by a DECIDE_THREADS block, in
+// one fixed order (used for the current, the trial and the reported cost).
+__device__ __forceinline__ double window_cost_sum(int g0, int g1, const double *__restrict__ group_cost,
+                                                  double *red) {
+    double c = 0.0;
+#pragma unroll 4
+    for (int i = g0 + threadIdx.x; i < g1; i += DECIDE_THREADS) c += group_cost[i];
+    return block_sum<DECIDE_THREADS / 64>(c, red);
+}
+
 __device__ __forceinline__ void decide_window(int w, const DecideArgs &da) {
     constexpr int NW = DECIDE_THREADS / 64;
     __shared__ double red[NW];
@@ -17,7 +27,7 @@ __device__ __forceinline__ void decide_window(int w, const DecideArgs &da) {
     __shared__ int s_acc;
     LMState &st = da.lm[w];
     if (st.done) return;
-    double q = 0.0, c = 0.0;
+    double q = 0.0, c;
     int info = 0x7fffffff;
     const int p0 = da.win_pose_ptr[w], p1 = da.win_pose_ptr[w + 1];
     const int g0 = da.win_group_ptr[w], g1 = da.win_group_ptr[w + 1];
@@ -26,10 +36,8 @@ __device__ __forceinline__ void decide_window(int w, const DecideArgs &da) {
         const int inf = da.pose_info[j];
         if (inf) info = min(info, inf);
     }
-#pragma unroll 4
-    for (int i = g0 + threadIdx.x; i < g1; i += DECIDE_THREADS) c += da.group_cost[i];
     q = block_sum<NW>(q, red);
-    c = block_sum<NW>(c, red);
+    c = window_cost_sum(g0, g1, da.group_cost, red);
     info = block_min_i<NW>(info, redi);
     if (threadIdx.x == 0) {
         const double qq = q, ct = c;
@@ -57,9 +65,12 @@ __device__ __forceinline__ void decide_window(int w, const DecideArgs &da) {
             const double fac = 1.0 - f * f * f;
             st.mu *= (fac > 1.0 / 3.0 ? fac : 1.0 / 3.0);
             st.nu = 2.0;
+            st.rejects = 0;
         } else {
             st.mu *= st.nu;
             st.nu *= 2.0;
+            st.rejects += 1;
+            if (da.max_rejects > 0 && st.rejects >= da.max_rejects) st.done = 2;
         }
     }
     __syncthreads();

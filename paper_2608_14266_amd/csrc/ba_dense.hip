@@ -577,6 +577,11 @@ void dense_release(Problem *P) {
 
 static int64_t linv_doubles(int64_t n) { return ((n + TB - 1) / TB) * (int64_t)TB * TB; }
 
+double *dense_hvec(Problem *P) {
+    DenseState *D = (DenseState *)P->dense_state;
+    return D ? D->h : nullptr;
+}
+
 int64_t dense_device_bytes(const Problem *P) {
     const DenseState *D = (const DenseState *)P->dense_state;
     return D ? (int64_t)D->mem.bytes : 0;
@@ -592,9 +597,9 @@ ba_status dense_prepare(Problem *P) {
     std::vector<int32_t> cvox(C), cscan(C);
     BA_HIP(hipMemcpy(cvox.data(), P->c_vox, sizeof(int32_t) * C, hipMemcpyDeviceToHost));
     BA_HIP(hipMemcpy(cscan.data(), P->c_scan, sizeof(int32_t) * C, hipMemcpyDeviceToHost));
-    // every (voxel, j <= k) pair, keyed by (j, k)
+    // every (voxel, j <= k) pair, keyed by (j, k): the clusters of a voxel are
+    // in scan order, so a pair (i <= j) of its clusters has j_scan >= i_scan
     std::vector<int32_t> pa, pb;
-    std::vector<uint64_t> key;
     for (int64_t a = 0; a < C;) {
         int64_t b = a;
         while (b < C && cvox[b] == cvox[a]) b++;
@@ -602,25 +607,37 @@ ba_status dense_prepare(Problem *P) {
             for (int64_t j = i; j < b; j++) {
                 pa.push_back((int32_t)i);
                 pb.push_back((int32_t)j);
-                key.push_back(((uint64_t)(uint32_t)cscan[i] << 32) | (uint32_t)cscan[j]);
             }
         a = b;
     }
     const int64_t E = (int64_t)pa.size();
-    std::vector<int64_t> ord(E);
-    std::iota(ord.begin(), ord.end(), 0);
-    std::stable_sort(ord.begin(), ord.end(), [&](int64_t x, int64_t y) { return key[x] < key[y]; });
+    // stable two-pass counting sort: by the second scan, then by the first
+    const int32_t NP = P->n_poses;
+    std::vector<int64_t> o1(E), ord(E), cnt(NP + 1);
+    std::fill(cnt.begin(), cnt.end(), 0);
+    for (int64_t q = 0; q < E; q++) cnt[cscan[pb[q]] + 1]++;
+    for (int32_t j = 0; j < NP; j++) cnt[j + 1] += cnt[j];
+    for (int64_t q = 0; q < E; q++) o1[cnt[cscan[pb[q]]]++] = q;
+    std::fill(cnt.begin(), cnt.end(), 0);
+    for (int64_t q = 0; q < E; q++) cnt[cscan[pa[q]] + 1]++;
+    for (int32_t j = 0; j < NP; j++) cnt[j + 1] += cnt[j];
+    for (int64_t r = 0; r < E; r++) {
+        const int64_t q = o1[r];
+        ord[cnt[cscan[pa[q]]]++] = q;
+    }
     std::vector<int32_t> spa(E), spb(E);
     std::vector<PairSeg> segs;
     for (int64_t q = 0; q < E; q++) {
-        spa[q] = pa[ord[q]];
-        spb[q] = pb[ord[q]];
-        if (q == 0 || key[ord[q]] != key[ord[q - 1]]) {
+        const int64_t o = ord[q];
+        spa[q] = pa[o];
+        spb[q] = pb[o];
+        const int32_t ja = cscan[pa[o]], jb = cscan[pb[o]];
+        if (q == 0 || ja != segs.back().ja || jb != segs.back().jb) {
             PairSeg sg;
             sg.start = q;
             sg.count = 0;
-            sg.ja = (int32_t)(key[ord[q]] >> 32);
-            sg.jb = (int32_t)(key[ord[q]] & 0xffffffffu);
+            sg.ja = ja;
+            sg.jb = jb;
             sg.pad = 0;
             segs.push_back(sg);
         }
@@ -685,8 +702,12 @@ ba_status dense_assemble(Problem *P, const double *poses, double *hess_out, bool
     double *dst = hess_out ? hess_out : P->dense;
     const LMState *lm = use_lm ? P->lm : nullptr;
     const int64_t C = P->n_clusters;
-    hipLaunchKernelGGL(k_hvec, dim3(nblk(C)), dim3(256), 0, s, C, P->c_N, P->c_mu, P->c_scan, P->c_slot, poses,
-                       P->vstate, (int64_t)P->n_groups * 64, P->pose_window, lm, D->h);
+    // the precision form takes h from the derivative pass (the same FP32
+    // clusters as the per-pose blocks, so the pair blocks cancel the diagonal
+    // blocks exactly along the translation gauge)
+    if (P->prec != BA_PREC_F32)
+        hipLaunchKernelGGL(k_hvec, dim3(nblk(C)), dim3(256), 0, s, C, P->c_N, P->c_mu, P->c_scan, P->c_slot, poses,
+                           P->vstate, (int64_t)P->n_groups * 64, P->pose_window, lm, D->h);
     // windows whose derivatives are stale are rebuilt whole; the others keep their matrix
     if (!use_lm) {
         const int64_t tot = P->dense_total;

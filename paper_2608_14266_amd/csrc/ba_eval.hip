@@ -33,6 +33,7 @@
 #include "ba_device.hpp"
 #include "ba_internal.hpp"
 #include "ba_kernels.hpp"
+#include "ba_decide.hpp"
 
 namespace ba {
 
@@ -57,6 +58,8 @@ struct SrcF32 {
     const float *N, *mu, *S;
     const double *ref_poses;   // [n_poses][12]
     const double *ref;         // [slots][4]
+    const int32_t *cidx;       // [C] (voxel, scan)-order index of each pose-major cluster
+    double *h;                 // [C][6] coupled pair vectors, written when not null
 };
 
 template <typename T>
@@ -249,23 +252,25 @@ __global__ __launch_bounds__(64 * SPLIT) void k_vox(const VoxBlock *__restrict__
 // sc = 2 / N_i.
 template <typename T>
 __device__ __forceinline__ void pose_terms(T n, const T *y, double e64, const T *St, const T *u, double sc,
-                                           double *acc) {
+                                           double *acc, bool grad = true) {
     const T e = (T)e64;
     T su[3];
     sym_mv(St, u, su);
     const T ne = n * e;
     const T w[3] = {fmaT(ne, y[0], su[0]), fmaT(ne, y[1], su[1]), fmaT(ne, y[2], su[2])};
-    T wxu[3], a[3];
-    cross(w, u, wxu);
+    T a[3];
     cross(y, u, a);
-    // gradient
-    acc[0] = fma(sc, (double)wxu[0], acc[0]);
-    acc[1] = fma(sc, (double)wxu[1], acc[1]);
-    acc[2] = fma(sc, (double)wxu[2], acc[2]);
-    const double sne = sc * ((double)n * e64);
-    acc[3] = fma(sne, (double)u[0], acc[3]);
-    acc[4] = fma(sne, (double)u[1], acc[4]);
-    acc[5] = fma(sne, (double)u[2], acc[5]);
+    if (grad) {
+        T wxu[3];
+        cross(w, u, wxu);
+        acc[0] = fma(sc, (double)wxu[0], acc[0]);
+        acc[1] = fma(sc, (double)wxu[1], acc[1]);
+        acc[2] = fma(sc, (double)wxu[2], acc[2]);
+        const double sne = sc * ((double)n * e64);
+        acc[3] = fma(sne, (double)u[0], acc[3]);
+        acc[4] = fma(sne, (double)u[1], acc[4]);
+        acc[5] = fma(sne, (double)u[2], acc[5]);
+    }
     // [u]x St [u]x^T : B = [u]x St, C = B [u]x^T
     const T Sf[3][3] = {{St[0], St[1], St[2]}, {St[1], St[3], St[4]}, {St[2], St[4], St[5]}};
     const T K[3][3] = {{T(0), -u[2], u[1]}, {u[2], T(0), -u[0]}, {-u[1], u[0], T(0)}};
@@ -325,36 +330,82 @@ __device__ __forceinline__ void pose_cluster(const SrcF64 &src, const PoseCtx &c
 
 // FP32 form: with q = c - t0 and G = I + E the pose change,
 //   y = R mu = G mu' + G q,   d = m - mbar = G mu' + (E q + dt + c - mbar);
-// E mu' and St = S' + D(E, S') in FP32; y is rounded to FP32 once, and the
-// plane offset e = u^T d is formed in FP64.
+// y, the plane offset e = u^T d and the gradient terms in FP64 from the FP32
+// cluster; D(E, S') and the Hessian terms in FP32 (FP64 in the coupled form).
+template <bool HESS64>
 __device__ __forceinline__ void pose_cluster(const SrcF32 &src, const PoseCtx &cx, int64_t q, int64_t C,
                                              const double *st, int32_t slot, double *acc) {
     const float n = src.N[q];
-    const float mu[3] = {src.mu[q], src.mu[C + q], src.mu[2 * C + q]};
+    const double mu[3] = {(double)src.mu[q], (double)src.mu[C + q], (double)src.mu[2 * C + q]};
     float S[6];
 #pragma unroll
     for (int k = 0; k < 6; k++) S[k] = src.S[k * C + q];
     const double *c = src.ref + 4LL * slot;
-    const double q0 = c[0] - cx.P0.t[0], q1 = c[1] - cx.P0.t[1], q2 = c[2] - cx.P0.t[2];
-    float Em[3], Dl[6];
-    rot(cx.E, mu, Em);
-    delta_sym(cx.E, S, Dl);
-    float y[3];
+    const double qv[3] = {c[0] - cx.P0.t[0], c[1] - cx.P0.t[1], c[2] - cx.P0.t[2]};
+    // FP64: G mu' = mu' + E mu', the lever arm y = G mu' + G q and the plane
+    // offset e = u^T (G mu' + E q + dt + c - mbar)
+    double Em[3], Eq[3], y64[3];
+    rot(cx.D.E, mu, Em);
+    rot(cx.D.E, qv, Eq);
     double e = 0.0;
 #pragma unroll
     for (int i = 0; i < 3; i++) {
-        const double eq = fma(cx.D.E[3 * i], q0, fma(cx.D.E[3 * i + 1], q1, cx.D.E[3 * i + 2] * q2));
-        const double qi = i == 0 ? q0 : (i == 1 ? q1 : q2);
-        const double gm = (double)mu[i] + (double)Em[i];
-        y[i] = (float)(gm + (qi + eq));
-        // d_i in FP64: its normal component e is centimetres out of metres
-        e = fma(st[i], gm + ((eq + cx.D.dt[i]) + (c[i] - st[3 + i])), e);
+        const double gm = mu[i] + Em[i];
+        y64[i] = gm + (qv[i] + Eq[i]);
+        e = fma(st[i], gm + ((Eq[i] + cx.D.dt[i]) + (c[i] - st[3 + i])), e);
+    }
+    const double u64[3] = {st[0], st[1], st[2]};
+    if constexpr (HESS64) {
+        if (src.h) {
+            // h = (N_ij / N_i) [y x u ; u] of the coupled form
+            const double f = (double)n * (0.5 * st[6]);
+            double a[3];
+            cross(y64, u64, a);
+            double *o = src.h + 6 * (int64_t)src.cidx[q];
+            o[0] = f * a[0]; o[1] = f * a[1]; o[2] = f * a[2];
+            o[3] = f * u64[0]; o[4] = f * u64[1]; o[5] = f * u64[2];
+        }
+        double Sd[6], Dl64[6], S64[6];
+#pragma unroll
+        for (int k = 0; k < 6; k++) Sd[k] = (double)S[k];
+        delta_sym(cx.D.E, Sd, Dl64);
+#pragma unroll
+        for (int k = 0; k < 6; k++) S64[k] = Sd[k] + Dl64[k];
+        pose_terms((double)n, y64, e, S64, u64, st[6], acc);
+        return;
+    }
+    // St = S' + D(E, S') with D in FP32 (of the size of the pose change)
+    float Dl[6];
+    delta_sym(cx.E, S, Dl);
+    // gradient terms in FP64: the iteration converges to where they cancel,
+    // so their rounding sets the accuracy of the result; the Hessian terms
+    // (most of the arithmetic) only steer the steps and stay FP32, except for
+    // the coupled form (HESS64), whose dense Newton-like step amplifies their
+    // rounding along the nearly singular gauge directions
+    {
+        double S64[6], su[3];
+#pragma unroll
+        for (int k = 0; k < 6; k++) S64[k] = (double)S[k] + (double)Dl[k];
+        sym_mv(S64, u64, su);
+        const double ne = (double)n * e;
+        const double w[3] = {fma(ne, y64[0], su[0]), fma(ne, y64[1], su[1]), fma(ne, y64[2], su[2])};
+        double wxu[3];
+        cross(w, u64, wxu);
+        const double sc = st[6];
+        acc[0] = fma(sc, wxu[0], acc[0]);
+        acc[1] = fma(sc, wxu[1], acc[1]);
+        acc[2] = fma(sc, wxu[2], acc[2]);
+        const double sne = sc * ne;
+        acc[3] = fma(sne, u64[0], acc[3]);
+        acc[4] = fma(sne, u64[1], acc[4]);
+        acc[5] = fma(sne, u64[2], acc[5]);
     }
     const float u[3] = {(float)st[0], (float)st[1], (float)st[2]};
+    const float y[3] = {(float)y64[0], (float)y64[1], (float)y64[2]};
     float St[6];
 #pragma unroll
     for (int k = 0; k < 6; k++) St[k] = S[k] + Dl[k];
-    pose_terms(n, y, e, St, u, st[6], acc);
+    pose_terms(n, y, e, St, u, st[6], acc, false);
 }
 
 // Block b of a launch runs on XCD b mod 8.  Renumbering the blocks so that
@@ -371,7 +422,7 @@ __device__ __forceinline__ int xcd_block(int b, int nb) {
 // Derivative pass: one wavefront per pose chunk, blocks renumbered per XCD.
 // With a persistent grid each wave walks the chunk list with a stride of the
 // number of waves.
-template <class Src, bool PERSIST>
+template <class Src, bool PERSIST, bool HESS64>
 __global__ __launch_bounds__(256) void k_pose(const ChunkDesc *__restrict__ chunks, int32_t n_chunks, int64_t C,
                                               Src src, const int32_t *__restrict__ pslot,
                                               const double *__restrict__ poses, const double *__restrict__ vstate,
@@ -405,7 +456,10 @@ __global__ __launch_bounds__(256) void k_pose(const ChunkDesc *__restrict__ chun
         for (int i = lane; i < ch.count; i += 64) {
             const int64_t q = ch.start + i;
             const int32_t slot = pslot[q];
-            pose_cluster(src, cx, q, C, vs + (int64_t)slot * VSTATE, slot, acc);
+            if constexpr (sizeof(*src.N) == 4)
+                pose_cluster<HESS64>(src, cx, q, C, vs + (int64_t)slot * VSTATE, slot, acc);
+            else
+                pose_cluster(src, cx, q, C, vs + (int64_t)slot * VSTATE, slot, acc);
         }
         // reduce-scatter over the wave: lane l ends with the sum of value l / 2
         double red[32];
@@ -451,21 +505,17 @@ __global__ void k_reduce_partials(int32_t n_poses, const int32_t *__restrict__ c
     }
 }
 
-// One block per window: fixed-order sum of the window's wave residuals.
-__global__ __launch_bounds__(256) void k_window_cost(int32_t n_windows, const int32_t *__restrict__ win_group_ptr,
-                                                     const double *__restrict__ wave_cost, double *__restrict__ out) {
-    __shared__ double red[256];
+// One block per window: the window's residual, summed in the order the LM
+// decision uses.
+__global__ __launch_bounds__(DECIDE_THREADS) void k_window_cost(int32_t n_windows,
+                                                                const int32_t *__restrict__ win_group_ptr,
+                                                                const double *__restrict__ wave_cost,
+                                                                double *__restrict__ out) {
+    __shared__ double red[DECIDE_THREADS / 64];
     const int w = blockIdx.x;
     if (w >= n_windows) return;
-    double s = 0.0;
-    for (int i = win_group_ptr[w] + threadIdx.x; i < win_group_ptr[w + 1]; i += 256) s += wave_cost[i];
-    red[threadIdx.x] = s;
-    __syncthreads();
-    for (int o = 128; o > 0; o >>= 1) {
-        if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) out[w] = red[0];
+    const double c = window_cost_sum(win_group_ptr[w], win_group_ptr[w + 1], wave_cost, red);
+    if (threadIdx.x == 0) out[w] = c;
 }
 
 // (lambda_min, u) per input voxel id
@@ -484,12 +534,13 @@ __global__ void k_voxel_eig(int64_t n_slots, const int32_t *__restrict__ slot_vo
 
 static inline unsigned nblk(int64_t n, int t = 256) { return (unsigned)((n + t - 1) / t); }
 
-static SrcF64 src64(const Problem *P, bool vox) {
+static SrcF64 src64(Problem *P, bool vox, bool = false) {
     return vox ? SrcF64{P->v_N, P->v_mu, P->v_S} : SrcF64{P->p_N, P->p_mu, P->p_S};
 }
-static SrcF32 src32(const Problem *P, bool vox) {
-    return vox ? SrcF32{P->v_N32, P->v_mu32, P->v_S32, P->ref_poses, P->v_ref}
-               : SrcF32{P->p_N32, P->p_mu32, P->p_S32, P->ref_poses, P->v_ref};
+static SrcF32 src32(Problem *P, bool vox, bool hvec = false) {
+    return vox ? SrcF32{P->v_N32, P->v_mu32, P->v_S32, P->ref_poses, P->v_ref, nullptr, nullptr}
+               : SrcF32{P->p_N32, P->p_mu32, P->p_S32, P->ref_poses, P->v_ref, P->p_cidx,
+                        hvec ? dense_hvec(P) : nullptr};
 }
 
 // Grid of a pass with `items` work items: one block per item, or a
@@ -532,32 +583,38 @@ void launch_vox(Problem *P, const double *poses, bool use_lm, bool trial, hipStr
 }
 
 void launch_window_cost(Problem *P, double *out, hipStream_t s) {
-    hipLaunchKernelGGL(k_window_cost, dim3(P->n_windows), dim3(256), 0, s, P->n_windows, P->win_group_ptr,
+    hipLaunchKernelGGL(k_window_cost, dim3(P->n_windows), dim3(DECIDE_THREADS), 0, s, P->n_windows, P->win_group_ptr,
                        P->wave_cost, out);
 }
 
-void launch_pose_chunks(Problem *P, const double *poses, bool use_lm, hipStream_t s) {
+void launch_pose_chunks(Problem *P, const double *poses, bool use_lm, hipStream_t s, bool hess64) {
     if (P->n_chunks == 0) return;
     ProfScope prof("k_pose", s);
     const int64_t ns = (int64_t)P->n_groups * 64;
     const LMState *lm = use_lm ? P->lm : nullptr;
     const dim3 grid(pass_grid(P->n_chunks, 4, P->tune.pose_grid, P->n_cu));
     const bool pers = P->tune.pose_grid > 0;
-#define BA_POSE(SRC, PER, MK)                                                                                      \
-    hipLaunchKernelGGL((k_pose<SRC, PER>), grid, dim3(256), 0, s, P->chunks, P->n_chunks, P->n_clusters,          \
-                       MK(P, false), P->p_slot, poses, P->vstate, ns, P->pose_window, lm, P->partials)
+#define BA_POSE(SRC, PER, H64, MK)                                                                                 \
+    hipLaunchKernelGGL((k_pose<SRC, PER, H64>), grid, dim3(256), 0, s, P->chunks, P->n_chunks, P->n_clusters,     \
+                       MK(P, false, H64), P->p_slot, poses, P->vstate, ns, P->pose_window, lm, P->partials)
     if (P->prec == BA_PREC_F32) {
-        if (pers) BA_POSE(SrcF32, true, src32);
-        else BA_POSE(SrcF32, false, src32);
+        if (hess64) {
+            if (pers) BA_POSE(SrcF32, true, true, src32);
+            else BA_POSE(SrcF32, false, true, src32);
+        } else {
+            if (pers) BA_POSE(SrcF32, true, false, src32);
+            else BA_POSE(SrcF32, false, false, src32);
+        }
     } else {
-        if (pers) BA_POSE(SrcF64, true, src64);
-        else BA_POSE(SrcF64, false, src64);
+        if (pers) BA_POSE(SrcF64, true, false, src64);
+        else BA_POSE(SrcF64, false, false, src64);
     }
 #undef BA_POSE
 }
 
-void launch_pose_derivs(Problem *P, const double *poses, bool use_lm, double *g, double *H, hipStream_t s) {
-    launch_pose_chunks(P, poses, use_lm, s);
+void launch_pose_derivs(Problem *P, const double *poses, bool use_lm, double *g, double *H, hipStream_t s,
+                        bool hess64) {
+    launch_pose_chunks(P, poses, use_lm, s, hess64);
     hipLaunchKernelGGL(k_reduce_partials, dim3(nblk((int64_t)P->n_poses * NPART)), dim3(256), 0, s, P->n_poses,
                        P->chunk_ptr, P->partials, P->pose_window, use_lm ? P->lm : nullptr, g, H);
 }
@@ -569,3 +626,4 @@ void launch_voxel_eig(Problem *P, double *out, hipStream_t s) {
 }
 
 }  // namespace ba
+

@@ -31,8 +31,8 @@ struct LMState {
     double q, rho;
     double gnorm, maxdiag;
     double cost0;
-    int32_t accepted, need_eval, info, done;
-    int32_t iters, n_accepted, cur, pad;
+    int32_t accepted, need_eval, info, done;   // done: 1 converged (||g|| < tol_g), 2 stalled
+    int32_t iters, n_accepted, cur, rejects;   // rejects: rejected steps in a row
 };
 
 // One residual-pass block: `ng` consecutive groups served one wave each
@@ -60,6 +60,7 @@ struct DecideArgs {
     LMState *lm;
     double *trace;
     int32_t it;
+    int32_t max_rejects;
     const double *poses_trial;
     double *poses;
 };
@@ -118,6 +119,7 @@ struct Problem {
     double *p_S = nullptr;      // [6][C]
     double *p_N = nullptr;      // [C]
     int32_t *p_slot = nullptr;  // [C]
+    int32_t *p_cidx = nullptr;  // [C] (voxel, scan)-order index of each pose-major cluster
     ChunkDesc *chunks = nullptr;
     int32_t *chunk_ptr = nullptr; // [n_poses+1]
     double *partials = nullptr; // [n_chunks][NPART]
@@ -156,6 +158,8 @@ struct Problem {
 
 ba_status replan_chunks(Problem *P, int32_t chunk_len, hipStream_t s);
 int64_t dense_device_bytes(const Problem *P);
+ba_status dense_prepare(Problem *P);
+double *dense_hvec(Problem *P);   // [C][6] pair vectors of the coupled form
 ba_status build_from_points(const ba_points *pts, const ba_build_options *opt, Problem *P, DevArena &keep,
                             hipStream_t s);
 ba_status build_from_sums(const ba_cluster_sums *cs, const ba_build_options *opt, Problem *P, DevArena &keep,

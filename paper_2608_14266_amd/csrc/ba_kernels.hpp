@@ -9,8 +9,10 @@ namespace ba {
 // evaluation (ba_eval.hip)
 void launch_vox(Problem *P, const double *poses, bool use_lm, bool trial, hipStream_t s);
 void launch_window_cost(Problem *P, double *out, hipStream_t s);
-void launch_pose_chunks(Problem *P, const double *poses, bool use_lm, hipStream_t s);
-void launch_pose_derivs(Problem *P, const double *poses, bool use_lm, double *g, double *H, hipStream_t s);
+// hess64: FP64 Hessian terms also in the precision form (the coupled form needs them)
+void launch_pose_chunks(Problem *P, const double *poses, bool use_lm, hipStream_t s, bool hess64 = false);
+void launch_pose_derivs(Problem *P, const double *poses, bool use_lm, double *g, double *H, hipStream_t s,
+                        bool hess64 = false);
 void launch_voxel_eig(Problem *P, double *out, hipStream_t s);
 
 // LM (ba_lm.hip)
@@ -22,8 +24,8 @@ void launch_lm_cost(Problem *P, hipStream_t s);
 void launch_window_stats(Problem *P, double tol_g, hipStream_t s);
 void launch_solve_mm_lm(Problem *P, const double *poses, hipStream_t s);
 void launch_window_solve_mm(Problem *P, const double *poses, double tol_g, hipStream_t s);
-DecideArgs decide_args(Problem *P, double *trace, int it, double *poses);
-void launch_decide(Problem *P, double *trace, int it, double *poses, hipStream_t s);
+DecideArgs decide_args(Problem *P, double *trace, int it, double *poses, int max_rejects);
+void launch_decide(Problem *P, double *trace, int it, double *poses, hipStream_t s, int max_rejects);
 void launch_commit(Problem *P, double *poses, hipStream_t s);
 
 }  // namespace ba

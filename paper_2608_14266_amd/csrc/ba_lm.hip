@@ -100,27 +100,22 @@ __global__ void k_lm_reset(int32_t W, LMState *__restrict__ lm, double mu0, doub
     s.gnorm = 0.0; s.maxdiag = 0.0; s.cost0 = 0.0;
     s.accepted = 0; s.need_eval = 1; s.info = 0;
     s.done = (win_group_ptr[w + 1] == win_group_ptr[w]) ? 1 : 0;   // a window without voxels has nothing to do
-    s.iters = 0; s.n_accepted = 0; s.cur = 0; s.pad = 0;
+    s.iters = 0; s.n_accepted = 0; s.cur = 0; s.rejects = 0;
     lm[w] = s;
 }
 
-// block per window: cost at the current poses from the wave residuals
-__global__ __launch_bounds__(256) void k_lm_cost(int32_t W, const int32_t *__restrict__ win_group_ptr,
-                                                 const double *__restrict__ wave_cost, LMState *__restrict__ lm) {
-    __shared__ double red[256];
+// block per window: cost at the current poses from the group residuals (the
+// same summation order as the trial cost of the decision kernel)
+__global__ __launch_bounds__(DECIDE_THREADS) void k_lm_cost(int32_t W, const int32_t *__restrict__ win_group_ptr,
+                                                            const double *__restrict__ wave_cost,
+                                                            LMState *__restrict__ lm) {
+    __shared__ double red[DECIDE_THREADS / 64];
     const int w = blockIdx.x;
     if (w >= W) return;
-    double s = 0.0;
-    for (int i = win_group_ptr[w] + threadIdx.x; i < win_group_ptr[w + 1]; i += 256) s += wave_cost[i];
-    red[threadIdx.x] = s;
-    __syncthreads();
-    for (int o = 128; o > 0; o >>= 1) {
-        if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
-        __syncthreads();
-    }
+    const double c = window_cost_sum(win_group_ptr[w], win_group_ptr[w + 1], wave_cost, red);
     if (threadIdx.x == 0) {
-        lm[w].cost = red[0];
-        lm[w].cost0 = red[0];
+        lm[w].cost = c;
+        lm[w].cost0 = c;
     }
 }
 
@@ -316,7 +311,7 @@ void launch_lm_reset(Problem *P, double mu0, double nu0, hipStream_t s) {
 }
 
 void launch_lm_cost(Problem *P, hipStream_t s) {
-    hipLaunchKernelGGL(k_lm_cost, dim3(P->n_windows), dim3(256), 0, s, P->n_windows, P->win_group_ptr,
+    hipLaunchKernelGGL(k_lm_cost, dim3(P->n_windows), dim3(DECIDE_THREADS), 0, s, P->n_windows, P->win_group_ptr,
                        P->wave_cost, P->lm);
 }
 
@@ -330,8 +325,9 @@ void launch_solve_mm_lm(Problem *P, const double *poses, hipStream_t s) {
                        P->win_pose_ptr, P->lm, P->H, P->g, poses, P->dx, P->pose_q, P->pose_info, P->poses_trial);
 }
 
-DecideArgs decide_args(Problem *P, double *trace, int it, double *poses) {
+DecideArgs decide_args(Problem *P, double *trace, int it, double *poses, int max_rejects) {
     DecideArgs da;
+    da.max_rejects = max_rejects;
     da.W = P->n_windows;
     da.win_pose_ptr = P->win_pose_ptr;
     da.win_group_ptr = P->win_group_ptr;
@@ -346,8 +342,8 @@ DecideArgs decide_args(Problem *P, double *trace, int it, double *poses) {
     return da;
 }
 
-void launch_decide(Problem *P, double *trace, int it, double *poses, hipStream_t s) {
-    DecideArgs da = decide_args(P, trace, it, poses);
+void launch_decide(Problem *P, double *trace, int it, double *poses, hipStream_t s, int max_rejects) {
+    DecideArgs da = decide_args(P, trace, it, poses, max_rejects);
     hipLaunchKernelGGL(k_decide, dim3(P->n_windows), dim3(DECIDE_THREADS), 0, s, da);
 }
 

@@ -316,3 +316,19 @@ def test_deterministic_bitwise(ba, dev, orc):
         outs.append([t.cpu().numpy().copy() for t in (cost, g, H, P2)])
     for a, b in zip(*outs):
         assert np.array_equal(a, b)
+
+
+def test_iterate_stops_after_consecutive_rejections(ba, dev, orc):
+    import torch
+    say("LM stagnation stop")
+    sc = scenes.tiny_config(seed=1000)
+    cl = orc.scene_clusters(sc)
+    prob = build_gpu(ba, sc, dev)
+    P = torch.as_tensor(sc.poses_init, device=dev).contiguous()
+    reps, tr = ba.iterate(prob, P, ba.MODE_MM, max_iters=60, max_rejects=4)
+    r = reps[0]
+    assert r["stalled"] == 1 and r["converged"] == 0 and r["iters"] < 60
+    tr = tr[: r["iters"], 0, :]
+    assert np.all(tr[-4:, 4] == 0)
+    _, rep_ref, c_ref = orc.lm(orc.MM, cl, sc.poses_init, 60, max_rejects=4)
+    assert abs(r["cost_final"] - c_ref) <= 1e-12 * c_ref

@@ -487,3 +487,23 @@ def test_lm_modes_reach_same_minimum(orc, tiny):
         acc = rep[:, 4] > 0
         costs = np.r_[rep[0, 0], rep[acc, 1]]
         assert np.all(np.diff(costs) <= 1e-15)
+
+
+def test_lm_stops_after_consecutive_rejections(orc):
+    """The stagnation stop: after max_rejects rejected steps in a row the loop
+    ends (near the optimum no step can be confirmed against the cost's
+    rounding); without it the loop runs to max_iters."""
+    import scenes
+    sc = scenes.tiny_config(seed=1000)
+    cl = orc.scene_clusters(sc)
+    _, rep_full, _ = orc.lm(orc.MM, cl, sc.poses_init, 60)
+    assert rep_full.shape[0] == 60
+    P, rep, c = orc.lm(orc.MM, cl, sc.poses_init, 60, max_rejects=4)
+    k = rep.shape[0]
+    assert k < 60
+    assert np.all(rep[-4:, 4] == 0)
+    assert np.array_equal(rep, rep_full[:k])
+    # no earlier run of 4 rejections
+    acc = rep[:, 4]
+    for i in range(k - 4):
+        assert np.any(acc[i:i + 4] == 1)
