@@ -128,6 +128,7 @@ def city(args):
         prob = _build(ba, sc, arrs, prec, P0)
         torch.cuda.synchronize()
         tb = time.perf_counter() - t0
+        tune = ba.tuned(prob, P0, cache_path=None, reps=3)
         inf = prob.info()
         dt, reps, P = _timed_solves(ba, prob, P0, mode, iters, args.steps, args.warmup)
         kt = _kernel_times(ba, prob, P0, mode, iters)
@@ -136,6 +137,7 @@ def city(args):
         vb = C * inf["cluster_bytes"] + V * (64 + (32 if prec == "f32" else 0)) + N * 96 * (2 if prec == "f32" else 1)
         kv = kt.get("k_vox", {}).get("avg_us", 0.0)
         res[prec] = {"ms_per_solve": 1e3 * dt, "evals_per_s": V * iters / dt, "build_s": round(tb, 3),
+                     "tuning": tune,
                      "device_bytes": inf["device_bytes"], "cluster_bytes": inf["cluster_bytes"], "kernels": kt,
                      "k_vox_algorithmic_gbs": round(vb / (kv * 1e-6) / 1e9, 1) if kv else None,
                      "k_vox_hbm_frac": round(vb / (kv * 1e-6) / 1e9 / HBM_PEAK_GBS, 4) if kv else None,

@@ -508,6 +508,7 @@ static ba_status make_plan(Problem *P, const std::vector<int32_t> &cvox, const s
         BA_TRY(keep.alloc(&P->p_S32, 6 * C));
         BA_TRY(keep.alloc(&P->p_N32, C));
         BA_TRY(keep.alloc(&P->v_ref, 4 * std::max<int64_t>(NS, 1)));
+        BA_TRY(keep.alloc(&P->pdelta, 16LL * N));
     } else {
         BA_TRY(keep.alloc(&P->p_mu, 3 * C));
         BA_TRY(keep.alloc(&P->p_S, 6 * C));

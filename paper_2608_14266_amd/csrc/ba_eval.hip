@@ -58,9 +58,32 @@ struct SrcF32 {
     const float *N, *mu, *S;
     const double *ref_poses;   // [n_poses][12]
     const double *ref;         // [slots][4]
+    const double *pdelta;      // [n_poses][16] pose changes of the evaluated poses (residual pass)
     const int32_t *cidx;       // [C] (voxel, scan)-order index of each pose-major cluster
     double *h;                 // [C][6] coupled pair vectors, written when not null
 };
+
+// Pose change of every scan for the precision form's residual pass:
+// E = R R0^T - I, dt = t - t0 and t0 (one thread per pose).
+__global__ void k_pose_delta(int32_t n, const double *__restrict__ poses, const double *__restrict__ ref_poses,
+                             double *__restrict__ pdelta) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    Pose P, P0;
+    load_pose(poses, j, P);
+    load_pose(ref_poses, j, P0);
+    PoseDelta D;
+    pose_delta(P, P0, D);
+    double *o = pdelta + 16LL * j;
+#pragma unroll
+    for (int e = 0; e < 9; e++) o[e] = D.E[e];
+#pragma unroll
+    for (int e = 0; e < 3; e++) {
+        o[9 + e] = D.dt[e];
+        o[12 + e] = P0.t[e];
+    }
+    o[15] = 0.0;
+}
 
 template <typename T>
 __device__ __forceinline__ void vox_add(VoxSums &a, T nk, const T *d, const T *St) {
@@ -94,16 +117,21 @@ __device__ __forceinline__ void vox_accumulate(const GroupDesc &g, int64_t slot,
         rot(P.r, mu, a.r);
         a.r[0] += P.t[0]; a.r[1] += P.t[1]; a.r[2] += P.t[2];
     }
+    // the scan id of the next cluster is loaded one iteration ahead, so the
+    // pose gather does not wait for a dependent round trip
+    int j_next = (k0 < g.m) ? vpose[g.cbase + 64LL * k0 + lane] : 0;
 #pragma unroll 2
     for (int k = k0; k < g.m; k += kstep) {
         const int64_t idx = g.cbase + 64LL * k + lane;
+        const int j = j_next;
+        if (k + kstep < g.m) j_next = vpose[idx + 64LL * kstep];
         const double nk = src.N[idx];
         const double mu[3] = {src.mu[idx], src.mu[c_pad + idx], src.mu[2 * c_pad + idx]};
         double S[6];
 #pragma unroll
         for (int q = 0; q < 6; q++) S[q] = src.S[q * c_pad + idx];
         Pose P;
-        load_pose(poses, vpose[idx], P);
+        load_pose(poses, j, P);
         double y[3], St[6];
         rot(P.r, mu, y);
         rot_sym(P.r, S, St);
@@ -123,21 +151,25 @@ __device__ __forceinline__ void vox_accumulate(const GroupDesc &g, int64_t slot,
     vox_zero(a);
     const double *c = src.ref + 4 * slot;
     a.r[0] = c[0]; a.r[1] = c[1]; a.r[2] = c[2];
+    int j_next = (k0 < g.m) ? vpose[g.cbase + 64LL * k0 + lane] : 0;
 #pragma unroll 1
     for (int k = k0; k < g.m; k += kstep) {
         const int64_t idx = g.cbase + 64LL * k + lane;
+        const int j = j_next;
+        if (k + kstep < g.m) j_next = vpose[idx + 64LL * kstep];
         const double nk = (double)src.N[idx];
         const double mu[3] = {(double)src.mu[idx], (double)src.mu[c_pad + idx], (double)src.mu[2 * c_pad + idx]};
         double S[6];
 #pragma unroll
         for (int q = 0; q < 6; q++) S[q] = (double)src.S[q * c_pad + idx];
-        const int j = vpose[idx];
-        Pose P, P0;
-        load_pose(poses, j, P);
-        load_pose(src.ref_poses, j, P0);
+        // pose change of scan j, formed once per evaluation (k_pose_delta)
+        const double *pd = src.pdelta + 16LL * j;
         PoseDelta D;
-        pose_delta(P, P0, D);
-        const double q[3] = {a.r[0] - P0.t[0], a.r[1] - P0.t[1], a.r[2] - P0.t[2]};
+#pragma unroll
+        for (int e = 0; e < 9; e++) D.E[e] = pd[e];
+#pragma unroll
+        for (int e = 0; e < 3; e++) D.dt[e] = pd[9 + e];
+        const double q[3] = {a.r[0] - pd[12], a.r[1] - pd[13], a.r[2] - pd[14]};
         double Em[3], Eq[3], Dl[6];
         rot(D.E, mu, Em);
         rot(D.E, q, Eq);
@@ -538,8 +570,8 @@ static SrcF64 src64(Problem *P, bool vox, bool = false) {
     return vox ? SrcF64{P->v_N, P->v_mu, P->v_S} : SrcF64{P->p_N, P->p_mu, P->p_S};
 }
 static SrcF32 src32(Problem *P, bool vox, bool hvec = false) {
-    return vox ? SrcF32{P->v_N32, P->v_mu32, P->v_S32, P->ref_poses, P->v_ref, nullptr, nullptr}
-               : SrcF32{P->p_N32, P->p_mu32, P->p_S32, P->ref_poses, P->v_ref, P->p_cidx,
+    return vox ? SrcF32{P->v_N32, P->v_mu32, P->v_S32, P->ref_poses, P->v_ref, P->pdelta, nullptr, nullptr}
+               : SrcF32{P->p_N32, P->p_mu32, P->p_S32, P->ref_poses, P->v_ref, nullptr, P->p_cidx,
                         hvec ? dense_hvec(P) : nullptr};
 }
 
@@ -558,6 +590,9 @@ void launch_vox(Problem *P, const double *poses, bool use_lm, bool trial, hipStr
     const LMState *lm = use_lm ? P->lm : nullptr;
     const dim3 grid(pass_grid(P->n_vblocks, 1, P->tune.vox_grid, P->n_cu));
     const int t = trial ? 1 : 0;
+    if (P->prec == BA_PREC_F32)
+        hipLaunchKernelGGL(k_pose_delta, dim3(nblk(P->n_poses)), dim3(256), 0, s, P->n_poses, poses, P->ref_poses,
+                           P->pdelta);
     const bool pers = P->tune.vox_grid > 0;
 #define BA_VOX(SRC, SPL, MK)                                                                                       \
     do {                                                                                                           \
