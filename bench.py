@@ -196,6 +196,7 @@ def main():
     pose_ms, pose_n = ba.profile_query("k_pose")
     syrk_ms, syrk_n = ba.profile_query("k_syrk")
     trsm_ms, trsm_n = ba.profile_query("k_trsm")
+    potf2_ms, potf2_n = ba.profile_query("k_potf2")
     ba.profile_reset()
     elapsed = t1 - t0
     ms_per_step = 1e3 * elapsed / args.steps
@@ -234,10 +235,11 @@ def main():
             if below > 0:
                 fl_trsm += below * 64 * 64 * 2
                 fl_syrk += below * below * 64
-        n_fact = syrk_n / max(1, sum(1 for st in range((n + 63) // 64) if n - 64 * (st + 1) > 0))
+        n_fact = potf2_n / ((n + 63) // 64)   # one diagonal-block factor per 64-wide step
         tfs = (fl_trsm + fl_syrk) * n_fact / ((syrk_ms + trsm_ms) * 1e-3) / 1e12
         kern["k_syrk"] = dict(avg_us=1e3 * syrk_ms / max(syrk_n, 1), launches=syrk_n)
         kern["k_trsm"] = dict(avg_us=1e3 * trsm_ms / max(trsm_n, 1), launches=trsm_n)
+        kern["k_potf2"] = dict(avg_us=1e3 * potf2_ms / max(potf2_n, 1), launches=potf2_n)
         kern["factorization"] = dict(count=n_fact, flops=fl_trsm + fl_syrk)
         roof = {"kernel": "k_syrk+k_trsm", "bound": "mfma", "achieved": round(tfs, 3),
                 "peak": FP64_MFMA_PEAK_TFS, "unit": "TFLOP/s", "frac": round(tfs / FP64_MFMA_PEAK_TFS, 4),

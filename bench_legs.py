@@ -99,7 +99,7 @@ def _kernel_times(ba, prob, P0, mode, iters):
     torch.cuda.synchronize()
     ba.profile_enable(False)
     out = {}
-    for k in ("k_vox", "k_pose", "k_syrk", "k_trsm"):
+    for k in ("k_vox", "k_pose", "k_syrk", "k_trsm", "k_potf2"):
         ms, n = ba.profile_query(k)
         if n:
             out[k] = {"avg_us": round(1e3 * ms / n, 3), "launches": n}
@@ -143,6 +143,19 @@ def city(args):
                      "k_vox_hbm_frac": round(vb / (kv * 1e-6) / 1e9 / HBM_PEAK_GBS, 4) if kv else None,
                      "cost_initial": float(cost0.cpu().numpy()[0]), "cost_final": reps[0]["cost_final"],
                      "grad_initial": g0.cpu().numpy().ravel()}
+        if "k_syrk" in kt and "k_trsm" in kt:
+            # dense factorization on FP64 matrix cores: flops of the panel
+            # solves and trailing updates of one 6N x 6N factorization
+            n = 6 * N
+            fl = sum(2 * 64 * 64 * (n - 64 * (st + 1)) + 64 * (n - 64 * (st + 1)) ** 2
+                     for st in range((n + 63) // 64) if n - 64 * (st + 1) > 0)
+            n_fact = kt["k_potf2"]["launches"] / ((n + 63) // 64)
+            t_mfma = 1e-6 * (kt["k_syrk"]["avg_us"] * kt["k_syrk"]["launches"]
+                             + kt["k_trsm"]["avg_us"] * kt["k_trsm"]["launches"])
+            tfs = fl * n_fact / t_mfma / 1e12
+            res[prec]["mfma_roofline"] = {"achieved_tflops": round(tfs, 3), "peak": 78.6,
+                                          "frac": round(tfs / 78.6, 4), "flops_per_factorization": fl,
+                                          "factorizations": n_fact}
         finals[prec] = P.cpu().numpy()
         log(f"city {prec}: {1e3 * dt:.2f} ms/solve, k_vox {kv} us, build {tb:.2f}s")
         prob.close()

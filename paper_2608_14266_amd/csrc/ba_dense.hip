@@ -111,9 +111,9 @@ __global__ __launch_bounds__(256) void k_pairs(int32_t n_seg, const PairSeg *__r
         const LMState &st = lm[w];
         if (st.done || !st.need_eval) return;
     }
-    double acc[36];
+    double acc[64];
 #pragma unroll
-    for (int q = 0; q < 36; q++) acc[q] = 0.0;
+    for (int q = 0; q < 64; q++) acc[q] = 0.0;
     for (int i = lane; i < sg.count; i += 64) {
         const int64_t a = pa[sg.start + i], b = pb[sg.start + i];
         double ha[6], hb[6];
@@ -127,14 +127,10 @@ __global__ __launch_bounds__(256) void k_pairs(int32_t n_seg, const PairSeg *__r
 #pragma unroll
             for (int s = 0; s < 6; s++) acc[6 * r + s] = fma(ha[r], hb[s], acc[6 * r + s]);
     }
-#pragma unroll
-    for (int q = 0; q < 36; q++) acc[q] = wave_sum(acc[q]);
+    // lane l < 36 ends with the wave total of entry l of the 6x6 block
+    const double v = wave_reduce_scatter64(acc, lane);
     if (lane < 36) {
         const int r = lane / 6, s = lane % 6;
-        double v = 0.0;
-#pragma unroll
-        for (int q = 0; q < 36; q++)
-            if (q == lane) v = acc[q];
         const int p0 = win_pose_ptr[w];
         const int64_t nw = 6LL * (win_pose_ptr[w + 1] - p0);
         const int la = sg.ja - p0, lb = sg.jb - p0;
@@ -185,12 +181,13 @@ __device__ __forceinline__ void mma_chunk(const double *__restrict__ As, const d
 __device__ __forceinline__ void tile_gemm_nt(double *__restrict__ As, double *__restrict__ Bs,
                                              const double *__restrict__ A, int64_t lda, int64_t ra, int64_t ka,
                                              int64_t nra, int64_t nca, const double *__restrict__ B, int64_t ldb,
-                                             int64_t rb, int64_t kb, int64_t nrb, int64_t ncb, d4 acc[2][2]) {
+                                             int64_t rb, int64_t kb, int64_t nrb, int64_t ncb, d4 acc[2][2],
+                                             int kw = 64) {
 #pragma unroll
     for (int i = 0; i < 2; i++)
 #pragma unroll
         for (int j = 0; j < 2; j++) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
-    for (int kc = 0; kc < 64; kc += 32) {
+    for (int kc = 0; kc < kw; kc += 32) {
         stage_chunk(As, A, lda, ra, ka + kc, nra, nca);
         stage_chunk(Bs, B, ldb, rb, kb + kc, nrb, ncb);
         __syncthreads();
@@ -351,27 +348,48 @@ __global__ __launch_bounds__(256) void k_trsm(const DenseDesc *__restrict__ desc
 }
 
 // Trailing update on matrix cores: C_IJ -= P_I P_J^T for tiles I >= J.
+// Symmetric update on matrix cores of the lower tiles of a region:
+// A[r][c] -= sum_k L[r][k] L[c][k] over the K columns [k0, k0 + kw), for
+// rows r >= T0 and columns T0 <= c < Cend (64x64 tiles, I >= J).  A panel
+// step updates only the rest of its panel (narrow column range); the update
+// after a panel covers the whole trailing matrix with the panel's width as K.
 __global__ __launch_bounds__(256) void k_syrk(const DenseDesc *__restrict__ desc, const DenseParam *__restrict__ prm,
-                                              double *__restrict__ work, int step) {
+                                              double *__restrict__ work, int kstep, int kw, int tstep, int cend_step) {
     __shared__ double sm[2 * TB * LDK];
     double *As = sm, *Bs = sm + TB * LDK;
     const int m = blockIdx.y;
     const DenseDesc d = desc[m];
     if (!prm[m].active || prm[m].info) return;
-    const int64_t k0 = (int64_t)TB * step;
-    const int64_t T0 = k0 + TB;
+    const int64_t k0 = (int64_t)TB * kstep;
+    const int64_t T0 = (int64_t)TB * tstep;
     if (T0 >= d.n) return;
-    const int64_t nt = (d.n - T0 + TB - 1) / TB;
+    const int64_t cend = std::min<int64_t>((int64_t)TB * cend_step, d.n);
+    const int64_t ntr = (d.n - T0 + TB - 1) / TB;            // tile rows
+    const int64_t ntc = (cend - T0 + TB - 1) / TB;           // tile columns
+    if (ntc <= 0) return;
     const int64_t idx = blockIdx.x;
-    if (idx >= nt * (nt + 1) / 2) return;
-    int64_t I = (int64_t)((sqrt(8.0 * (double)idx + 1.0) - 1.0) * 0.5);
-    while (I * (I + 1) / 2 > idx) I--;
-    while ((I + 1) * (I + 2) / 2 <= idx) I++;
-    const int64_t J = idx - I * (I + 1) / 2;
+    int64_t I, J;
+    if (ntc == ntr) {   // whole lower triangle: idx = I (I + 1) / 2 + J
+        if (idx >= ntr * (ntr + 1) / 2) return;
+        I = (int64_t)((sqrt(8.0 * (double)idx + 1.0) - 1.0) * 0.5);
+        while (I * (I + 1) / 2 > idx) I--;
+        while ((I + 1) * (I + 2) / 2 <= idx) I++;
+        J = idx - I * (I + 1) / 2;
+    } else {            // a few tile columns: column J holds tile rows J..ntr-1
+        int64_t r = idx;
+        J = 0;
+        while (J < ntc && r >= ntr - J) {
+            r -= ntr - J;
+            J++;
+        }
+        if (J >= ntc) return;
+        I = J + r;
+    }
     const int64_t ri = T0 + TB * I, rj = T0 + TB * J;
+    const int64_t kend = std::min<int64_t>(k0 + kw, d.n);
     double *A = work + d.a_off;
     d4 acc[2][2];
-    tile_gemm_nt(As, Bs, A, d.n, ri, k0, d.n, k0 + TB, A, d.n, rj, k0, d.n, k0 + TB, acc);
+    tile_gemm_nt(As, Bs, A, d.n, ri, k0, d.n, kend, A, d.n, rj, k0, d.n, kend, acc, kw);
 #pragma unroll
     for (int rb = 0; rb < 2; rb++)
 #pragma unroll
@@ -379,7 +397,7 @@ __global__ __launch_bounds__(256) void k_syrk(const DenseDesc *__restrict__ desc
 #pragma unroll
             for (int r = 0; r < 4; r++) {
                 const int64_t row = ri + ACC_ROW(rb, r), col = rj + ACC_COL(cb);
-                if (row < d.n && col < d.n) A[row * d.n + col] -= acc[rb][cb][r];
+                if (row < d.n && col < cend) A[row * d.n + col] -= acc[rb][cb][r];
             }
 }
 
@@ -625,12 +643,21 @@ ba_status dense_prepare(Problem *P) {
         const int64_t q = o1[r];
         ord[cnt[cscan[pa[q]]]++] = q;
     }
+    // the precision form keeps h in pose-major order (written by the
+    // derivative pass): the pair lists then index that order
+    std::vector<int32_t> q_of_c;
+    if (P->prec == BA_PREC_F32) {
+        std::vector<int32_t> cidx(C);
+        BA_HIP(hipMemcpy(cidx.data(), P->p_cidx, sizeof(int32_t) * C, hipMemcpyDeviceToHost));
+        q_of_c.resize(C);
+        for (int64_t q = 0; q < C; q++) q_of_c[cidx[q]] = (int32_t)q;
+    }
     std::vector<int32_t> spa(E), spb(E);
     std::vector<PairSeg> segs;
     for (int64_t q = 0; q < E; q++) {
         const int64_t o = ord[q];
-        spa[q] = pa[o];
-        spb[q] = pb[o];
+        spa[q] = q_of_c.empty() ? pa[o] : q_of_c[pa[o]];
+        spb[q] = q_of_c.empty() ? pb[o] : q_of_c[pb[o]];
         const int32_t ja = cscan[pa[o]], jb = cscan[pb[o]];
         if (q == 0 || ja != segs.back().ja || jb != segs.back().jb) {
             PairSeg sg;
@@ -729,18 +756,39 @@ static void launch_factor_solve(DenseState *D, int32_t nmat, int32_t max_n, cons
     const int64_t nn = (int64_t)max_n * max_n;
     hipLaunchKernelGGL(k_damp_copy, dim3((unsigned)std::min<int64_t>(nblk(nn), 4096), nmat), dim3(256), 0, s,
                        D->desc, D->prm, H, h_off, g, D->work);
-    for (int st = 0; st < nsteps; st++) {
-        hipLaunchKernelGGL(k_potf2, dim3(1, nmat), dim3(64), 0, s, D->desc, D->prm, D->work, st);
-        const int64_t below = nsteps - st - 1;
-        if (below > 0) {
+    // blocked right-looking Cholesky: panels of PANEL 64-wide steps; a step
+    // updates the rest of its panel, each panel then the trailing matrix with
+    // K = the panel's width (one read and write of the trailing matrix per
+    // panel instead of per step)
+    constexpr int PANEL = 4;
+    for (int p = 0; p < nsteps; p += PANEL) {
+        const int pe = std::min(p + PANEL, nsteps);
+        for (int st = p; st < pe; st++) {
             {
-                ProfScope prof("k_trsm", s);
-                hipLaunchKernelGGL(k_trsm, dim3((unsigned)below, nmat), dim3(256), 0, s, D->desc, D->prm, D->work,
-                                   st);
+                ProfScope prof("k_potf2", s);
+                hipLaunchKernelGGL(k_potf2, dim3(1, nmat), dim3(64), 0, s, D->desc, D->prm, D->work, st);
             }
+            const int64_t below = nsteps - st - 1;
+            if (below > 0) {
+                {
+                    ProfScope prof("k_trsm", s);
+                    hipLaunchKernelGGL(k_trsm, dim3((unsigned)below, nmat), dim3(256), 0, s, D->desc, D->prm,
+                                       D->work, st);
+                }
+                const int64_t cols = pe - st - 1;   // tile columns left in the panel
+                if (cols > 0) {
+                    const int64_t tiles = cols * below - cols * (cols - 1) / 2;
+                    ProfScope prof("k_syrk", s);
+                    hipLaunchKernelGGL(k_syrk, dim3((unsigned)tiles, nmat), dim3(256), 0, s, D->desc, D->prm,
+                                       D->work, st, TB, st + 1, pe);
+                }
+            }
+        }
+        const int64_t rest = nsteps - pe;
+        if (rest > 0) {
             ProfScope prof("k_syrk", s);
-            hipLaunchKernelGGL(k_syrk, dim3((unsigned)(below * (below + 1) / 2), nmat), dim3(256), 0, s, D->desc,
-                               D->prm, D->work, st);
+            hipLaunchKernelGGL(k_syrk, dim3((unsigned)(rest * (rest + 1) / 2), nmat), dim3(256), 0, s, D->desc,
+                               D->prm, D->work, p, TB * (pe - p), pe, nsteps);
         }
     }
     for (int st = nsteps - 1; st >= 0; st--)

@@ -102,6 +102,21 @@ __device__ __forceinline__ double wave_reduce_scatter32(double (&a)[32], int lan
     return a[0] + __shfl_xor(a[0], 1, BA_WAVE);
 }
 
+// Reduce-scatter of 64 per-lane values: after six halving exchanges lane l
+// holds the sum over all 64 lanes of value l (fixed order, deterministic).
+__device__ __forceinline__ double wave_reduce_scatter64(double (&a)[64], int lane) {
+#pragma unroll
+    for (int w = 32; w >= 1; w >>= 1) {
+        const bool hi = lane & w;
+#pragma unroll
+        for (int i = 0; i < w; i++) {
+            const double mine = hi ? a[w + i] : a[i], other = hi ? a[i] : a[w + i];
+            a[i] = mine + __shfl_xor(other, w, BA_WAVE);
+        }
+    }
+    return a[0];
+}
+
 // ---------------------------------------------------------------- error-free transforms
 // Knuth TwoSum: s + e == a + b exactly.
 __device__ __forceinline__ void two_sum(double a, double b, double &s, double &e) {

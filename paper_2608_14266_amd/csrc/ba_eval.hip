@@ -393,7 +393,7 @@ __device__ __forceinline__ void pose_cluster(const SrcF32 &src, const PoseCtx &c
             const double f = (double)n * (0.5 * st[6]);
             double a[3];
             cross(y64, u64, a);
-            double *o = src.h + 6 * (int64_t)src.cidx[q];
+            double *o = src.h + 6 * q;   // pose-major order (the pair plan indexes it so)
             o[0] = f * a[0]; o[1] = f * a[1]; o[2] = f * a[2];
             o[3] = f * u64[0]; o[4] = f * u64[1]; o[5] = f * u64[2];
         }
