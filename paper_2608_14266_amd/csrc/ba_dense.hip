@@ -143,19 +143,6 @@ __global__ __launch_bounds__(256) void k_pairs(int32_t n_seg, const PairSeg *__r
 }
 
 // ---------------------------------------------------------------- MFMA tile helpers
-// Stage a 64 x 32 chunk (rows r0.., columns k0..k0+31) of a row-major matrix
-// (leading dimension ld, valid rows < nr, valid columns < nc) into LDS.
-__device__ __forceinline__ void stage_chunk(double *__restrict__ lds, const double *__restrict__ M, int64_t ld,
-                                            int64_t r0, int64_t k0, int64_t nr, int64_t nc) {
-#pragma unroll
-    for (int e = 0; e < 8; e++) {
-        const int idx = threadIdx.x + 256 * e;
-        const int row = idx >> 5, col = idx & 31;
-        const int64_t gr = r0 + row, gc = k0 + col;
-        lds[row * LDK + col] = (gr < nr && gc < nc) ? M[gr * ld + gc] : 0.0;
-    }
-}
-
 // acc += A_chunk (64x32) * B_chunk (64x32)^T for this wave's 32x32 quadrant.
 // v_mfma_f64_16x16x4f64 operand layout on gfx950 (lane l): A[l%16][l/16],
 // B[l/16][l%16]; accumulator register r holds D[l/16 + 4r][l%16].
@@ -177,7 +164,30 @@ __device__ __forceinline__ void mma_chunk(const double *__restrict__ As, const d
     }
 }
 
-// tile(64x64) = A(rows ra.., cols ka..ka+63) * B(rows rb.., cols kb..kb+63)^T, result in acc
+// The 8 elements of a 64 x 32 chunk this thread stages (rows r0.., columns
+// k0..k0+31 of a row-major matrix; zero outside rows < nr, columns < nc).
+__device__ __forceinline__ void load_chunk(double (&v)[8], const double *__restrict__ M, int64_t ld, int64_t r0,
+                                           int64_t k0, int64_t nr, int64_t nc) {
+#pragma unroll
+    for (int e = 0; e < 8; e++) {
+        const int idx = threadIdx.x + 256 * e;
+        const int row = idx >> 5, col = idx & 31;
+        const int64_t gr = r0 + row, gc = k0 + col;
+        v[e] = (gr < nr && gc < nc) ? M[gr * ld + gc] : 0.0;
+    }
+}
+
+__device__ __forceinline__ void store_chunk(double *__restrict__ lds, const double (&v)[8]) {
+#pragma unroll
+    for (int e = 0; e < 8; e++) {
+        const int idx = threadIdx.x + 256 * e;
+        lds[(idx >> 5) * LDK + (idx & 31)] = v[e];
+    }
+}
+
+// tile(64x64) = A(rows ra.., cols ka..ka+kw-1) * B(rows rb.., cols kb..kb+kw-1)^T,
+// result in acc.  The next K chunk is loaded into registers while the
+// matrix cores work on the current one.
 __device__ __forceinline__ void tile_gemm_nt(double *__restrict__ As, double *__restrict__ Bs,
                                              const double *__restrict__ A, int64_t lda, int64_t ra, int64_t ka,
                                              int64_t nra, int64_t nca, const double *__restrict__ B, int64_t ldb,
@@ -187,10 +197,17 @@ __device__ __forceinline__ void tile_gemm_nt(double *__restrict__ As, double *__
     for (int i = 0; i < 2; i++)
 #pragma unroll
         for (int j = 0; j < 2; j++) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+    double va[8], vb[8];
+    load_chunk(va, A, lda, ra, ka, nra, nca);
+    load_chunk(vb, B, ldb, rb, kb, nrb, ncb);
     for (int kc = 0; kc < kw; kc += 32) {
-        stage_chunk(As, A, lda, ra, ka + kc, nra, nca);
-        stage_chunk(Bs, B, ldb, rb, kb + kc, nrb, ncb);
+        store_chunk(As, va);
+        store_chunk(Bs, vb);
         __syncthreads();
+        if (kc + 32 < kw) {
+            load_chunk(va, A, lda, ra, ka + kc + 32, nra, nca);
+            load_chunk(vb, B, ldb, rb, kb + kc + 32, nrb, ncb);
+        }
         mma_chunk(As, Bs, acc);
         __syncthreads();
     }
