@@ -246,12 +246,37 @@ __device__ __forceinline__ double bcast(double v, int src) {
     return __hiloint2double(hi, lo);
 }
 
-// Factor diagonal block `step`, invert it, forward-substitute its slice of
-// the right-hand side, all in the registers of one wavefront: lane i holds
-// row i of the 64x64 tile; the entries of column j that other lanes need are
-// broadcast as scalars (fully unrolled right-looking sweeps).
-__global__ __launch_bounds__(64) void k_potf2(const DenseDesc *__restrict__ desc, DenseParam *__restrict__ prm,
-                                              double *__restrict__ work, int step) {
+// Orders this lane's LDS writes before the other lanes' later reads within
+// the wavefront (LDS operations of one wavefront complete in issue order).
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Factor diagonal block `step` (A_kk = L L^T), forward-substitute its slice of
+// the right-hand side (y = L^-1 b) and invert the factor (X = L^-1), with two
+// wavefronts working one chunk of POTF2_CHUNK steps apart.
+//  - wave 0, right-looking factorization: lane i holds row i of the tile in
+//    registers; step j scales column j, publishes it as row j of `lt` in LDS
+//    (lt[j][r] = L_rj) and updates the columns to its right from there.  The
+//    next pivot is formed from the lane's own entries and broadcast as a
+//    scalar, so it does not wait for the LDS round trip.  Entries above the
+//    diagonal (c > i) are never read, so updates run on all lanes unmasked.
+//    1/sqrt(pivot) comes from the hardware estimate refined by two Newton
+//    steps r <- r (3 - p r^2) / 2 (about 1 ulp).  y rides along in a register.
+//  - wave 1, inverse: lane c solves L x = e_c for column c of X, right-looking,
+//    reading each column of L from `lt` once wave 0 has published it.
+// A workgroup barrier separates the chunks; within wave 0 the column it
+// publishes is read back after a wavefront-level fence.  A pivot that is not
+// a positive normal number stops the factorization (prm.info = its index + 1).
+static constexpr int LTS = TB + 1;        // padded LDS row stride of the published columns
+static constexpr int POTF2_CHUNK = 8;     // factor steps between the two waves' barriers
+__global__ __launch_bounds__(128) void k_potf2(const DenseDesc *__restrict__ desc, DenseParam *__restrict__ prm,
+                                               double *__restrict__ work, int step) {
+    __shared__ __align__(16) double rdiag[TB];
+    __shared__ __align__(16) double lt[TB * LTS];
+    __shared__ int sfail;
     const int m = blockIdx.y;
     const DenseDesc d = desc[m];
     if (!prm[m].active || prm[m].info) return;
@@ -259,70 +284,78 @@ __global__ __launch_bounds__(64) void k_potf2(const DenseDesc *__restrict__ desc
     if (k0 >= d.n) return;
     const int nb = (int)std::min<int64_t>(TB, d.n - k0);
     double *A = work + d.a_off;
-    const int i = threadIdx.x;
+    const int w = threadIdx.x >> 6;
+    const int i = threadIdx.x & 63;
+    // wave 0: a = row i of the tile (identity outside the nb x nb block);
+    // wave 1: a = column i of the identity, turned into column i of X
     double a[TB];
-#pragma unroll
-    for (int c = 0; c < TB; c++)
-        a[c] = (i < nb && c < nb) ? A[(k0 + i) * d.n + k0 + c] : (i == c ? 1.0 : 0.0);
-    // Cholesky: a[c] of lane i becomes L_ic (c <= i)
-    int fail = 0;
-#pragma unroll
-    for (int j = 0; j < TB; j++) {
-        const double p = bcast(a[j], j);
-        if (!(p > 0.0)) {
-            fail = (int)(k0 + j + 1);
-            break;
-        }
-        const double dj = sqrt(p);
-        if (i == j) a[j] = dj;
-        if (i > j) a[j] = a[j] / dj;
-#pragma unroll
-        for (int c = j + 1; c < TB; c++) {
-            const double lcj = bcast(a[j], c);
-            if (c <= i) a[c] = fma(-a[j], lcj, a[c]);
-        }
-    }
-    if (fail) {   // fail is wave-uniform (the pivot is a broadcast)
-        if (i == 0 && fail <= d.n) prm[m].info = fail;
-        return;
-    }
-    if (i < nb) {
+    double bi = 0.0;
+    if (w == 0) {
 #pragma unroll
         for (int c = 0; c < TB; c++)
-            if (c <= i && c < nb) A[(k0 + i) * d.n + k0 + c] = a[c];
+            a[c] = (i < nb && c < nb) ? A[(k0 + i) * d.n + k0 + c] : (i == c ? 1.0 : 0.0);
+        bi = (i < nb) ? work[d.v_off + k0 + i] : 0.0;
+    } else {
+#pragma unroll
+        for (int r = 0; r < TB; r++) a[r] = (r == i) ? 1.0 : 0.0;
     }
-    // Inverse X = L^-1, right-looking: step k finishes row k of X
-    // (X_k. = T_k. / L_kk), then rows i > k subtract L_ik X_k..  Lane i keeps
-    // L_ik in a[k] until step k, after which a[k] accumulates T_ik.
+    if (threadIdx.x == 0) sfail = 0;
+    __syncthreads();
+    double p = bcast(a[0], 0);
+    int fail = 0, stop = 0;
 #pragma unroll
-    for (int k = 0; k < TB; k++) {
-        const double lkk = bcast(a[k], k);
-        const double rk = 1.0 / lkk;
-        const double lik = (i > k) ? a[k] : 0.0;
-        if (i > k) a[k] = 0.0;
-        if (i == k) {
+    for (int j = 0; j < TB + POTF2_CHUNK; j++) {
+        if (stop) continue;
+        if (w == 0 && j < TB && !fail) {
+            if (!(p >= 2.2250738585072014e-308)) {
+                fail = (int)(k0 + j + 1);
+            } else {
+                double rj = __builtin_amdgcn_rsq(p);
+                rj = rj * fma(-0.5 * p * rj, rj, 1.5);
+                rj = rj * fma(-0.5 * p * rj, rj, 1.5);
+                const double dj = p * rj;
+                a[j] = (i == j) ? dj : a[j] * rj;
+                if (j + 1 < TB) p = bcast(fma(-a[j], a[j], a[j + 1]), j + 1);
+                const double yj = bcast(bi, j) * rj;
+                if (i > j) bi = fma(-a[j], yj, bi);
+                else if (i == j) bi = yj;
+                lt[j * LTS + i] = a[j];
+                if (i == 0) rdiag[j] = rj;
+                if (j + 1 < TB) {
+                    wave_sync();
 #pragma unroll
-            for (int c = 0; c < k; c++) a[c] *= rk;
-            a[k] = rk;
+                    for (int c = j + 1; c < TB; c++) a[c] = fma(-a[j], lt[j * LTS + c], a[c]);
+                }
+            }
         }
+        if (w == 1 && j >= POTF2_CHUNK) {
+            const int r = j - POTF2_CHUNK;
+            a[r] *= rdiag[r];
 #pragma unroll
-        for (int c = 0; c <= k; c++) {
-            const double xkc = bcast(a[c], k);
-            if (i > k) a[c] = fma(-lik, xkc, a[c]);
+            for (int q = r + 1; q < TB; q++) a[q] = fma(-lt[r * LTS + q], a[r], a[q]);
+        }
+        if (j % POTF2_CHUNK == POTF2_CHUNK - 1) {
+            if (w == 0 && i == 0 && fail) sfail = fail;
+            __syncthreads();
+            stop = sfail;
         }
     }
-    double *linv = work + d.linv_off + (int64_t)step * TB * TB;
-#pragma unroll
-    for (int c = 0; c < TB; c++) linv[i * TB + c] = (c <= i) ? a[c] : 0.0;
-    // y_k = L_kk^-1 b_k
-    const double bi = (i < nb) ? work[d.v_off + k0 + i] : 0.0;
-    double y = 0.0;
-#pragma unroll
-    for (int c = 0; c < TB; c++) {
-        const double bc = bcast(bi, c);
-        if (c <= i) y = fma(a[c], bc, y);
+    if (stop) {
+        if (threadIdx.x == 0 && stop <= d.n) prm[m].info = stop;
+        return;
     }
-    if (i < nb) work[d.v_off + k0 + i] = y;
+    if (w == 0) {
+        if (i < nb) {
+#pragma unroll
+            for (int c = 0; c < TB; c++)
+                if (c <= i && c < nb) A[(k0 + i) * d.n + k0 + c] = a[c];
+            work[d.v_off + k0 + i] = bi;
+        }
+    } else {
+        double *linv = work + d.linv_off + (int64_t)step * TB * TB;
+#pragma unroll
+        for (int r = 0; r < TB; r++) linv[r * TB + i] = a[r];
+    }
 }
 
 // Panel solve on matrix cores: rows below block `step`:  P <- P L_kk^-T,
@@ -783,7 +816,7 @@ static void launch_factor_solve(DenseState *D, int32_t nmat, int32_t max_n, cons
         for (int st = p; st < pe; st++) {
             {
                 ProfScope prof("k_potf2", s);
-                hipLaunchKernelGGL(k_potf2, dim3(1, nmat), dim3(64), 0, s, D->desc, D->prm, D->work, st);
+                hipLaunchKernelGGL(k_potf2, dim3(1, nmat), dim3(128), 0, s, D->desc, D->prm, D->work, st);
             }
             const int64_t below = nsteps - st - 1;
             if (below > 0) {
