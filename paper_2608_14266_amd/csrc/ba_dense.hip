@@ -453,7 +453,8 @@ __global__ __launch_bounds__(256) void k_syrk(const DenseDesc *__restrict__ desc
 
 // Backward substitution, block row `step` (descending): x_k = L_kk^-T y_k and
 // y_J -= L_kJ^T x_k for the column tiles J < k (one tile per workgroup).
-// Four threads share each 64-term dot product.
+// Four threads share each 64-term dot product.  The L_kJ tile is loaded
+// before x_k is formed, so the two global reads overlap.
 __global__ __launch_bounds__(256) void k_backsub(const DenseDesc *__restrict__ desc,
                                                  const DenseParam *__restrict__ prm, double *__restrict__ work,
                                                  double *__restrict__ x, const int64_t *__restrict__ x_off, int step) {
@@ -469,30 +470,34 @@ __global__ __launch_bounds__(256) void k_backsub(const DenseDesc *__restrict__ d
     const int nb = (int)std::min<int64_t>(TB, d.n - k0);
     const double *linv = work + d.linv_off + (int64_t)step * TB * TB;
     const int t = threadIdx.x, o = t >> 2, part = t & 3;
+    const bool upd = J < step;
+    const double *A = work + d.a_off;
+    double lkj[16];
+#pragma unroll
+    for (int q = 0; q < 16; q++) {
+        const int r = part + 4 * q;
+        lkj[q] = (upd && r < nb) ? A[(k0 + r) * d.n + TB * J + o] : 0.0;
+    }
+    double li[16];
+#pragma unroll
+    for (int q = 0; q < 16; q++) li[q] = linv[(part + 4 * q) * TB + o];
     if (t < TB) yk[t] = (t < nb) ? work[d.v_off + k0 + t] : 0.0;
     __syncthreads();
     {   // x_k[o] = sum_c Linv[c][o] y[c]
         double s = 0.0;
 #pragma unroll
-        for (int q = 0; q < 16; q++) {
-            const int c = part + 4 * q;
-            s += linv[c * TB + o] * yk[c];
-        }
+        for (int q = 0; q < 16; q++) s += li[q] * yk[part + 4 * q];
         s += __shfl_xor(s, 1, 64);
         s += __shfl_xor(s, 2, 64);
         if (part == 0) xk[o] = s;
     }
     __syncthreads();
     if (J == 0 && t < nb) x[x_off[m] + k0 + t] = xk[t];
-    if (J >= step) return;
-    const double *A = work + d.a_off;
+    if (!upd) return;
     {   // y_J[o] -= sum_r L[k0 + r][64 J + o] x_k[r]
         double s = 0.0;
 #pragma unroll
-        for (int q = 0; q < 16; q++) {
-            const int r = part + 4 * q;
-            if (r < nb) s += A[(k0 + r) * d.n + TB * J + o] * xk[r];
-        }
+        for (int q = 0; q < 16; q++) s += lkj[q] * xk[part + 4 * q];
         s += __shfl_xor(s, 1, 64);
         s += __shfl_xor(s, 2, 64);
         if (part == 0) work[d.v_off + TB * J + o] -= s;

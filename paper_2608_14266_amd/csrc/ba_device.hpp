@@ -102,18 +102,28 @@ __device__ __forceinline__ double wave_reduce_scatter32(double (&a)[32], int lan
     return a[0] + __shfl_xor(a[0], 1, BA_WAVE);
 }
 
+// One halving exchange of a reduce-scatter: lanes with bit W set keep the
+// upper W of the live values, the others the lower W, each adding its
+// partner's copy (constant trip count, so the array stays in registers).
+template <int W>
+__device__ __forceinline__ void reduce_scatter_stage(double (&a)[64], int lane) {
+    const bool hi = lane & W;
+#pragma unroll
+    for (int i = 0; i < W; i++) {
+        const double mine = hi ? a[W + i] : a[i], other = hi ? a[i] : a[W + i];
+        a[i] = mine + __shfl_xor(other, W, BA_WAVE);
+    }
+}
+
 // Reduce-scatter of 64 per-lane values: after six halving exchanges lane l
 // holds the sum over all 64 lanes of value l (fixed order, deterministic).
 __device__ __forceinline__ double wave_reduce_scatter64(double (&a)[64], int lane) {
-#pragma unroll
-    for (int w = 32; w >= 1; w >>= 1) {
-        const bool hi = lane & w;
-#pragma unroll
-        for (int i = 0; i < w; i++) {
-            const double mine = hi ? a[w + i] : a[i], other = hi ? a[i] : a[w + i];
-            a[i] = mine + __shfl_xor(other, w, BA_WAVE);
-        }
-    }
+    reduce_scatter_stage<32>(a, lane);
+    reduce_scatter_stage<16>(a, lane);
+    reduce_scatter_stage<8>(a, lane);
+    reduce_scatter_stage<4>(a, lane);
+    reduce_scatter_stage<2>(a, lane);
+    reduce_scatter_stage<1>(a, lane);
     return a[0];
 }
 
