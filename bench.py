@@ -93,13 +93,18 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--iters", type=int, default=20, help="LM iterations per solve")
     ap.add_argument("--mode", choices=["mm", "coupled"], default="mm")
-    ap.add_argument("--workload", choices=["window", "tiny", "city", "batch", "served"], default="window",
+    ap.add_argument("--workload", choices=["window", "tiny", "city", "batch", "served", "scaling"], default="window",
                     help="window: 500-pose single window (the headline); city: 2000-pose 5 km precision-form "
-                         "map; batch: 256 uneven windows; served: Poisson request stream")
+                         "map; batch: 256 uneven windows; served: Poisson request stream; scaling: "
+                         "build time against points and per-iteration times against clusters and poses")
     ap.add_argument("--rate", type=float, default=20.0, help="served: request arrival rate (req/s)")
     ap.add_argument("--requests", type=int, default=24, help="served: number of requests")
     ap.add_argument("--slots", type=int, default=4, help="served: concurrent requests")
     ap.add_argument("--windows", type=int, default=256, help="batch: number of windows")
+    ap.add_argument("--sweep-poses", type=str, default="1000,2000,5000,10000,20000",
+                    help="scaling: pose counts of the city-law sweep")
+    ap.add_argument("--sweep-points", type=str, default="0.25,0.5,1,2",
+                    help="scaling: window-scene scale factors of the preprocessing sweep (1 = 117M points)")
     ap.add_argument("--cpu-iters", type=int, default=None,
                     help="oracle LM iterations timed for cpu_baseline (default: 20 mm, 1 coupled)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -127,9 +132,10 @@ def main():
         hb.build()
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
-    if args.workload in ("city", "batch", "served"):
+    if args.workload in ("city", "batch", "served", "scaling"):
         import bench_legs
-        out = {"city": bench_legs.city, "batch": bench_legs.batch, "served": bench_legs.served}[args.workload](args)
+        out = {"city": bench_legs.city, "batch": bench_legs.batch, "served": bench_legs.served,
+               "scaling": bench_legs.scaling}[args.workload](args)
         print(json.dumps(out), flush=True)
         return
 

@@ -13,6 +13,12 @@
             slots, device-memory budget), against serial plain FP64 solves of
             the same requests under the same arrivals: p50/p99 latency and
             solves/s.
+  scaling — the three series of the paper's time analysis (Sec. V, Fig. 3):
+            build time against raw points (point-based windows of growing
+            size), per-iteration evaluation time against clusters and
+            per-iteration increment-solve time against poses (the city law at
+            1k..20k poses, loop length grown with the pose count), each with
+            a least-squares line and its R^2.
 
 Inputs are seeded synthetic raw-sum clusters (scenes.sums); every leg
 returns one JSON-ready dict.
@@ -99,7 +105,7 @@ def _kernel_times(ba, prob, P0, mode, iters):
     torch.cuda.synchronize()
     ba.profile_enable(False)
     out = {}
-    for k in ("k_vox", "k_pose", "k_syrk", "k_trsm", "k_potf2"):
+    for k in ("k_vox", "k_pose", "k_syrk", "k_trsm", "k_potf2", "k_window_solve_mm", "k_decide"):
         ms, n = ba.profile_query(k)
         if n:
             out[k] = {"avg_us": round(1e3 * ms / n, 3), "launches": n}
@@ -361,3 +367,96 @@ def served(args):
                                  "gnorm_final_max": float(g64.max())},
             "accuracy": {"served_f32_vs_serial_f64_pose_diff": {"rad": worst_rad, "m": worst_m},
                          "ape_rel_diff_max": ape_rel}}
+
+
+# ---------------------------------------------------------------- scaling
+def _line_fit(x, y):
+    """Least-squares y = a + b x and its coefficient of determination."""
+    x = np.asarray(x, np.float64)
+    y = np.asarray(y, np.float64)
+    A = np.stack([np.ones_like(x), x], axis=1)
+    (a, b), *_ = np.linalg.lstsq(A, y, rcond=None)
+    ss_res = float(((y - (a + b * x)) ** 2).sum())
+    ss_tot = float(((y - y.mean()) ** 2).sum())
+    return {"intercept": float(a), "slope": float(b), "r2": 1.0 - ss_res / ss_tot if ss_tot > 0 else 1.0}
+
+
+def scaling(args):
+    import torch
+    import paper_2608_14266_amd as ba
+    import scenes
+    import scenes.sums as ss
+    dev = torch.device("cuda:0")
+    f = lambda a, dt: torch.as_tensor(np.ascontiguousarray(a), dtype=dt, device=dev)
+    # series 1: build (a0) from device-resident points against the point count
+    pre = []
+    for fac in [float(v) for v in args.sweep_points.split(",") if v]:
+        t0 = time.perf_counter()
+        sc = scenes.window_scene(seed=2000, n_scans=max(8, int(round(500 * fac))),
+                                 n_planes=int(round(200_000 * fac)), length=2000.0 * fac)
+        log(f"scaling: window x{fac}: {sc.n_points} points, generated in {time.perf_counter() - t0:.1f}s")
+        xs, ys, zs = f(sc.x, torch.float64), f(sc.y, torch.float64), f(sc.z, torch.float64)
+        scan, vox = f(sc.scan, torch.int32), f(sc.voxel, torch.int32)
+        ms = []
+        for _ in range(3):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            prob = ba.build_clusters(xs, ys, zs, scan, vox, sc.n_scans, sc.n_voxels)
+            torch.cuda.synchronize()
+            ms.append(1e3 * (time.perf_counter() - t0))
+            C = prob.info()["n_clusters"]
+            prob.close()
+        pre.append({"scale": fac, "points": sc.n_points, "clusters": C, "poses": sc.n_scans,
+                    "build_ms": round(min(ms), 3)})
+        log(f"scaling: build {min(ms):.1f} ms for {sc.n_points} points")
+        del xs, ys, zs, scan, vox, sc
+        torch.cuda.empty_cache()
+    # series 2 and 3: per-iteration evaluation and increment solve (MM)
+    iters = args.iters
+    pts = []
+    for n in [int(v) for v in args.sweep_poses.split(",") if v]:
+        t0 = time.perf_counter()
+        sc = ss.city_sweep_scene(n)
+        log(f"scaling: city sweep {n} poses: {sc.n_clusters} clusters, generated in {time.perf_counter() - t0:.1f}s")
+        arrs = _dev_sums(sc, dev)
+        P0 = torch.as_tensor(sc.poses_init, device=dev)
+        row = {"poses": n, "voxels": sc.n_voxels, "clusters": sc.n_clusters, "virtual_points": sc.n_points}
+        for prec in ("f64", "f32"):
+            prob = _build(ba, sc, arrs, prec, P0)
+            torch.cuda.synchronize()
+            tune = ba.tuned(prob, P0, cache_path=None, reps=3)
+            dt, reps, _ = _timed_solves(ba, prob, P0, ba.MODE_MM, iters, args.steps, args.warmup)
+            kt = _kernel_times(ba, prob, P0, ba.MODE_MM, iters)
+            per = lambda k: kt[k]["avg_us"] if k in kt else 0.0
+            row[prec] = {"ms_per_iteration": round(1e3 * dt / iters, 4),
+                         "eval_us_per_iteration": round(per("k_vox") * kt.get("k_vox", {}).get("launches", 0) / iters
+                                                        + per("k_pose") * kt.get("k_pose", {}).get("launches", 0)
+                                                        / iters, 3),
+                         "k_vox_us": per("k_vox"), "k_pose_us": per("k_pose"),
+                         "solve_us": per("k_window_solve_mm"), "decide_us": per("k_decide"),
+                         "cost_final": reps[0]["cost_final"], "device_bytes": prob.info()["device_bytes"],
+                         "tuning": tune}
+            log(f"scaling: {n} poses {prec}: {row[prec]['ms_per_iteration']:.3f} ms/iteration, "
+                f"k_vox {per('k_vox')} us, k_pose {per('k_pose')} us, solve {per('k_window_solve_mm')} us")
+            prob.close()
+        pts.append(row)
+        del arrs, P0, sc
+        torch.cuda.empty_cache()
+    fits = {"build_ms_vs_points": _line_fit([r["points"] for r in pre], [r["build_ms"] for r in pre])}
+    for prec in ("f64", "f32"):
+        C = [r["clusters"] for r in pts]
+        N = [r["poses"] for r in pts]
+        fits[f"{prec}_eval_us_vs_clusters"] = _line_fit(C, [r[prec]["eval_us_per_iteration"] for r in pts])
+        fits[f"{prec}_iteration_ms_vs_clusters"] = _line_fit(C, [r[prec]["ms_per_iteration"] for r in pts])
+        fits[f"{prec}_solve_us_vs_poses"] = _line_fit(N, [r[prec]["solve_us"] for r in pts])
+    big = pts[-1]
+    V = big["voxels"]
+    return {"metric": "plane-voxel evals/s", "value": V / (1e-3 * big["f32"]["ms_per_iteration"]),
+            "unit": "plane-voxel evals/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+            "higher_is_better": True, "dtype": "f32 clusters / f64 solve (value); f64 alongside",
+            "data": "synthetic",
+            "config": {"workload": f"scaling sweep: city law at {', '.join(str(r['poses']) for r in pts)} poses "
+                                   f"(MM, {iters} LM iterations per solve); window build at "
+                                   f"{', '.join(str(r['points']) for r in pre)} points",
+                       "largest": {k: big[k] for k in ("poses", "voxels", "clusters", "virtual_points")}},
+            "preprocessing": pre, "iterations": pts, "fits": fits}

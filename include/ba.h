@@ -336,8 +336,9 @@ ba_status ba_server_destroy(ba_server *s);
  * Kernel timing (instrumentation, not part of the method): when enabled,
  * later calls record a pair of HIP events on their stream around each launch
  * of the residual kernel ("k_vox"), the derivative kernel ("k_pose"), the
- * diagonal-block factor ("k_potf2") and the matrix-core factorization kernels
- * ("k_trsm", "k_syrk"); ba_iterate then
+ * diagonal-block factor ("k_potf2"), the matrix-core factorization kernels
+ * ("k_trsm", "k_syrk"), the per-window MM increment solve ("k_window_solve_mm")
+ * and the LM decision ("k_decide"); ba_iterate then
  * runs its launches eagerly instead of replaying a captured graph.
  * ba_profile_query waits for the recorded events and returns the summed
  * elapsed time and the launch count of one kernel; ba_profile_reset drops

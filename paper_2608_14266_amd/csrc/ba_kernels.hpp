@@ -22,7 +22,6 @@ void launch_solve_mm_plain(int32_t n, const double *H, const double *g, double m
 void launch_lm_reset(Problem *P, double mu0, double nu0, hipStream_t s);
 void launch_lm_cost(Problem *P, hipStream_t s);
 void launch_window_stats(Problem *P, double tol_g, hipStream_t s);
-void launch_solve_mm_lm(Problem *P, const double *poses, hipStream_t s);
 void launch_window_solve_mm(Problem *P, const double *poses, double tol_g, hipStream_t s);
 DecideArgs decide_args(Problem *P, double *trace, int it, double *poses, int max_rejects);
 void launch_decide(Problem *P, double *trace, int it, double *poses, hipStream_t s, int max_rejects);

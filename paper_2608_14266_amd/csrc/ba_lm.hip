@@ -187,52 +187,60 @@ __global__ void k_commit(int32_t n_poses, const int32_t *__restrict__ pose_windo
     if (!st.done && st.accepted) poses[i] = poses_trial[i];
 }
 
-// One block per window: (when the poses moved, after the per-pose partial
-// reduction) the window's gradient norm, damping floor and convergence test;
-// then every pose's damped 6x6 solve, predicted-reduction share and trial pose.
 // One 512-thread block per window: when the derivatives are fresh, the
-// window's gradient norm and largest Hessian diagonal (same order as
-// k_window_stats); then every pose's damped 6x6 system is solved and the
-// trial pose T (+) dx formed (one pose per thread for windows up to 512 poses).
+// window's gradient norm and largest Hessian diagonal (per thread over poses
+// p0 + t, p0 + t + 512, ..., then the wave totals in wave order) and the
+// convergence test; then every pose's damped 6x6 system is solved and the
+// trial pose T (+) dx formed.  Windows of more than SPLIT_SOLVE_POSES poses
+// take two launches instead, the same statistics in the same order
+// (k_window_stats_mm) and one thread per pose over the whole grid
+// (k_solve_mm_lm), so the results do not depend on which form runs.
 static constexpr int WSOLVE_THREADS = 512;
+static constexpr int SPLIT_SOLVE_POSES = 1024;
+
+// Returns whether the window is finished (block-uniform).
+__device__ __forceinline__ bool window_fresh_stats(LMState &st, const double *__restrict__ g,
+                                                   const double *__restrict__ H, int p0, int p1, double tol_g,
+                                                   double *red, int *s_done) {
+    constexpr int NW = WSOLVE_THREADS / 64;
+    if (!st.need_eval) return false;
+    double gs = 0.0, mx = 0.0;
+    for (int j = p0 + threadIdx.x; j < p1; j += WSOLVE_THREADS) {
+#pragma unroll
+        for (int k = 0; k < 6; k++) {
+            const double gk = g[6LL * j + k];
+            gs = fma(gk, gk, gs);
+            mx = fmax(mx, H[36LL * j + 7 * k]);
+        }
+    }
+    gs = block_sum<NW>(gs, red);
+    mx = block_max<NW>(mx, red);
+    if (threadIdx.x == 0) {
+        st.gnorm = sqrt(gs);
+        st.maxdiag = mx;
+        st.need_eval = 0;
+        if (tol_g > 0.0 && st.gnorm < tol_g) {
+            st.done = 1;
+            st.accepted = 0;
+        }
+        *s_done = st.done;
+    }
+    __syncthreads();
+    return *s_done != 0;
+}
 
 __global__ __launch_bounds__(WSOLVE_THREADS) void k_window_solve_mm(
     int32_t W, const int32_t *__restrict__ win_pose_ptr, LMState *__restrict__ lm, const double *__restrict__ g,
     const double *__restrict__ H, const double *__restrict__ poses, double *__restrict__ dx,
     double *__restrict__ pose_q, int32_t *__restrict__ pose_info, double *__restrict__ poses_trial, double tol_g) {
-    constexpr int NW = WSOLVE_THREADS / 64;
-    __shared__ double red[NW];
+    __shared__ double red[WSOLVE_THREADS / 64];
     __shared__ int s_done;
     const int w = blockIdx.x;
     if (w >= W) return;
     LMState &st = lm[w];
     if (st.done) return;
     const int p0 = win_pose_ptr[w], p1 = win_pose_ptr[w + 1];
-    if (st.need_eval) {
-        double gs = 0.0, mx = 0.0;
-        for (int j = p0 + threadIdx.x; j < p1; j += WSOLVE_THREADS) {
-#pragma unroll
-            for (int k = 0; k < 6; k++) {
-                const double gk = g[6LL * j + k];
-                gs = fma(gk, gk, gs);
-                mx = fmax(mx, H[36LL * j + 7 * k]);
-            }
-        }
-        gs = block_sum<NW>(gs, red);
-        mx = block_max<NW>(mx, red);
-        if (threadIdx.x == 0) {
-            st.gnorm = sqrt(gs);
-            st.maxdiag = mx;
-            st.need_eval = 0;
-            if (tol_g > 0.0 && st.gnorm < tol_g) {
-                st.done = 1;
-                st.accepted = 0;
-            }
-            s_done = st.done;
-        }
-        __syncthreads();
-        if (s_done) return;
-    }
+    if (window_fresh_stats(st, g, H, p0, p1, tol_g, red, &s_done)) return;
     const double mu = st.mu, fl = 1e-12 * st.maxdiag;
     for (int j = p0 + threadIdx.x; j < p1; j += WSOLVE_THREADS) {
         double q;
@@ -243,7 +251,33 @@ __global__ __launch_bounds__(WSOLVE_THREADS) void k_window_solve_mm(
     }
 }
 
+__global__ __launch_bounds__(WSOLVE_THREADS) void k_window_stats_mm(int32_t W,
+                                                                    const int32_t *__restrict__ win_pose_ptr,
+                                                                    LMState *__restrict__ lm,
+                                                                    const double *__restrict__ g,
+                                                                    const double *__restrict__ H, double tol_g) {
+    __shared__ double red[WSOLVE_THREADS / 64];
+    __shared__ int s_done;
+    const int w = blockIdx.x;
+    if (w >= W) return;
+    LMState &st = lm[w];
+    if (st.done) return;
+    (void)window_fresh_stats(st, g, H, win_pose_ptr[w], win_pose_ptr[w + 1], tol_g, red, &s_done);
+}
+
 void launch_window_solve_mm(Problem *P, const double *poses, double tol_g, hipStream_t s) {
+    int32_t widest = 0;
+    for (int32_t w = 0; w < P->n_windows; w++)
+        widest = std::max(widest, P->h_win_pose_ptr[w + 1] - P->h_win_pose_ptr[w]);
+    ProfScope prof("k_window_solve_mm", s);
+    if (widest > SPLIT_SOLVE_POSES) {
+        hipLaunchKernelGGL(k_window_stats_mm, dim3(P->n_windows), dim3(WSOLVE_THREADS), 0, s, P->n_windows,
+                           P->win_pose_ptr, P->lm, P->g, P->H, tol_g);
+        hipLaunchKernelGGL(k_solve_mm_lm, dim3((unsigned)((P->n_poses + 255) / 256)), dim3(256), 0, s, P->n_poses,
+                           P->pose_window, P->win_pose_ptr, P->lm, P->H, P->g, poses, P->dx, P->pose_q, P->pose_info,
+                           P->poses_trial);
+        return;
+    }
     hipLaunchKernelGGL(k_window_solve_mm, dim3(P->n_windows), dim3(WSOLVE_THREADS), 0, s, P->n_windows,
                        P->win_pose_ptr, P->lm, P->g, P->H, poses, P->dx, P->pose_q, P->pose_info, P->poses_trial,
                        tol_g);
@@ -320,11 +354,6 @@ void launch_window_stats(Problem *P, double tol_g, hipStream_t s) {
                        P->H, P->lm, tol_g);
 }
 
-void launch_solve_mm_lm(Problem *P, const double *poses, hipStream_t s) {
-    hipLaunchKernelGGL(k_solve_mm_lm, dim3(nblk(P->n_poses)), dim3(256), 0, s, P->n_poses, P->pose_window,
-                       P->win_pose_ptr, P->lm, P->H, P->g, poses, P->dx, P->pose_q, P->pose_info, P->poses_trial);
-}
-
 DecideArgs decide_args(Problem *P, double *trace, int it, double *poses, int max_rejects) {
     DecideArgs da;
     da.max_rejects = max_rejects;
@@ -344,6 +373,7 @@ DecideArgs decide_args(Problem *P, double *trace, int it, double *poses, int max
 
 void launch_decide(Problem *P, double *trace, int it, double *poses, hipStream_t s, int max_rejects) {
     DecideArgs da = decide_args(P, trace, it, poses, max_rejects);
+    ProfScope prof("k_decide", s);
     hipLaunchKernelGGL(k_decide, dim3(P->n_windows), dim3(DECIDE_THREADS), 0, s, da);
 }
 

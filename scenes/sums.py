@@ -110,7 +110,8 @@ def _nearest_observers(t_true, centres, m, obs_radius):
     tree = cKDTree(t_true)
     n_planes = centres.shape[0]
     kq = int(min(m.max(), t_true.shape[0]))
-    dist, idx = tree.query(centres, k=kq, distance_upper_bound=obs_radius)
+    import os
+    dist, idx = tree.query(centres, k=kq, distance_upper_bound=obs_radius, workers=min(16, os.cpu_count() or 1))
     dist = dist.reshape(n_planes, kq)
     idx = idx.reshape(n_planes, kq)
     valid = np.isfinite(dist) & (np.arange(kq)[None, :] < m[:, None])
@@ -280,3 +281,66 @@ def request_scene(seed: int, n_poses: int, vox_per_pose: int = 400, **kw) -> Sum
     init = _perturb(rng, r, t, math.radians(kw.get("rot_bound_deg", 0.5)), kw.get("trans_bound", 0.05))
     return SumsScene(f"request-{n_poses}pose", seed, ov, os_, npts, s1, s2, n_poses, vox_per_pose * n_poses,
                      _pack(r, t), init)
+
+
+_SWEEP: dict = {}
+
+
+def _sweep_sums_job(args):
+    seed, k, a, b = args
+    g = _SWEEP
+    # chunk k draws from its own stream: Philox keyed by the seed, advanced by
+    # (k + 1) jumps of 2^128 draws (the main stream is the unjumped one)
+    rng = np.random.Generator(np.random.Philox(key=int(seed)).jumped(k + 1))
+    return _cluster_sums(rng, g["centres"], g["nrm"], g["obs_v"][a:b], g["obs_s"][a:b], g["npts"][a:b],
+                         g["r_true"], g["t_true"], g["sigma"], chunk=b - a)
+
+
+def city_sweep_scene(n_scans: int, planes_per_pose: int = 500, seed: int = 5000, geom_p: float = 0.15,
+                     m_max: int = 30, pts_range=(20, 1000), sigma: float = 0.03, rot_bound_deg: float = 1.0,
+                     trans_bound: float = 0.10, place_radius: float = 40.0, obs_radius: float = 80.0,
+                     chunk: int = 1 << 20, workers: int | None = None) -> SumsScene:
+    """A member of the scaling sweep: the city law (``city_config``) with the
+    loop grown in proportion to the pose count, so pose spacing (6.5 m),
+    planes per pose and observers per plane stay fixed and the cluster count
+    grows linearly with ``n_scans`` (2000 poses: a 5 km x 1 km loop).  The
+    cluster statistics are drawn in chunks of ``chunk`` observations, each
+    from its own jumped Philox stream, by up to ``workers`` processes
+    (default: min(16, cpu count)); the result does not depend on it."""
+    import os
+    rng = _rng(seed)
+    f = n_scans / 2000.0
+    t_true, head = _city_trajectory(n_scans, width=5000.0 * f, height=1000.0 * f)
+    r_true = _rz(head)
+    n_planes = planes_per_pose * n_scans
+    nrm = _unit_normals(rng, n_planes)
+    anchor = rng.integers(0, n_scans, size=n_planes)
+    d = rng.standard_normal((n_planes, 3))
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    centres = t_true[anchor] + d * (place_radius * np.cbrt(rng.uniform(0.0, 1.0, size=n_planes)))[:, None]
+    m = _truncated_geometric(rng, geom_p, m_max, n_planes)
+    obs_v, obs_s = _nearest_observers(t_true, centres, m, obs_radius)
+    npts = _loglog_counts(rng, pts_range[0], pts_range[1], obs_v.shape[0])
+    C = obs_v.shape[0]
+    jobs = [(seed, k, a, min(C, a + chunk)) for k, a in enumerate(range(0, C, chunk))]
+    _SWEEP.clear()
+    _SWEEP.update(centres=centres, nrm=nrm, obs_v=obs_v, obs_s=obs_s, npts=npts, r_true=r_true, t_true=t_true,
+                  sigma=sigma)
+    workers = workers or min(16, os.cpu_count() or 1)
+    try:
+        if workers > 1 and len(jobs) > 1:
+            from concurrent.futures import ProcessPoolExecutor
+            import multiprocessing as mp
+            with ProcessPoolExecutor(max_workers=workers, mp_context=mp.get_context("fork")) as ex:
+                parts = list(ex.map(_sweep_sums_job, jobs, chunksize=1))
+        else:
+            parts = [_sweep_sums_job(j) for j in jobs]
+    finally:
+        _SWEEP.clear()
+    s1 = np.concatenate([p[0] for p in parts])
+    s2 = np.concatenate([p[1] for p in parts])
+    init = _perturb(rng, r_true, t_true, math.radians(rot_bound_deg), trans_bound)
+    return SumsScene(f"city-sweep-{n_scans}pose-{n_planes}vox", seed, obs_v, obs_s, npts, s1, s2, n_scans,
+                     n_planes, _pack(r_true, t_true), init,
+                     meta=dict(sigma=sigma, geom_p=geom_p, m_max=m_max, pts_range=pts_range,
+                               planes_per_pose=planes_per_pose))

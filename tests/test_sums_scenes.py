@@ -67,3 +67,22 @@ def test_batch_windows_are_disjoint_and_parallel_generation_is_exact():
         assert sw.voxel.min() >= 0 and sw.voxel.max() < sw.n_voxels
         tot += sw.n_clusters
     assert tot == a.n_clusters
+
+
+def test_city_sweep_parallel_generation_is_exact_and_scales_linearly():
+    """The scaling-sweep scenes do not depend on the number of generator
+    processes, keep the pose spacing of the 2000-pose city loop, and grow
+    their cluster count in proportion to the pose count."""
+    a = ss.city_sweep_scene(400, planes_per_pose=60, chunk=1 << 13, workers=3)
+    b = ss.city_sweep_scene(400, planes_per_pose=60, chunk=1 << 13, workers=1)
+    for k in ("voxel", "scan", "count", "sum", "sumsq", "poses_true", "poses_init"):
+        assert np.array_equal(getattr(a, k), getattr(b, k)), k
+    c = ss.city_sweep_scene(800, planes_per_pose=60, chunk=1 << 13, workers=2)
+    step = lambda sc: np.median(np.linalg.norm(np.diff(sc.poses_true[:, 9:], axis=0), axis=1))
+    # 13 km of route (12 km loop + 1 km cross street) for 2000 poses: 6.5 m
+    # between poses at every size
+    assert abs(step(a) - 6.5) < 0.05 and abs(step(c) - 6.5) < 0.05
+    assert abs(c.n_clusters / a.n_clusters - 2.0) < 0.1
+    # every cluster's scatter is positive semi-definite in the scan frame
+    n, mu, S = _centred(c)
+    assert np.all(np.linalg.eigvalsh(S)[:, 0] > -1e-9 * np.abs(S).max(axis=(1, 2)))
