@@ -17,10 +17,10 @@ Definitions followed here (readings in the design notes):
     clusters of the same scan whose cells share a parent;
   - selection: the voxel covariance A of a cell's clusters mapped by the poses
     (Eq. 1, centred), eigenvalues l0 <= l1 <= l2; the cell is kept when
-    l0 < tau * l1 (the paper's test) and l1 > 1e-10 * l2 (a reading: a
-    covariance of rank below two -- one point, or points on a line -- is not a
-    plane, and its l1 is pure rounding), and (an option beyond the paper's
-    rule) when at least min_scans scans observe it;
+    l0 < tau * l1 (the paper's test), the cell holds at least three points
+    and l1 > 1e-10 * l2 (readings: fewer than three points, or points on a
+    line, span no plane, and such a covariance's l1 is only rounding), and (an
+    option beyond the paper's rule) when at least min_scans scans observe it;
   - output: the kept cells of all levels concatenated in (level, cell, scan)
     order, voxel ids numbered densely in that order.
 """
@@ -87,8 +87,9 @@ def select(cl, poses, tau, min_scans=1):
     A = np.add.reduceat(Sw + n[:, None, None] * d[:, :, None] * d[:, None, :], vstart, axis=0) / Nv[:, None, None]
     lam = np.linalg.eigvalsh(A)
     n_scans = np.diff(np.append(vstart, cell.shape[0]))
-    keep = (lam[:, 1] > RANK2 * lam[:, 2]) & (lam[:, 0] < tau * lam[:, 1]) & (n_scans >= min_scans)
-    return dict(vstart=vstart, lam=lam, keep=keep, n_scans=n_scans, n_voxels=V)
+    keep = ((Nv >= 3) & (lam[:, 1] > RANK2 * lam[:, 2]) & (lam[:, 0] < tau * lam[:, 1])
+            & (n_scans >= min_scans))
+    return dict(vstart=vstart, lam=lam, keep=keep, n_scans=n_scans, n_points=Nv.astype(np.int64), n_voxels=V)
 
 
 def voxelize(x, y, z, scan, poses, d, levels, tau, min_scans=1):
