@@ -406,10 +406,25 @@ def scaling(args):
             ms.append(1e3 * (time.perf_counter() - t0))
             C = prob.info()["n_clusters"]
             prob.close()
+        # the paper's preprocessing: bottom-up voxelization of the unlabelled
+        # points at the initial poses (d = 0.5 m, 3 levels, tau = 0.05, seen by
+        # at least 2 scans)
+        P0 = f(sc.poses_init, torch.float64)
+        vms = []
+        for _ in range(3):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            vm = ba.voxelize(xs, ys, zs, scan, P0, 0.5, 3, 0.05, 2)
+            torch.cuda.synchronize()
+            vms.append(1e3 * (time.perf_counter() - t0))
+            vinf = vm.info()
+            vm.close()
         pre.append({"scale": fac, "points": sc.n_points, "clusters": C, "poses": sc.n_scans,
-                    "build_ms": round(min(ms), 3)})
-        log(f"scaling: build {min(ms):.1f} ms for {sc.n_points} points")
-        del xs, ys, zs, scan, vox, sc
+                    "build_ms": round(min(ms), 3), "voxelize_ms": round(min(vms), 3),
+                    "voxelize": {k: vinf[k] for k in ("n_voxels", "n_clusters", "level_voxels", "level_clusters",
+                                                      "level_kept_voxels")}})
+        log(f"scaling: build {min(ms):.1f} ms, voxelize {min(vms):.1f} ms for {sc.n_points} points")
+        del xs, ys, zs, scan, vox, sc, P0
         torch.cuda.empty_cache()
     # series 2 and 3: per-iteration evaluation and increment solve (MM)
     iters = args.iters
@@ -442,7 +457,8 @@ def scaling(args):
         pts.append(row)
         del arrs, P0, sc
         torch.cuda.empty_cache()
-    fits = {"build_ms_vs_points": _line_fit([r["points"] for r in pre], [r["build_ms"] for r in pre])}
+    fits = {"build_ms_vs_points": _line_fit([r["points"] for r in pre], [r["build_ms"] for r in pre]),
+            "voxelize_ms_vs_points": _line_fit([r["points"] for r in pre], [r["voxelize_ms"] for r in pre])}
     for prec in ("f64", "f32"):
         C = [r["clusters"] for r in pts]
         N = [r["poses"] for r in pts]

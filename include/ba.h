@@ -333,6 +333,80 @@ ba_status ba_server_wait(ba_server *s, int64_t id, double *poses_out, ba_request
 ba_status ba_server_destroy(ba_server *s);
 
 /*
+ * Bottom-up multi-level voxelization and planar voxel selection (Sec. IV-A:
+ * Eq. 4-5, Alg. 1 BottomUpVoxelization and Selection).  Turns unlabelled
+ * body-frame points into the planar voxels the problem is built from:
+ *   1. every point p of scan j is mapped to the world at the given poses,
+ *      w = R_j p + t_j, each component evaluated as ((R_r0 p_x + R_r1 p_y) +
+ *      R_r2 p_z) + t_r with every product and sum rounded on its own, and
+ *      assigned the level-1 cell floor(w / d) per axis (Eq. 4);
+ *   2. points of one scan in one cell form a cluster (N, sum p, sum p p^T) in
+ *      the scan's body frame (Eq. 2);
+ *   3. level k = 2..L halves the cell indices of level k-1 (floor, Eq. 5) and
+ *      merges the clusters of one scan that share a parent cell;
+ *   4. every cell of every level is tested: its clusters mapped by the poses
+ *      give the voxel covariance (Eq. 1) with eigenvalues l0 <= l1 <= l2; the
+ *      cell is kept when l0 < tau * l1 (the paper's test), it holds at
+ *      least three points and l1 > 1e-10 * l2 (fewer points or a line span no
+ *      plane; their l1 is only rounding), and at least min_scans scans observe
+ *      it (min_scans is an option beyond the paper's rule; 0 or 1 leaves the
+ *      planarity test alone);
+ *   5. the kept cells of all levels are concatenated in (level, cell x, cell
+ *      y, cell z) order and numbered 0..n_voxels-1 in that order; each keeps
+ *      its clusters in scan order.
+ * A point contributes to one cell per level, so a kept fine cell and its kept
+ * parent both carry it (the multi-resolution features of Sec. IV-A).  The
+ * exported clusters are the raw-sum input of ba_build_clusters_from_sums.
+ * Sums are formed in a fixed order (bitwise reproducible).
+ */
+#define BA_VOXEL_MAX_LEVELS 16
+
+typedef struct ba_voxel_map ba_voxel_map;
+
+typedef struct ba_voxelize_options {
+    double d;            /* edge of the level-1 cells, > 0 (the minimal resolution of Sec. IV-A) */
+    int32_t levels;      /* L, 1..BA_VOXEL_MAX_LEVELS: level k has edge 2^(k-1) d */
+    int32_t min_scans;   /* a kept cell is observed by at least this many scans (0 or 1: no requirement) */
+    double tau;          /* planarity threshold, > 0: kept when l0 < tau * l1 */
+} ba_voxelize_options;
+
+typedef struct ba_voxel_map_info {
+    int64_t n_points;
+    int64_t n_clusters;   /* exported clusters (those of the kept cells) */
+    int32_t n_voxels;     /* kept cells over all levels */
+    int32_t levels;
+    int32_t n_scans;
+    int32_t reserved;
+    int64_t level_voxels[BA_VOXEL_MAX_LEVELS];         /* cells formed at each level */
+    int64_t level_clusters[BA_VOXEL_MAX_LEVELS];       /* (cell, scan) clusters formed at each level */
+    int64_t level_kept_voxels[BA_VOXEL_MAX_LEVELS];    /* cells kept at each level */
+    int64_t level_kept_clusters[BA_VOXEL_MAX_LEVELS];  /* their clusters */
+    int64_t device_bytes;                              /* device memory held by the map */
+} ba_voxel_map_info;
+
+/* Voxelize n body-frame points (device x, y, z, scan, length n; 0 <= scan <
+ * n_scans) at the poses (device [n_scans][12]).  Synchronous.  On success
+ * *out owns the kept clusters in device memory (release with
+ * ba_voxel_map_destroy); on error *out is NULL.  Errors: BA_E_ARG (null
+ * argument, n outside [1, 2^32), options out of range, a scan id out of
+ * range, a non-finite world point or a cell index beyond 2^30 at edge d),
+ * BA_E_UNSUPPORTED (the cloud's cell range and scan count need more than 64
+ * key bits: use a larger d), BA_E_NOMEM, BA_E_HIP. */
+ba_status ba_voxelize(const double *x, const double *y, const double *z, const int32_t *scan, int64_t n,
+                      int32_t n_scans, const double *poses, const ba_voxelize_options *opt, ba_voxel_map **out,
+                      hipStream_t stream);
+ba_status ba_voxel_map_get_info(const ba_voxel_map *m, ba_voxel_map_info *info);
+/* Copy the kept clusters into caller-owned device arrays (any may be NULL to
+ * skip it): voxel, scan [n_clusters] int32; count [n_clusters] int64; sum
+ * [n_clusters][3] and sumsq [n_clusters][6] f64 (body frame, [xx xy xz yy yz
+ * zz]); voxel_level [n_voxels] int32 (1..L); voxel_cell [n_voxels][3] int32
+ * (the cell's integer indices at its level).  Clusters are ordered by (voxel,
+ * scan).  Asynchronous on the stream. */
+ba_status ba_voxel_map_export(const ba_voxel_map *m, int32_t *voxel, int32_t *scan, int64_t *count, double *sum,
+                              double *sumsq, int32_t *voxel_level, int32_t *voxel_cell, hipStream_t stream);
+ba_status ba_voxel_map_destroy(ba_voxel_map *m);
+
+/*
  * Kernel timing (instrumentation, not part of the method): when enabled,
  * later calls record a pair of HIP events on their stream around each launch
  * of the residual kernel ("k_vox"), the derivative kernel ("k_pose"), the

@@ -16,6 +16,7 @@ from ._lib import (  # noqa: F401
     BAError,
     Problem,
     Server,
+    VoxelMap,
     autotune,
     build_clusters,
     build_clusters_from_sums,
@@ -31,5 +32,6 @@ from ._lib import (  # noqa: F401
     request_footprint,
     solve_increment,
     solve_increment_workspace,
+    voxelize,
 )
 from .tuning import tuned  # noqa: F401,E402

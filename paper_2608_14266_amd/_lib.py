@@ -85,6 +85,21 @@ class _ReqStatus(ct.Structure):
 _lib = None
 
 
+VOXEL_MAX_LEVELS = 16
+
+
+class _VoxOpts(ct.Structure):
+    _fields_ = [("d", ct.c_double), ("levels", ct.c_int32), ("min_scans", ct.c_int32), ("tau", ct.c_double)]
+
+
+class _VoxInfo(ct.Structure):
+    _fields_ = [("n_points", ct.c_int64), ("n_clusters", ct.c_int64), ("n_voxels", ct.c_int32),
+                ("levels", ct.c_int32), ("n_scans", ct.c_int32), ("reserved", ct.c_int32),
+                ("level_voxels", ct.c_int64 * VOXEL_MAX_LEVELS), ("level_clusters", ct.c_int64 * VOXEL_MAX_LEVELS),
+                ("level_kept_voxels", ct.c_int64 * VOXEL_MAX_LEVELS),
+                ("level_kept_clusters", ct.c_int64 * VOXEL_MAX_LEVELS), ("device_bytes", ct.c_int64)]
+
+
 def lib_path() -> str:
     return _LIB_PATH
 
@@ -145,6 +160,14 @@ def load():
     L.ba_server_wait.argtypes = [P, ct.c_int64, P, ct.POINTER(_ReqStatus)]
     L.ba_server_destroy.restype = i32
     L.ba_server_destroy.argtypes = [P]
+    L.ba_voxelize.restype = i32
+    L.ba_voxelize.argtypes = [P, P, P, P, ct.c_int64, i32, P, ct.POINTER(_VoxOpts), ct.POINTER(P), P]
+    L.ba_voxel_map_get_info.restype = i32
+    L.ba_voxel_map_get_info.argtypes = [P, ct.POINTER(_VoxInfo)]
+    L.ba_voxel_map_export.restype = i32
+    L.ba_voxel_map_export.argtypes = [P, P, P, P, P, P, P, P, P]
+    L.ba_voxel_map_destroy.restype = i32
+    L.ba_voxel_map_destroy.argtypes = [P]
     _lib = L
     return L
 
@@ -455,3 +478,70 @@ class Server:
             self.close()
         except Exception:
             pass
+
+
+# ---------------------------------------------------------------- voxelization
+class VoxelMap:
+    """Kept planar cells of a multi-level voxelization (:func:`voxelize`)."""
+
+    def __init__(self, handle: ct.c_void_p):
+        self._h = handle
+
+    def info(self) -> dict:
+        inf = _VoxInfo()
+        _check(load().ba_voxel_map_get_info(self._h, ct.byref(inf)))
+        L = inf.levels
+        return {"n_points": inf.n_points, "n_clusters": inf.n_clusters, "n_voxels": inf.n_voxels, "levels": L,
+                "n_scans": inf.n_scans, "level_voxels": list(inf.level_voxels[:L]),
+                "level_clusters": list(inf.level_clusters[:L]), "level_kept_voxels": list(inf.level_kept_voxels[:L]),
+                "level_kept_clusters": list(inf.level_kept_clusters[:L]), "device_bytes": inf.device_bytes}
+
+    def export(self) -> dict:
+        """voxel, scan (C,) int32; count (C,) int64; sum (C,3), sumsq (C,6) f64;
+        voxel_level (V,) int32; voxel_cell (V,3) int32 -- device tensors."""
+        inf = self.info()
+        C, V = inf["n_clusters"], inf["n_voxels"]
+        dev = torch.cuda.current_device()
+        out = {"voxel": torch.empty(C, dtype=torch.int32, device=dev),
+               "scan": torch.empty(C, dtype=torch.int32, device=dev),
+               "count": torch.empty(C, dtype=torch.int64, device=dev),
+               "sum": torch.empty((C, 3), dtype=torch.float64, device=dev),
+               "sumsq": torch.empty((C, 6), dtype=torch.float64, device=dev),
+               "voxel_level": torch.empty(V, dtype=torch.int32, device=dev),
+               "voxel_cell": torch.empty((V, 3), dtype=torch.int32, device=dev)}
+        o = out
+        _check(load().ba_voxel_map_export(self._h, _ptr(o["voxel"]), _ptr(o["scan"]), _ptr(o["count"]),
+                                          _ptr(o["sum"]), _ptr(o["sumsq"]), _ptr(o["voxel_level"]),
+                                          _ptr(o["voxel_cell"]), _stream()))
+        return out
+
+    def close(self):
+        if self._h:
+            load().ba_voxel_map_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def voxelize(x, y, z, scan, poses, d: float, levels: int, tau: float, min_scans: int = 1,
+             n_scans: int | None = None) -> VoxelMap:
+    """ba_voxelize: body-frame points (device tensors) at the poses -> kept
+    planar cells of every level.  Synchronous."""
+    x = _dev(x, torch.float64, "x"); y = _dev(y, torch.float64, "y"); z = _dev(z, torch.float64, "z")
+    scan = _dev(scan, torch.int32, "scan")
+    poses = _dev(poses, torch.float64, "poses")
+    n = x.numel()
+    if not (y.numel() == n and z.numel() == n and scan.numel() == n):
+        raise ValueError("point arrays have inconsistent sizes")
+    N = poses.numel() // 12 if n_scans is None else int(n_scans)
+    if poses.numel() != 12 * N:
+        raise ValueError("poses must hold 12 doubles per scan")
+    o = _VoxOpts(float(d), int(levels), int(min_scans), float(tau))
+    h = ct.c_void_p()
+    _check(load().ba_voxelize(_ptr(x), _ptr(y), _ptr(z), _ptr(scan), n, N, _ptr(poses), ct.byref(o), ct.byref(h),
+                              _stream()))
+    return VoxelMap(h)

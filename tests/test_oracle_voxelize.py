@@ -129,3 +129,19 @@ def test_plane_is_kept_and_blob_rejected():
         dense = np.add.reduceat(lvl["count"], lvl["vstart"]) >= 50
         assert np.all(lvl["keep"][plane_cells & dense])
         assert not np.any(lvl["keep"][~plane_cells & dense])
+
+
+def test_cells_of_fewer_than_three_points_or_a_line_are_not_planes():
+    """One or two points, or points on a line, span no plane (their l1 is
+    rounding); three points in general position always lie in a plane."""
+    P = np.array([[1.0, 0, 0, 0, 1, 0, 0, 0, 1, 0, 0, 0]])
+    cases = {  # cell centre offsets inside [0, 1)^3 cells at d = 1
+        "one": [[0.5, 0.5, 0.5]],
+        "two": [[0.2, 0.3, 0.4], [0.7, 0.6, 0.5]],
+        "line": [[0.1, 0.1, 0.1], [0.4, 0.4, 0.4], [0.9, 0.9, 0.9]],
+        "three": [[0.1, 0.2, 0.3], [0.8, 0.2, 0.5], [0.4, 0.9, 0.1]],
+    }
+    for name, pts in cases.items():
+        p = np.asarray(pts) + np.array([3.0, -2.0, 7.0])
+        res = vz.voxelize(p[:, 0], p[:, 1], p[:, 2], np.zeros(len(p), np.int64), P, 1.0, 1, tau=0.5)
+        assert bool(res["levels"][0]["keep"][0]) == (name == "three"), name
