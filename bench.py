@@ -93,10 +93,12 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--iters", type=int, default=20, help="LM iterations per solve")
     ap.add_argument("--mode", choices=["mm", "coupled"], default="mm")
-    ap.add_argument("--workload", choices=["window", "tiny", "city", "batch", "served", "scaling"], default="window",
+    ap.add_argument("--workload", choices=["window", "tiny", "city", "batch", "served", "scaling", "pipeline"],
+                    default="window",
                     help="window: 500-pose single window (the headline); city: 2000-pose 5 km precision-form "
                          "map; batch: 256 uneven windows; served: Poisson request stream; scaling: "
-                         "build time against points and per-iteration times against clusters and poses")
+                         "build time against points and per-iteration times against clusters and poses; "
+                         "pipeline: unlabelled points -> voxelize -> build -> solve")
     ap.add_argument("--rate", type=float, default=20.0, help="served: request arrival rate (req/s)")
     ap.add_argument("--requests", type=int, default=24, help="served: number of requests")
     ap.add_argument("--slots", type=int, default=4, help="served: concurrent requests")
@@ -132,10 +134,10 @@ def main():
         hb.build()
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
-    if args.workload in ("city", "batch", "served", "scaling"):
+    if args.workload in ("city", "batch", "served", "scaling", "pipeline"):
         import bench_legs
         out = {"city": bench_legs.city, "batch": bench_legs.batch, "served": bench_legs.served,
-               "scaling": bench_legs.scaling}[args.workload](args)
+               "scaling": bench_legs.scaling, "pipeline": bench_legs.pipeline}[args.workload](args)
         print(json.dumps(out), flush=True)
         return
 
