@@ -376,7 +376,7 @@ typedef struct ba_voxel_map_info {
     int32_t n_voxels;     /* kept cells over all levels */
     int32_t levels;
     int32_t n_scans;
-    int32_t reserved;
+    int32_t n_batches;    /* batches of ba_voxelize_host (0 for ba_voxelize) */
     int64_t level_voxels[BA_VOXEL_MAX_LEVELS];         /* cells formed at each level */
     int64_t level_clusters[BA_VOXEL_MAX_LEVELS];       /* (cell, scan) clusters formed at each level */
     int64_t level_kept_voxels[BA_VOXEL_MAX_LEVELS];    /* cells kept at each level */
@@ -395,6 +395,28 @@ typedef struct ba_voxel_map_info {
 ba_status ba_voxelize(const double *x, const double *y, const double *z, const int32_t *scan, int64_t n,
                       int32_t n_scans, const double *poses, const ba_voxelize_options *opt, ba_voxel_map **out,
                       hipStream_t stream);
+/* Adaptive asynchronous loader (Sec. IV-A): the same voxelization for points
+ * held in host memory, for clouds larger than device memory.  Device memory is
+ * split by the ratio alpha: a point segment sized alpha x (free device memory)
+ * holds two batches in flight, the rest holds clusters.  Batch b + 1 is staged
+ * (when the host arrays are not pinned: copied into pinned buffers by a few
+ * host threads) and transferred on a second stream while batch b is turned
+ * into level-1 clusters; all batches' clusters of one (cell, scan) are then
+ * merged by one sort (raw sums added in batch order), and the levels,
+ * selection and export proceed as in ba_voxelize.  Cells, counts and kept
+ * cells equal ba_voxelize's; sums agree to rounding (different addition
+ * order).  Synchronous. */
+typedef struct ba_stream_options {
+    double alpha;           /* share of the free device memory for the point batches, (0, 1]; 0 -> 0.5 */
+    int64_t batch_points;   /* points per batch (>= 1024); 0 -> derived from alpha */
+} ba_stream_options;
+
+/* x, y, z, scan: host arrays of length n (pinned or pageable); poses: device
+ * [n_scans][12]; so may be NULL (defaults).  Errors as ba_voxelize, plus
+ * BA_E_ARG for alpha outside (0, 1] or a negative batch size. */
+ba_status ba_voxelize_host(const double *x, const double *y, const double *z, const int32_t *scan, int64_t n,
+                           int32_t n_scans, const double *poses, const ba_voxelize_options *opt,
+                           const ba_stream_options *so, ba_voxel_map **out, hipStream_t stream);
 ba_status ba_voxel_map_get_info(const ba_voxel_map *m, ba_voxel_map_info *info);
 /* Copy the kept clusters into caller-owned device arrays (any may be NULL to
  * skip it): voxel, scan [n_clusters] int32; count [n_clusters] int64; sum

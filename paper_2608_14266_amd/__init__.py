@@ -33,5 +33,6 @@ from ._lib import (  # noqa: F401
     solve_increment,
     solve_increment_workspace,
     voxelize,
+    voxelize_host,
 )
 from .tuning import tuned  # noqa: F401,E402

@@ -92,9 +92,13 @@ class _VoxOpts(ct.Structure):
     _fields_ = [("d", ct.c_double), ("levels", ct.c_int32), ("min_scans", ct.c_int32), ("tau", ct.c_double)]
 
 
+class _StreamOpts(ct.Structure):
+    _fields_ = [("alpha", ct.c_double), ("batch_points", ct.c_int64)]
+
+
 class _VoxInfo(ct.Structure):
     _fields_ = [("n_points", ct.c_int64), ("n_clusters", ct.c_int64), ("n_voxels", ct.c_int32),
-                ("levels", ct.c_int32), ("n_scans", ct.c_int32), ("reserved", ct.c_int32),
+                ("levels", ct.c_int32), ("n_scans", ct.c_int32), ("n_batches", ct.c_int32),
                 ("level_voxels", ct.c_int64 * VOXEL_MAX_LEVELS), ("level_clusters", ct.c_int64 * VOXEL_MAX_LEVELS),
                 ("level_kept_voxels", ct.c_int64 * VOXEL_MAX_LEVELS),
                 ("level_kept_clusters", ct.c_int64 * VOXEL_MAX_LEVELS), ("device_bytes", ct.c_int64)]
@@ -162,6 +166,9 @@ def load():
     L.ba_server_destroy.argtypes = [P]
     L.ba_voxelize.restype = i32
     L.ba_voxelize.argtypes = [P, P, P, P, ct.c_int64, i32, P, ct.POINTER(_VoxOpts), ct.POINTER(P), P]
+    L.ba_voxelize_host.restype = i32
+    L.ba_voxelize_host.argtypes = [P, P, P, P, ct.c_int64, i32, P, ct.POINTER(_VoxOpts), ct.POINTER(_StreamOpts),
+                                   ct.POINTER(P), P]
     L.ba_voxel_map_get_info.restype = i32
     L.ba_voxel_map_get_info.argtypes = [P, ct.POINTER(_VoxInfo)]
     L.ba_voxel_map_export.restype = i32
@@ -492,7 +499,7 @@ class VoxelMap:
         _check(load().ba_voxel_map_get_info(self._h, ct.byref(inf)))
         L = inf.levels
         return {"n_points": inf.n_points, "n_clusters": inf.n_clusters, "n_voxels": inf.n_voxels, "levels": L,
-                "n_scans": inf.n_scans, "level_voxels": list(inf.level_voxels[:L]),
+                "n_scans": inf.n_scans, "n_batches": inf.n_batches, "level_voxels": list(inf.level_voxels[:L]),
                 "level_clusters": list(inf.level_clusters[:L]), "level_kept_voxels": list(inf.level_kept_voxels[:L]),
                 "level_kept_clusters": list(inf.level_kept_clusters[:L]), "device_bytes": inf.device_bytes}
 
@@ -544,4 +551,39 @@ def voxelize(x, y, z, scan, poses, d: float, levels: int, tau: float, min_scans:
     h = ct.c_void_p()
     _check(load().ba_voxelize(_ptr(x), _ptr(y), _ptr(z), _ptr(scan), n, N, _ptr(poses), ct.byref(o), ct.byref(h),
                               _stream()))
+    return VoxelMap(h)
+
+
+def voxelize_host(x, y, z, scan, poses, d: float, levels: int, tau: float, min_scans: int = 1,
+                  alpha: float = 0.5, batch_points: int = 0, n_scans: int | None = None) -> VoxelMap:
+    """ba_voxelize_host: points in host memory (numpy arrays or CPU tensors,
+    pinned or not) streamed to the device in batches, then the same
+    voxelization as :func:`voxelize`.  Synchronous."""
+    import numpy as np
+
+    def host(a, dt, name):
+        if isinstance(a, torch.Tensor):
+            if a.is_cuda:
+                raise TypeError(f"{name} must be in host memory")
+            a = a.contiguous()
+            if a.dtype != dt:
+                raise TypeError(f"{name} must be {dt}")
+            return a, a.data_ptr()
+        npdt = {torch.float64: np.float64, torch.int32: np.int32}[dt]
+        arr = np.ascontiguousarray(a, dtype=npdt)
+        return arr, arr.ctypes.data
+    xs, px = host(x, torch.float64, "x")
+    ys, py = host(y, torch.float64, "y")
+    zs, pz = host(z, torch.float64, "z")
+    ss, ps = host(scan, torch.int32, "scan")
+    n = len(xs)
+    if not (len(ys) == n and len(zs) == n and len(ss) == n):
+        raise ValueError("point arrays have inconsistent sizes")
+    poses = _dev(poses, torch.float64, "poses")
+    N = poses.numel() // 12 if n_scans is None else int(n_scans)
+    o = _VoxOpts(float(d), int(levels), int(min_scans), float(tau))
+    so = _StreamOpts(float(alpha), int(batch_points))
+    h = ct.c_void_p()
+    _check(load().ba_voxelize_host(ct.c_void_p(px), ct.c_void_p(py), ct.c_void_p(pz), ct.c_void_p(ps), n, N,
+                                   _ptr(poses), ct.byref(o), ct.byref(so), ct.byref(h), _stream()))
     return VoxelMap(h)

@@ -22,6 +22,8 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <thread>
+#include <vector>
 
 #include "ba.h"
 #include "ba_device.hpp"
@@ -368,6 +370,54 @@ __global__ void k_vx_emit(int64_t V, const int64_t *__restrict__ vstart, const u
     }
 }
 
+// cell and scan of each cluster, written out (batches of the host stream)
+__global__ void k_vx_decode(int64_t C, const uint64_t *__restrict__ ckey, CellLayout L, int32_t *__restrict__ cell,
+                            int32_t *__restrict__ cscan) {
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= C) return;
+    int64_t cc[3];
+    int32_t sc;
+    vx_unpack(L, ckey[c], cc, sc);
+#pragma unroll
+    for (int r = 0; r < 3; r++) cell[3 * c + r] = (int32_t)cc[r];
+    cscan[c] = sc;
+}
+
+// bounding box of explicit cluster cells (block partials in the layout of
+// k_vx_cells, flags 0)
+__global__ __launch_bounds__(VX_THREADS) void k_vx_cell_box(int64_t C, const int32_t *__restrict__ cell,
+                                                            int32_t *__restrict__ bpart) {
+    constexpr int NW = VX_THREADS / 64;
+    __shared__ int red[NW];
+    int lo[3] = {INT32_MAX, INT32_MAX, INT32_MAX}, nhi[3] = {INT32_MAX, INT32_MAX, INT32_MAX};
+    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < C; c += (int64_t)gridDim.x * blockDim.x) {
+#pragma unroll
+        for (int r = 0; r < 3; r++) {
+            lo[r] = min(lo[r], cell[3 * c + r]);
+            nhi[r] = min(nhi[r], -cell[3 * c + r]);
+        }
+    }
+    int *out = bpart + 7LL * blockIdx.x;
+#pragma unroll
+    for (int r = 0; r < 3; r++) {
+        const int a = block_min_i<NW>(lo[r], red);
+        const int b = block_min_i<NW>(nhi[r], red);
+        if (threadIdx.x == 0) {
+            out[r] = a;
+            out[3 + r] = b;
+        }
+    }
+    if (threadIdx.x == 0) out[6] = 0;
+}
+
+__global__ void k_vx_keys_cells(int64_t C, const int32_t *__restrict__ cell, const int32_t *__restrict__ cscan,
+                                CellLayout L, uint64_t *__restrict__ keys, uint32_t *__restrict__ vals) {
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= C) return;
+    keys[c] = vx_pack(L, cell[3 * c], cell[3 * c + 1], cell[3 * c + 2], cscan[c]);
+    vals[c] = (uint32_t)c;
+}
+
 // one level's clusters (keys in (cell, scan) order) and its selection
 struct VxLevel {
     CellLayout L;
@@ -378,12 +428,21 @@ struct VxLevel {
     int64_t *vstart = nullptr, *keep = nullptr, *vrank = nullptr, *coff = nullptr;
 };
 
+// sort and scan buffers for up to cap entries
+struct VxWork {
+    uint64_t *keys = nullptr;
+    uint32_t *vals = nullptr;
+    int64_t *flags = nullptr, *total = nullptr;
+    char *ws = nullptr;
+    int64_t cap = 0;
+};
+
 }  // namespace ba
 
 struct ba_voxel_map {
     ba::DevArena mem;
     int64_t n_points = 0, n_clusters = 0;
-    int32_t n_voxels = 0, levels = 0, n_scans = 0;
+    int32_t n_voxels = 0, levels = 0, n_scans = 0, n_batches = 0;
     int64_t lv[BA_VOXEL_MAX_LEVELS][4] = {};
     int32_t *voxel = nullptr, *scan = nullptr, *vlevel = nullptr, *vcell = nullptr;
     int64_t *count = nullptr;
@@ -398,33 +457,77 @@ static ba_status sync_read(void *dst, const void *src, size_t bytes, hipStream_t
     return BA_OK;
 }
 
+static ba_status work_alloc(DevArena &a, VxWork &w, int64_t cap) {
+    w.cap = cap;
+    BA_TRY(a.alloc(&w.keys, cap));
+    BA_TRY(a.alloc(&w.vals, cap));
+    BA_TRY(a.alloc(&w.flags, cap + 1));
+    BA_TRY(a.alloc(&w.total, 1));
+    BA_TRY(a.alloc(&w.ws, (int64_t)std::max(radix_sort_workspace_bytes(cap), scan_workspace_bytes(cap))));
+    return BA_OK;
+}
+
 // segments of sorted keys that agree above bit `shift`: their number and
 // their starts (length n_seg + 1)
-static ba_status vx_segments(DevArena &tmp, const uint64_t *keys, int64_t n, int shift, int64_t *flags,
-                             int64_t *total, void *ws, int64_t **starts, int64_t *n_seg, hipStream_t s) {
-    hipLaunchKernelGGL(k_vx_heads, dim3(vx_nblk(n)), dim3(VX_THREADS), 0, s, n, keys, shift, flags);
-    BA_HIP(exclusive_scan_i64(flags, flags, n, total, ws, s));
-    BA_TRY(sync_read(n_seg, total, sizeof(int64_t), s));
+static ba_status vx_segments(DevArena &tmp, VxWork &w, const uint64_t *keys, int64_t n, int shift,
+                             int64_t **starts, int64_t *n_seg, hipStream_t s) {
+    hipLaunchKernelGGL(k_vx_heads, dim3(vx_nblk(n)), dim3(VX_THREADS), 0, s, n, keys, shift, w.flags);
+    BA_HIP(exclusive_scan_i64(w.flags, w.flags, n, w.total, w.ws, s));
+    BA_TRY(sync_read(n_seg, w.total, sizeof(int64_t), s));
     BA_TRY(tmp.alloc(starts, *n_seg + 1));
-    hipLaunchKernelGGL(k_vx_starts, dim3(vx_nblk(n)), dim3(VX_THREADS), 0, s, n, keys, shift, flags, *starts, *n_seg);
+    hipLaunchKernelGGL(k_vx_starts, dim3(vx_nblk(n)), dim3(VX_THREADS), 0, s, n, keys, shift, w.flags, *starts,
+                       *n_seg);
     BA_HIP(hipGetLastError());
     return BA_OK;
 }
 
-static ba_status voxelize(const double *x, const double *y, const double *z, const int32_t *scan, int64_t n,
-                          int32_t n_scans, const double *poses, const ba_voxelize_options *opt, ba_voxel_map *M,
-                          hipStream_t s) {
-    const int levels = opt->levels;
-    DevArena tmp;
-    int32_t *cell, *bpart, *box;
-    BA_TRY(tmp.alloc(&cell, 3 * n));
-    BA_TRY(tmp.alloc(&bpart, 7LL * VX_BOX_BLOCKS));
-    BA_TRY(tmp.alloc(&box, 7));
-    const int nb = (int)std::min<int64_t>(VX_BOX_BLOCKS, vx_nblk(n));
-    hipLaunchKernelGGL(k_vx_cells, dim3(nb), dim3(VX_THREADS), 0, s, n, x, y, z, scan, n_scans, poses, opt->d, cell,
-                       bpart);
-    hipLaunchKernelGGL(k_vx_bbox, dim3(1), dim3(VX_THREADS), 0, s, nb, bpart, box);
+static ba_status check_layout(const CellLayout &L) {
+    if (L.total > 64) {
+        set_error("cell range needs %d key bits (at most 64): use a larger d", L.total);
+        return BA_E_UNSUPPORTED;
+    }
+    return BA_OK;
+}
+
+// Sort the m keys in w (layout cur.L) and form cur's clusters: raw sums of
+// points (x non-null) or of the child clusters.
+static ba_status vx_form_level(DevArena &tmp, VxWork &w, int64_t m, const double *x, const double *y,
+                               const double *z, const int64_t *ccount, const double *cs1, const double *cs2,
+                               VxLevel &cur, hipStream_t s) {
+    BA_HIP(radix_sort_pairs(w.keys, w.vals, m, cur.L.total, w.ws, s));
+    int64_t *starts;
+    BA_TRY(vx_segments(tmp, w, w.keys, m, 0, &starts, &cur.C, s));
+    BA_TRY(tmp.alloc(&cur.ckey, cur.C));
+    BA_TRY(tmp.alloc(&cur.count, cur.C));
+    BA_TRY(tmp.alloc(&cur.s1, 3 * cur.C));
+    BA_TRY(tmp.alloc(&cur.s2, 6 * cur.C));
+    if (x)
+        hipLaunchKernelGGL(k_vx_sum_points, dim3(vx_nblk(cur.C)), dim3(VX_THREADS), 0, s, cur.C, starts, w.keys, w.vals,
+                           x, y, z, cur.ckey, cur.count, cur.s1, cur.s2);
+    else
+        hipLaunchKernelGGL(k_vx_sum_clusters, dim3(vx_nblk(cur.C)), dim3(VX_THREADS), 0, s, cur.C, starts, w.keys,
+                           w.vals, ccount, cs1, cs2, cur.ckey, cur.count, cur.s1, cur.s2);
     BA_HIP(hipGetLastError());
+    return BA_OK;
+}
+
+// World cells of n device points (asynchronous; box receives the bounding box
+// and flags) and, after a wait, the layout from that box.
+static ba_status vx_cells_launch(DevArena &tmp, const double *x, const double *y, const double *z,
+                                 const int32_t *scan, int64_t n, int32_t n_scans, const double *poses, double d,
+                                 int32_t *cell, int32_t **box, hipStream_t s) {
+    int32_t *bpart;
+    BA_TRY(tmp.alloc(&bpart, 7LL * VX_BOX_BLOCKS));
+    BA_TRY(tmp.alloc(box, 7));
+    const int nb = (int)std::min<int64_t>(VX_BOX_BLOCKS, vx_nblk(n));
+    hipLaunchKernelGGL(k_vx_cells, dim3(nb), dim3(VX_THREADS), 0, s, n, x, y, z, scan, n_scans, poses, d, cell,
+                       bpart);
+    hipLaunchKernelGGL(k_vx_bbox, dim3(1), dim3(VX_THREADS), 0, s, nb, bpart, *box);
+    BA_HIP(hipGetLastError());
+    return BA_OK;
+}
+
+static ba_status vx_cells_layout(const int32_t *box, int32_t n_scans, CellLayout *L, hipStream_t s) {
     int32_t hb[7];
     BA_TRY(sync_read(hb, box, sizeof(hb), s));
     if (hb[6]) {
@@ -434,70 +537,49 @@ static ba_status voxelize(const double *x, const double *y, const double *z, con
         return BA_E_ARG;
     }
     int64_t lo[3] = {hb[0], hb[1], hb[2]}, hi[3] = {-(int64_t)hb[3], -(int64_t)hb[4], -(int64_t)hb[5]};
-    CellLayout L = make_layout(lo, hi, n_scans);
-    if (L.total > 64) {
-        set_error("cell range needs %d key bits (at most 64): use a larger d", L.total);
-        return BA_E_UNSUPPORTED;
-    }
-    // sort buffers sized for the points (the largest level)
-    uint64_t *keys;
-    uint32_t *vals;
-    int64_t *flags, *total;
-    BA_TRY(tmp.alloc(&keys, n));
-    BA_TRY(tmp.alloc(&vals, n));
-    BA_TRY(tmp.alloc(&flags, n + 1));
-    BA_TRY(tmp.alloc(&total, 1));
-    char *ws;
-    BA_TRY(tmp.alloc(&ws, (int64_t)std::max(radix_sort_workspace_bytes(n), scan_workspace_bytes(n))));
-    std::vector<VxLevel> lv(levels);
-    for (int k = 0; k < levels; k++) {
+    *L = make_layout(lo, hi, n_scans);
+    return check_layout(*L);
+}
+
+// Planarity decisions of one level and its kept counts.
+static ba_status vx_select_level(DevArena &tmp, VxWork &w, VxLevel &cur, const double *poses,
+                                 const ba_voxelize_options *opt, hipStream_t s) {
+    // cells of this level: segments of the cluster keys without the scan bits
+    BA_TRY(vx_segments(tmp, w, cur.ckey, cur.C, cur.L.sbits, &cur.vstart, &cur.V, s));
+    BA_TRY(tmp.alloc(&cur.keep, cur.V + 1));
+    BA_TRY(tmp.alloc(&cur.coff, cur.V + 1));
+    BA_TRY(tmp.alloc(&cur.vrank, cur.V + 1));
+    hipLaunchKernelGGL(k_vx_select, dim3(vx_nblk(cur.V)), dim3(VX_THREADS), 0, s, cur.V, cur.vstart, cur.ckey,
+                       cur.count, cur.s1, cur.s2, cur.L, poses, opt->tau, opt->min_scans, cur.keep, cur.coff,
+                       (double *)nullptr);
+    BA_HIP(hipGetLastError());
+    BA_HIP(exclusive_scan_i64(cur.keep, cur.vrank, cur.V, w.total, w.ws, s));
+    BA_TRY(sync_read(&cur.Vk, w.total, sizeof(int64_t), s));
+    BA_HIP(exclusive_scan_i64(cur.coff, cur.coff, cur.V, w.total, w.ws, s));
+    BA_TRY(sync_read(&cur.Ck, w.total, sizeof(int64_t), s));
+    return BA_OK;
+}
+
+// From the level-1 clusters in lv[0]: levels 2..L (Eq. 5), the selection of
+// every level and the concatenated output.
+static ba_status vx_finish(DevArena &tmp, VxWork &w, std::vector<VxLevel> &lv, int32_t n_scans,
+                           const double *poses, const ba_voxelize_options *opt, ba_voxel_map *M, hipStream_t s) {
+    const int levels = (int)lv.size();
+    BA_TRY(vx_select_level(tmp, w, lv[0], poses, opt, s));
+    for (int k = 1; k < levels; k++) {
         VxLevel &cur = lv[k];
-        int64_t m;
-        if (k == 0) {
-            cur.L = L;
-            m = n;
-            hipLaunchKernelGGL(k_vx_keys_points, dim3(vx_nblk(n)), dim3(VX_THREADS), 0, s, n, cell, scan, cur.L, keys,
-                               vals);
-        } else {
-            const VxLevel &prev = lv[k - 1];
-            int64_t plo[3], phi[3];
-            for (int r = 0; r < 3; r++) {
-                plo[r] = prev.L.lo[r] >> 1;
-                phi[r] = prev.L.hi[r] >> 1;
-            }
-            cur.L = make_layout(plo, phi, n_scans);
-            m = prev.C;
-            hipLaunchKernelGGL(k_vx_keys_up, dim3(vx_nblk(m)), dim3(VX_THREADS), 0, s, m, prev.ckey, prev.L, cur.L,
-                               keys, vals);
+        const VxLevel &prev = lv[k - 1];
+        int64_t plo[3], phi[3];
+        for (int r = 0; r < 3; r++) {
+            plo[r] = prev.L.lo[r] >> 1;
+            phi[r] = prev.L.hi[r] >> 1;
         }
+        cur.L = make_layout(plo, phi, n_scans);
+        hipLaunchKernelGGL(k_vx_keys_up, dim3(vx_nblk(prev.C)), dim3(VX_THREADS), 0, s, prev.C, prev.ckey, prev.L,
+                           cur.L, w.keys, w.vals);
         BA_HIP(hipGetLastError());
-        BA_HIP(radix_sort_pairs(keys, vals, m, cur.L.total, ws, s));
-        int64_t *starts;
-        BA_TRY(vx_segments(tmp, keys, m, 0, flags, total, ws, &starts, &cur.C, s));
-        BA_TRY(tmp.alloc(&cur.ckey, cur.C));
-        BA_TRY(tmp.alloc(&cur.count, cur.C));
-        BA_TRY(tmp.alloc(&cur.s1, 3 * cur.C));
-        BA_TRY(tmp.alloc(&cur.s2, 6 * cur.C));
-        if (k == 0)
-            hipLaunchKernelGGL(k_vx_sum_points, dim3(vx_nblk(cur.C)), dim3(VX_THREADS), 0, s, cur.C, starts, keys, vals,
-                               x, y, z, cur.ckey, cur.count, cur.s1, cur.s2);
-        else
-            hipLaunchKernelGGL(k_vx_sum_clusters, dim3(vx_nblk(cur.C)), dim3(VX_THREADS), 0, s, cur.C, starts, keys,
-                               vals, lv[k - 1].count, lv[k - 1].s1, lv[k - 1].s2, cur.ckey, cur.count, cur.s1, cur.s2);
-        BA_HIP(hipGetLastError());
-        // cells of this level: segments of the cluster keys without the scan bits
-        BA_TRY(vx_segments(tmp, cur.ckey, cur.C, cur.L.sbits, flags, total, ws, &cur.vstart, &cur.V, s));
-        BA_TRY(tmp.alloc(&cur.keep, cur.V + 1));
-        BA_TRY(tmp.alloc(&cur.coff, cur.V + 1));
-        BA_TRY(tmp.alloc(&cur.vrank, cur.V + 1));
-        hipLaunchKernelGGL(k_vx_select, dim3(vx_nblk(cur.V)), dim3(VX_THREADS), 0, s, cur.V, cur.vstart, cur.ckey,
-                           cur.count, cur.s1, cur.s2, cur.L, poses, opt->tau, opt->min_scans, cur.keep, cur.coff,
-                           (double *)nullptr);
-        BA_HIP(hipGetLastError());
-        BA_HIP(exclusive_scan_i64(cur.keep, cur.vrank, cur.V, total, ws, s));
-        BA_TRY(sync_read(&cur.Vk, total, sizeof(int64_t), s));
-        BA_HIP(exclusive_scan_i64(cur.coff, cur.coff, cur.V, total, ws, s));
-        BA_TRY(sync_read(&cur.Ck, total, sizeof(int64_t), s));
+        BA_TRY(vx_form_level(tmp, w, prev.C, nullptr, nullptr, nullptr, prev.count, prev.s1, prev.s2, cur, s));
+        BA_TRY(vx_select_level(tmp, w, cur, poses, opt, s));
     }
     int64_t Vout = 0, Cout = 0;
     for (auto &l : lv) {
@@ -530,11 +612,218 @@ static ba_status voxelize(const double *x, const double *y, const double *z, con
         bc += l.Ck;
     }
     BA_HIP(hipStreamSynchronize(s));
-    M->n_points = n;
     M->n_clusters = Cout;
     M->n_voxels = (int32_t)Vout;
     M->levels = levels;
     M->n_scans = n_scans;
+    return BA_OK;
+}
+
+static ba_status voxelize(const double *x, const double *y, const double *z, const int32_t *scan, int64_t n,
+                          int32_t n_scans, const double *poses, const ba_voxelize_options *opt, ba_voxel_map *M,
+                          hipStream_t s) {
+    DevArena tmp;
+    int32_t *cell;
+    BA_TRY(tmp.alloc(&cell, 3 * n));
+    std::vector<VxLevel> lv(opt->levels);
+    int32_t *box;
+    BA_TRY(vx_cells_launch(tmp, x, y, z, scan, n, n_scans, poses, opt->d, cell, &box, s));
+    BA_TRY(vx_cells_layout(box, n_scans, &lv[0].L, s));
+    VxWork w;
+    BA_TRY(work_alloc(tmp, w, n));   // the points are the largest level
+    hipLaunchKernelGGL(k_vx_keys_points, dim3(vx_nblk(n)), dim3(VX_THREADS), 0, s, n, cell, scan, lv[0].L, w.keys,
+                       w.vals);
+    BA_HIP(hipGetLastError());
+    BA_TRY(vx_form_level(tmp, w, n, x, y, z, nullptr, nullptr, nullptr, lv[0], s));
+    BA_TRY(vx_finish(tmp, w, lv, n_scans, poses, opt, M, s));
+    M->n_points = n;
+    return BA_OK;
+}
+
+// ---------------------------------------------------------------- host stream
+// Copies of host memory by a few threads (pageable sources are staged into
+// pinned buffers before their transfer).
+static void parallel_copy(void *dst, const void *src, size_t bytes) {
+    constexpr size_t CHUNK = (size_t)8 << 20;
+    const int nt = (int)std::min<size_t>(8, (bytes + CHUNK - 1) / CHUNK);
+    if (nt <= 1) {
+        std::memcpy(dst, src, bytes);
+        return;
+    }
+    std::vector<std::thread> th;
+    const size_t per = (bytes + nt - 1) / nt;
+    for (int t = 0; t < nt; t++) {
+        const size_t a = per * t, b = std::min(bytes, a + per);
+        if (a >= b) break;
+        th.emplace_back([=] { std::memcpy((char *)dst + a, (const char *)src + a, b - a); });
+    }
+    for (auto &t : th) t.join();
+}
+
+static bool host_pinned(const void *p) {
+    hipPointerAttribute_t at;
+    hipError_t e = hipPointerGetAttributes(&at, p);
+    (void)hipGetLastError();
+    return e == hipSuccess && at.type == hipMemoryTypeHost;
+}
+
+// one batch's level-1 clusters with their cells written out
+struct VxBatch {
+    int64_t C = 0;
+    int32_t *cell = nullptr, *scan = nullptr;
+    int64_t *count = nullptr;
+    double *s1 = nullptr, *s2 = nullptr;
+};
+
+struct HostStream {
+    hipStream_t copy = nullptr;
+    hipEvent_t copied[2] = {nullptr, nullptr}, consumed[2] = {nullptr, nullptr};
+    void *pinned[2] = {nullptr, nullptr};
+    ~HostStream() {
+        if (copy) (void)hipStreamSynchronize(copy);
+        for (int k = 0; k < 2; k++) {
+            if (copied[k]) (void)hipEventSynchronize(copied[k]);
+            if (consumed[k]) (void)hipEventSynchronize(consumed[k]);
+        }
+        for (int k = 0; k < 2; k++) {
+            if (pinned[k]) (void)hipHostFree(pinned[k]);
+            if (copied[k]) (void)hipEventDestroy(copied[k]);
+            if (consumed[k]) (void)hipEventDestroy(consumed[k]);
+        }
+        if (copy) (void)hipStreamDestroy(copy);
+    }
+};
+
+static ba_status voxelize_host(const double *hx, const double *hy, const double *hz, const int32_t *hscan,
+                               int64_t n, int32_t n_scans, const double *poses, const ba_voxelize_options *opt,
+                               const ba_stream_options *so, ba_voxel_map *M, hipStream_t s) {
+    constexpr int64_t WORK_BYTES = 2 * 28 + 12 + 8 + 4 + 8 + 12 + 16;   // per batch point: buffers, cells, sort
+    int64_t B = so ? so->batch_points : 0;
+    if (B <= 0) {
+        size_t fr = 0, tot = 0;
+        BA_HIP(hipMemGetInfo(&fr, &tot));
+        const double alpha = (so && so->alpha > 0.0) ? so->alpha : 0.5;
+        B = (int64_t)(alpha * (double)fr / (double)WORK_BYTES);
+    }
+    B = std::max<int64_t>(1024, std::min<int64_t>(B, n));
+    const bool pinned_in = host_pinned(hx) && host_pinned(hy) && host_pinned(hz) && host_pinned(hscan);
+    HostStream hs;
+    BA_HIP(hipStreamCreateWithFlags(&hs.copy, hipStreamNonBlocking));
+    for (int k = 0; k < 2; k++) {
+        BA_HIP(hipEventCreateWithFlags(&hs.copied[k], hipEventDisableTiming));
+        BA_HIP(hipEventCreateWithFlags(&hs.consumed[k], hipEventDisableTiming));
+        if (!pinned_in) BA_HIP(hipHostMalloc(&hs.pinned[k], (size_t)B * 28, hipHostMallocDefault));
+    }
+    DevArena tmp;
+    double *dx[2], *dy[2], *dz[2];
+    int32_t *ds[2], *cell;
+    for (int k = 0; k < 2; k++) {
+        BA_TRY(tmp.alloc(&dx[k], B));
+        BA_TRY(tmp.alloc(&dy[k], B));
+        BA_TRY(tmp.alloc(&dz[k], B));
+        BA_TRY(tmp.alloc(&ds[k], B));
+    }
+    BA_TRY(tmp.alloc(&cell, 3 * B));
+    VxWork w;
+    BA_TRY(work_alloc(tmp, w, B));
+    const int64_t nbat = (n + B - 1) / B;
+    std::vector<VxBatch> bat(nbat);
+    // stage batch b into pinned buffer b % 2 (pageable input) and start its transfer
+    auto start_copy = [&](int64_t b) -> ba_status {
+        const int k = (int)(b & 1);
+        const int64_t a = b * B, m = std::min(B, n - a);
+        const double *sx = hx + a, *sy = hy + a, *sz = hz + a;
+        const int32_t *ss = hscan + a;
+        if (!pinned_in) {
+            BA_HIP(hipEventSynchronize(hs.copied[k]));   // the buffer's previous transfer has finished
+            char *pb = (char *)hs.pinned[k];
+            parallel_copy(pb, sx, (size_t)m * 8);
+            parallel_copy(pb + (size_t)B * 8, sy, (size_t)m * 8);
+            parallel_copy(pb + (size_t)B * 16, sz, (size_t)m * 8);
+            parallel_copy(pb + (size_t)B * 24, ss, (size_t)m * 4);
+            sx = (const double *)pb;
+            sy = (const double *)(pb + (size_t)B * 8);
+            sz = (const double *)(pb + (size_t)B * 16);
+            ss = (const int32_t *)(pb + (size_t)B * 24);
+        }
+        // the device buffer k is free once batch b - 2 has been clustered
+        BA_HIP(hipStreamWaitEvent(hs.copy, hs.consumed[k], 0));
+        BA_HIP(hipMemcpyAsync(dx[k], sx, (size_t)m * 8, hipMemcpyHostToDevice, hs.copy));
+        BA_HIP(hipMemcpyAsync(dy[k], sy, (size_t)m * 8, hipMemcpyHostToDevice, hs.copy));
+        BA_HIP(hipMemcpyAsync(dz[k], sz, (size_t)m * 8, hipMemcpyHostToDevice, hs.copy));
+        BA_HIP(hipMemcpyAsync(ds[k], ss, (size_t)m * 4, hipMemcpyHostToDevice, hs.copy));
+        BA_HIP(hipEventRecord(hs.copied[k], hs.copy));
+        return BA_OK;
+    };
+    BA_TRY(start_copy(0));
+    for (int64_t b = 0; b < nbat; b++) {
+        const int k = (int)(b & 1);
+        const int64_t m = std::min(B, n - b * B);
+        BA_HIP(hipStreamWaitEvent(s, hs.copied[k], 0));
+        VxLevel l1;
+        int32_t *box;
+        BA_TRY(vx_cells_launch(tmp, dx[k], dy[k], dz[k], ds[k], m, n_scans, poses, opt->d, cell, &box, s));
+        // the next batch is staged and its transfer queued while this one is clustered
+        if (b + 1 < nbat) BA_TRY(start_copy(b + 1));
+        BA_TRY(vx_cells_layout(box, n_scans, &l1.L, s));
+        hipLaunchKernelGGL(k_vx_keys_points, dim3(vx_nblk(m)), dim3(VX_THREADS), 0, s, m, cell, ds[k], l1.L, w.keys,
+                           w.vals);
+        BA_HIP(hipGetLastError());
+        BA_TRY(vx_form_level(tmp, w, m, dx[k], dy[k], dz[k], nullptr, nullptr, nullptr, l1, s));
+        VxBatch &o = bat[b];
+        o.C = l1.C;
+        BA_TRY(tmp.alloc(&o.cell, 3 * o.C));
+        BA_TRY(tmp.alloc(&o.scan, o.C));
+        o.count = l1.count;
+        o.s1 = l1.s1;
+        o.s2 = l1.s2;
+        hipLaunchKernelGGL(k_vx_decode, dim3(vx_nblk(o.C)), dim3(VX_THREADS), 0, s, o.C, l1.ckey, l1.L, o.cell,
+                           o.scan);
+        BA_HIP(hipGetLastError());
+        BA_HIP(hipEventRecord(hs.consumed[k], s));
+    }
+    // merge the batches' clusters of equal (cell, scan): one sort, raw sums added
+    int64_t C = 0;
+    for (auto &o : bat) C += o.C;
+    int32_t *acell, *ascan;
+    int64_t *acount;
+    double *as1, *as2;
+    BA_TRY(tmp.alloc(&acell, 3 * C));
+    BA_TRY(tmp.alloc(&ascan, C));
+    BA_TRY(tmp.alloc(&acount, C));
+    BA_TRY(tmp.alloc(&as1, 3 * C));
+    BA_TRY(tmp.alloc(&as2, 6 * C));
+    int64_t off = 0;
+    for (auto &o : bat) {
+        BA_HIP(hipMemcpyAsync(acell + 3 * off, o.cell, (size_t)o.C * 12, hipMemcpyDeviceToDevice, s));
+        BA_HIP(hipMemcpyAsync(ascan + off, o.scan, (size_t)o.C * 4, hipMemcpyDeviceToDevice, s));
+        BA_HIP(hipMemcpyAsync(acount + off, o.count, (size_t)o.C * 8, hipMemcpyDeviceToDevice, s));
+        BA_HIP(hipMemcpyAsync(as1 + 3 * off, o.s1, (size_t)o.C * 24, hipMemcpyDeviceToDevice, s));
+        BA_HIP(hipMemcpyAsync(as2 + 6 * off, o.s2, (size_t)o.C * 48, hipMemcpyDeviceToDevice, s));
+        off += o.C;
+    }
+    int32_t *bpart, *box;
+    BA_TRY(tmp.alloc(&bpart, 7LL * VX_BOX_BLOCKS));
+    BA_TRY(tmp.alloc(&box, 7));
+    const int nb = (int)std::min<int64_t>(VX_BOX_BLOCKS, vx_nblk(C));
+    hipLaunchKernelGGL(k_vx_cell_box, dim3(nb), dim3(VX_THREADS), 0, s, C, acell, bpart);
+    hipLaunchKernelGGL(k_vx_bbox, dim3(1), dim3(VX_THREADS), 0, s, nb, bpart, box);
+    BA_HIP(hipGetLastError());
+    int32_t hb[7];
+    BA_TRY(sync_read(hb, box, sizeof(hb), s));
+    std::vector<VxLevel> lv(opt->levels);
+    int64_t lo[3] = {hb[0], hb[1], hb[2]}, hi[3] = {-(int64_t)hb[3], -(int64_t)hb[4], -(int64_t)hb[5]};
+    lv[0].L = make_layout(lo, hi, n_scans);
+    BA_TRY(check_layout(lv[0].L));
+    VxWork wm;
+    BA_TRY(work_alloc(tmp, wm, C));
+    hipLaunchKernelGGL(k_vx_keys_cells, dim3(vx_nblk(C)), dim3(VX_THREADS), 0, s, C, acell, ascan, lv[0].L, wm.keys,
+                       wm.vals);
+    BA_HIP(hipGetLastError());
+    BA_TRY(vx_form_level(tmp, wm, C, nullptr, nullptr, nullptr, acount, as1, as2, lv[0], s));
+    BA_TRY(vx_finish(tmp, wm, lv, n_scans, poses, opt, M, s));
+    M->n_points = n;
+    M->n_batches = (int32_t)nbat;
     return BA_OK;
 }
 
@@ -544,9 +833,9 @@ using namespace ba;
 
 extern "C" {
 
-ba_status ba_voxelize(const double *x, const double *y, const double *z, const int32_t *scan, int64_t n,
-                      int32_t n_scans, const double *poses, const ba_voxelize_options *opt, ba_voxel_map **out,
-                      hipStream_t stream) {
+static ba_status check_voxelize_args(const void *x, const void *y, const void *z, const void *scan, int64_t n,
+                                     int32_t n_scans, const void *poses, const ba_voxelize_options *opt,
+                                     ba_voxel_map **out) {
     if (!out) {
         set_error("out is null");
         return BA_E_ARG;
@@ -566,8 +855,35 @@ ba_status ba_voxelize(const double *x, const double *y, const double *z, const i
                   opt->tau, opt->min_scans);
         return BA_E_ARG;
     }
+    return BA_OK;
+}
+
+ba_status ba_voxelize(const double *x, const double *y, const double *z, const int32_t *scan, int64_t n,
+                      int32_t n_scans, const double *poses, const ba_voxelize_options *opt, ba_voxel_map **out,
+                      hipStream_t stream) {
+    BA_TRY(check_voxelize_args(x, y, z, scan, n, n_scans, poses, opt, out));
     ba_voxel_map *M = new ba_voxel_map();
     ba_status st = voxelize(x, y, z, scan, n, n_scans, poses, opt, M, stream);
+    if (st != BA_OK) {
+        (void)hipStreamSynchronize(stream);
+        delete M;
+        return st;
+    }
+    *out = M;
+    return BA_OK;
+}
+
+ba_status ba_voxelize_host(const double *x, const double *y, const double *z, const int32_t *scan, int64_t n,
+                           int32_t n_scans, const double *poses, const ba_voxelize_options *opt,
+                           const ba_stream_options *so, ba_voxel_map **out, hipStream_t stream) {
+    BA_TRY(check_voxelize_args(x, y, z, scan, n, n_scans, poses, opt, out));
+    if (so && (so->alpha < 0.0 || so->alpha > 1.0 || !std::isfinite(so->alpha) || so->batch_points < 0)) {
+        set_error("stream options out of range (alpha %g, batch_points %lld)", so->alpha,
+                  (long long)so->batch_points);
+        return BA_E_ARG;
+    }
+    ba_voxel_map *M = new ba_voxel_map();
+    ba_status st = voxelize_host(x, y, z, scan, n, n_scans, poses, opt, so, M, stream);
     if (st != BA_OK) {
         (void)hipStreamSynchronize(stream);
         delete M;
@@ -588,6 +904,7 @@ ba_status ba_voxel_map_get_info(const ba_voxel_map *m, ba_voxel_map_info *info) 
     info->n_voxels = m->n_voxels;
     info->levels = m->levels;
     info->n_scans = m->n_scans;
+    info->n_batches = m->n_batches;
     for (int k = 0; k < m->levels; k++) {
         info->level_voxels[k] = m->lv[k][0];
         info->level_clusters[k] = m->lv[k][1];

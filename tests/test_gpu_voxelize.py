@@ -196,3 +196,61 @@ def test_voxelize_rejects_bad_input(ba, dev):
         _run(ba, dev, x, y, z, scan, P, 0.0, 2, 0.3)
     with pytest.raises(ba.BAError, match="options out of range"):
         _run(ba, dev, x, y, z, scan, P, 0.5, 17, 0.3)
+
+
+# ---------------------------------------------------------------- host stream (adaptive loader)
+def _run_host(ba, dev, x, y, z, scan, poses, d, L, tau, min_scans=1, **so):
+    import torch
+    m = ba.voxelize_host(x, y, z, scan, torch.as_tensor(poses, device=dev), d, L, tau, min_scans, **so)
+    try:
+        inf = m.info()
+        out = {k: v.cpu().numpy() for k, v in m.export().items()}
+    finally:
+        m.close()
+    return inf, out
+
+
+def _same_map(a, b):
+    """Equal cells, scans and counts; sums equal to rounding (the batches add
+    their partial sums in another order)."""
+    for k in ("voxel", "scan", "count", "voxel_level", "voxel_cell"):
+        assert np.array_equal(a[k], b[k]), k
+    assert np.allclose(a["sum"], b["sum"], rtol=1e-13, atol=1e-13)
+    assert np.allclose(a["sumsq"], b["sumsq"], rtol=1e-13, atol=1e-11)
+
+
+def test_host_stream_in_many_batches_matches_oracle_and_device_path(ba, dev):
+    x, y, z, scan, P = _cloud(11, 20_000, 9)
+    say("voxelize_host: 20000 points in batches of 1024")
+    inf, out = _run_host(ba, dev, x, y, z, scan, P, 0.31, 4, 0.2, 2, batch_points=1024)
+    assert inf["n_batches"] == 20
+    ref = ovx.voxelize(x, y, z, scan, P, 0.31, 4, 0.2, 2)
+    _compare(inf, out, ref, 0.2)
+    _, dout = _run(ba, dev, x, y, z, scan, P, 0.31, 4, 0.2, 2)
+    _same_map(out, dout)
+
+
+def test_host_stream_window_scene_pinned_and_pageable(ba, dev):
+    import torch
+    sc = scenes.scaled_window(seed=2001, n_scans=60, n_planes=3000)
+    say(f"voxelize_host: window scene {sc.n_points} points, pageable and pinned")
+    _, dout = _run(ba, dev, sc.x, sc.y, sc.z, sc.scan, sc.poses_init, 0.5, 3, 0.05, 2)
+    inf, out = _run_host(ba, dev, sc.x, sc.y, sc.z, sc.scan, sc.poses_init, 0.5, 3, 0.05, 2, batch_points=50_000)
+    assert inf["n_batches"] == (sc.n_points + 49_999) // 50_000
+    _same_map(out, dout)
+    pin = lambda a, dt: torch.as_tensor(a, dtype=dt).pin_memory()
+    px, py, pz = pin(sc.x, torch.float64), pin(sc.y, torch.float64), pin(sc.z, torch.float64)
+    ps = pin(sc.scan, torch.int32)
+    _, out2 = _run_host(ba, dev, px, py, pz, ps, sc.poses_init, 0.5, 3, 0.05, 2, batch_points=50_000)
+    _same_map(out2, dout)
+    inf3, out3 = _run_host(ba, dev, px, py, pz, ps, sc.poses_init, 0.5, 3, 0.05, 2)   # one batch
+    assert inf3["n_batches"] == 1
+    _same_map(out3, dout)
+
+
+def test_host_stream_rejects_bad_options(ba, dev):
+    x, y, z, scan, P = _cloud(12, 100, 2)
+    with pytest.raises(ba.BAError, match="stream options out of range"):
+        _run_host(ba, dev, x, y, z, scan, P, 0.5, 2, 0.3, alpha=1.5)
+    with pytest.raises(ba.BAError, match="stream options out of range"):
+        _run_host(ba, dev, x, y, z, scan, P, 0.5, 2, 0.3, batch_points=-1)
