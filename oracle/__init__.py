@@ -64,7 +64,7 @@ def _load():
     lib.orc_apply_increment.restype = None
     lib.orc_apply_increment.argtypes = [i32, P, P, P]
     lib.orc_lm.restype = cint
-    lib.orc_lm.argtypes = [cint, i64, P, P, P, P, P, i32, i32, P, cint, dbl, dbl, dbl, cint, P, P]
+    lib.orc_lm.argtypes = [cint, i64, P, P, P, P, P, i32, i32, P, cint, dbl, dbl, dbl, cint, dbl, P, P]
     _lib = lib
     return lib
 
@@ -213,12 +213,12 @@ def apply_increment(poses, dx):
 
 
 def lm(mode: int, cl: Clusters, poses, max_iters: int, mu0: float = 1e-2, nu0: float = 2.0, tol_g: float = 0.0,
-       max_rejects: int = 0):
+       max_rejects: int = 0, exact_below: float = 0.0):
     """Returns (final poses, report (iters, 8), final cost)."""
     lib = _load()
     P = _c(poses, np.float64).copy()
     rep = np.zeros((max(max_iters, 1), 8))
     cf = ct.c_double(0.0)
     it = lib.orc_lm(mode, *cl.args(), _p(P), int(max_iters), float(mu0), float(nu0), float(tol_g),
-                    int(max_rejects), _p(rep), ct.byref(cf))
+                    int(max_rejects), float(exact_below), _p(rep), ct.byref(cf))
     return P, rep[:it].copy(), cf.value

@@ -779,13 +779,17 @@ void orc_apply_increment(int32_t Np, const double *poses, const double *dx, doub
  * (tol_g <= 0 disables that), or after max_rejects rejections in a row
  * (max_rejects <= 0 disables that): near the optimum the predicted reduction
  * falls below the resolution of the cost and no step can be confirmed.
+ * Coupled mode with exact_below > 0: wherever the gradient norm at the
+ * current poses is below exact_below, the step uses the exact Hessian of
+ * Eq. 1 at those poses instead of the coupled one (a hybrid near
+ * convergence, where the exact Hessian is positive semi-definite).
  * report (may be NULL) holds 8 doubles per iteration:
  *   [cost, cost_trial, rho, mu_used, accepted, gnorm, info, q]
  * Returns the number of iterations run; final cost in *cost_final.
  */
 int orc_lm(int mode, int64_t C, const int32_t *vox, const int32_t *scan, const int64_t *n, const double *mu_c,
            const double *S, int32_t V, int32_t Np, double *poses, int max_iters, double mu0, double nu0,
-           double tol_g, int max_rejects, double *report, double *cost_final) {
+           double tol_g, int max_rejects, double exact_below, double *report, double *cost_final) {
     int64_t D = 6 * (int64_t)Np;
     size_t hsz = (mode == ORC_MM) ? 36 * (size_t)Np : (size_t)(D * D);
     double *g = (double *)malloc(sizeof(double) * (size_t)D);
@@ -796,13 +800,20 @@ int orc_lm(int mode, int64_t C, const int32_t *vox, const int32_t *scan, const i
     int need_eval = 1, it, rejects = 0;
     for (it = 0; it < max_iters; it++) {
         if (max_rejects > 0 && rejects >= max_rejects) break;
+        double gn = 0.0;
         if (need_eval) {
             if (orc_eval(mode, C, vox, scan, n, mu_c, S, V, Np, poses, &cost, g, H, NULL)) break;
+            for (int64_t k = 0; k < D; k++) gn += g[k] * g[k];
+            gn = sqrt(gn);
+            /* near convergence (coupled mode): the exact Hessian of Eq. 1 at
+             * the same poses; its gradient is the same */
+            if (mode == ORC_COUPLED && exact_below > 0.0 && gn < exact_below)
+                if (orc_eval(ORC_EXACT, C, vox, scan, n, mu_c, S, V, Np, poses, &cost, g, H, NULL)) break;
             need_eval = 0;
+        } else {
+            for (int64_t k = 0; k < D; k++) gn += g[k] * g[k];
+            gn = sqrt(gn);
         }
-        double gn = 0.0;
-        for (int64_t k = 0; k < D; k++) gn += g[k] * g[k];
-        gn = sqrt(gn);
         if (tol_g > 0 && gn < tol_g) break;
         int info = orc_solve(mode, Np, H, g, lm_mu, dx);
         double q = 0.0, ct = cost, rho = 0.0;

@@ -507,3 +507,27 @@ def test_lm_stops_after_consecutive_rejections(orc):
     acc = rep[:, 4]
     for i in range(k - 4):
         assert np.any(acc[i:i + 4] == 1)
+
+
+def test_hybrid_exact_newton_converges_superlinearly(orc):
+    """Coupled LM switching to the exact Hessian below a gradient norm of 0.1:
+    identical to plain coupled LM before the switch, then the local Newton
+    steps of the exact Hessian converge superlinearly, reaching ||g|| < 1e-8
+    in fewer iterations than the linearly converging coupled steps."""
+    sc = scenes.scaled_window(seed=2004, n_scans=30, n_planes=1500)
+    cl = orc.scene_clusters(sc)
+    _, rc, _ = orc.lm(orc.COUPLED, cl, sc.poses_init, 25, tol_g=0.0)
+    _, rh, _ = orc.lm(orc.COUPLED, cl, sc.poses_init, 25, tol_g=0.0, exact_below=0.1)
+    first = int(np.argmax(rc[:, 5] < 0.1))          # first evaluation below the switch
+    assert first >= 1
+    # the steps before the switch are the coupled ones; the switch step starts
+    # from the same cost
+    assert np.array_equal(rc[:first, :5], rh[:first, :5]) and rc[first, 0] == rh[first, 0]
+    reach = lambda r: int(np.argmax(r[:, 5] < 1e-8)) if np.any(r[:, 5] < 1e-8) else 99
+    assert reach(rh) < reach(rc)
+    # quadratic phase: after the switch each accepted step at least squares
+    # the gradient norm's ratio to the switch value
+    g = rh[first:, 5]
+    acc = rh[first:, 4] > 0
+    k = np.flatnonzero(acc)[:2]
+    assert g[k[0] + 1] <= 0.1 * g[k[0]]
