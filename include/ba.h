@@ -59,6 +59,8 @@ typedef int32_t ba_status;
 /* Hessian forms (mode arguments). */
 #define BA_MODE_MM 0       /* Eq. 3 surrogate: block-diagonal, [N][6][6] full symmetric */
 #define BA_MODE_COUPLED 1  /* Hessian of u^T A(T) u with u frozen: dense per window */
+#define BA_MODE_EXACT 2    /* exact Hessian of Eq. 1 (diagnostic; FP64 problems): dense per window, the coupled
+                            * one plus sum_l 2/(l0 - l_l) F^l F^l^T per voxel (l = 1, 2; gaps <= 1e-12 l2 dropped) */
 
 typedef struct ba_problem ba_problem;
 
@@ -116,6 +118,9 @@ typedef struct ba_lm_options {
     double tol_g;        /* stop a window once ||g||_2 < tol_g at its current poses (<= 0: never) */
     int32_t max_rejects; /* stop a window after this many rejected steps in a row (<= 0: never) */
     int32_t reserved;    /* 0 */
+    double exact_below;  /* BA_MODE_COUPLED only: a window whose gradient norm at its current poses is below this
+                          * takes the exact Hessian of Eq. 1 (BA_MODE_EXACT) for its step, the coupled one otherwise
+                          * (FP64 problems; <= 0: never) */
 } ba_lm_options;
 
 typedef struct ba_lm_report {  /* one per window */
@@ -197,7 +202,10 @@ ba_status ba_problem_export_clusters(const ba_problem *p, int32_t *voxel, int32_
  *              symmetric 6x6 block per scan ([N][36]);
  *              mode BA_MODE_COUPLED: Hessian of u^T A_i(T) u with u frozen
  *              (adds -2 h_j h_k^T pose-pair blocks), one dense row-major
- *              (6 N_w)^2 matrix per window, windows concatenated.
+ *              (6 N_w)^2 matrix per window, windows concatenated;
+ *              mode BA_MODE_EXACT: the exact Hessian of Eq. 1 in the same
+ *              layout (FP64 problems; BA_E_UNSUPPORTED for the precision
+ *              form): a diagnostic, e.g. of the gauge null space.
  * poses: device [n_scans][12].  cost: device [n_windows].  grad: device
  * [n_scans][6].  hess: device, layout above (NULL: skip the Hessian and the
  * derivative pass entirely; grad must then be NULL too).  voxel_eig: device
@@ -215,8 +223,8 @@ size_t ba_solve_increment_workspace(int32_t mode, int32_t n_scans);
  * D = diag(H) floored at 1e-12 max_k H_kk (reading of "mu Diag(H)", which a
  * scan no voxel constrains would otherwise make singular).
  *   BA_MODE_MM: n_scans independent 6x6 LDL^T factorizations; hess is [N][36].
- *   BA_MODE_COUPLED: one dense Cholesky of the (6N)^2 row-major hess,
- *   blocked, trailing updates on FP64 matrix cores.
+ *   BA_MODE_COUPLED (or BA_MODE_EXACT): one dense Cholesky of the (6N)^2
+ *   row-major hess, blocked, trailing updates on FP64 matrix cores.
  * hess, grad: device inputs (unchanged).  dx: device [N][6] output.
  * info: device int32 output, 0 or the 1-based index of the first
  * non-positive pivot (dx is then zero).  ws: device workspace of at least

@@ -10,6 +10,7 @@ from __future__ import annotations
 
 from ._lib import (  # noqa: F401
     MODE_COUPLED,
+    MODE_EXACT,
     MODE_MM,
     PREC_F32,
     PREC_F64,

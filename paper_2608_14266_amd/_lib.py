@@ -14,6 +14,7 @@ _LIB_PATH = os.path.join(_HERE, "libba.so")
 
 MODE_MM = 0
 MODE_COUPLED = 1
+MODE_EXACT = 2
 PREC_F64 = 0
 PREC_F32 = 1
 
@@ -51,7 +52,8 @@ class _Info(ct.Structure):
 
 class _LMOpts(ct.Structure):
     _fields_ = [("mode", ct.c_int32), ("max_iters", ct.c_int32), ("mu0", ct.c_double), ("nu0", ct.c_double),
-                ("tol_g", ct.c_double), ("max_rejects", ct.c_int32), ("reserved", ct.c_int32)]
+                ("tol_g", ct.c_double), ("max_rejects", ct.c_int32), ("reserved", ct.c_int32),
+                ("exact_below", ct.c_double)]
 
 
 class _Tuning(ct.Structure):
@@ -301,7 +303,7 @@ def build_clusters_from_sums(voxel, scan, count, sums, sumsq, n_scans: int, n_vo
 def eval_residual_grad_hessian(problem: Problem, poses, mode: int = MODE_MM, derivatives: bool = True,
                                voxel_eig: bool = False):
     """ba_eval_residual_grad_hessian.  Returns (cost[n_windows], grad (N,6) or None,
-    hess ((N,6,6) for MM, dense per-window for COUPLED) or None, eig (V_in,4) or None)."""
+    hess ((N,6,6) for MM, dense per-window for COUPLED and EXACT) or None, eig (V_in,4) or None)."""
     poses = _dev(poses, torch.float64, "poses")
     inf = problem.info()
     N, W = inf["n_scans"], inf["n_windows"]
@@ -344,13 +346,15 @@ def solve_increment(mode: int, hess, grad, mu: float):
 
 
 def iterate(problem: Problem, poses, mode: int = MODE_MM, max_iters: int = 10, mu0: float = 1e-2,
-            nu0: float = 2.0, tol_g: float = 0.0, trace: bool = True, max_rejects: int = 0):
+            nu0: float = 2.0, tol_g: float = 0.0, trace: bool = True, max_rejects: int = 0,
+            exact_below: float = 0.0):
     """ba_iterate: LM on the device, poses updated in place.  Synchronous.
     Returns (reports: list of dicts per window, trace ndarray (iters, W, 8) or None)."""
     if not (poses.is_cuda and poses.dtype == torch.float64 and poses.is_contiguous()):
         raise TypeError("poses must be a contiguous float64 device tensor (updated in place)")
     W = problem.info()["n_windows"]
-    o = _LMOpts(int(mode), int(max_iters), float(mu0), float(nu0), float(tol_g), int(max_rejects), 0)
+    o = _LMOpts(int(mode), int(max_iters), float(mu0), float(nu0), float(tol_g), int(max_rejects), 0,
+                float(exact_below))
     reps = (_LMReport * W)()
     tr = np.zeros((max(int(max_iters), 1), W, 8)) if trace else None
     trp = tr.ctypes.data_as(ct.c_void_p) if trace else ct.c_void_p(0)

@@ -44,9 +44,12 @@ void set_error(const char *fmt, ...) {
 // dense coupled path (ba_dense.hip)
 size_t dense_solve_workspace(int64_t n);
 ba_status dense_assemble(Problem *P, const double *poses, double *hess_out, bool use_lm, hipStream_t s);
+ba_status dense_assemble_exact(Problem *P, const double *poses, double *hess_out, bool use_lm, double exact_below,
+                               hipStream_t s);
 ba_status dense_solve(int64_t n, const double *A, const double *g, double mu, double *dx, int32_t *info, void *ws,
                       size_t ws_bytes, hipStream_t s);
 ba_status dense_lm_step(Problem *P, const double *poses, double tol_g, hipStream_t s);
+void launch_dense_gnorm(Problem *P, hipStream_t s);
 void dense_release(Problem *P);
 ba_status dense_prepare(Problem *P);
 
@@ -137,7 +140,14 @@ static ba_status enqueue_lm(Problem *P, double *poses, const ba_lm_options *opt,
             launch_window_solve_mm(P, poses, opt->tol_g, s);
         } else {
             launch_pose_derivs(P, poses, true, P->g, P->H, s, true);
-            BA_TRY(dense_assemble(P, poses, nullptr, true, s));
+            if (opt->exact_below > 0.0) {
+                // near convergence the exact Hessian: the switch reads the
+                // gradient norm at the poses the matrix is built at
+                launch_dense_gnorm(P, s);
+                BA_TRY(dense_assemble_exact(P, poses, nullptr, true, opt->exact_below, s));
+            } else {
+                BA_TRY(dense_assemble(P, poses, nullptr, true, s));
+            }
             BA_TRY(dense_lm_step(P, poses, opt->tol_g, s));
         }
         // trial residual, then the per-window decision and commit
@@ -158,7 +168,7 @@ struct IterGraph {
     // key
     double *poses = nullptr, *trace = nullptr;
     int32_t mode = -1, iters = -1, tune_gen = -1, max_rejects = 0;
-    double mu0 = 0, nu0 = 0, tol_g = 0;
+    double mu0 = 0, nu0 = 0, tol_g = 0, exact_below = 0;
     ~IterGraph() {
         if (exec) (void)hipGraphExecDestroy(exec);
         if (cap) (void)hipStreamDestroy(cap);
@@ -337,7 +347,7 @@ ba_status ba_eval_residual_grad_hessian(ba_problem *p, const double *poses, int3
         set_error("null problem, poses or cost");
         return BA_E_ARG;
     }
-    if (mode != BA_MODE_MM && mode != BA_MODE_COUPLED) {
+    if (mode != BA_MODE_MM && mode != BA_MODE_COUPLED && mode != BA_MODE_EXACT) {
         set_error("unknown mode %d", mode);
         return BA_E_UNSUPPORTED;
     }
@@ -351,9 +361,14 @@ ba_status ba_eval_residual_grad_hessian(ba_problem *p, const double *poses, int3
     if (voxel_eig) launch_voxel_eig(P, voxel_eig, stream);
     if (grad) {
         double *Hmm = (mode == BA_MODE_MM) ? hess : P->H;
-        if (mode == BA_MODE_COUPLED) BA_TRY(dense_prepare(P));   // the derivative pass may fill its h vectors
+        if (mode == BA_MODE_EXACT && P->prec != BA_PREC_F64) {
+            set_error("the exact Hessian is built for FP64 problems only");
+            return BA_E_UNSUPPORTED;
+        }
+        if (mode != BA_MODE_MM) BA_TRY(dense_prepare(P));   // the derivative pass may fill its h vectors
         launch_pose_derivs(P, poses, false, grad, Hmm, stream, mode == BA_MODE_COUPLED);
         if (mode == BA_MODE_COUPLED) BA_TRY(dense_assemble(P, poses, hess, false, stream));
+        if (mode == BA_MODE_EXACT) BA_TRY(dense_assemble_exact(P, poses, hess, false, 0.0, stream));
     }
     BA_HIP(hipGetLastError());
     return BA_OK;
@@ -362,7 +377,7 @@ ba_status ba_eval_residual_grad_hessian(ba_problem *p, const double *poses, int3
 size_t ba_solve_increment_workspace(int32_t mode, int32_t n_scans) {
     if (n_scans < 1) return 0;
     if (mode == BA_MODE_MM) return solve_mm_workspace(n_scans);
-    if (mode == BA_MODE_COUPLED) return dense_solve_workspace(6LL * n_scans);
+    if (mode == BA_MODE_COUPLED || mode == BA_MODE_EXACT) return dense_solve_workspace(6LL * n_scans);
     return 0;
 }
 
@@ -373,7 +388,7 @@ ba_status ba_solve_increment(int32_t mode, int32_t n_scans, const double *hess, 
         return BA_E_ARG;
     }
     const size_t need = ba_solve_increment_workspace(mode, n_scans);
-    if (mode != BA_MODE_MM && mode != BA_MODE_COUPLED) {
+    if (mode != BA_MODE_MM && mode != BA_MODE_COUPLED && mode != BA_MODE_EXACT) {
         set_error("unknown mode %d", mode);
         return BA_E_UNSUPPORTED;
     }
@@ -404,6 +419,10 @@ ba_status ba_iterate(ba_problem *p, double *poses_inout, const ba_lm_options *op
         return BA_E_ARG;
     }
     Problem *P = &p->P;
+    if (opt->exact_below > 0.0 && (opt->mode != BA_MODE_COUPLED || P->prec != BA_PREC_F64)) {
+        set_error("exact_below needs the coupled mode on an FP64 problem");
+        return BA_E_UNSUPPORTED;
+    }
     const int W = P->n_windows;
     const int iters = opt->max_iters;
     const double mu0 = opt->mu0 > 0 ? opt->mu0 : 1e-2;
@@ -424,7 +443,8 @@ ba_status ba_iterate(ba_problem *p, double *poses_inout, const ba_lm_options *op
         IterGraph *G = (IterGraph *)P->iter_graph;
         const bool same = G && G->exec && G->poses == poses_inout && G->trace == dtrace && G->mode == opt->mode &&
                           G->iters == iters && G->mu0 == mu0 && G->nu0 == nu0 && G->tol_g == opt->tol_g &&
-                          G->tune_gen == P->tune_gen && G->max_rejects == opt->max_rejects;
+                          G->tune_gen == P->tune_gen && G->max_rejects == opt->max_rejects &&
+                          G->exact_below == opt->exact_below;
         if (!same) {
             graph_release(P);
             G = new IterGraph();
@@ -450,6 +470,7 @@ ba_status ba_iterate(ba_problem *p, double *poses_inout, const ba_lm_options *op
                 G->tol_g = opt->tol_g;
                 G->tune_gen = P->tune_gen;
                 G->max_rejects = opt->max_rejects;
+                G->exact_below = opt->exact_below;
             } else {
                 graph_release(P);
                 G = nullptr;

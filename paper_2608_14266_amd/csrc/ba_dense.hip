@@ -142,6 +142,158 @@ __global__ __launch_bounds__(256) void k_pairs(int32_t n_seg, const PairSeg *__r
     }
 }
 
+// ---------------------------------------------------------------- exact Hessian (diagnostic)
+// The exact Hessian of Eq. 1 adds, per voxel, sum_l 2 / (l0 - l_l) F^l F^l^T
+// (l = 1, 2) to the coupled one, with per cluster
+//     F^l_c = (1/N_i) [ w0 x u_l + w_l x u0 ; N_c (e0 u_l + e_l u0) ],
+//     w_k = N_c e_k ybar + St u_k,  e_k = u_k^T (m_c - mbar),
+// (ybar = R mu_c, m_c = ybar + t, St = R S_c R^T).  All pair terms are
+// negative semi-definite outer products, so each cluster carries three scaled
+// vectors v_0 = sqrt(2) h, v_l = sqrt(2 / (l_l - l0)) F^l and a pair block is
+// -sum_k v_k,a v_k,b^T.  Terms of a gap l_l - l0 <= 1e-12 l2 are dropped.
+// One thread per voxel recomputes the voxel covariance at the poses and its
+// full eigen-decomposition from the centred clusters (voxel-major order).
+__global__ void k_exact_vecs(int32_t n_vx, const int64_t *__restrict__ vptr, const double *__restrict__ cN,
+                             const double *__restrict__ cmu, const double *__restrict__ cS,
+                             const int32_t *__restrict__ cscan, const double *__restrict__ poses,
+                             double *__restrict__ ev) {
+    const int v = blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= n_vx) return;
+    const int64_t a = vptr[v], b = vptr[v + 1];
+    double Nv = 0.0, mb[3] = {0, 0, 0};
+    for (int64_t c = a; c < b; c++) {
+        Pose P;
+        load_pose(poses, cscan[c], P);
+        const double n = cN[c];
+        double y[3];
+        rot(P.r, cmu + 3 * c, y);
+#pragma unroll
+        for (int r = 0; r < 3; r++) mb[r] += n * (y[r] + P.t[r]);
+        Nv += n;
+    }
+#pragma unroll
+    for (int r = 0; r < 3; r++) mb[r] /= Nv;
+    double A[6] = {0, 0, 0, 0, 0, 0};
+    for (int64_t c = a; c < b; c++) {
+        Pose P;
+        load_pose(poses, cscan[c], P);
+        const double n = cN[c];
+        double y[3], St[6], d[3];
+        rot(P.r, cmu + 3 * c, y);
+        rot_sym(P.r, cS + 6 * c, St);
+#pragma unroll
+        for (int r = 0; r < 3; r++) d[r] = y[r] + P.t[r] - mb[r];
+        A[0] += St[0] + n * d[0] * d[0];
+        A[1] += St[1] + n * d[0] * d[1];
+        A[2] += St[2] + n * d[0] * d[2];
+        A[3] += St[3] + n * d[1] * d[1];
+        A[4] += St[4] + n * d[1] * d[2];
+        A[5] += St[5] + n * d[2] * d[2];
+    }
+#pragma unroll
+    for (int k = 0; k < 6; k++) A[k] /= Nv;
+    double lam[3], U[9];
+    eig_sym3_full(A, lam, U);
+    const double tol = 1e-12 * fabs(lam[2]);
+    double wl[3] = {sqrt(2.0), 0.0, 0.0};
+    for (int l = 1; l <= 2; l++) {
+        const double gap = lam[l] - lam[0];
+        wl[l] = gap > tol ? sqrt(2.0 / gap) : 0.0;
+    }
+    const double *u0 = U;
+    for (int64_t c = a; c < b; c++) {
+        Pose P;
+        load_pose(poses, cscan[c], P);
+        const double n = cN[c];
+        double y[3], St[6], d[3], w0[3], su[3], ya[3];
+        rot(P.r, cmu + 3 * c, y);
+        rot_sym(P.r, cS + 6 * c, St);
+#pragma unroll
+        for (int r = 0; r < 3; r++) d[r] = y[r] + P.t[r] - mb[r];
+        const double e0 = dot(u0, d);
+        sym_mv(St, u0, su);
+#pragma unroll
+        for (int r = 0; r < 3; r++) w0[r] = n * e0 * y[r] + su[r];
+        double *o = ev + 18 * c;
+        cross(y, u0, ya);
+#pragma unroll
+        for (int r = 0; r < 3; r++) {
+            o[r] = wl[0] * (n / Nv) * ya[r];
+            o[3 + r] = wl[0] * (n / Nv) * u0[r];
+        }
+        for (int l = 1; l <= 2; l++) {
+            const double *ul = U + 3 * l;
+            const double el = dot(ul, d);
+            double sl[3], wlv[3], x1[3], x2[3];
+            sym_mv(St, ul, sl);
+#pragma unroll
+            for (int r = 0; r < 3; r++) wlv[r] = n * el * y[r] + sl[r];
+            cross(w0, ul, x1);
+            cross(wlv, u0, x2);
+#pragma unroll
+            for (int r = 0; r < 3; r++) {
+                o[6 * l + r] = wl[l] * (x1[r] + x2[r]) / Nv;
+                o[6 * l + 3 + r] = wl[l] * n * (e0 * ul[r] + el * u0[r]) / Nv;
+            }
+        }
+    }
+}
+
+// One wavefront per pose-pair key: block(ja, jb) = [H_MM(ja) if ja == jb]
+// - sum over the key's cluster pairs of sum_k v_k,a v_k,b^T, with k over the
+// coupled vector only for windows that take the coupled form (exact_below:
+// the exact terms are used while the window's gradient norm is below it; a
+// null lm uses them everywhere).
+__global__ __launch_bounds__(256) void k_pairs_x(int32_t n_seg, const PairSeg *__restrict__ segs,
+                                                 const int32_t *__restrict__ pa, const int32_t *__restrict__ pb,
+                                                 const double *__restrict__ ev, const double *__restrict__ Hmm,
+                                                 const int32_t *__restrict__ pose_window,
+                                                 const int32_t *__restrict__ win_pose_ptr,
+                                                 const int64_t *__restrict__ win_off, const LMState *__restrict__ lm,
+                                                 double exact_below, double *__restrict__ dense) {
+    const int wave = (int)(((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6);
+    const int lane = threadIdx.x & 63;
+    if (wave >= n_seg) return;
+    const PairSeg sg = segs[wave];
+    const int w = pose_window[sg.ja];
+    int nk = 3;
+    if (lm) {
+        const LMState &st = lm[w];
+        if (st.done || !st.need_eval) return;
+        if (!(st.gnorm < exact_below)) nk = 1;
+    }
+    double acc[64];
+#pragma unroll
+    for (int q = 0; q < 64; q++) acc[q] = 0.0;
+    for (int i = lane; i < sg.count; i += 64) {
+        const int64_t a = pa[sg.start + i], b = pb[sg.start + i];
+        for (int k = 0; k < nk; k++) {
+            double va[6], vb[6];
+#pragma unroll
+            for (int q = 0; q < 6; q++) {
+                va[q] = ev[18 * a + 6 * k + q];
+                vb[q] = ev[18 * b + 6 * k + q];
+            }
+#pragma unroll
+            for (int r = 0; r < 6; r++)
+#pragma unroll
+                for (int t = 0; t < 6; t++) acc[6 * r + t] = fma(va[r], vb[t], acc[6 * r + t]);
+        }
+    }
+    const double v = wave_reduce_scatter64(acc, lane);
+    if (lane < 36) {
+        const int r = lane / 6, t = lane % 6;
+        const int p0 = win_pose_ptr[w];
+        const int64_t nw = 6LL * (win_pose_ptr[w + 1] - p0);
+        const int la = sg.ja - p0, lb = sg.jb - p0;
+        double *D = dense + win_off[w];
+        double out = -v;
+        if (sg.ja == sg.jb) out += Hmm[36LL * sg.ja + 6 * r + t];
+        D[(6LL * la + r) * nw + 6 * lb + t] = out;
+        if (sg.ja != sg.jb) D[(6LL * lb + t) * nw + 6 * la + r] = out;
+    }
+}
+
 // ---------------------------------------------------------------- MFMA tile helpers
 // acc += A_chunk (64x32) * B_chunk (64x32)^T for this wave's 32x32 quadrant.
 // v_mfma_f64_16x16x4f64 operand layout on gfx950 (lane l): A[l%16][l/16],
@@ -506,6 +658,31 @@ __global__ __launch_bounds__(256) void k_backsub(const DenseDesc *__restrict__ d
 
 // ---------------------------------------------------------------- LM glue
 // Per-window damping parameters from the LM state and the dense diagonal.
+// Gradient norm of every window with fresh derivatives, formed exactly as
+// k_dense_params forms it (same partial sums and tree), for a decision that
+// must be taken before the dense matrix is assembled.
+__global__ __launch_bounds__(256) void k_dense_gnorm(int32_t W, const DenseDesc *__restrict__ desc,
+                                                     LMState *__restrict__ lm, const double *__restrict__ g) {
+    __shared__ double rs[256];
+    const int w = blockIdx.x;
+    if (w >= W) return;
+    LMState &st = lm[w];
+    if (st.done || !st.need_eval) return;
+    const DenseDesc d = desc[w];
+    double s = 0.0;
+    for (int i = threadIdx.x; i < d.n; i += 256) {
+        const double gi = g[6LL * d.pose0 + i];
+        s = fma(gi, gi, s);
+    }
+    rs[threadIdx.x] = s;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) rs[threadIdx.x] += rs[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) st.gnorm = sqrt(rs[0]);
+}
+
 __global__ __launch_bounds__(256) void k_dense_params(int32_t W, const DenseDesc *__restrict__ desc,
                                                       const double *__restrict__ H, const int64_t *__restrict__ h_off,
                                                       LMState *__restrict__ lm, DenseParam *__restrict__ prm,
@@ -526,7 +703,7 @@ __global__ __launch_bounds__(256) void k_dense_params(int32_t W, const DenseDesc
         for (int i = threadIdx.x; i < d.n; i += 256) {
             mx = fmax(mx, Hm[(int64_t)i * d.n + i]);
             const double gi = g[6LL * d.pose0 + i];
-            s += gi * gi;
+            s = fma(gi, gi, s);
         }
     }
     rm[threadIdx.x] = mx;
@@ -631,6 +808,10 @@ struct DenseState {
     PairSeg *segs = nullptr;
     int32_t *pa = nullptr, *pb = nullptr;
     double *h = nullptr;
+    // exact form: voxel ranges of the voxel-major clusters, 3 vectors per cluster
+    int32_t n_vx = 0;
+    int64_t *vptr = nullptr;
+    double *ev = nullptr;
     // matrices
     DenseDesc *desc = nullptr;
     DenseParam *prm = nullptr;
@@ -673,9 +854,11 @@ ba_status dense_prepare(Problem *P) {
     // every (voxel, j <= k) pair, keyed by (j, k): the clusters of a voxel are
     // in scan order, so a pair (i <= j) of its clusters has j_scan >= i_scan
     std::vector<int32_t> pa, pb;
+    std::vector<int64_t> vptr;
     for (int64_t a = 0; a < C;) {
         int64_t b = a;
         while (b < C && cvox[b] == cvox[a]) b++;
+        vptr.push_back(a);
         for (int64_t i = a; i < b; i++)
             for (int64_t j = i; j < b; j++) {
                 pa.push_back((int32_t)i);
@@ -683,6 +866,10 @@ ba_status dense_prepare(Problem *P) {
             }
         a = b;
     }
+    vptr.push_back(C);
+    D->n_vx = (int32_t)vptr.size() - 1;
+    BA_TRY(D->mem.alloc(&D->vptr, (int64_t)vptr.size()));
+    BA_HIP(hipMemcpy(D->vptr, vptr.data(), sizeof(int64_t) * vptr.size(), hipMemcpyHostToDevice));
     const int64_t E = (int64_t)pa.size();
     // stable two-pass counting sort: by the second scan, then by the first
     const int32_t NP = P->n_poses;
@@ -805,6 +992,37 @@ ba_status dense_assemble(Problem *P, const double *poses, double *hess_out, bool
     return BA_OK;
 }
 
+// Exact Hessian at `poses` (FP64 problems; the per-pose blocks P->H must hold
+// the MM Hessian at the same poses) into hess_out, or with the LM the
+// per-window dense buffers with the exact terms for windows whose gradient
+// norm is below exact_below.
+ba_status dense_assemble_exact(Problem *P, const double *poses, double *hess_out, bool use_lm, double exact_below,
+                               hipStream_t s) {
+    BA_TRY(dense_prepare(P));
+    DenseState *D = dense_state(P);
+    if (P->prec != BA_PREC_F64) {
+        set_error("the exact Hessian is built for FP64 problems only");
+        return BA_E_UNSUPPORTED;
+    }
+    if (!D->ev) BA_TRY(D->mem.alloc(&D->ev, 18 * std::max<int64_t>(P->n_clusters, 1)));
+    double *dst = hess_out ? hess_out : P->dense;
+    const LMState *lm = use_lm ? P->lm : nullptr;
+    hipLaunchKernelGGL(k_exact_vecs, dim3(nblk(D->n_vx)), dim3(256), 0, s, D->n_vx, D->vptr, P->c_N, P->c_mu,
+                       P->c_S, P->c_scan, poses, D->ev);
+    if (!use_lm) {
+        const int64_t tot = P->dense_total;
+        hipLaunchKernelGGL(k_fill, dim3(nblk(tot)), dim3(256), 0, s, tot, dst, 0.0);
+    } else {
+        hipLaunchKernelGGL(k_dense_zero_stale, dim3(2048), dim3(256), 0, s, P->n_windows, D->desc, D->h_off, lm,
+                           dst);
+    }
+    if (D->n_seg)
+        hipLaunchKernelGGL(k_pairs_x, dim3(nblk((int64_t)D->n_seg * 64)), dim3(256), 0, s, D->n_seg, D->segs, D->pa,
+                           D->pb, D->ev, P->H, P->pose_window, P->win_pose_ptr, D->h_off, lm, exact_below, dst);
+    BA_HIP(hipGetLastError());
+    return BA_OK;
+}
+
 static void launch_factor_solve(DenseState *D, int32_t nmat, int32_t max_n, const double *H, const int64_t *h_off,
                                 const double *g, double *x, const int64_t *x_off, hipStream_t s) {
     const int nsteps = (max_n + TB - 1) / TB;
@@ -849,6 +1067,11 @@ static void launch_factor_solve(DenseState *D, int32_t nmat, int32_t max_n, cons
     for (int st = nsteps - 1; st >= 0; st--)
         hipLaunchKernelGGL(k_backsub, dim3((unsigned)std::max(st, 1), nmat), dim3(256), 0, s, D->desc, D->prm,
                            D->work, x, x_off, st);
+}
+
+void launch_dense_gnorm(Problem *P, hipStream_t s) {
+    DenseState *D = dense_state(P);
+    hipLaunchKernelGGL(k_dense_gnorm, dim3(P->n_windows), dim3(256), 0, s, P->n_windows, D->desc, P->lm, P->g);
 }
 
 ba_status dense_lm_step(Problem *P, const double *poses, double tol_g, hipStream_t s) {

@@ -315,6 +315,34 @@ __device__ __forceinline__ void eig_sym3(const double *A, double *lam, double *u
     u[0] = vs[0]; u[1] = vs[1]; u[2] = vs[2];
 }
 
+// All three eigenpairs of the same Jacobi iteration: lam ascending and the
+// matching unit eigenvectors U[3 * k .. 3 * k + 2] (k = 0, 1, 2); lam and
+// U[0..2] equal eig_sym3's outputs.
+__device__ __forceinline__ void eig_sym3_full(const double *A, double *lam, double *U) {
+    double a00 = A[0], a01 = A[1], a02 = A[2], a11 = A[3], a12 = A[4], a22 = A[5];
+    double v0[3] = {1, 0, 0}, v1[3] = {0, 1, 0}, v2[3] = {0, 0, 1};
+    for (int sweep = 0; sweep < 12; sweep++) {
+        double scale = fabs(a00) + fabs(a11) + fabs(a22);
+        double off = fabs(a01) + fabs(a02) + fabs(a12);
+        if (off <= 1e-22 * scale || off == 0.0) break;
+        jacobi_rot(a00, a11, a01, a02, a12, v0, v1);
+        jacobi_rot(a00, a22, a02, a01, a12, v0, v2);
+        jacobi_rot(a11, a22, a12, a01, a02, v1, v2);
+    }
+    double d[3] = {a00, a11, a22};
+    int i0 = 0, i1 = 1, i2 = 2;
+    if (d[i1] < d[i0]) { int t = i0; i0 = i1; i1 = t; }
+    if (d[i2] < d[i1]) { int t = i1; i1 = i2; i2 = t; }
+    if (d[i1] < d[i0]) { int t = i0; i0 = i1; i1 = t; }
+    const int ord[3] = {i0, i1, i2};
+#pragma unroll
+    for (int k = 0; k < 3; k++) {
+        lam[k] = d[ord[k]];
+        const double *vs = (ord[k] == 0) ? v0 : (ord[k] == 1 ? v1 : v2);
+        U[3 * k] = vs[0]; U[3 * k + 1] = vs[1]; U[3 * k + 2] = vs[2];
+    }
+}
+
 // Exp(phi) as the rotation of the unit quaternion (cos(th/2), sin(th/2) phi/th);
 // the ratio sin(th/2)/th uses its Taylor series below 1e-4 rad.
 __device__ __forceinline__ void so3_exp(const double *phi, double *E) {

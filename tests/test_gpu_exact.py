@@ -1,0 +1,163 @@
+"""The exact Hessian of Eq. 1 on the GPU (diagnostic mode BA_MODE_EXACT):
+parity with the oracle's, the translation gauge in its null space at any
+poses and at full size, and all six gauge directions at the optimum of a
+noise-free scene."""
+import numpy as np
+import pytest
+
+import scenes
+from helpers import build_gpu, rel
+from test_oracle_pins import gauge_basis
+
+pytestmark = pytest.mark.gpu
+
+
+def say(msg):
+    print(f"[gpu-case] {msg}", flush=True)
+
+
+@pytest.fixture(scope="module")
+def dev():
+    import torch
+    d = torch.device("cuda:0")
+    torch.cuda.set_device(d)
+    return d
+
+
+@pytest.fixture(scope="module")
+def ba():
+    import os
+    from paper_2608_14266_amd import build as hb
+    if not os.path.exists(hb.LIB):
+        hb.build()
+    import paper_2608_14266_amd as m
+    m.load()
+    return m
+
+
+def _exact(ba, dev, prob, poses, mode=None):
+    import torch
+    P = torch.as_tensor(poses, device=dev)
+    _, g, H, _ = ba.eval_residual_grad_hessian(prob, P, ba.MODE_EXACT if mode is None else mode)
+    return g.cpu().numpy().ravel(), H.cpu().numpy()
+
+
+SCENES = {
+    "tiny": lambda: scenes.tiny_config(seed=1000),
+    "window-60": lambda: scenes.scaled_window(seed=2001, n_scans=60, n_planes=3000),
+}
+
+
+@pytest.mark.parametrize("name", list(SCENES))
+@pytest.mark.parametrize("at", ["init", "truth"])
+def test_exact_hessian_matches_oracle(ba, dev, orc, name, at):
+    sc = SCENES[name]()
+    cl = orc.scene_clusters(sc)
+    poses = sc.poses_init if at == "init" else sc.poses_true
+    say(f"exact Hessian {name} at {at}")
+    prob = build_gpu(ba, sc, dev)
+    try:
+        g, H = _exact(ba, dev, prob, poses)
+    finally:
+        prob.close()
+    _, g_ref, H_ref, nd = orc.evaluate(orc.EXACT, cl, poses)
+    assert nd == 0
+    # eigenvector rounding enters the extra terms amplified by l2 / (l1 - l0)
+    lam = orc.voxel_stats(cl, poses)["lam"]
+    seen = lam[:, 2] > 0
+    kappa = float(np.max(lam[seen, 2] / (lam[seen, 1] - lam[seen, 0])))
+    tol = 1e-12 * max(1.0, kappa)
+    err = rel(H, H_ref)
+    print(f"  {name}/{at}: exact Hessian rel err {err:.2e}, gap factor {kappa:.2e}, tolerance {tol:.2e}")
+    assert err <= tol
+    assert np.abs(H - H.T).max() <= 1e-14 * np.abs(H).max()
+
+
+def test_translation_gauge_is_in_the_null_space_at_full_size(ba, dev):
+    """The cost is invariant under a common translation of all poses, a
+    straight line in the chart, so H e_t = 0 exactly at any poses (coupled
+    and exact forms); checked on the 500-pose window (3000 x 3000)."""
+    sc = scenes.window_config(seed=2000)
+    say("exact Hessian, full-size window, translation gauge")
+    prob = build_gpu(ba, sc, dev)
+    try:
+        for mode in (ba.MODE_COUPLED, ba.MODE_EXACT):
+            _, H = _exact(ba, dev, prob, sc.poses_init, mode)
+            N = sc.n_scans
+            for k in range(3):
+                xi = np.zeros(6 * N)
+                xi[6 * np.arange(N) + 3 + k] = 1.0
+                r = np.linalg.norm(H @ xi) / (np.linalg.norm(H) * np.linalg.norm(xi))
+                print(f"  mode {mode} axis {k}: |H xi| / (|H| |xi|) = {r:.2e}")
+                assert r <= 1e-12
+    finally:
+        prob.close()
+
+
+def test_six_gauge_directions_at_the_optimum(ba, dev):
+    """Noise-free scene at the true poses (the optimum, cost 0): all six gauge
+    directions lie in the exact Hessian's null space and no seventh does."""
+    sc = scenes.tiny_config(seed=1002, sigma=0.0)
+    prob = build_gpu(ba, sc, dev)
+    try:
+        _, H = _exact(ba, dev, prob, sc.poses_true)
+    finally:
+        prob.close()
+    Vq, _ = np.linalg.qr(gauge_basis(sc.poses_true))
+    assert np.linalg.norm(H @ Vq) <= 1e-11 * np.linalg.norm(H)
+    ev = np.sort(np.abs(np.linalg.eigvalsh(H)))
+    assert ev[5] <= 1e-12 * ev[-1]
+    assert ev[6] >= 1e-8 * ev[-1]
+
+
+def test_exact_mode_refuses_the_precision_form(ba, dev):
+    import torch
+    sc = scenes.tiny_config(seed=1000)
+    P = torch.as_tensor(sc.poses_init, device=dev)
+    prob = build_gpu(ba, sc, dev, precision=ba.PREC_F32, ref_poses=P)
+    try:
+        with pytest.raises(ba.BAError, match="FP64 problems only"):
+            ba.eval_residual_grad_hessian(prob, P, ba.MODE_EXACT)
+    finally:
+        prob.close()
+
+
+def test_hybrid_lm_matches_oracle(ba, dev, orc):
+    """Coupled LM that switches to the exact Hessian once the gradient norm at
+    the current poses is below 0.1 (the oracle's gradient norms on this scene
+    are 1.1e2, 3.6, 8.8e-2, ...: the switch is not near a rounding tie):
+    decisions, costs and final poses as the oracle's."""
+    import torch
+    from helpers import resolved_prefix
+    sc = scenes.scaled_window(seed=2004, n_scans=30, n_planes=1500)
+    cl = orc.scene_clusters(sc)
+    P_ref, rep_ref, c_ref = orc.lm(orc.COUPLED, cl, sc.poses_init, 12, tol_g=1e-9, exact_below=0.1)
+    prob = build_gpu(ba, sc, dev)
+    try:
+        P = torch.as_tensor(sc.poses_init, device=dev).contiguous()
+        reps, tr = ba.iterate(prob, P, ba.MODE_COUPLED, max_iters=12, tol_g=1e-9, exact_below=0.1)
+    finally:
+        prob.close()
+    tr = tr[:, 0, :]
+    k = resolved_prefix(tr, rep_ref)
+    say(f"hybrid: {k} resolved iterations of {len(rep_ref)}")
+    assert k >= 4
+    assert np.array_equal(tr[:k, 4], rep_ref[:k, 4])
+    scale = np.abs(rep_ref[:k, [0, 1]])
+    assert np.all(np.abs(tr[:k, [0, 1]] - rep_ref[:k, [0, 1]]) <= 1e-10 * scale)
+    assert abs(reps[0]["cost_final"] - c_ref) <= 1e-10 * c_ref
+    assert reps[0]["converged"] == 1
+    dP = np.abs(P.cpu().numpy() - P_ref)
+    assert np.all(dP <= 1e-8 * (1.0 + np.abs(P_ref)))
+
+
+def test_hybrid_option_needs_coupled_fp64(ba, dev):
+    import torch
+    sc = scenes.tiny_config(seed=1000)
+    prob = build_gpu(ba, sc, dev)
+    try:
+        P = torch.as_tensor(sc.poses_init, device=dev).contiguous()
+        with pytest.raises(ba.BAError, match="exact_below needs the coupled mode"):
+            ba.iterate(prob, P, ba.MODE_MM, max_iters=2, exact_below=0.1)
+    finally:
+        prob.close()
