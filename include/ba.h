@@ -141,7 +141,8 @@ typedef struct ba_lm_report {  /* one per window */
  * rounding level between settings), never what is computed; for one setting
  * results stay bitwise reproducible. */
 typedef struct ba_tuning {
-    int32_t vox_split;  /* waves sharing one 64-voxel group in the residual pass: 1, 2 or 4 */
+    int32_t vox_split;  /* waves sharing one 64-voxel group in the residual pass: 1, 2 or 4; 0: chosen per
+                         * group by its clusters per voxel (1 up to 4, 2 up to 8, 4 beyond) */
     int32_t vox_grid;   /* residual pass: 0 = one block per group; 1..64 = persistent grid of that many blocks per CU */
     int32_t pose_grid;  /* derivative pass: 0 = one wavefront per chunk; 1..64 = persistent, blocks of 4 waves per CU */
     int32_t chunk_len;  /* clusters per derivative-pass chunk, 32..2^20 */

@@ -509,7 +509,8 @@ ba_status ba_iterate(ba_problem *p, double *poses_inout, const ba_lm_options *op
 namespace ba {
 
 static ba_status check_tuning(const ba_tuning *t) {
-    if (!(t->vox_split == 1 || t->vox_split == 2 || t->vox_split == 4) || t->vox_grid < 0 || t->vox_grid > 64 ||
+    if (!(t->vox_split == 0 || t->vox_split == 1 || t->vox_split == 2 || t->vox_split == 4) || t->vox_grid < 0 ||
+        t->vox_grid > 64 ||
         t->pose_grid < 0 || t->pose_grid > 64 || t->chunk_len < MIN_CHUNK || t->chunk_len > (1 << 20)) {
         set_error("tuning out of range (vox_split %d, vox_grid %d, pose_grid %d, chunk_len %d)", t->vox_split,
                   t->vox_grid, t->pose_grid, t->chunk_len);
@@ -597,7 +598,7 @@ ba_status ba_autotune(ba_problem *p, const double *poses, int32_t reps, ba_tunin
     Problem *P = &p->P;
     ba_tuning cur = export_tuning(P);
     // residual pass: cluster split x grid
-    const int splits[3] = {4, 2, 1};
+    const int splits[4] = {4, 2, 1, 0};
     const int vgrids[5] = {0, 1, 2, 4, 8};
     float best_ms = 1e30f;
     ba_tuning t = cur, win = cur;

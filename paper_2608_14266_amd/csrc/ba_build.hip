@@ -447,6 +447,28 @@ static ba_status make_plan(Problem *P, const std::vector<int32_t> &cvox, const s
         for (int32_t gi = win_group_ptr[w + 1] - 1; gi >= win_group_ptr[w]; gi--)
             vblocks.push_back(VoxBlock{gi, 1, 4, w});
     P->n_vblocks = (int32_t)vblocks.size();
+    // the same groups with a split chosen per group: one wave up to 4
+    // clusters per voxel, two up to 8, four beyond, so that no wave walks more
+    // than about five clusters; a 256-thread block takes four one-wave, two
+    // two-wave or one four-wave group of one window, largest counts first
+    std::vector<VoxBlock> vmix;
+    for (int32_t w = 0; w < W; w++) {
+        int32_t gi = win_group_ptr[w + 1] - 1;
+        while (gi >= win_group_ptr[w]) {
+            const int32_t m = groups[gi].m;
+            const int32_t sp = m <= 4 ? 1 : (m <= 8 ? 2 : 4);
+            int32_t ng = 0;
+            // groups gi, gi-1, ... of the same split (counts are non-increasing downwards)
+            while (ng < 4 / sp && gi - ng >= win_group_ptr[w]) {
+                const int32_t mm = groups[gi - ng].m;
+                if ((mm <= 4 ? 1 : (mm <= 8 ? 2 : 4)) != sp) break;
+                ng++;
+            }
+            vmix.push_back(VoxBlock{gi - ng + 1, ng, sp, w});
+            gi -= ng;
+        }
+    }
+    P->n_vblocks_mix = (int32_t)vmix.size();
     // pose-major order (scan, slot): a stable counting sort by scan of the
     // clusters listed in slot order (a voxel's clusters have distinct scans)
     std::vector<int32_t> porder(C);
@@ -497,6 +519,7 @@ static ba_status make_plan(Problem *P, const std::vector<int32_t> &cvox, const s
     BA_TRY(keep.alloc(&P->v_pose, CP));
     BA_TRY(keep.alloc(&P->groups, std::max<int64_t>(P->n_groups, 1)));
     BA_TRY(keep.alloc(&P->vblocks, std::max<int64_t>(P->n_vblocks, 1)));
+    BA_TRY(keep.alloc(&P->vblocks_mix, std::max<int64_t>(P->n_vblocks_mix, 1)));
     BA_TRY(keep.alloc(&P->slot_vox, std::max<int64_t>(NS, 1)));
     BA_TRY(keep.alloc(&P->vstate, 2 * std::max<int64_t>(NS, 1) * VSTATE));
     BA_TRY(keep.alloc(&P->wave_cost, std::max<int64_t>(P->n_groups, 1)));
@@ -539,6 +562,8 @@ static ba_status make_plan(Problem *P, const std::vector<int32_t> &cvox, const s
     BA_HIP(hipMemsetAsync(P->vstate, 0, sizeof(double) * 2 * std::max<int64_t>(NS, 1) * VSTATE, s));
     BA_HIP(hipMemcpyAsync(P->groups, groups.data(), sizeof(GroupDesc) * groups.size(), hipMemcpyHostToDevice, s));
     BA_HIP(hipMemcpyAsync(P->vblocks, vblocks.data(), sizeof(VoxBlock) * vblocks.size(), hipMemcpyHostToDevice, s));
+    if (!vmix.empty())
+        BA_HIP(hipMemcpyAsync(P->vblocks_mix, vmix.data(), sizeof(VoxBlock) * vmix.size(), hipMemcpyHostToDevice, s));
     BA_HIP(hipMemcpyAsync(P->slot_vox, slot_vox.data(), sizeof(int32_t) * slot_vox.size(), hipMemcpyHostToDevice, s));
     BA_TRY(replan_chunks(P, P->chunk_len, s));
     BA_HIP(hipMemcpyAsync(P->win_group_ptr, win_group_ptr.data(), sizeof(int32_t) * (W + 1), hipMemcpyHostToDevice, s));

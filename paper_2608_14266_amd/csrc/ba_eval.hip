@@ -278,6 +278,67 @@ __global__ __launch_bounds__(64 * SPLIT) void k_vox(const VoxBlock *__restrict__
     }
 }
 
+// Residual pass with the split chosen per group (plan table vblocks_mix):
+// a 256-thread block takes 4 / split groups of one window, `split` waves per
+// group sharing its clusters (k = part, part + split, ...); the first wave of
+// each group adds the others' partial sums in wave order through LDS and
+// finishes the voxels.  Every wave reaches the one barrier.
+template <class Src, bool PERSIST>
+__global__ __launch_bounds__(256) void k_vox_mixed(const VoxBlock *__restrict__ blocks, int32_t n_blocks,
+                                                   const GroupDesc *__restrict__ groups, int64_t c_pad, Src src,
+                                                   const int32_t *__restrict__ vpose,
+                                                   const double *__restrict__ poses, double *__restrict__ vstate,
+                                                   int64_t n_slots, const LMState *__restrict__ lm, int trial,
+                                                   double *__restrict__ group_cost) {
+    __shared__ double part[4][10][64];
+    const int w = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    for (int bi = blockIdx.x; bi < n_blocks; bi += (PERSIST ? gridDim.x : n_blocks)) {
+        const VoxBlock b = blocks[bi];
+        const int sp = b.split;
+        const int gsub = w / sp, pt = w % sp;
+        const bool has_group = gsub < b.ng;
+        const int gi = b.g0 + (has_group ? gsub : 0);
+        int buf = 0;
+        bool run = has_group;
+        if (lm) {
+            const LMState &st = lm[b.window];
+            run = run && !st.done;
+            buf = trial ? 1 - st.cur : st.cur;
+        }
+        const GroupDesc g = groups[gi];
+        const bool active = run && lane < g.nvox;
+        VoxSums a;
+        vox_zero(a);
+        if (active && pt < g.m) vox_accumulate(g, (int64_t)gi * 64 + lane, lane, pt, sp, c_pad, src, vpose, poses, a);
+        if (pt > 0) {
+            double *pp = &part[w][0][0];
+            pp[lane] = a.n;
+            pp[64 + lane] = a.s0; pp[128 + lane] = a.s1; pp[192 + lane] = a.s2;
+#pragma unroll
+            for (int q = 0; q < 6; q++) pp[(4 + q) * 64 + lane] = a.M[q];
+        }
+        __syncthreads();
+        if (pt == 0 && run) {
+            double *vs = vstate + (int64_t)buf * n_slots * VSTATE;
+            double lam0 = 0.0;
+            if (active) {
+                for (int v = 1; v < sp; v++) {
+                    const double *pp = &part[w + v][0][0];
+                    a.n += pp[lane];
+                    a.s0 += pp[64 + lane]; a.s1 += pp[128 + lane]; a.s2 += pp[192 + lane];
+#pragma unroll
+                    for (int q = 0; q < 6; q++) a.M[q] += pp[(4 + q) * 64 + lane];
+                }
+                lam0 = vox_finish(a, vs + ((int64_t)gi * 64 + lane) * VSTATE);
+            }
+            const double c = wave_sum(lam0);
+            if (lane == 0) group_cost[gi] = c;
+        }
+        if (PERSIST) __syncthreads();   // part[] is reused by the next item
+    }
+}
+
 // Per-cluster surrogate gradient and Hessian terms (formulas in the header of
 // this file) in arithmetic T from y = R mu (lever arm), e = u^T (m - mbar)
 // (FP64), St and u, added into the FP64 accumulators with the voxel scale
@@ -605,7 +666,22 @@ void launch_vox(Problem *P, const double *poses, bool use_lm, bool trial, hipStr
                                P->groups, P->c_pad, MK(P, true), P->v_pose, poses, P->vstate, ns, lm, t,           \
                                P->wave_cost);                                                                      \
     } while (0)
-    if (P->prec == BA_PREC_F32) {
+#define BA_VOX_MIX(SRC, MK)                                                                                       \
+    do {                                                                                                           \
+        const dim3 gm(pass_grid(P->n_vblocks_mix, 1, P->tune.vox_grid, P->n_cu));                                   \
+        if (pers)                                                                                                  \
+            hipLaunchKernelGGL((k_vox_mixed<SRC, true>), gm, dim3(256), 0, s, P->vblocks_mix, P->n_vblocks_mix,    \
+                               P->groups, P->c_pad, MK(P, true), P->v_pose, poses, P->vstate, ns, lm, t,           \
+                               P->wave_cost);                                                                      \
+        else                                                                                                       \
+            hipLaunchKernelGGL((k_vox_mixed<SRC, false>), gm, dim3(256), 0, s, P->vblocks_mix, P->n_vblocks_mix,   \
+                               P->groups, P->c_pad, MK(P, true), P->v_pose, poses, P->vstate, ns, lm, t,           \
+                               P->wave_cost);                                                                      \
+    } while (0)
+    if (P->tune.vox_split == 0) {
+        if (P->prec == BA_PREC_F32) BA_VOX_MIX(SrcF32, src32);
+        else BA_VOX_MIX(SrcF64, src64);
+    } else if (P->prec == BA_PREC_F32) {
         if (P->tune.vox_split == 1) BA_VOX(SrcF32, 1, src32);
         else if (P->tune.vox_split == 2) BA_VOX(SrcF32, 2, src32);
         else BA_VOX(SrcF32, 4, src32);

@@ -70,7 +70,7 @@ static constexpr int NPART = 27;    // g[6] + Hpp[6] + Hpt[9] + Htt[6]
 
 // Launch choices of the two evaluation passes (ba_tuning).
 struct Tuning {
-    int32_t vox_split = 4;   // waves sharing one 64-voxel group in the residual pass
+    int32_t vox_split = 4;   // waves sharing one 64-voxel group in the residual pass (0: per group, by its size)
     int32_t vox_grid = 0;    // 0: one block per group; k > 0: persistent grid of k blocks per CU
     int32_t pose_grid = 0;   // 0: one wave per chunk; k > 0: persistent grid of k blocks per CU
     int32_t chunk_len = 256; // clusters per derivative-pass chunk
@@ -104,6 +104,8 @@ struct Problem {
     GroupDesc *groups = nullptr;
     VoxBlock *vblocks = nullptr;
     int32_t n_vblocks = 0;
+    VoxBlock *vblocks_mix = nullptr;   // per-group split: 4 one-wave, 2 two-wave or 1 four-wave group per block
+    int32_t n_vblocks_mix = 0;
     int32_t *slot_vox = nullptr; // slot -> input voxel id (-1 padding), n_groups*64
     double *vstate = nullptr;   // [2][n_groups*64][VSTATE]
     double *wave_cost = nullptr; // [n_groups]

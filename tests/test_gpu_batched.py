@@ -102,6 +102,8 @@ TUNINGS = [
     dict(vox_split=2, vox_grid=2, pose_grid=4, chunk_len=64),
     dict(vox_split=4, vox_grid=1, pose_grid=1, chunk_len=1024),
     dict(vox_split=4, vox_grid=8, pose_grid=8, chunk_len=32),
+    dict(vox_split=0, vox_grid=0, pose_grid=0, chunk_len=512),   # split chosen per group
+    dict(vox_split=0, vox_grid=2, pose_grid=2, chunk_len=128),
 ]
 
 
@@ -143,7 +145,7 @@ def test_autotune_applies_a_valid_choice(ba, dev, batch, tmp_path):
     ref = [t.cpu().numpy() for t in ba.eval_residual_grad_hessian(pb, P, ba.MODE_MM)[:3]]
     cache = str(tmp_path / "tuning.json")
     t1 = ba.tuned(pb, P, cache_path=cache, reps=2)
-    assert not t1["cached"] and t1["vox_split"] in (1, 2, 4) and t1["chunk_len"] >= 32
+    assert not t1["cached"] and t1["vox_split"] in (0, 1, 2, 4) and t1["chunk_len"] >= 32
     assert ba.problem_get_tuning(pb) == {k: t1[k] for k in ("vox_split", "vox_grid", "pose_grid", "chunk_len")}
     a = [t.cpu().numpy() for t in ba.eval_residual_grad_hessian(pb, P, ba.MODE_MM)[:3]]
     assert np.all(np.abs(a[0] - ref[0]) <= TOL * np.abs(ref[0])) and rel(a[2], ref[2]) <= TOL
