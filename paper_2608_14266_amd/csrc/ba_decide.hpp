@@ -11,18 +11,44 @@ namespace ba {
 static constexpr int DECIDE_THREADS = 1024;
 
 // Sum of a window's group residuals [g0, g1) by a DECIDE_THREADS block, in
-// one fixed order (used for the current, the trial and the reported cost).
-__device__ __forceinline__ double window_cost_sum(int g0, int g1, const double *__restrict__ group_cost,
-                                                  double *red) {
+// one fixed order (used for the current, the trial and the reported cost):
+// each thread's groups g0 + t, g0 + t + DECIDE_THREADS, ... in turn, then the
+// block reduction in wave order.
+__device__ __forceinline__ double window_cost_part(int g0, int g1, const double *__restrict__ group_cost) {
     double c = 0.0;
 #pragma unroll 4
     for (int i = g0 + threadIdx.x; i < g1; i += DECIDE_THREADS) c += group_cost[i];
-    return block_sum<DECIDE_THREADS / 64>(c, red);
+    return c;
+}
+
+__device__ __forceinline__ double window_cost_sum(int g0, int g1, const double *__restrict__ group_cost,
+                                                  double *red) {
+    return block_sum<DECIDE_THREADS / 64>(window_cost_part(g0, g1, group_cost), red);
+}
+
+// Copy of a window's 12 * n pose values, eight loads in flight per thread
+// before their stores (the two arrays never overlap).
+__device__ __forceinline__ void copy_window_poses(const double *__restrict__ src, double *__restrict__ dst,
+                                                  int64_t n) {
+    constexpr int U = 8;
+    for (int64_t b = threadIdx.x; b < n; b += (int64_t)U * DECIDE_THREADS) {
+        double v[U];
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+            const int64_t i = b + (int64_t)u * DECIDE_THREADS;
+            v[u] = i < n ? src[i] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+            const int64_t i = b + (int64_t)u * DECIDE_THREADS;
+            if (i < n) dst[i] = v[u];
+        }
+    }
 }
 
 __device__ __forceinline__ void decide_window(int w, const DecideArgs &da) {
     constexpr int NW = DECIDE_THREADS / 64;
-    __shared__ double red[NW];
+    __shared__ double red_q[NW], red_c[NW];
     __shared__ int redi[NW];
     __shared__ int s_acc;
     LMState &st = da.lm[w];
@@ -36,9 +62,8 @@ __device__ __forceinline__ void decide_window(int w, const DecideArgs &da) {
         const int inf = da.pose_info[j];
         if (inf) info = min(info, inf);
     }
-    q = block_sum<NW>(q, red);
-    c = window_cost_sum(g0, g1, da.group_cost, red);
-    info = block_min_i<NW>(info, redi);
+    c = window_cost_part(g0, g1, da.group_cost);
+    block_sum2_min<NW>(q, c, info, red_q, red_c, redi);
     if (threadIdx.x == 0) {
         const double qq = q, ct = c;
         const int inf = (info == 0x7fffffff) ? 0 : info;
@@ -74,10 +99,7 @@ __device__ __forceinline__ void decide_window(int w, const DecideArgs &da) {
         }
     }
     __syncthreads();
-    if (s_acc) {
-        const int64_t a = 12LL * p0, b = 12LL * p1;
-        for (int64_t i = a + threadIdx.x; i < b; i += DECIDE_THREADS) da.poses[i] = da.poses_trial[i];
-    }
+    if (s_acc) copy_window_poses(da.poses_trial + 12LL * p0, da.poses + 12LL * p0, 12LL * (p1 - p0));
 }
 
 }  // namespace ba

@@ -54,6 +54,53 @@ __device__ __forceinline__ double block_max(double v, double *lds) {
     return s;
 }
 
+// Several block reductions behind one barrier: each value is reduced exactly
+// as block_sum / block_max / block_min_i reduce it (same wave order, so the
+// results are bitwise those of the separate calls).  The block synchronises
+// once; the caller synchronises again before it writes these LDS arrays anew.
+template <int NW>
+__device__ __forceinline__ void block_sum_max(double &s, double &m, double *lds_s, double *lds_m) {
+    s = wave_sum(s);
+    m = wave_max(m);
+    if ((threadIdx.x & 63) == 0) {
+        lds_s[threadIdx.x >> 6] = s;
+        lds_m[threadIdx.x >> 6] = m;
+    }
+    __syncthreads();
+    double a = 0.0, b = lds_m[0];
+#pragma unroll
+    for (int i = 0; i < NW; i++) a += lds_s[i];
+#pragma unroll
+    for (int i = 1; i < NW; i++) b = fmax(b, lds_m[i]);
+    s = a;
+    m = b;
+}
+
+template <int NW>
+__device__ __forceinline__ void block_sum2_min(double &s0, double &s1, int &k, double *lds_s0, double *lds_s1,
+                                               int *lds_k) {
+    s0 = wave_sum(s0);
+    s1 = wave_sum(s1);
+    k = wave_min_i(k);
+    if ((threadIdx.x & 63) == 0) {
+        lds_s0[threadIdx.x >> 6] = s0;
+        lds_s1[threadIdx.x >> 6] = s1;
+        lds_k[threadIdx.x >> 6] = k;
+    }
+    __syncthreads();
+    double a = 0.0, b = 0.0;
+    int c = lds_k[0];
+#pragma unroll
+    for (int i = 0; i < NW; i++) a += lds_s0[i];
+#pragma unroll
+    for (int i = 0; i < NW; i++) b += lds_s1[i];
+#pragma unroll
+    for (int i = 1; i < NW; i++) c = min(c, lds_k[i]);
+    s0 = a;
+    s1 = b;
+    k = c;
+}
+
 template <int NW>
 __device__ __forceinline__ int block_min_i(int v, int *lds) {
     v = wave_min_i(v);

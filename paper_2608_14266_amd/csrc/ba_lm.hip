@@ -198,7 +198,8 @@ __global__ void k_commit(int32_t n_poses, const int32_t *__restrict__ pose_windo
 static constexpr int WSOLVE_THREADS = 512;
 static constexpr int SPLIT_SOLVE_POSES = 1024;
 
-// Returns whether the window is finished (block-uniform).
+// Returns whether the window is finished (block-uniform).  `red` holds
+// 2 * WSOLVE_THREADS / 64 doubles.
 __device__ __forceinline__ bool window_fresh_stats(LMState &st, const double *__restrict__ g,
                                                    const double *__restrict__ H, int p0, int p1, double tol_g,
                                                    double *red, int *s_done) {
@@ -213,8 +214,7 @@ __device__ __forceinline__ bool window_fresh_stats(LMState &st, const double *__
             mx = fmax(mx, H[36LL * j + 7 * k]);
         }
     }
-    gs = block_sum<NW>(gs, red);
-    mx = block_max<NW>(mx, red);
+    block_sum_max<NW>(gs, mx, red, red + NW);
     if (threadIdx.x == 0) {
         st.gnorm = sqrt(gs);
         st.maxdiag = mx;
@@ -233,7 +233,7 @@ __global__ __launch_bounds__(WSOLVE_THREADS) void k_window_solve_mm(
     int32_t W, const int32_t *__restrict__ win_pose_ptr, LMState *__restrict__ lm, const double *__restrict__ g,
     const double *__restrict__ H, const double *__restrict__ poses, double *__restrict__ dx,
     double *__restrict__ pose_q, int32_t *__restrict__ pose_info, double *__restrict__ poses_trial, double tol_g) {
-    __shared__ double red[WSOLVE_THREADS / 64];
+    __shared__ double red[2 * (WSOLVE_THREADS / 64)];
     __shared__ int s_done;
     const int w = blockIdx.x;
     if (w >= W) return;
@@ -256,7 +256,7 @@ __global__ __launch_bounds__(WSOLVE_THREADS) void k_window_stats_mm(int32_t W,
                                                                     LMState *__restrict__ lm,
                                                                     const double *__restrict__ g,
                                                                     const double *__restrict__ H, double tol_g) {
-    __shared__ double red[WSOLVE_THREADS / 64];
+    __shared__ double red[2 * (WSOLVE_THREADS / 64)];
     __shared__ int s_done;
     const int w = blockIdx.x;
     if (w >= W) return;
