@@ -92,6 +92,7 @@ __device__ __forceinline__ void decide_window(int w, const DecideArgs &da) {
             st.nu = 2.0;
             st.rejects = 0;
         } else {
+            st.need_eval = 0;
             st.mu *= st.nu;
             st.nu *= 2.0;
             st.rejects += 1;

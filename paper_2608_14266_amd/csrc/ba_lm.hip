@@ -3,11 +3,11 @@
 // sequentially on the CPU, Fig. 1; PredResReduction and Adjust of Alg. 2 are
 // declared there but not printed).
 //
-//  k_solve_mm   — Alg. 2 Solver: one thread per scan factors the 6x6
+//  k_window_solve_mm — Alg. 2 Solver: per-window gradient norm and damping
+//                 floor, then one thread per scan factors the 6x6
 //                 H_jj + mu D_jj by LDL^T, solves for dx_j, forms the trial
 //                 pose T_j (+) dx_j and its share of the predicted reduction.
-//  k_window_stats / k_decide — per-window gradient norm and damping floor;
-//                 gain ratio, damping update and commit of accepted poses.
+//  k_decide     — gain ratio, damping update and commit of accepted poses.
 #include <hip/hip_runtime.h>
 
 #include "ba.h"
@@ -187,82 +187,140 @@ __global__ void k_commit(int32_t n_poses, const int32_t *__restrict__ pose_windo
     if (!st.done && st.accepted) poses[i] = poses_trial[i];
 }
 
-// One 512-thread block per window: when the derivatives are fresh, the
-// window's gradient norm and largest Hessian diagonal (per thread over poses
-// p0 + t, p0 + t + 512, ..., then the wave totals in wave order) and the
-// convergence test; then every pose's damped 6x6 system is solved and the
-// trial pose T (+) dx formed.  Windows of more than SPLIT_SOLVE_POSES poses
-// take two launches instead, the same statistics in the same order
-// (k_window_stats_mm) and one thread per pose over the whole grid
-// (k_solve_mm_lm), so the results do not depend on which form runs.
-static constexpr int WSOLVE_THREADS = 512;
+// The increment solve of windows of up to SPLIT_SOLVE_POSES poses: blocks of
+// WSOLVE_BLOCK threads, blockIdx.y selecting a range of WSOLVE_BLOCK poses of
+// window blockIdx.x.  When the derivatives are fresh every block forms the
+// window's gradient norm and largest Hessian diagonal itself (all blocks
+// compute the same bits; the window's first block records them) and applies
+// the convergence test; then each block solves its poses' damped 6x6 systems
+// and forms the trial poses T (+) dx.  Wider windows take two launches, the
+// statistics in one block (k_window_stats_mm), then one thread per pose over
+// the whole grid (k_solve_mm_lm).  The statistics always follow one order,
+// that of a WSTAT_THREADS-thread pass: virtual thread v sums poses p0 + v,
+// p0 + v + WSTAT_THREADS, ... (g_k^2 by fma in k order, max over the
+// diagonal), and the virtual wave totals are added in wave order.  So the
+// results do not depend on which form runs.
+static constexpr int WSTAT_THREADS = 512;
+static constexpr int WSOLVE_BLOCK = 256;
 static constexpr int SPLIT_SOLVE_POSES = 1024;
 
-// Returns whether the window is finished (block-uniform).  `red` holds
-// 2 * WSOLVE_THREADS / 64 doubles.
-__device__ __forceinline__ bool window_fresh_stats(LMState &st, const double *__restrict__ g,
-                                                   const double *__restrict__ H, int p0, int p1, double tol_g,
-                                                   double *red, int *s_done) {
-    constexpr int NW = WSOLVE_THREADS / 64;
-    if (!st.need_eval) return false;
-    double gs = 0.0, mx = 0.0;
-    for (int j = p0 + threadIdx.x; j < p1; j += WSOLVE_THREADS) {
+// Window statistics in the WSTAT_THREADS order by a block of B threads, thread
+// t playing virtual threads t, t + B, ...; `red` holds 2 * WSTAT_THREADS / 64
+// doubles.  The block synchronises once; every thread returns the totals.
+template <int B>
+__device__ __forceinline__ void window_stats_ordered(const double *__restrict__ g, const double *__restrict__ H,
+                                                     int p0, int p1, double *red, double &gs_out,
+                                                     double &mx_out) {
+    static_assert(WSTAT_THREADS % B == 0 && B % 64 == 0, "block must tile the statistics pass");
+    constexpr int V = WSTAT_THREADS / B, NWB = B / 64, NW = WSTAT_THREADS / 64;
+    double gs[V], mx[V];
 #pragma unroll
-        for (int k = 0; k < 6; k++) {
-            const double gk = g[6LL * j + k];
-            gs = fma(gk, gk, gs);
-            mx = fmax(mx, H[36LL * j + 7 * k]);
+    for (int v = 0; v < V; v++) gs[v] = mx[v] = 0.0;
+    for (int base = p0 + threadIdx.x; base < p1; base += WSTAT_THREADS) {
+#pragma unroll
+        for (int v = 0; v < V; v++) {
+            const int j = base + v * B;
+            if (j < p1) {
+#pragma unroll
+                for (int k = 0; k < 6; k++) {
+                    const double gk = g[6LL * j + k];
+                    gs[v] = fma(gk, gk, gs[v]);
+                    mx[v] = fmax(mx[v], H[36LL * j + 7 * k]);
+                }
+            }
         }
     }
-    block_sum_max<NW>(gs, mx, red, red + NW);
-    if (threadIdx.x == 0) {
-        st.gnorm = sqrt(gs);
+    const int wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int v = 0; v < V; v++) {
+        gs[v] = wave_sum(gs[v]);
+        mx[v] = wave_max(mx[v]);
+    }
+    if ((threadIdx.x & 63) == 0) {
+#pragma unroll
+        for (int v = 0; v < V; v++) {
+            red[v * NWB + wave] = gs[v];
+            red[NW + v * NWB + wave] = mx[v];
+        }
+    }
+    __syncthreads();
+    double a = 0.0, m = red[NW];
+#pragma unroll
+    for (int i = 0; i < NW; i++) a += red[i];
+#pragma unroll
+    for (int i = 1; i < NW; i++) m = fmax(m, red[NW + i]);
+    gs_out = a;
+    mx_out = m;
+}
+
+// Records fresh statistics and the convergence test; returns whether the
+// window has converged.
+__device__ __forceinline__ bool record_stats(LMState &st, double gs, double mx, double tol_g, bool write) {
+    const double gn = sqrt(gs);
+    const bool conv = tol_g > 0.0 && gn < tol_g;
+    if (write) {
+        st.gnorm = gn;
         st.maxdiag = mx;
-        st.need_eval = 0;
-        if (tol_g > 0.0 && st.gnorm < tol_g) {
+        if (conv) {
             st.done = 1;
             st.accepted = 0;
         }
-        *s_done = st.done;
     }
-    __syncthreads();
-    return *s_done != 0;
+    return conv;
 }
 
-__global__ __launch_bounds__(WSOLVE_THREADS) void k_window_solve_mm(
+__global__ __launch_bounds__(WSOLVE_BLOCK) void k_window_solve_mm(
     int32_t W, const int32_t *__restrict__ win_pose_ptr, LMState *__restrict__ lm, const double *__restrict__ g,
     const double *__restrict__ H, const double *__restrict__ poses, double *__restrict__ dx,
     double *__restrict__ pose_q, int32_t *__restrict__ pose_info, double *__restrict__ poses_trial, double tol_g) {
-    __shared__ double red[2 * (WSOLVE_THREADS / 64)];
+    __shared__ double red[2 * (WSTAT_THREADS / 64)];
     __shared__ int s_done;
     const int w = blockIdx.x;
     if (w >= W) return;
     LMState &st = lm[w];
-    if (st.done) return;
+    // Only the window's first block writes st here, and only the statistics
+    // (read by the other blocks only when the derivatives are not fresh) and
+    // the converged flag (which every block derives itself as well).  The
+    // flag is read once per block, so the block decides as one.
+    // The state and index reads are issued together, before the barrier.
     const int p0 = win_pose_ptr[w], p1 = win_pose_ptr[w + 1];
-    if (window_fresh_stats(st, g, H, p0, p1, tol_g, red, &s_done)) return;
-    const double mu = st.mu, fl = 1e-12 * st.maxdiag;
-    for (int j = p0 + threadIdx.x; j < p1; j += WSOLVE_THREADS) {
-        double q;
-        const int info = solve_pose(H + 36LL * j, g + 6LL * j, mu, fl, dx + 6LL * j, q);
-        pose_q[j] = q;
-        pose_info[j] = info ? 6 * (j - p0) + info : 0;
-        pose_plus(poses + 12LL * j, dx + 6LL * j, poses_trial + 12LL * j);
+    const int fresh = st.need_eval;
+    const double mu = st.mu, md = fresh ? 0.0 : st.maxdiag;   // maxdiag is rewritten only when fresh
+    if (threadIdx.x == 0) s_done = st.done;
+    __syncthreads();
+    if (s_done) return;
+    const int j = p0 + (int)blockIdx.y * WSOLVE_BLOCK + (int)threadIdx.x;
+    if (blockIdx.y > 0 && p0 + (int)blockIdx.y * WSOLVE_BLOCK >= p1) return;   // block-uniform
+    double fl;
+    if (fresh) {
+        double gs, mx;
+        window_stats_ordered<WSOLVE_BLOCK>(g, H, p0, p1, red, gs, mx);
+        if (record_stats(st, gs, mx, tol_g, blockIdx.y == 0 && threadIdx.x == 0)) return;
+        fl = 1e-12 * mx;
+    } else {
+        fl = 1e-12 * md;
     }
+    if (j >= p1) return;
+    double q;
+    const int info = solve_pose(H + 36LL * j, g + 6LL * j, mu, fl, dx + 6LL * j, q);
+    pose_q[j] = q;
+    pose_info[j] = info ? 6 * (j - p0) + info : 0;
+    pose_plus(poses + 12LL * j, dx + 6LL * j, poses_trial + 12LL * j);
 }
 
-__global__ __launch_bounds__(WSOLVE_THREADS) void k_window_stats_mm(int32_t W,
-                                                                    const int32_t *__restrict__ win_pose_ptr,
-                                                                    LMState *__restrict__ lm,
-                                                                    const double *__restrict__ g,
-                                                                    const double *__restrict__ H, double tol_g) {
-    __shared__ double red[2 * (WSOLVE_THREADS / 64)];
-    __shared__ int s_done;
+__global__ __launch_bounds__(WSTAT_THREADS) void k_window_stats_mm(int32_t W,
+                                                                   const int32_t *__restrict__ win_pose_ptr,
+                                                                   LMState *__restrict__ lm,
+                                                                   const double *__restrict__ g,
+                                                                   const double *__restrict__ H, double tol_g) {
+    __shared__ double red[2 * (WSTAT_THREADS / 64)];
     const int w = blockIdx.x;
     if (w >= W) return;
     LMState &st = lm[w];
-    if (st.done) return;
-    (void)window_fresh_stats(st, g, H, win_pose_ptr[w], win_pose_ptr[w + 1], tol_g, red, &s_done);
+    if (st.done || !st.need_eval) return;
+    double gs, mx;
+    window_stats_ordered<WSTAT_THREADS>(g, H, win_pose_ptr[w], win_pose_ptr[w + 1], red, gs, mx);
+    (void)record_stats(st, gs, mx, tol_g, threadIdx.x == 0);
 }
 
 void launch_window_solve_mm(Problem *P, const double *poses, double tol_g, hipStream_t s) {
@@ -271,14 +329,15 @@ void launch_window_solve_mm(Problem *P, const double *poses, double tol_g, hipSt
         widest = std::max(widest, P->h_win_pose_ptr[w + 1] - P->h_win_pose_ptr[w]);
     ProfScope prof("k_window_solve_mm", s);
     if (widest > SPLIT_SOLVE_POSES) {
-        hipLaunchKernelGGL(k_window_stats_mm, dim3(P->n_windows), dim3(WSOLVE_THREADS), 0, s, P->n_windows,
+        hipLaunchKernelGGL(k_window_stats_mm, dim3(P->n_windows), dim3(WSTAT_THREADS), 0, s, P->n_windows,
                            P->win_pose_ptr, P->lm, P->g, P->H, tol_g);
         hipLaunchKernelGGL(k_solve_mm_lm, dim3((unsigned)((P->n_poses + 255) / 256)), dim3(256), 0, s, P->n_poses,
                            P->pose_window, P->win_pose_ptr, P->lm, P->H, P->g, poses, P->dx, P->pose_q, P->pose_info,
                            P->poses_trial);
         return;
     }
-    hipLaunchKernelGGL(k_window_solve_mm, dim3(P->n_windows), dim3(WSOLVE_THREADS), 0, s, P->n_windows,
+    const unsigned nb = (unsigned)std::max(1, (widest + WSOLVE_BLOCK - 1) / WSOLVE_BLOCK);
+    hipLaunchKernelGGL(k_window_solve_mm, dim3(P->n_windows, nb), dim3(WSOLVE_BLOCK), 0, s, P->n_windows,
                        P->win_pose_ptr, P->lm, P->g, P->H, poses, P->dx, P->pose_q, P->pose_info, P->poses_trial,
                        tol_g);
 }
