@@ -222,9 +222,10 @@ def batch_windows(seed: int = 4000, n_windows: int = 256, poses_range=(20, 400),
                   vox_range=(5000, 80000), m_range=(3, 8), pts: int = 50, sigma: float = 0.02,
                   rot_bound_deg: float = 0.5, trans_bound: float = 0.05, spacing: float = 2.0,
                   offset: float = 30.0, near: int = 16, workers: int | None = None,
-                  name: str | None = None) -> SumsScene:
+                  name: str | None = None, poses=None) -> SumsScene:
     """Batched workload: ``n_windows`` independent windows with poses per
-    window log-uniform in ``poses_range`` and clip(vox_per_pose * N_w,
+    window log-uniform in ``poses_range`` (or the counts ``poses``, one per
+    window, when given) and clip(vox_per_pose * N_w,
     vox_range) planes, each window with the tiny-scene law (3..8 observers,
     50 points, sigma = 2 cm, +-0.5 deg / +-5 cm) on a straight path with
     ``spacing`` metres between poses.  Scan and voxel ids are global; window w
@@ -233,6 +234,9 @@ def batch_windows(seed: int = 4000, n_windows: int = 256, poses_range=(20, 400),
     import os
     rng = _rng(seed)
     Nw = _loglog_counts(rng, poses_range[0], poses_range[1], n_windows)
+    if poses is not None:
+        assert len(poses) == n_windows and min(poses) >= 1
+        Nw = np.asarray(poses, dtype=Nw.dtype)
     Vw = np.clip(vox_per_pose * Nw, vox_range[0], vox_range[1])
     kw = dict(spacing=spacing, m_range=m_range, pts=pts, sigma=sigma, offset=offset, near=near)
     jobs = [(seed, w, int(Nw[w]), int(Vw[w]), kw) for w in range(n_windows)]

@@ -78,6 +78,39 @@ def test_batched_windows_equal_solo_bitwise(ba, dev, batch, prec, mode):
         s0 += sw.n_scans
 
 
+@pytest.mark.parametrize("sizes", [(8, 255, 256, 257, 513), (255, 257, 513, 1030)])
+def test_solve_forms_equal_bitwise(ba, dev, sizes):
+    """The MM increment solve covers a window with one block per 256 poses,
+    or, once a window of the problem exceeds 1024 poses, with one statistics
+    block per window plus one thread per pose over the whole grid.  A window's
+    LM run must be bitwise the same whichever form and block count its problem
+    takes: windows at and around the block boundaries, solved in a batch and
+    alone (the second batch runs the two-launch form, its windows alone the
+    block form)."""
+    import torch
+    sc = ss.batch_windows(seed=4200, n_windows=len(sizes), poses=list(sizes), vox_per_pose=8,
+                          vox_range=(300, 8000), workers=1)
+    say(f"solve forms: windows {sizes}, {sc.n_clusters} clusters")
+    pb = build_gpu_sums(ba, sc, dev)
+    P = torch.as_tensor(sc.poses_init, device=dev).contiguous()
+    reps, tr = ba.iterate(pb, P, ba.MODE_MM, max_iters=10)
+    pb.close()
+    Pb = P.cpu().numpy()
+    s0 = 0
+    for w in range(sc.n_windows):
+        sw = ss.window_of(sc, w)
+        ps = build_gpu_sums(ba, sw, dev)
+        Q = torch.as_tensor(sw.poses_init, device=dev).contiguous()
+        r1, t1 = ba.iterate(ps, Q, ba.MODE_MM, max_iters=10)
+        ps.close()
+        assert np.array_equal(Q.cpu().numpy(), Pb[s0:s0 + sw.n_scans]), f"window {w} poses"
+        assert np.array_equal(t1[:, 0, :], tr[:, w, :]), f"window {w} trace"
+        assert r1[0]["n_accepted"] >= 3, f"window {w} made no progress"
+        for k in ("iters", "n_accepted", "cost_final", "gnorm_final", "mu_final"):
+            assert r1[0][k] == reps[w][k], (w, k)
+        s0 += sw.n_scans
+
+
 def test_batched_eval_matches_oracle_per_window(ba, dev, orc, batch):
     import torch
     say("batched eval vs oracle")
