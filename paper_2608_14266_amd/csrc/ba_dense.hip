@@ -411,7 +411,9 @@ __device__ __forceinline__ void wave_sync() {
 // wavefronts working one chunk of POTF2_CHUNK steps apart.
 //  - wave 0, right-looking factorization: lane i holds row i of the tile in
 //    registers; step j scales column j, publishes it as row j of `lt` in LDS
-//    (lt[j][r] = L_rj) and updates the columns to its right from there.  The
+//    (lt[j][r] = L_rj) and updates the columns to its right from there (the
+//    row is read into registers in one burst before the FMAs, so the LDS
+//    latency is paid once per step rather than once per few columns).  The
 //    next pivot is formed from the lane's own entries and broadcast as a
 //    scalar, so it does not wait for the LDS round trip.  Entries above the
 //    diagonal (c > i) are never read, so updates run on all lanes unmasked.
@@ -475,16 +477,22 @@ __global__ __launch_bounds__(128) void k_potf2(const DenseDesc *__restrict__ des
                 if (i == 0) rdiag[j] = rj;
                 if (j + 1 < TB) {
                     wave_sync();
+                    double l[TB];
 #pragma unroll
-                    for (int c = j + 1; c < TB; c++) a[c] = fma(-a[j], lt[j * LTS + c], a[c]);
+                    for (int c = j + 1; c < TB; c++) l[c] = lt[j * LTS + c];
+#pragma unroll
+                    for (int c = j + 1; c < TB; c++) a[c] = fma(-a[j], l[c], a[c]);
                 }
             }
         }
         if (w == 1 && j >= POTF2_CHUNK) {
             const int r = j - POTF2_CHUNK;
             a[r] *= rdiag[r];
+            double l[TB];
 #pragma unroll
-            for (int q = r + 1; q < TB; q++) a[q] = fma(-lt[r * LTS + q], a[r], a[q]);
+            for (int q = r + 1; q < TB; q++) l[q] = lt[r * LTS + q];
+#pragma unroll
+            for (int q = r + 1; q < TB; q++) a[q] = fma(-l[q], a[r], a[q]);
         }
         if (j % POTF2_CHUNK == POTF2_CHUNK - 1) {
             if (w == 0 && i == 0 && fail) sfail = fail;
