@@ -398,6 +398,15 @@ __device__ __forceinline__ double bcast(double v, int src) {
     return __hiloint2double(hi, lo);
 }
 
+// 1/sqrt(p): the hardware estimate refined by two Newton steps
+// r <- r (3 - p r^2) / 2 (about 1 ulp for a positive normal p).
+__device__ __forceinline__ double rsq_refined(double p) {
+    double r = __builtin_amdgcn_rsq(p);
+    r = r * fma(-0.5 * p * r, r, 1.5);
+    r = r * fma(-0.5 * p * r, r, 1.5);
+    return r;
+}
+
 // Orders this lane's LDS writes before the other lanes' later reads within
 // the wavefront (LDS operations of one wavefront complete in issue order).
 __device__ __forceinline__ void wave_sync() {
@@ -456,6 +465,7 @@ __global__ __launch_bounds__(128) void k_potf2(const DenseDesc *__restrict__ des
     if (threadIdx.x == 0) sfail = 0;
     __syncthreads();
     double p = bcast(a[0], 0);
+    double rn = rsq_refined(p);   // 1/sqrt of the next pivot, formed a step ahead
     int fail = 0, stop = 0;
 #pragma unroll
     for (int j = 0; j < TB + POTF2_CHUNK; j++) {
@@ -464,9 +474,7 @@ __global__ __launch_bounds__(128) void k_potf2(const DenseDesc *__restrict__ des
             if (!(p >= 2.2250738585072014e-308)) {
                 fail = (int)(k0 + j + 1);
             } else {
-                double rj = __builtin_amdgcn_rsq(p);
-                rj = rj * fma(-0.5 * p * rj, rj, 1.5);
-                rj = rj * fma(-0.5 * p * rj, rj, 1.5);
+                const double rj = rn;
                 const double dj = p * rj;
                 a[j] = (i == j) ? dj : a[j] * rj;
                 if (j + 1 < TB) p = bcast(fma(-a[j], a[j], a[j + 1]), j + 1);
@@ -482,6 +490,9 @@ __global__ __launch_bounds__(128) void k_potf2(const DenseDesc *__restrict__ des
                     for (int c = j + 1; c < TB; c++) l[c] = lt[j * LTS + c];
 #pragma unroll
                     for (int c = j + 1; c < TB; c++) a[c] = fma(-a[j], l[c], a[c]);
+                    // the next step's reciprocal square root, free to interleave
+                    // with this step's updates
+                    rn = rsq_refined(p);
                 }
             }
         }
