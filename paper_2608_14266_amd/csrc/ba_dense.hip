@@ -623,7 +623,9 @@ __global__ __launch_bounds__(256) void k_syrk(const DenseDesc *__restrict__ desc
 }
 
 // Backward substitution, block row `step` (descending): x_k = L_kk^-T y_k and
-// y_J -= L_kJ^T x_k for the column tiles J < k (one tile per workgroup).
+// y_J -= L_kJ^T x_k for the column tiles J < k (one tile per workgroup).  The
+// factorization runs it for block row 0 when the row count is odd; the other
+// rows go two per launch (k_backsub2).
 // Four threads share each 64-term dot product.  The L_kJ tile is loaded
 // before x_k is formed, so the two global reads overlap.
 __global__ __launch_bounds__(256) void k_backsub(const DenseDesc *__restrict__ desc,
@@ -672,6 +674,98 @@ __global__ __launch_bounds__(256) void k_backsub(const DenseDesc *__restrict__ d
         s += __shfl_xor(s, 1, 64);
         s += __shfl_xor(s, 2, 64);
         if (part == 0) work[d.v_off + TB * J + o] -= s;
+    }
+}
+
+// Two steps of the backward substitution in one launch, block rows `step`
+// (k) and step - 1 (h), with the arithmetic of two k_backsub launches in the
+// same order.  Every workgroup forms x_k, then y_h - L_kh^T x_k and x_h itself
+// (the L_kh tile and both inverse factors are read by every workgroup, all
+// loads issued before the first product), and workgroup J < h applies
+// y_J <- (y_J - L_kJ^T x_k) - L_hJ^T x_h.  A matrix smaller than block row k
+// takes only the step h part.
+__global__ __launch_bounds__(256) void k_backsub2(const DenseDesc *__restrict__ desc,
+                                                  const DenseParam *__restrict__ prm, double *__restrict__ work,
+                                                  double *__restrict__ x, const int64_t *__restrict__ x_off,
+                                                  int step) {
+    __shared__ double xk[TB], yk[TB], xh[TB], yh[TB];
+    const int m = blockIdx.y;
+    const DenseDesc d = desc[m];
+    if (!prm[m].active || prm[m].info) return;
+    const int64_t k0 = (int64_t)TB * step, h0 = k0 - TB;
+    if (h0 >= d.n) return;
+    const int64_t J = blockIdx.x;
+    const int hstep = step - 1;
+    if (J > 0 && J >= hstep) return;
+    const bool has_k = k0 < d.n;
+    const int nbk = has_k ? (int)std::min<int64_t>(TB, d.n - k0) : 0;   // block row h is full when k exists
+    const int nbh = (int)std::min<int64_t>(TB, d.n - h0);
+    const int t = threadIdx.x, o = t >> 2, part = t & 3;
+    const bool upd = J < hstep;
+    const double *A = work + d.a_off;
+    const double *linv_k = work + d.linv_off + (int64_t)step * TB * TB;
+    const double *linv_h = work + d.linv_off + (int64_t)hstep * TB * TB;
+    double lkj[16], lhj[16], lkh[16], lik[16], lih[16];
+#pragma unroll
+    for (int q = 0; q < 16; q++) {
+        const int r = part + 4 * q;
+        lkj[q] = (upd && r < nbk) ? A[(k0 + r) * d.n + TB * J + o] : 0.0;
+        lhj[q] = (upd && r < nbh) ? A[(h0 + r) * d.n + TB * J + o] : 0.0;
+        lkh[q] = (r < nbk) ? A[(k0 + r) * d.n + h0 + o] : 0.0;
+        lik[q] = has_k ? linv_k[r * TB + o] : 0.0;
+        lih[q] = linv_h[r * TB + o];
+    }
+    if (t < TB) {
+        yk[t] = (t < nbk) ? work[d.v_off + k0 + t] : 0.0;
+        yh[t] = (t < nbh) ? work[d.v_off + h0 + t] : 0.0;
+    }
+    __syncthreads();
+    {   // x_k[o] = sum_c Linv_k[c][o] y_k[c]
+        double s = 0.0;
+#pragma unroll
+        for (int q = 0; q < 16; q++) s += lik[q] * yk[part + 4 * q];
+        s += __shfl_xor(s, 1, 64);
+        s += __shfl_xor(s, 2, 64);
+        if (part == 0) xk[o] = s;
+    }
+    __syncthreads();
+    if (J == 0 && t < nbk) x[x_off[m] + k0 + t] = xk[t];
+    {   // y_h[o] -= sum_r L[k0 + r][h0 + o] x_k[r]
+        double s = 0.0;
+#pragma unroll
+        for (int q = 0; q < 16; q++) s += lkh[q] * xk[part + 4 * q];
+        s += __shfl_xor(s, 1, 64);
+        s += __shfl_xor(s, 2, 64);
+        if (part == 0 && has_k) yh[o] -= s;
+    }
+    __syncthreads();
+    {   // x_h[o] = sum_c Linv_h[c][o] y_h[c]
+        double s = 0.0;
+#pragma unroll
+        for (int q = 0; q < 16; q++) s += lih[q] * yh[part + 4 * q];
+        s += __shfl_xor(s, 1, 64);
+        s += __shfl_xor(s, 2, 64);
+        if (part == 0) xh[o] = s;
+    }
+    __syncthreads();
+    if (J == 0 && t < nbh) x[x_off[m] + h0 + t] = xh[t];
+    if (!upd) return;
+    {   // y_J[o] <- (y_J[o] - sum_r L[k0 + r][64 J + o] x_k[r]) - sum_r L[h0 + r][64 J + o] x_h[r]
+        double sk = 0.0, sh = 0.0;
+#pragma unroll
+        for (int q = 0; q < 16; q++) sk += lkj[q] * xk[part + 4 * q];
+#pragma unroll
+        for (int q = 0; q < 16; q++) sh += lhj[q] * xh[part + 4 * q];
+        sk += __shfl_xor(sk, 1, 64);
+        sk += __shfl_xor(sk, 2, 64);
+        sh += __shfl_xor(sh, 1, 64);
+        sh += __shfl_xor(sh, 2, 64);
+        if (part == 0) {
+            double *yJ = work + d.v_off + TB * J + o;
+            double v = *yJ;
+            if (has_k) v -= sk;
+            *yJ = v - sh;
+        }
     }
 }
 
@@ -1083,9 +1177,14 @@ static void launch_factor_solve(DenseState *D, int32_t nmat, int32_t max_n, cons
                                D->prm, D->work, p, TB * (pe - p), pe, nsteps);
         }
     }
-    for (int st = nsteps - 1; st >= 0; st--)
-        hipLaunchKernelGGL(k_backsub, dim3((unsigned)std::max(st, 1), nmat), dim3(256), 0, s, D->desc, D->prm,
-                           D->work, x, x_off, st);
+    // backward substitution two block rows per launch, the first row alone
+    // when the count is odd
+    int st = nsteps - 1;
+    for (; st >= 1; st -= 2)
+        hipLaunchKernelGGL(k_backsub2, dim3((unsigned)std::max(st - 1, 1), nmat), dim3(256), 0, s, D->desc,
+                           D->prm, D->work, x, x_off, st);
+    if (st == 0)
+        hipLaunchKernelGGL(k_backsub, dim3(1, nmat), dim3(256), 0, s, D->desc, D->prm, D->work, x, x_off, 0);
 }
 
 void launch_dense_gnorm(Problem *P, hipStream_t s) {
