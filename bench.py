@@ -108,7 +108,7 @@ def main():
     ap.add_argument("--sweep-points", type=str, default="0.25,0.5,1,2",
                     help="scaling: window-scene scale factors of the preprocessing sweep (1 = 117M points)")
     ap.add_argument("--cpu-iters", type=int, default=None,
-                    help="oracle LM iterations timed for cpu_baseline (default: 20 mm, 1 coupled)")
+                    help="oracle LM iterations timed for cpu_baseline (default: 50 mm, about 12 s on one core; 1 coupled)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-precision-leg", action="store_true",
                     help="skip the FP32 precision-form run on the same workload")
@@ -118,7 +118,7 @@ def main():
                          "(a plain copy kernel of known size, to scale hardware byte counters)")
     args = ap.parse_args()
     if args.cpu_iters is None:
-        args.cpu_iters = 20 if args.mode == "mm" else 1
+        args.cpu_iters = 50 if args.mode == "mm" else 1
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(see the sharding design notes); run with --gpus 1", file=sys.stderr)
