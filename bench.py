@@ -120,8 +120,8 @@ def main():
     if args.cpu_iters is None:
         args.cpu_iters = 50 if args.mode == "mm" else 1
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(see the sharding design notes); run with --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU only: the library has no multi-GPU path; run with --gpus 1",
+              file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
