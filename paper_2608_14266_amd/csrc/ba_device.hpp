@@ -362,6 +362,123 @@ __device__ __forceinline__ void eig_sym3(const double *A, double *lam, double *u
     u[0] = vs[0]; u[1] = vs[1]; u[2] = vs[2];
 }
 
+// Adjugate (cofactor matrix) of a symmetric 3x3 (6 unique), same layout.  For
+// B = A - x I with eigenpairs (l_k - x, u_k), adj(B) = sum_k prod_{l != k}
+// (l_l - x) u_k u_k^T: as x approaches the smallest eigenvalue its columns all
+// turn towards u_0.
+__device__ __forceinline__ void adj_sym3(double a00, double a01, double a02, double a11, double a12, double a22,
+                                         double *c) {
+    c[0] = fma(a11, a22, -a12 * a12);
+    c[1] = fma(a02, a12, -a01 * a22);
+    c[2] = fma(a01, a12, -a02 * a11);
+    c[3] = fma(a00, a22, -a02 * a02);
+    c[4] = fma(a01, a02, -a00 * a12);
+    c[5] = fma(a00, a11, -a01 * a01);
+}
+
+// 1/sqrt(x) for x > 0: the hardware estimate (about half the FP64 mantissa)
+// and two Newton steps, which bring it to a few ulp (used to normalise
+// vectors, whose unit length the convergence test below relies on).
+__device__ __forceinline__ double rsqrt_nr(double x) {
+    double y = __builtin_amdgcn_rsq(x);
+    y = y * fma(-0.5 * x * y, y, 1.5);
+    return y * fma(-0.5 * x * y, y, 1.5);
+}
+
+// Smallest eigenpair of a symmetric positive semi-definite 3x3 (6 unique).
+//  1. Newton's method on the characteristic polynomial p(x) = det(A - x I),
+//     started at x = 0: for a cubic with real roots that starts below the
+//     smallest root, the iterates rise monotonically towards it (p is convex
+//     there), so the shift approaches lambda_0 from below whatever the
+//     spacing of the other two.
+//  2. u = the largest column of adj(A - x I), normalised.
+//  3. Rayleigh quotient iteration (Parlett, The Symmetric Eigenvalue
+//     Problem, Ch. 4) with the inverse step taken as adj(A - s I) u,
+//     s = u^T A u, until two iterates agree to rounding.
+//  4. lambda_0 = u^T A u; its absolute error is of order eps ||A||, as for
+//     any backward-stable method.
+// Returns false (and leaves lam0/u unspecified) when the matrix has rank
+// below two (lambda_0 = lambda_1 = 0) or the iteration did not end at the
+// smallest eigenvalue; the caller then takes the Jacobi path.
+__device__ __forceinline__ bool eig_min_sym3(const double *A, double &lam0, double *u) {
+    const double a00 = A[0], a01 = A[1], a02 = A[2], a11 = A[3], a12 = A[4], a22 = A[5];
+    double c[6];
+    adj_sym3(a00, a01, a02, a11, a12, a22, c);
+    const double c2 = a00 + a11 + a22;        // trace
+    const double c1 = c[0] + c[3] + c[5];     // sum of the principal 2x2 minors
+    const double c0 = fma(a00, c[0], fma(a01, c[1], a02 * c[2]));   // determinant
+    if (!(c1 > 1e-28 * c2 * c2)) return false;
+    double x = 0.0;
+    for (int it = 0; it < 40; it++) {
+        const double p = fma(-x, fma(-x, c2 - x, c1), c0);    // c0 - x (c1 - x (c2 - x))
+        const double dp = fma(x, fma(-3.0, x, 2.0 * c2), -c1);
+        const double dx = -p / dp;
+        x += dx;
+        if (!(fabs(dx) > 1e-4 * x)) break;
+    }
+    double b[6];
+    adj_sym3(a00 - x, a01, a02, a11 - x, a12, a22 - x, b);
+    {
+        const double n0 = fma(b[0], b[0], fma(b[1], b[1], b[2] * b[2]));
+        const double n1 = fma(b[1], b[1], fma(b[3], b[3], b[4] * b[4]));
+        const double n2 = fma(b[2], b[2], fma(b[4], b[4], b[5] * b[5]));
+        double v0 = b[0], v1 = b[1], v2 = b[2], nn = n0;
+        if (n1 > nn) { v0 = b[1]; v1 = b[3]; v2 = b[4]; nn = n1; }
+        if (n2 > nn) { v0 = b[2]; v1 = b[4]; v2 = b[5]; nn = n2; }
+        if (!(nn > 0.0)) return false;
+        const double r = rsqrt_nr(nn);
+        u[0] = v0 * r; u[1] = v1 * r; u[2] = v2 * r;
+    }
+    bool conv = false;
+    for (int it = 0; it < 6; it++) {
+        const double au0 = fma(a00, u[0], fma(a01, u[1], a02 * u[2]));
+        const double au1 = fma(a01, u[0], fma(a11, u[1], a12 * u[2]));
+        const double au2 = fma(a02, u[0], fma(a12, u[1], a22 * u[2]));
+        const double s = fma(u[0], au0, fma(u[1], au1, u[2] * au2));
+        adj_sym3(a00 - s, a01, a02, a11 - s, a12, a22 - s, b);
+        const double x0 = fma(b[0], u[0], fma(b[1], u[1], b[2] * u[2]));
+        const double x1 = fma(b[1], u[0], fma(b[3], u[1], b[4] * u[2]));
+        const double x2 = fma(b[2], u[0], fma(b[4], u[1], b[5] * u[2]));
+        const double nn = fma(x0, x0, fma(x1, x1, x2 * x2));
+        if (!(nn > 0.0)) {   // u is an exact eigenvector of the rounded matrix
+            conv = true;
+            break;
+        }
+        const double r = rsqrt_nr(nn);
+        const double y0 = x0 * r, y1 = x1 * r, y2 = x2 * r;
+        const double cs = fabs(fma(y0, u[0], fma(y1, u[1], y2 * u[2])));
+        u[0] = y0; u[1] = y1; u[2] = y2;
+        if (cs >= 1.0 - 4.0 * 2.220446049250313e-16) {
+            conv = true;
+            break;
+        }
+    }
+    const double au0 = fma(a00, u[0], fma(a01, u[1], a02 * u[2]));
+    const double au1 = fma(a01, u[0], fma(a11, u[1], a12 * u[2]));
+    const double au2 = fma(a02, u[0], fma(a12, u[1], a22 * u[2]));
+    const double l = fma(u[0], au0, fma(u[1], au1, u[2] * au2));
+    // the other two eigenvalues are the roots of y^2 - s2 y + pr with
+    // s2 = trace - l and pr = c1 - l s2; l is the smallest iff it lies at or
+    // below both (up to rounding of the coefficients)
+    const double s2 = c2 - l;
+    const double pr = fma(-l, s2, c1);
+    const double f = fma(l, l - s2, pr);
+    const double tol = 1e-12 * c2;
+    if (!conv || f < -tol * c2 || 2.0 * l > s2 + tol) return false;
+    lam0 = l;
+    return true;
+}
+
+// Smallest eigenpair by eig_min_sym3, with the Jacobi iteration for the
+// matrices it declines (rank below two, or a pair it cannot separate).
+__device__ __forceinline__ void eig_min_sym3_safe(const double *A, double &lam0, double *u) {
+    if (!eig_min_sym3(A, lam0, u)) {
+        double lam[3];
+        eig_sym3(A, lam, u);
+        lam0 = lam[0];
+    }
+}
+
 // All three eigenpairs of the same Jacobi iteration: lam ascending and the
 // matching unit eigenvectors U[3 * k .. 3 * k + 2] (k = 0, 1, 2); lam and
 // U[0..2] equal eig_sym3's outputs.

@@ -5,8 +5,9 @@
 //            block's four waves).  Each lane transforms its voxel's clusters by
 //            the current poses (Eq. 2), forms the voxel covariance A_i (Eq. 1)
 //            by the parallel-axis theorem about a per-voxel reference point,
-//            takes the smallest eigenpair with register-resident Jacobi
-//            rotations, and stores (u, mbar, 2/N_i, lambda_min) for the
+//            takes the smallest eigenpair in registers (Newton shift on the
+//            characteristic polynomial, then Rayleigh quotient iteration on
+//            the adjugate), and stores (u, mbar, 2/N_i, lambda_min) for the
 //            derivative pass.  The residual of a group is reduced in-wave.
 //  k_pose  — derivative pass, one wavefront per pose chunk (clusters of one
 //            scan, pose-major copy).  Each lane evaluates the per-cluster
@@ -194,13 +195,13 @@ __device__ __forceinline__ double vox_finish(const VoxSums &a, double *__restric
     A[3] = (a.M[3] - a.s1 * b1) * inv;
     A[4] = (a.M[4] - a.s1 * b2) * inv;
     A[5] = (a.M[5] - a.s2 * b2) * inv;
-    double lam[3], u[3];
-    eig_sym3(A, lam, u);
+    double lam0, u[3];
+    eig_min_sym3_safe(A, lam0, u);
     st[0] = u[0]; st[1] = u[1]; st[2] = u[2];
     st[3] = a.r[0] + b0; st[4] = a.r[1] + b1; st[5] = a.r[2] + b2;
     st[6] = 2.0 * inv;
-    st[7] = lam[0];
-    return lam[0];
+    st[7] = lam0;
+    return lam0;
 }
 
 template <class Src, int SPLIT>
