@@ -57,6 +57,8 @@ def _load():
     lib.orc_majorizer.argtypes = [cint, i64, P, P, P, P, P, i32, i32, P, P]
     lib.orc_eval.restype = cint
     lib.orc_eval.argtypes = [cint, i64, P, P, P, P, P, i32, i32, P, P, P, P, P]
+    lib.orc_eval_abs.restype = cint
+    lib.orc_eval_abs.argtypes = [cint, i64, P, P, P, P, P, i32, i32, P, P, P, P, P, P]
     lib.orc_solve.restype = cint
     lib.orc_solve.argtypes = [cint, i32, P, P, dbl, P]
     lib.orc_so3_exp.restype = None
@@ -185,6 +187,25 @@ def evaluate(mode: int, cl: Clusters, poses):
     if rc:
         raise ValueError(f"oracle: invalid clusters ({rc})")
     return c.value, g, H, nd.value
+
+
+def evaluate_abs(mode: int, cl: Clusters, poses):
+    """evaluate() plus the per-entry sums of absolute contributions.  Returns
+    (cost, grad, hess, grad_abs, hess_abs); the last two have the layouts of
+    grad and hess and give the rounding scale of every pose block."""
+    lib = _load()
+    poses = _c(poses, np.float64)
+    Np = cl.n_scans
+    g = np.empty(6 * Np)
+    ga = np.empty(6 * Np)
+    shape = (Np, 6, 6) if mode == MM else (6 * Np, 6 * Np)
+    H = np.empty(shape)
+    Ha = np.empty(shape)
+    c = ct.c_double(0.0)
+    rc = lib.orc_eval_abs(mode, *cl.args(), _p(poses), ct.byref(c), _p(g), _p(H), _p(ga), _p(Ha))
+    if rc:
+        raise ValueError(f"oracle: invalid clusters ({rc})")
+    return c.value, g, H, ga, Ha
 
 
 def solve(mode: int, n_poses: int, hess, grad, mu: float):

@@ -471,18 +471,27 @@ static void add_block(double *H, int64_t ld, int64_t r0, int64_t c0, const doubl
  * Returns 0, or a negative error.  n_degenerate (may be NULL) counts voxels
  * whose EXACT term was dropped.
  */
-int orc_eval(int mode, int64_t C, const int32_t *vox, const int32_t *scan, const int64_t *n, const double *mu,
-             const double *S, int32_t V, int32_t Np, const double *poses, double *cost_out, double *grad,
-             double *hess, int64_t *n_degenerate) {
+/*
+ * Evaluation at `poses` (Alg. 2 CalRes and CalJH; cost Eq. 1, gradient and
+ * Hessian of the Eq. 3 surrogate or of its refinements, see the file header).
+ * When gabs / habs are given (same layouts as grad / hess) they receive the
+ * sums of the absolute values of every per-cluster (and, for the dense modes,
+ * per-pair) contribution: the magnitude any summation order's rounding error
+ * is proportional to, used by the tests as the scale of each pose block.
+ */
+static int eval_impl(int mode, int64_t C, const int32_t *vox, const int32_t *scan, const int64_t *n,
+                     const double *mu, const double *S, int32_t V, int32_t Np, const double *poses,
+                     double *cost_out, double *grad, double *hess, int64_t *n_degenerate, double *gabs,
+                     double *habs) {
     orc_problem p;
     int rc = problem_init(&p, C, vox, scan, n, mu, S, V, Np);
     if (rc) { problem_free(&p); return rc; }
     int64_t D = 6 * (int64_t)Np;
     memset(grad, 0, sizeof(double) * (size_t)D);
-    if (mode == ORC_MM)
-        memset(hess, 0, sizeof(double) * 36 * (size_t)Np);
-    else
-        memset(hess, 0, sizeof(double) * (size_t)(D * D));
+    const size_t hsize = (mode == ORC_MM) ? 36 * (size_t)Np : (size_t)(D * D);
+    memset(hess, 0, sizeof(double) * hsize);
+    if (gabs) memset(gabs, 0, sizeof(double) * (size_t)D);
+    if (habs) memset(habs, 0, sizeof(double) * hsize);
     double cost = 0.0;
     int64_t ndeg = 0;
     int maxm = 0;
@@ -533,6 +542,11 @@ int orc_eval(int mode, int64_t C, const int32_t *vox, const int32_t *scan, const
                 grad[6 * j + i] += w0 * wxu[i];
                 grad[6 * j + 3 + i] += w0 * nc * e * u[i];
             }
+            if (gabs)
+                for (int i = 0; i < 3; i++) {
+                    gabs[6 * j + i] += fabs(w0 * wxu[i]);
+                    gabs[6 * j + 3 + i] += fabs(w0 * nc * e * u[i]);
+                }
             /* H_ij */
             double M[3][3], t1[3][3], t2[3][3];
             for (int r = 0; r < 3; r++)
@@ -552,6 +566,15 @@ int orc_eval(int mode, int64_t C, const int32_t *vox, const int32_t *scan, const
                 add_block(hess + 36 * (int64_t)j, 6, 0, 0, blk, w0);
             else
                 add_block(hess, D, 6 * (int64_t)j, 6 * (int64_t)j, blk, w0);
+            if (habs) {
+                double ab[6][6];
+                for (int r = 0; r < 6; r++)
+                    for (int s2 = 0; s2 < 6; s2++) ab[r][s2] = fabs(w0 * blk[r][s2]);
+                if (mode == ORC_MM)
+                    add_block(habs + 36 * (int64_t)j, 6, 0, 0, ab, 1.0);
+                else
+                    add_block(habs, D, 6 * (int64_t)j, 6 * (int64_t)j, ab, 1.0);
+            }
             if (mode != ORC_MM) {
                 double *h = hv + 6 * (k - k0);
                 for (int i = 0; i < 3; i++) { h[i] = nc / vs.Ni * a[i]; h[3 + i] = nc / vs.Ni * u[i]; }
@@ -595,6 +618,7 @@ int orc_eval(int mode, int64_t C, const int32_t *vox, const int32_t *scan, const
                                 }
                             }
                             hess[(6 * ja + r) * D + 6 * jb + s] += val;
+                            if (habs) habs[(6 * ja + r) * D + 6 * jb + s] += fabs(val);
                         }
                 }
         }
@@ -604,6 +628,18 @@ int orc_eval(int mode, int64_t C, const int32_t *vox, const int32_t *scan, const
     *cost_out = cost;
     if (n_degenerate) *n_degenerate = ndeg;
     return 0;
+}
+
+int orc_eval(int mode, int64_t C, const int32_t *vox, const int32_t *scan, const int64_t *n, const double *mu,
+             const double *S, int32_t V, int32_t Np, const double *poses, double *cost_out, double *grad,
+             double *hess, int64_t *n_degenerate) {
+    return eval_impl(mode, C, vox, scan, n, mu, S, V, Np, poses, cost_out, grad, hess, n_degenerate, NULL, NULL);
+}
+
+int orc_eval_abs(int mode, int64_t C, const int32_t *vox, const int32_t *scan, const int64_t *n, const double *mu,
+                 const double *S, int32_t V, int32_t Np, const double *poses, double *cost_out, double *grad,
+                 double *hess, double *gabs, double *habs) {
+    return eval_impl(mode, C, vox, scan, n, mu, S, V, Np, poses, cost_out, grad, hess, NULL, gabs, habs);
 }
 
 /* ------------------------------------------------------------------ */

@@ -531,3 +531,21 @@ def test_hybrid_exact_newton_converges_superlinearly(orc):
     acc = rh[first:, 4] > 0
     k = np.flatnonzero(acc)[:2]
     assert g[k[0] + 1] <= 0.1 * g[k[0]]
+
+
+def test_eval_abs_scales_bound_and_match(orc):
+    """The per-entry absolute scales of evaluate_abs leave the outputs of
+    evaluate unchanged, bound them elementwise, and equal them where each
+    entry has a single contribution (one voxel, each pose one cluster)."""
+    import scenes
+    sc = scenes.tiny_config(seed=1000)
+    cl = orc.scene_clusters(sc)
+    for mode in (orc.MM, orc.COUPLED):
+        c, g, H, _ = orc.evaluate(mode, cl, sc.poses_init)
+        c2, g2, H2, ga, Ha = orc.evaluate_abs(mode, cl, sc.poses_init)
+        assert c == c2 and np.array_equal(g, g2) and np.array_equal(H, H2)
+        assert np.all(ga >= np.abs(g)) and np.all(Ha >= np.abs(H))
+    one = scenes.small_scene(seed=81, n_scans=3, n_planes=1, m_range=(3, 3), pts_per_obs=(20, 20))
+    cl1 = orc.scene_clusters(one)
+    _, g, H, ga, Ha = orc.evaluate_abs(orc.MM, cl1, one.poses_init)
+    assert np.array_equal(ga, np.abs(g)) and np.array_equal(Ha, np.abs(H))
