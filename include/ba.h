@@ -131,9 +131,12 @@ typedef struct ba_lm_report {  /* one per window */
     double cost_initial;
     double cost_final;
     double gnorm_final;   /* ||g|| at the last evaluated point */
-    double mu_final;
+    double mu_final;      /* damping mu after the last decision */
     int32_t stalled;      /* stopped after max_rejects rejections in a row */
     int32_t reserved;
+    double nu_final;      /* damping growth nu after the last decision: a later call with
+                           * mu0 = mu_final and nu0 = nu_final continues the run exactly
+                           * (the derivatives are re-evaluated at the same poses) */
 } ba_lm_report;
 
 /* Launch choices of the two evaluation passes.  They change the order in

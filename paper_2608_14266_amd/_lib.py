@@ -76,7 +76,7 @@ class _LMReport(ct.Structure):
     _fields_ = [("iters", ct.c_int32), ("n_accepted", ct.c_int32), ("converged", ct.c_int32),
                 ("last_info", ct.c_int32), ("cost_initial", ct.c_double), ("cost_final", ct.c_double),
                 ("gnorm_final", ct.c_double), ("mu_final", ct.c_double), ("stalled", ct.c_int32),
-                ("reserved", ct.c_int32)]
+                ("reserved", ct.c_int32), ("nu_final", ct.c_double)]
 
 
 class _ReqStatus(ct.Structure):

@@ -49,7 +49,7 @@ ba_status dense_assemble_exact(Problem *P, const double *poses, double *hess_out
 ba_status dense_solve(int64_t n, const double *A, const double *g, double mu, double *dx, int32_t *info, void *ws,
                       size_t ws_bytes, hipStream_t s);
 ba_status dense_lm_step(Problem *P, const double *poses, double tol_g, hipStream_t s);
-void launch_dense_gnorm(Problem *P, hipStream_t s);
+void launch_dense_gnorm(Problem *P, hipStream_t s, double tol_g = 0.0);
 void dense_release(Problem *P);
 ba_status dense_prepare(Problem *P);
 
@@ -157,7 +157,14 @@ static ba_status enqueue_lm(Problem *P, double *poses, const ba_lm_options *opt,
     // derivatives at the final poses (windows whose last step was accepted),
     // so that the reported gradient norm belongs to the returned poses
     launch_pose_derivs(P, poses, true, P->g, P->H, s, opt->mode == BA_MODE_COUPLED);
-    launch_window_stats(P, opt->tol_g, s);
+    // the reported norm and convergence flag in the order the mode's in-loop
+    // test forms them, so the two agree bitwise
+    if (opt->mode == BA_MODE_MM) {
+        launch_window_stats(P, opt->tol_g, s);
+    } else {
+        BA_TRY(dense_prepare(P));
+        launch_dense_gnorm(P, s, opt->tol_g);
+    }
     BA_HIP(hipGetLastError());
     return BA_OK;
 }
@@ -497,6 +504,7 @@ ba_status ba_iterate(ba_problem *p, double *poses_inout, const ba_lm_options *op
             rep[w].cost_final = st[w].cost;
             rep[w].gnorm_final = st[w].gnorm;
             rep[w].mu_final = st[w].mu;
+            rep[w].nu_final = st[w].nu;
             rep[w].cost_initial = st[w].cost0;
         }
     }

@@ -772,10 +772,12 @@ __global__ __launch_bounds__(256) void k_backsub2(const DenseDesc *__restrict__ 
 // ---------------------------------------------------------------- LM glue
 // Per-window damping parameters from the LM state and the dense diagonal.
 // Gradient norm of every window with fresh derivatives, formed exactly as
-// k_dense_params forms it (same partial sums and tree), for a decision that
-// must be taken before the dense matrix is assembled.
+// k_dense_params forms it (same partial sums and tree): for a decision that
+// must be taken before the dense matrix is assembled, and for the report at
+// the end of a run (tol_g > 0: the same convergence test as k_dense_params).
 __global__ __launch_bounds__(256) void k_dense_gnorm(int32_t W, const DenseDesc *__restrict__ desc,
-                                                     LMState *__restrict__ lm, const double *__restrict__ g) {
+                                                     LMState *__restrict__ lm, const double *__restrict__ g,
+                                                     double tol_g) {
     __shared__ double rs[256];
     const int w = blockIdx.x;
     if (w >= W) return;
@@ -793,7 +795,13 @@ __global__ __launch_bounds__(256) void k_dense_gnorm(int32_t W, const DenseDesc 
         if ((int)threadIdx.x < o) rs[threadIdx.x] += rs[threadIdx.x + o];
         __syncthreads();
     }
-    if (threadIdx.x == 0) st.gnorm = sqrt(rs[0]);
+    if (threadIdx.x == 0) {
+        st.gnorm = sqrt(rs[0]);
+        if (tol_g > 0.0 && st.gnorm < tol_g) {
+            st.done = 1;
+            st.accepted = 0;
+        }
+    }
 }
 
 __global__ __launch_bounds__(256) void k_dense_params(int32_t W, const DenseDesc *__restrict__ desc,
@@ -1187,9 +1195,10 @@ static void launch_factor_solve(DenseState *D, int32_t nmat, int32_t max_n, cons
         hipLaunchKernelGGL(k_backsub, dim3(1, nmat), dim3(256), 0, s, D->desc, D->prm, D->work, x, x_off, 0);
 }
 
-void launch_dense_gnorm(Problem *P, hipStream_t s) {
+void launch_dense_gnorm(Problem *P, hipStream_t s, double tol_g) {
     DenseState *D = dense_state(P);
-    hipLaunchKernelGGL(k_dense_gnorm, dim3(P->n_windows), dim3(256), 0, s, P->n_windows, D->desc, P->lm, P->g);
+    hipLaunchKernelGGL(k_dense_gnorm, dim3(P->n_windows), dim3(256), 0, s, P->n_windows, D->desc, P->lm, P->g,
+                       tol_g);
 }
 
 ba_status dense_lm_step(Problem *P, const double *poses, double tol_g, hipStream_t s) {

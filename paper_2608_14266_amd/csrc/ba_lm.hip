@@ -119,42 +119,6 @@ __global__ __launch_bounds__(DECIDE_THREADS) void k_lm_cost(int32_t W, const int
     }
 }
 
-// block per window: ||g|| and max diag(H) at freshly evaluated poses; convergence test.
-// Gradient norm and largest Hessian diagonal of every window whose
-// derivatives are fresh, in the order the fused MM solve forms them (per pose,
-// then the wave totals in wave order).
-__global__ __launch_bounds__(1024) void k_window_stats(int32_t W, const int32_t *__restrict__ win_pose_ptr,
-                                                       const double *__restrict__ g, const double *__restrict__ H,
-                                                       LMState *__restrict__ lm, double tol_g) {
-    constexpr int NW = 1024 / 64;
-    __shared__ double red[NW];
-    const int w = blockIdx.x;
-    if (w >= W) return;
-    LMState &st = lm[w];
-    if (st.done || !st.need_eval) return;
-    double s = 0.0, m = 0.0;
-    const int p0 = win_pose_ptr[w], p1 = win_pose_ptr[w + 1];
-    for (int j = p0 + threadIdx.x; j < p1; j += 1024) {
-#pragma unroll
-        for (int k = 0; k < 6; k++) {
-            const double gk = g[6LL * j + k];
-            s = fma(gk, gk, s);
-            m = fmax(m, H[36LL * j + 7 * k]);
-        }
-    }
-    s = block_sum<NW>(s, red);
-    m = block_max<NW>(m, red);
-    if (threadIdx.x == 0) {
-        st.gnorm = sqrt(s);
-        st.maxdiag = m;
-        st.need_eval = 0;
-        if (tol_g > 0.0 && st.gnorm < tol_g) {
-            st.done = 1;
-            st.accepted = 0;
-        }
-    }
-}
-
 __global__ void k_solve_mm_lm(int32_t n_poses, const int32_t *__restrict__ pose_window,
                               const int32_t *__restrict__ win_pose_ptr, const LMState *__restrict__ lm,
                               const double *__restrict__ H, const double *__restrict__ g,
@@ -408,9 +372,12 @@ void launch_lm_cost(Problem *P, hipStream_t s) {
                        P->wave_cost, P->lm);
 }
 
+// Statistics and convergence test at the end of an MM run, in the order of
+// the in-loop test (window_stats_ordered), so the reported gradient norm and
+// flag are bitwise the ones the next iteration's solve would form.
 void launch_window_stats(Problem *P, double tol_g, hipStream_t s) {
-    hipLaunchKernelGGL(k_window_stats, dim3(P->n_windows), dim3(1024), 0, s, P->n_windows, P->win_pose_ptr, P->g,
-                       P->H, P->lm, tol_g);
+    hipLaunchKernelGGL(k_window_stats_mm, dim3(P->n_windows), dim3(WSTAT_THREADS), 0, s, P->n_windows,
+                       P->win_pose_ptr, P->lm, P->g, P->H, tol_g);
 }
 
 DecideArgs decide_args(Problem *P, double *trace, int it, double *poses, int max_rejects) {
