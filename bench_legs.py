@@ -301,7 +301,8 @@ def served(args):
     t0 = time.perf_counter()
     from concurrent.futures import ProcessPoolExecutor
     import multiprocessing as mp
-    with ProcessPoolExecutor(max_workers=min(16, os.cpu_count() or 1), mp_context=mp.get_context("fork")) as ex:
+    # fresh worker processes (spawn): this process already holds a GPU context
+    with ProcessPoolExecutor(max_workers=min(16, os.cpu_count() or 1), mp_context=mp.get_context("spawn")) as ex:
         reqs = list(ex.map(_gen_request, [(6000 + i, int(n)) for i, n in enumerate(sizes)]))
     log(f"served: {R} requests ({sizes.min()}..{sizes.max()} poses, {sum(r.n_clusters for r in reqs)} clusters), "
         f"generated in {time.perf_counter() - t0:.1f}s")

@@ -97,6 +97,15 @@ def _cluster_sums(rng, centres, normals, obs_v, obs_s, npts, r_true, t_true, sig
     return s1, s2
 
 
+def _pool(workers: int):
+    """Worker processes for the scene generators.  They are started fresh
+    (spawn), never forked: the caller may already hold a GPU context, which a
+    forked child must not inherit."""
+    from concurrent.futures import ProcessPoolExecutor
+    import multiprocessing as mp
+    return ProcessPoolExecutor(max_workers=workers, mp_context=mp.get_context("spawn"))
+
+
 def _truncated_geometric(rng, p, m_max, size):
     k = np.arange(1, m_max + 1)
     pk = (1 - p) ** (k - 1) * p
@@ -242,9 +251,7 @@ def batch_windows(seed: int = 4000, n_windows: int = 256, poses_range=(20, 400),
     jobs = [(seed, w, int(Nw[w]), int(Vw[w]), kw) for w in range(n_windows)]
     workers = workers or min(16, os.cpu_count() or 1)
     if workers > 1 and n_windows > 1:
-        from concurrent.futures import ProcessPoolExecutor
-        import multiprocessing as mp
-        with ProcessPoolExecutor(max_workers=workers, mp_context=mp.get_context("fork")) as ex:
+        with _pool(workers) as ex:
             parts = list(ex.map(_window_job, jobs, chunksize=1))
     else:
         parts = [_window_job(j) for j in jobs]
@@ -287,17 +294,14 @@ def request_scene(seed: int, n_poses: int, vox_per_pose: int = 400, **kw) -> Sum
                      _pack(r, t), init)
 
 
-_SWEEP: dict = {}
-
-
 def _sweep_sums_job(args):
-    seed, k, a, b = args
-    g = _SWEEP
+    seed, k, centres, nrm, obs_s, npts, r_true, t_true, sigma = args
     # chunk k draws from its own stream: Philox keyed by the seed, advanced by
-    # (k + 1) jumps of 2^128 draws (the main stream is the unjumped one)
+    # (k + 1) jumps of 2^128 draws (the main stream is the unjumped one); its
+    # planes arrive as one row per observation (plane index = row)
     rng = np.random.Generator(np.random.Philox(key=int(seed)).jumped(k + 1))
-    return _cluster_sums(rng, g["centres"], g["nrm"], g["obs_v"][a:b], g["obs_s"][a:b], g["npts"][a:b],
-                         g["r_true"], g["t_true"], g["sigma"], chunk=b - a)
+    local = np.arange(obs_s.shape[0], dtype=np.int64)
+    return _cluster_sums(rng, centres, nrm, local, obs_s, npts, r_true, t_true, sigma, chunk=obs_s.shape[0])
 
 
 def city_sweep_scene(n_scans: int, planes_per_pose: int = 500, seed: int = 5000, geom_p: float = 0.15,
@@ -326,21 +330,17 @@ def city_sweep_scene(n_scans: int, planes_per_pose: int = 500, seed: int = 5000,
     obs_v, obs_s = _nearest_observers(t_true, centres, m, obs_radius)
     npts = _loglog_counts(rng, pts_range[0], pts_range[1], obs_v.shape[0])
     C = obs_v.shape[0]
-    jobs = [(seed, k, a, min(C, a + chunk)) for k, a in enumerate(range(0, C, chunk))]
-    _SWEEP.clear()
-    _SWEEP.update(centres=centres, nrm=nrm, obs_v=obs_v, obs_s=obs_s, npts=npts, r_true=r_true, t_true=t_true,
-                  sigma=sigma)
+    def jobs():
+        for k, a in enumerate(range(0, C, chunk)):
+            b = min(C, a + chunk)
+            v = obs_v[a:b]
+            yield (seed, k, centres[v], nrm[v], obs_s[a:b], npts[a:b], r_true, t_true, sigma)
     workers = workers or min(16, os.cpu_count() or 1)
-    try:
-        if workers > 1 and len(jobs) > 1:
-            from concurrent.futures import ProcessPoolExecutor
-            import multiprocessing as mp
-            with ProcessPoolExecutor(max_workers=workers, mp_context=mp.get_context("fork")) as ex:
-                parts = list(ex.map(_sweep_sums_job, jobs, chunksize=1))
-        else:
-            parts = [_sweep_sums_job(j) for j in jobs]
-    finally:
-        _SWEEP.clear()
+    if workers > 1 and C > chunk:
+        with _pool(workers) as ex:
+            parts = list(ex.map(_sweep_sums_job, jobs(), chunksize=1))
+    else:
+        parts = [_sweep_sums_job(j) for j in jobs()]
     s1 = np.concatenate([p[0] for p in parts])
     s2 = np.concatenate([p[1] for p in parts])
     init = _perturb(rng, r_true, t_true, math.radians(rot_bound_deg), trans_bound)

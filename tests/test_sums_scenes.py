@@ -86,3 +86,14 @@ def test_city_sweep_parallel_generation_is_exact_and_scales_linearly():
     # every cluster's scatter is positive semi-definite in the scan frame
     n, mu, S = _centred(c)
     assert np.all(np.linalg.eigvalsh(S)[:, 0] > -1e-9 * np.abs(S).max(axis=(1, 2)))
+
+
+def test_sweep_scene_does_not_depend_on_the_worker_count():
+    """The scaling-sweep generator draws each chunk from its own stream and
+    hands every worker its chunk's data: one process and three give the same
+    clusters."""
+    a = ss.city_sweep_scene(40, planes_per_pose=20, chunk=500, workers=1)
+    b = ss.city_sweep_scene(40, planes_per_pose=20, chunk=500, workers=3)
+    assert a.n_clusters > 4 * 500
+    for f in ("voxel", "scan", "count", "sum", "sumsq", "poses_init"):
+        assert np.array_equal(getattr(a, f), getattr(b, f))
