@@ -118,3 +118,72 @@ def oracle_clusters_from_sums(orc, sc):
     mu, S = orc.center_raw_sums(sc.count[order], sc.sum[order], sc.sumsq[order])
     return orc.Clusters(sc.voxel[order].astype(np.int32), sc.scan[order].astype(np.int32),
                         sc.count[order].astype(np.int64), mu, S, sc.n_voxels, sc.n_scans)
+
+
+def _worst_ratio(d, s):
+    """max over blocks of d / s; a block whose scale is zero must be exact."""
+    d = np.asarray(d, dtype=np.float64)
+    s = np.asarray(s, dtype=np.float64)
+    if np.any((s == 0) & (d != 0)):
+        return float("inf")
+    ok = s > 0
+    return float(np.max(d[ok] / s[ok])) if np.any(ok) else 0.0
+
+
+def block_err_g(g, g_ref, g_abs):
+    """Largest per-pose gradient error, each pose's 6-vector against its own
+    rounding scale: the norm of that pose's summed absolute per-cluster
+    contributions (oracle.evaluate_abs).  Any summation order of the pose's
+    terms is exact up to a multiple of eps times that scale, so a wrong block
+    of a weakly observed pose cannot hide behind the strongly observed ones."""
+    d = np.linalg.norm((np.asarray(g, dtype=np.float64).ravel() - np.asarray(g_ref).ravel()).reshape(-1, 6), axis=1)
+    s = np.linalg.norm(np.asarray(g_abs).reshape(-1, 6), axis=1)
+    return _worst_ratio(d, s)
+
+
+def block_err_h(H, H_ref, H_abs):
+    """Largest per-block Hessian error (Frobenius), each 6x6 block against the
+    Frobenius norm of its summed absolute contributions.  MM: blocks [N][6][6];
+    dense (6N, 6N): every (j, k) pose-pair block."""
+    H = np.asarray(H, dtype=np.float64)
+    H_ref = np.asarray(H_ref)
+    H_abs = np.asarray(H_abs)
+    if H_ref.ndim == 3:
+        d = np.sqrt(((H.reshape(H_ref.shape) - H_ref) ** 2).sum(axis=(1, 2)))
+        s = np.sqrt((H_abs ** 2).sum(axis=(1, 2)))
+        return _worst_ratio(d, s)
+    n = H_ref.shape[0] // 6
+    blk = lambda A: A.reshape(n, 6, n, 6)
+    d = np.sqrt(((blk(H) - blk(H_ref)) ** 2).sum(axis=(1, 3)))
+    s = np.sqrt((blk(H_abs) ** 2).sum(axis=(1, 3)))
+    return _worst_ratio(d, s)
+
+
+def dense_backward_error(A, x, b):
+    """Normwise backward error of a solve A x = b (Rigal-Gaches):
+    ||A x - b||_inf / (||A||_inf ||x||_inf + ||b||_inf)."""
+    r = A @ x - b
+    return float(np.abs(r).max() / (np.abs(A).sum(axis=1).max() * np.abs(x).max() + np.abs(b).max()))
+
+
+def lm_rounding_spread(orc, mode, cl, poses, iters, **kw):
+    """Rounding sensitivity of the oracle's own LM run: the same run started
+    from the poses moved by one ulp in every entry (up, then down).  Two
+    correct FP64 executions of the iteration (different summation orders)
+    differ by perturbations of this size, amplified by the same conditioning
+    of the damped systems, so the spread is the yardstick for comparisons of
+    whole LM runs where the steps amplify rounding beyond 1e-12.
+    Returns (dtrace (iters, 8), dcost_final, dposes), the largest absolute
+    differences of the perturbed runs from the unperturbed one."""
+    P0 = np.asarray(poses, dtype=np.float64)
+    P_a, rep_a, c_a = orc.lm(mode, cl, P0, iters, **kw)
+    dtr = np.zeros((rep_a.shape[0], 8))
+    dc = 0.0
+    dP = np.zeros_like(P0)
+    for direction in (np.inf, -np.inf):
+        P_b, rep_b, c_b = orc.lm(mode, cl, np.nextafter(P0, direction), iters, **kw)
+        k = min(rep_a.shape[0], rep_b.shape[0])
+        dtr[:k] = np.maximum(dtr[:k], np.abs(rep_a[:k] - rep_b[:k]))
+        dc = max(dc, abs(c_a - c_b))
+        dP = np.maximum(dP, np.abs(P_a - P_b))
+    return dtr, dc, dP

@@ -5,7 +5,8 @@ import numpy as np
 import pytest
 
 import scenes
-from helpers import build_gpu, cost_floor, grad_rel_err, rel, resolved_prefix
+from helpers import (block_err_g, block_err_h, build_gpu, cost_floor, grad_rel_err, lm_rounding_spread, rel,
+                     resolved_prefix)
 
 pytestmark = pytest.mark.gpu
 TOL = 1e-12
@@ -55,14 +56,17 @@ def test_coupled_hessian_matches_oracle(ba, dev, orc, case):
     for poses in (sc.poses_init, sc.poses_true):
         P = torch.as_tensor(poses, device=dev)
         cost, g, H, _ = ba.eval_residual_grad_hessian(prob, P, ba.MODE_COUPLED)
-        c_ref, g_ref, H_ref, _ = orc.evaluate(orc.COUPLED, cl, poses)
+        c_ref, g_ref, H_ref, ga, Ha = orc.evaluate_abs(orc.COUPLED, cl, poses)
         assert abs(cost.cpu().numpy()[0] - c_ref) <= TOL * c_ref + cost_floor(orc, cl, poses)
         Hg = H.cpu().numpy()
         assert rel(Hg, H_ref) <= TOL
+        # every pose-pair block against its own rounding scale
+        assert block_err_h(Hg, H_ref, Ha) <= TOL
+        assert block_err_g(g.cpu().numpy(), g_ref, ga) <= TOL
         assert np.array_equal(Hg, Hg.T)            # both triangles written from one sum
 
 
-@pytest.mark.parametrize("n", [6, 60, 66, 126, 198, 330, 384])
+@pytest.mark.parametrize("n", [6, 60, 66, 126, 150, 198, 300, 330, 384])
 def test_dense_cholesky_solve_against_lapack(ba, dev, orc, n):
     import torch
     say(f"dense solve random SPD n={n}")
@@ -131,9 +135,16 @@ def test_iterate_coupled_matches_oracle(ba, dev, orc, case, iters):
     k = resolved_prefix(tr, rep_ref)
     assert k >= 3          # the coupled step is Newton-like: a few resolved iterations
     assert np.array_equal(tr[:k, 4], rep_ref[:k, 4])
+    # 1e-12, or ten times the oracle's own spread under one-ulp perturbations
+    # of the start where the dense damped solve amplifies rounding beyond it
+    dtr, dc, _ = lm_rounding_spread(orc, orc.COUPLED, cl, sc.poses_init, iters)
     scale = np.maximum(np.abs(rep_ref[:k, [0, 1]]), 1e-3 * rep_ref[0, 0])
-    assert np.all(np.abs(tr[:k, [0, 1]] - rep_ref[:k, [0, 1]]) <= 1e-10 * scale)
-    assert abs(reps[0]["cost_final"] - c_ref) <= 1e-10 * max(c_ref, 1e-3 * rep_ref[0, 0])
+    tol = np.maximum(TOL * scale, 10 * dtr[:k, 0:2])
+    err = np.abs(tr[:k, [0, 1]] - rep_ref[:k, [0, 1]])
+    print(f"  {name}: worst trace error / (TOL scale) {np.max(err / (TOL * scale)):.2e}, "
+          f"oracle spread / (TOL scale) {np.max(dtr[:k, 0:2] / (TOL * scale)):.2e}")
+    assert np.all(err <= tol)
+    assert abs(reps[0]["cost_final"] - c_ref) <= max(TOL * max(c_ref, 1e-3 * rep_ref[0, 0]), 10 * dc)
 
 
 def test_mm_and_coupled_reach_same_minimum(ba, dev, orc):

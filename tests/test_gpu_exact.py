@@ -143,12 +143,20 @@ def test_hybrid_lm_matches_oracle(ba, dev, orc):
     say(f"hybrid: {k} resolved iterations of {len(rep_ref)}")
     assert k >= 4
     assert np.array_equal(tr[:k, 4], rep_ref[:k, 4])
+    # 1e-12, or ten times the oracle's own spread under one-ulp perturbations
+    # of the start: the undamped Newton steps of the exact stage amplify
+    # rounding along the nearly flat gauge directions
+    from helpers import lm_rounding_spread
+    dtr, dc, dPs = lm_rounding_spread(orc, orc.COUPLED, cl, sc.poses_init, 12, tol_g=1e-9, exact_below=0.1)
     scale = np.abs(rep_ref[:k, [0, 1]])
-    assert np.all(np.abs(tr[:k, [0, 1]] - rep_ref[:k, [0, 1]]) <= 1e-10 * scale)
-    assert abs(reps[0]["cost_final"] - c_ref) <= 1e-10 * c_ref
+    err = np.abs(tr[:k, [0, 1]] - rep_ref[:k, [0, 1]])
+    print(f"  hybrid: worst trace error / (1e-12 scale) {np.max(err / (1e-12 * scale)):.2e}, "
+          f"oracle spread {np.max(dtr[:k, 0:2] / (1e-12 * scale)):.2e}, pose spread {dPs.max():.2e}")
+    assert np.all(err <= np.maximum(1e-12 * scale, 10 * dtr[:k, 0:2]))
+    assert abs(reps[0]["cost_final"] - c_ref) <= max(1e-12 * c_ref, 10 * dc)
     assert reps[0]["converged"] == 1
     dP = np.abs(P.cpu().numpy() - P_ref)
-    assert np.all(dP <= 1e-8 * (1.0 + np.abs(P_ref)))
+    assert np.all(dP <= np.maximum(1e-11 * (1.0 + np.abs(P_ref)), 10 * dPs))
 
 
 def test_hybrid_option_needs_coupled_fp64(ba, dev):

@@ -6,7 +6,7 @@ import numpy as np
 import pytest
 
 import scenes
-from helpers import cost_floor, grad_rel_err, rel, resolved_prefix, to_dev
+from helpers import block_err_g, block_err_h, cost_floor, grad_rel_err, rel, resolved_prefix, to_dev
 
 pytestmark = [pytest.mark.gpu, pytest.mark.timeout(900)]
 
@@ -54,10 +54,13 @@ def test_fullsize_eval(full, orc):
     say("full-size eval MM at the initial poses")
     P = torch.as_tensor(sc.poses_init, device=dev)
     cost, g, H, _ = ba.eval_residual_grad_hessian(prob, P, ba.MODE_MM)
-    c_ref, g_ref, H_ref, _ = orc.evaluate(orc.MM, cl, sc.poses_init)
+    c_ref, g_ref, H_ref, ga, Ha = orc.evaluate_abs(orc.MM, cl, sc.poses_init)
     assert abs(cost.cpu().numpy()[0] - c_ref) <= TOL * c_ref + cost_floor(orc, cl, sc.poses_init)
     assert grad_rel_err(g.cpu().numpy().ravel(), g_ref, np.abs(g_ref).sum()) <= TOL
     assert rel(H.cpu().numpy(), H_ref) <= TOL
+    eg, eh = block_err_g(g.cpu().numpy(), g_ref, ga), block_err_h(H.cpu().numpy(), H_ref, Ha)
+    print(f"  full size: worst gradient block {eg:.2e}, Hessian block {eh:.2e}")
+    assert eg <= TOL and eh <= TOL
 
 
 def test_fullsize_lm(full, orc):

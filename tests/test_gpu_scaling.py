@@ -86,6 +86,12 @@ def test_wide_window_lm_matches_oracle(orc):
     assert k >= 6
     assert np.array_equal(tr[:k, 4], rep_ref[:k, 4])
     assert np.all(np.abs(tr[:k, [0, 1]] - rep_ref[:k, [0, 1]]) <= TOL * np.abs(rep_ref[:k, [0, 1]]))
-    assert abs(reps[0]["cost_final"] - c_ref) <= 1e-10 * c_ref
+    # past the resolved prefix rounding decides: 1e-12, or ten times the
+    # oracle's own spread under one-ulp perturbations of the start
+    from helpers import lm_rounding_spread
+    _, dc, dPs = lm_rounding_spread(orc, orc.MM, cl, sc.poses_init, 12)
+    print(f"  wide window: final cost error {abs(reps[0]['cost_final'] - c_ref) / c_ref:.2e}, "
+          f"oracle spread {dc / c_ref:.2e}, pose spread {dPs.max():.2e}")
+    assert abs(reps[0]["cost_final"] - c_ref) <= max(TOL * c_ref, 10 * dc)
     dP = np.abs(P.cpu().numpy() - P_ref)
-    assert np.all(dP <= (1e-11 if k == 12 else 1e-8) * (1.0 + np.abs(P_ref)))
+    assert np.all(dP <= np.maximum(1e-11 * (1.0 + np.abs(P_ref)), 10 * dPs))

@@ -4,7 +4,9 @@ gradient tolerance.
 
 Bar: every request's result (poses and LM report) is bitwise identical
 whether it is served alone or in a mix of concurrent requests; served
-results agree with the FP64 oracle at 1e-12 (cost at the returned poses);
+results agree with the oracle's own LM run with the same options (cost and
+poses at 1e-12, or at ten times the oracle's rounding spread where rounding
+decides the late steps);
 the footprint used for admission bounds the real device memory; a budget
 that fits one request at a time serialises the requests."""
 import numpy as np
@@ -74,16 +76,41 @@ def test_each_result_is_the_same_alone_and_in_the_mix(ba, dev, requests, prec, m
     assert overlap >= 1
 
 
-def test_served_results_match_oracle(ba, dev, orc, requests):
-    say("served vs oracle")
-    res = _serve(ba, requests[:4], 4, 8 * GB, max_iters=40, tol_g=1e-6)
-    for r, (P, st) in zip(requests[:4], res):
+@pytest.mark.parametrize("mode", ["mm", "coupled"])
+def test_served_results_match_oracle_lm(ba, dev, orc, requests, mode):
+    """Each served request against the oracle's own LM run with the same
+    options (gradient tolerance 1e-6, 10 rejections in a row stop a request):
+    final cost and poses to 1e-12, or ten times the oracle's own spread under
+    one-ulp perturbations of the start once rounding decides the late steps;
+    the iteration and acceptance counts where the oracle's perturbed runs agree
+    on them.  The coupled form reaches the gradient tolerance; the MM form on
+    these chain-like windows does not within the cap (its block-diagonal step
+    leaves the slow along-chain modes: see the design notes)."""
+    from helpers import lm_rounding_spread
+    say(f"served vs oracle LM ({mode})")
+    m_ba = ba.MODE_MM if mode == "mm" else ba.MODE_COUPLED
+    m_orc = orc.MM if mode == "mm" else orc.COUPLED
+    iters = 40 if mode == "mm" else 25
+    res = _serve(ba, requests[:4], 4, 8 * GB, mode=m_ba, max_iters=iters, tol_g=1e-6, max_rejects=10)
+    for i, (r, (P, st)) in enumerate(zip(requests[:4], res)):
         cl = oracle_clusters_from_sums(orc, r)
-        c_ref = orc.cost(cl, P)
+        P_ref, rep_ref, c_ref = orc.lm(m_orc, cl, r.poses_init, iters, tol_g=1e-6, max_rejects=10)
+        dtr, dc, dP = lm_rounding_spread(orc, m_orc, cl, r.poses_init, iters, tol_g=1e-6, max_rejects=10)
         rep = st["report"]
-        assert abs(rep["cost_final"] - c_ref) <= 1e-12 * c_ref
-        assert rep["converged"] == 1 or rep["iters"] == 40
+        ec = abs(rep["cost_final"] - c_ref)
+        ep = np.abs(P - P_ref)
+        print(f"  request {i} ({r.n_scans} poses): cost err {ec / c_ref:.2e} (spread {dc / c_ref:.2e}), "
+              f"pose err {ep.max():.2e} (spread {dP.max():.2e}), iters {rep['iters']} / {len(rep_ref)}, "
+              f"gnorm {rep['gnorm_final']:.2e}")
+        assert ec <= max(1e-12 * c_ref, 10 * dc)
+        assert np.all(ep <= np.maximum(1e-11 * (1.0 + np.abs(P_ref)), 10 * dP))
+        if dc == 0.0 and not np.any(dP):
+            # the oracle's iteration does not depend on rounding here
+            assert rep["iters"] == len(rep_ref)
+            assert rep["n_accepted"] == int(rep_ref[:, 4].sum())
         assert rep["cost_final"] < rep["cost_initial"]
+        if mode == "coupled":
+            assert rep["converged"] == 1 and rep["gnorm_final"] < 1e-6
 
 
 def test_budget_of_one_request_serialises(ba, dev, requests):
