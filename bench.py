@@ -1,13 +1,19 @@
 #!/usr/bin/env python3
 """Benchmark of the LiDAR bundle-adjustment hot path on one MI355X.
 
-A step is one complete LM solve of the single-window workload (500 scans on a
-2 km figure-eight, 200k planar voxels, 1..20 observers per voxel, 20..500
-points per observation, 20 LM iterations; synthetic, seeded): every
-iteration evaluates all voxel residuals at the trial poses, the surrogate
-gradient and Hessian at accepted poses, and solves the damped increment, all
-on the device.  The problem (clusters and plan) is built once before the
-timed region from device-resident points; its build time is reported apart.
+Default workload (the headline): 256 independent window problems with 20..400
+poses and 5k..80k planar voxels each (the batched workload; seeded synthetic
+raw-sum clusters, 37M clusters, 1.85G virtual points) held in one problem in
+the precision form (FP32 voxel-centred clusters, FP64 eigensolve, increment
+solves and pose update).  A step is one complete 10-iteration LM solve of all
+windows: every iteration evaluates all voxel residuals at the trial poses, the
+surrogate gradient and Hessian at accepted poses, and solves the damped
+increments, all on the device, replayed from one captured graph.  The batched
+FP64 form and the plain per-problem FP64 path run beside it.  The problem is
+built once before the timed region; its build time is reported apart.
+
+Other workloads: --workload window (500-pose single window built from 117M
+points), city, served, scaling, pipeline.
 
 Prints one JSON line.  Progress goes to stderr.
 """
@@ -94,9 +100,9 @@ def main():
     ap.add_argument("--iters", type=int, default=20, help="LM iterations per solve")
     ap.add_argument("--mode", choices=["mm", "coupled"], default="mm")
     ap.add_argument("--workload", choices=["window", "tiny", "city", "batch", "served", "scaling", "pipeline"],
-                    default="window",
-                    help="window: 500-pose single window (the headline); city: 2000-pose 5 km precision-form "
-                         "map; batch: 256 uneven windows; served: Poisson request stream; scaling: "
+                    default="batch",
+                    help="batch: 256 uneven windows (the headline); window: 500-pose single window; city: "
+                         "2000-pose 5 km precision-form map; served: Poisson request stream; scaling: "
                          "build time against points and per-iteration times against clusters and poses; "
                          "pipeline: unlabelled points -> voxelize -> build -> solve")
     ap.add_argument("--rate", type=float, default=20.0, help="served: request arrival rate (req/s)")
@@ -113,6 +119,8 @@ def main():
     ap.add_argument("--no-precision-leg", action="store_true",
                     help="skip the FP32 precision-form run on the same workload")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default launch choices")
+    ap.add_argument("--no-plain-leg", action="store_true",
+                    help="batch: skip the plain per-problem FP64 path (for counter runs of the batched passes)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="after the run, copy a buffer of this many MiB device to device three times "
                          "(a plain copy kernel of known size, to scale hardware byte counters)")
@@ -139,6 +147,7 @@ def main():
         out = {"city": bench_legs.city, "batch": bench_legs.batch, "served": bench_legs.served,
                "scaling": bench_legs.scaling, "pipeline": bench_legs.pipeline}[args.workload](args)
         print(json.dumps(out), flush=True)
+        _calibration_copy(args, dev)
         return
 
     t0 = time.perf_counter()
@@ -339,14 +348,22 @@ def main():
         "precision_form": prec,
     }
     print(json.dumps(out), flush=True)
-    if args.calib_copy_mib > 0:
-        nb = args.calib_copy_mib << 20
-        src = torch.ones(nb // 4, dtype=torch.float32, device=dev)
-        dst = torch.empty_like(src)
-        for _ in range(3):
-            dst.copy_(src)
-        torch.cuda.synchronize()
-        log(f"calibration copy: 3 x {args.calib_copy_mib} MiB")
+    _calibration_copy(args, dev)
+
+
+def _calibration_copy(args, dev):
+    """A plain device-to-device copy of known size (three times), after the
+    measured work: the reference that scales hardware byte counters."""
+    if args.calib_copy_mib <= 0:
+        return
+    import torch
+    nb = args.calib_copy_mib << 20
+    src = torch.ones(nb // 4, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    log(f"calibration copy: 3 x {args.calib_copy_mib} MiB")
 
 
 if __name__ == "__main__":

@@ -203,8 +203,164 @@ def city(args):
             "f32": res["f32"], "f64": res["f64"], "accuracy": acc}
 
 
-# ---------------------------------------------------------------- batch
+# ---------------------------------------------------------------- batch (headline)
+HBM_PEAK = HBM_PEAK_GBS
+
+
+def _cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
+def _host_cores() -> int:
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))   # the GPU machine's host share is 16 threads per GPU
+
+
+def _window_counts(sc):
+    """Clusters, voxels and poses of every window of a batch scene."""
+    W = sc.n_windows
+    wc = np.bincount(sc.scan_window[sc.scan], minlength=W)
+    wn = np.bincount(sc.scan_window, minlength=W)
+    wv = np.asarray(sc.meta["voxels"], dtype=np.int64)
+    return wc.astype(np.int64), wv, wn.astype(np.int64)
+
+
+def _eval_bytes(kernel, prec, C, V, N):
+    """Algorithmic HBM bytes of one pass over C clusters, V voxels and N poses
+    (per-evaluation figures of the hot-path measurement plan): the cluster
+    stream (80 B FP64 / 44 B FP32 per cluster), 8 B per voxel (its cluster
+    range) plus 24 B of FP64 reference point in the precision form, 96 B of
+    pose per scan, and for the derivative pass 216 B of gradient and Hessian
+    out per scan.  Voxel-state traffic between the two passes is not counted."""
+    bc = 44 if prec == "f32" else 80
+    bv = 8 + (24 if prec == "f32" else 0)
+    bn = 96 + (216 if kernel == "k_pose" else 0)
+    return bc * C + bv * V + bn * N
+
+
+def _oracle_windows(sc, windows):
+    """Oracle clusters and initial poses of the given windows (untimed setup)."""
+    import oracle
+    import scenes.sums as ss
+    out = []
+    for w in windows:
+        sw = ss.window_of(sc, w)
+        order = np.lexsort((sw.scan, sw.voxel))
+        mu, S = oracle.center_raw_sums(sw.count[order], sw.sum[order], sw.sumsq[order])
+        cl = oracle.Clusters(sw.voxel[order].astype(np.int32), sw.scan[order].astype(np.int32),
+                             sw.count[order].astype(np.int64), mu, S, sw.n_voxels, sw.n_scans)
+        out.append((cl, sw.poses_init.copy(), int(np.unique(sw.voxel).shape[0])))
+    return out
+
+
+def _cpu_baseline_batch(sc, iters, sample_every):
+    """The FP64 oracle as it stands on a sample of the batch's windows: each
+    window's LM run of `iters` iterations (evaluation at the initial poses,
+    then per iteration the solve, the trial cost and the derivatives at
+    accepted poses), on one host thread and on all host threads (windows
+    spread over a thread pool; the oracle's C code runs outside the
+    interpreter lock, and each window's arithmetic is the same either way)."""
+    import oracle
+    from concurrent.futures import ThreadPoolExecutor
+    windows = list(range(0, sc.n_windows, sample_every))
+    t0 = time.perf_counter()
+    prep = _oracle_windows(sc, windows)
+    t_prep = time.perf_counter() - t0
+    V = sum(p[2] for p in prep)
+    C = sum(p[0].C for p in prep)
+    run = lambda p: oracle.lm(oracle.MM, p[0], p[1], iters)[2]
+    t0 = time.perf_counter()
+    c1 = [run(p) for p in prep]
+    t1 = time.perf_counter() - t0
+    cores = _host_cores()
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(max_workers=cores) as ex:
+        cn = list(ex.map(run, prep))
+    tn = time.perf_counter() - t0
+    assert cn == c1, "oracle results differ between the serial and the threaded run"
+    sample = (f"{len(windows)} of {sc.n_windows} windows (every {sample_every}th; {C} clusters, {V} voxels), "
+              f"{iters} LM iterations each (MM, FP64); cluster centring untimed ({t_prep:.1f}s)")
+    cpu = {"value": V * iters / t1, "unit": "plane-voxel evals/s", "cores": 1, "kind": "oracle", "sample": sample,
+           "seconds": round(t1, 3), "cpu_model": _cpu_model(), "nproc": os.cpu_count()}
+    cpu_all = {"value": V * iters / tn, "unit": "plane-voxel evals/s", "cores": cores, "kind": "oracle",
+               "sample": sample, "seconds": round(tn, 3)}
+    return cpu, cpu_all
+
+
+def _profile_lm(ba, prob, P0, iters):
+    """One eager LM run with HIP events around every launch: per-kernel summed
+    time and launch count, plus the per-window acceptance trace."""
+    import torch
+    ba.profile_reset()
+    ba.profile_enable(True)
+    P = P0.clone().contiguous()
+    reps, tr = ba.iterate(prob, P, ba.MODE_MM, max_iters=iters, trace=True)
+    torch.cuda.synchronize()
+    ba.profile_enable(False)
+    kt = {}
+    for k in ("k_vox", "k_pose", "k_window_solve_mm", "k_decide"):
+        ms, n = ba.profile_query(k)
+        if n:
+            kt[k] = {"total_ms": ms, "launches": n, "avg_us": 1e3 * ms / n}
+    ba.profile_reset()
+    return kt, tr
+
+
+def _pass_bytes(kernel, prec, tr, wc, wv, wn):
+    """Algorithmic bytes summed over the LM run's launches of one pass: the
+    residual pass covers every window at every launch (initial point and each
+    trial point); the derivative pass covers, at the start and after each
+    iteration, the windows whose last step was accepted (the others keep their
+    derivatives)."""
+    W = len(wc)
+    full = _eval_bytes(kernel, prec, int(wc.sum()), int(wv.sum()), int(wn.sum()))
+    iters = tr.shape[0]
+    if kernel == "k_vox":
+        return full * (iters + 1), iters + 1
+    total = full          # derivatives at the initial poses: every window
+    for it in range(iters):
+        acc = tr[it, :, 4] > 0.5
+        if acc.any():
+            total += _eval_bytes(kernel, prec, int(wc[acc].sum()), int(wv[acc].sum()), int(wn[acc].sum()))
+    return total, iters + 1
+
+
+def _measured_traffic_batch(kernel, prec):
+    """Counter-measured HBM bytes per launch of one pass on this workload from
+    the committed rocprofv3 summary, or None once the kernel source differs
+    from the one the counters were taken on."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "batch256_traffic.md")
+    src = os.path.join(ROOT, "paper_2608_14266_amd", "csrc", "ba_eval.hip")
+    try:
+        vals = dict(line.split()[:2] for line in open(path) if line.startswith("traffic_"))
+        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    except (OSError, ValueError):
+        return None
+    key = f"traffic_{kernel}_{prec}_bytes"
+    if vals.get("traffic_source_sha256") != sha or key not in vals:
+        return None
+    return int(float(vals[key]))
+
+
 def batch(args):
+    """Headline: 256 uneven windows (20..400 poses, 5k..80k voxels each) in
+    one problem, precision form (FP32 voxel-centred clusters, FP64 eigensolve,
+    solves and pose update), autotuned launches, every LM run one captured
+    graph; a step is one 10-iteration LM solve of all windows.  Beside it the
+    batched FP64 form and the plain per-problem FP64 path (every window its
+    own problem, one after another)."""
     import torch
     import paper_2608_14266_amd as ba
     import scenes.sums as ss
@@ -213,31 +369,44 @@ def batch(args):
     sc = ss.batch_windows(seed=4000, n_windows=args.windows)
     log(f"batch: {sc.n_windows} windows, {sc.n_scans} poses, {sc.n_clusters} clusters, generated in "
         f"{time.perf_counter() - t0:.1f}s")
-    mode = ba.MODE_MM if args.mode == "mm" else ba.MODE_COUPLED
+    wc, wv, wn = _window_counts(sc)
     iters = 10
     arrs = _dev_sums(sc, dev)
     P0 = torch.as_tensor(sc.poses_init, device=dev)
     out = {}
     finals = {}
     for prec in ("f32", "f64"):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
         prob = _build(ba, sc, arrs, prec, P0)
-        tune = None
-        if prec == "f32":
-            t0 = time.perf_counter()
-            tune = ba.tuned(prob, P0, cache_path=None, reps=3)
-            log(f"autotuned in {time.perf_counter() - t0:.1f}s: {tune}")
-        dt, reps, P = _timed_solves(ba, prob, P0, mode, iters, args.steps, args.warmup)
-        kt = _kernel_times(ba, prob, P0, mode, iters)
-        out[f"batched_{prec}"] = {"ms_per_batch": 1e3 * dt, "solves_per_s": sc.n_windows / dt,
-                                  "tuning": tune, "kernels": kt, "device_bytes": prob.info()["device_bytes"]}
+        torch.cuda.synchronize()
+        build_ms = 1e3 * (time.perf_counter() - t0)
+        t0 = time.perf_counter()
+        tune = None if args.no_autotune else ba.tuned(prob, P0, cache_path=None, reps=3)
+        log(f"batched {prec}: built in {build_ms:.1f} ms, autotuned in {time.perf_counter() - t0:.1f}s: {tune}")
+        dt, reps, P = _timed_solves(ba, prob, P0, ba.MODE_MM, iters, args.steps, args.warmup)
+        kt, tr = _profile_lm(ba, prob, P0, iters)
+        inf = prob.info()
+        for k in ("k_vox", "k_pose"):
+            if k in kt:
+                b, n = _pass_bytes(k, prec, tr, wc, wv, wn)
+                kt[k]["algorithmic_bytes_per_launch"] = b / n
+                kt[k]["gbs"] = b / (kt[k]["total_ms"] * 1e-3) / 1e9
+        out[prec] = {"ms_per_batch": 1e3 * dt, "evals_per_s": int(wv.sum()) * iters / dt,
+                     "solves_per_s": sc.n_windows / dt, "build_ms": round(build_ms, 3), "tuning": tune,
+                     "kernels": {k: {kk: (round(vv, 3) if isinstance(vv, float) else vv) for kk, vv in d.items()}
+                                 for k, d in kt.items()},
+                     "device_bytes": inf["device_bytes"], "cluster_bytes": inf["cluster_bytes"],
+                     "accepted_mean": float(np.mean([r["n_accepted"] for r in reps]))}
         finals[prec] = P.cpu().numpy()
-        log(f"batched {prec}: {1e3 * dt:.2f} ms per {sc.n_windows} windows")
+        log(f"batched {prec}: {1e3 * dt:.2f} ms per batch of {sc.n_windows} windows; "
+            + ", ".join(f"{k} {d['avg_us']:.1f} us" for k, d in kt.items()))
         prob.close()
     del arrs
     torch.cuda.empty_cache()
     # plain per-problem FP64: every window its own problem, one after another
     probs, p0s = [], []
-    for w in range(sc.n_windows):
+    for w in range(0 if args.no_plain_leg else sc.n_windows):
         sw = ss.window_of(sc, w)
         a = _dev_sums(sw, dev)
         probs.append((sw, ba.build_clusters_from_sums(*a, sw.n_scans, sw.n_voxels)))
@@ -245,16 +414,18 @@ def batch(args):
     Ps = [p.clone().contiguous() for p in p0s]
     for (sw, pr), p0, P in zip(probs, p0s, Ps):      # warm-up: capture every window's graph
         P.copy_(p0)
-        ba.iterate(pr, P, mode, max_iters=iters, trace=False)
+        ba.iterate(pr, P, ba.MODE_MM, max_iters=iters, trace=False)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
         for (sw, pr), p0, P in zip(probs, p0s, Ps):
             P.copy_(p0)
-            ba.iterate(pr, P, mode, max_iters=iters, trace=False)
+            ba.iterate(pr, P, ba.MODE_MM, max_iters=iters, trace=False)
     torch.cuda.synchronize()
-    dt = (time.perf_counter() - t0) / args.steps
-    out["plain_per_problem_f64"] = {"ms_per_batch": 1e3 * dt, "solves_per_s": sc.n_windows / dt}
+    dt = (time.perf_counter() - t0) / args.steps if probs else float("nan")
+    out["plain_f64"] = {"ms_per_batch": 1e3 * dt, "evals_per_s": int(wv.sum()) * iters / dt,
+                        "solves_per_s": sc.n_windows / dt}
+    log(f"plain per-problem f64: {1e3 * dt:.2f} ms per batch")
     # accuracy per window: batched FP32 vs per-problem FP64, gauge-aligned; APE vs truth
     worst_rad = worst_m = 0.0
     ape32, ape64 = [], []
@@ -268,19 +439,46 @@ def batch(args):
         ape32.append(_ape(a, sw.poses_true)); ape64.append(_ape(b, sw.poses_true))
         s0 += n
         pr.close()
-    rel_ape = float(np.max(np.abs(np.array(ape32) - np.array(ape64)) / np.array(ape64)))
+    del probs, p0s, Ps
+    rel_ape = float(np.max(np.abs(np.array(ape32) - np.array(ape64)) / np.array(ape64))) if ape64 else None
     acc = {"batched_f32_vs_plain_f64_pose_diff": {"rad": worst_rad, "m": worst_m},
-           "ape_f32_mean_m": float(np.mean(ape32)), "ape_f64_mean_m": float(np.mean(ape64)),
-           "ape_rel_diff_max": rel_ape}
-    bf = out["batched_f32"]["solves_per_s"]
-    return {"metric": "window solves/s", "value": bf, "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
-            "warmup": args.warmup, "higher_is_better": True, "dtype": "f32 clusters / f64 solve",
+           "ape_f32_mean_m": float(np.mean(ape32)) if ape32 else None,
+           "ape_f64_mean_m": float(np.mean(ape64)) if ape64 else None, "ape_rel_diff_max": rel_ape}
+    # roofline of the dominant pass of the headline (FP32 batched) run
+    kt = out["f32"]["kernels"]
+    dom = max(("k_vox", "k_pose"), key=lambda k: kt.get(k, {}).get("total_ms", 0.0))
+    ach = kt[dom]["gbs"]
+    roof = {"kernel": dom, "bound": "hbm", "achieved": round(ach, 2), "peak": HBM_PEAK, "unit": "GB/s",
+            "frac": round(ach / HBM_PEAK, 4), "traffic": _measured_traffic_batch(dom, "f32"),
+            "bytes_per_launch": int(kt[dom]["algorithmic_bytes_per_launch"]),
+            "avg_launch_us": kt[dom]["avg_us"]}
+    other = "k_pose" if dom == "k_vox" else "k_vox"
+    if other in kt:
+        roof["other_pass"] = {"kernel": other, "achieved": round(kt[other]["gbs"], 2),
+                              "frac": round(kt[other]["gbs"] / HBM_PEAK, 4), "avg_launch_us": kt[other]["avg_us"]}
+    cpu = cpu_all = None
+    if not args.no_cpu_baseline:
+        log("cpu baseline: oracle on every second window, 2 LM iterations, 1 thread and all threads")
+        cpu, cpu_all = _cpu_baseline_batch(sc, 2, 2)
+        cpu["all_cores"] = cpu_all
+        log(f"cpu baseline: {cpu['value']:.4g} evals/s on 1 thread ({cpu['seconds']}s), "
+            f"{cpu_all['value']:.4g} on {cpu_all['cores']} ({cpu_all['seconds']}s); {cpu['cpu_model']}")
+    f32, f64, plain = out["f32"], out["f64"], out["plain_f64"]
+    return {"metric": "plane-voxel evals/s", "value": f32["evals_per_s"], "unit": "plane-voxel evals/s",
+            "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": f32["ms_per_batch"],
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32/f64",
             "data": "synthetic",
-            "config": {"workload": f"batch-{sc.n_windows}win ({args.mode}, {iters} LM iterations per window)",
-                       "windows": sc.n_windows, "poses": sc.n_scans, "voxels": sc.n_voxels,
-                       "clusters": sc.n_clusters, "virtual_points": sc.n_points},
-            "speedup_vs_plain_per_problem_f64": bf / out["plain_per_problem_f64"]["solves_per_s"],
-            **out, "accuracy": acc}
+            "config": {"workload": f"batch-{sc.n_windows}win-20to400pose (precision form, MM, {iters} LM "
+                                   f"iterations per window per step)",
+                       "windows": sc.n_windows, "poses": sc.n_scans, "voxels": int(wv.sum()),
+                       "clusters": sc.n_clusters, "virtual_points": sc.n_points, "lm_iters": iters},
+            "lm_iters_per_s": iters / (1e-3 * f32["ms_per_batch"]),
+            "window_solves_per_s": f32["solves_per_s"],
+            "vs_fp64": {"batched_f64_evals_per_s": f64["evals_per_s"], "plain_f64_evals_per_s": plain["evals_per_s"],
+                        "speedup_vs_batched_f64": f64["ms_per_batch"] / f32["ms_per_batch"],
+                        "speedup_vs_plain_f64": plain["ms_per_batch"] / f32["ms_per_batch"]},
+            "kernels": f32["kernels"], "roofline": roof, "cpu_baseline": cpu,
+            "batched_f32": f32, "batched_f64": f64, "plain_per_problem_f64": plain, "accuracy": acc}
 
 
 # ---------------------------------------------------------------- served
