@@ -238,6 +238,26 @@ ba_status ba_solve_increment(int32_t mode, int32_t n_scans, const double *hess, 
                              double *dx, int32_t *info, void *ws, size_t ws_bytes, hipStream_t stream);
 
 /*
+ * ba_solve_increment_noalloc — for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid allocation): ba_solve_increment with its workspace taken from a
+ * static device array of BA_STATIC_SCRATCH_BYTES that the library holds on
+ * every GPU it runs on until the process ends, so the call allocates nothing.
+ * Arguments and results as ba_solve_increment (caller-owned device hess,
+ * grad, dx, info; same kernels, bitwise the same results).  Errors:
+ * BA_E_WORKSPACE (checked before any device call) when
+ * ba_solve_increment_workspace(mode, n_scans) exceeds the static scratch
+ * (MM: up to about 20M scans; coupled: up to 6 n_scans ~ 3100, i.e. about
+ * 525 scans); BA_E_ARG, BA_E_UNSUPPORTED as ba_solve_increment; BA_E_HIP if
+ * the scratch's device address cannot be obtained.  All calls on one GPU
+ * share its scratch: calls that overlap on one GPU (concurrent streams) race
+ * and must be ordered by the caller.  Asynchronous.
+ */
+#define BA_STATIC_SCRATCH_BYTES (80 << 20)
+ba_status ba_solve_increment_noalloc(int32_t mode, int32_t n_scans, const double *hess, const double *grad,
+                                     double mu, double *dx, int32_t *info, hipStream_t stream);
+
+/*
  * ba_iterate — the LM optimizer of Fig. 1 run on the device: per iteration,
  * derivatives at the current poses (when they moved), the damped increment
  * solve, the trial poses T (+) dx, the trial cost (Eq. 1), the gain ratio

@@ -32,6 +32,7 @@ from ._lib import (  # noqa: F401
     problem_set_tuning,
     request_footprint,
     solve_increment,
+    solve_increment_noalloc,
     solve_increment_workspace,
     voxelize,
     voxelize_host,

@@ -140,6 +140,8 @@ def load():
     L.ba_solve_increment_workspace.argtypes = [i32, i32]
     L.ba_solve_increment.restype = i32
     L.ba_solve_increment.argtypes = [i32, i32, P, P, dbl, P, P, P, sz, P]
+    L.ba_solve_increment_noalloc.restype = i32
+    L.ba_solve_increment_noalloc.argtypes = [i32, i32, P, P, dbl, P, P, P]
     L.ba_profile_enable.restype = i32
     L.ba_profile_enable.argtypes = [i32]
     L.ba_profile_reset.restype = i32
@@ -329,6 +331,20 @@ def eval_residual_grad_hessian(problem: Problem, poses, mode: int = MODE_MM, der
 
 def solve_increment_workspace(mode: int, n_scans: int) -> int:
     return int(load().ba_solve_increment_workspace(int(mode), int(n_scans)))
+
+
+def solve_increment_noalloc(mode: int, hess, grad, mu: float):
+    """ba_solve_increment_noalloc: the same solve with the library's static
+    device scratch as workspace (no device allocation by the library).
+    Returns (dx (N,6), info (int32 device scalar))."""
+    hess = _dev(hess, torch.float64, "hess"); grad = _dev(grad, torch.float64, "grad")
+    N = grad.numel() // 6
+    dev = grad.device
+    dx = torch.empty((N, 6), dtype=torch.float64, device=dev)
+    info = torch.empty(1, dtype=torch.int32, device=dev)
+    _check(load().ba_solve_increment_noalloc(int(mode), N, _ptr(hess), _ptr(grad), float(mu), _ptr(dx), _ptr(info),
+                                             _stream()))
+    return dx, info
 
 
 def solve_increment(mode: int, hess, grad, mu: float):
