@@ -51,6 +51,7 @@ typedef int32_t ba_status;
 #define BA_E_NOMEM (-6)        /* device allocation failed */
 #define BA_E_BUDGET (-7)       /* a served request can never fit the server's device-memory budget */
 #define BA_E_NOT_FOUND (-8)    /* unknown or already collected request id */
+#define BA_E_CANCELLED (-9)    /* a served request was cancelled before it finished */
 
 /* Cluster storage precision of a problem (ba_build_options.precision). */
 #define BA_PREC_F64 0      /* clusters stored and evaluated in FP64 */
@@ -117,7 +118,8 @@ typedef struct ba_lm_options {
     double nu0;          /* initial damping growth (0 -> 2) */
     double tol_g;        /* stop a window once ||g||_2 < tol_g at its current poses (<= 0: never) */
     int32_t max_rejects; /* stop a window after this many rejected steps in a row (<= 0: never) */
-    int32_t reserved;    /* 0 */
+    int32_t rejects0;    /* rejected steps in a row before this call (0; to resume a run exactly:
+                          * the previous report's rejects_final) */
     double exact_below;  /* BA_MODE_COUPLED only: a window whose gradient norm at its current poses is below this
                           * takes the exact Hessian of Eq. 1 (BA_MODE_EXACT) for its step, the coupled one otherwise
                           * (FP64 problems; <= 0: never) */
@@ -133,10 +135,11 @@ typedef struct ba_lm_report {  /* one per window */
     double gnorm_final;   /* ||g|| at the last evaluated point */
     double mu_final;      /* damping mu after the last decision */
     int32_t stalled;      /* stopped after max_rejects rejections in a row */
-    int32_t reserved;
+    int32_t rejects_final; /* rejected steps in a row at the end of the call */
     double nu_final;      /* damping growth nu after the last decision: a later call with
-                           * mu0 = mu_final and nu0 = nu_final continues the run exactly
-                           * (the derivatives are re-evaluated at the same poses) */
+                           * mu0 = mu_final, nu0 = nu_final and rejects0 = rejects_final
+                           * continues the run exactly (the derivatives are re-evaluated at
+                           * the same poses) */
 } ba_lm_report;
 
 /* Launch choices of the two evaluation passes.  They change the order in
@@ -315,7 +318,10 @@ typedef struct ba_server_options {
     int64_t hbm_budget;    /* device bytes the admitted requests may reserve together (> 0) */
     int32_t slots;         /* requests on the device at once, 1..64 */
     int32_t precision;     /* BA_PREC_F64 or BA_PREC_F32 (references placed by each request's initial poses) */
-    ba_lm_options lm;      /* LM options of every request (mode, max_iters, mu0, nu0, tol_g) */
+    ba_lm_options lm;      /* LM options of every request (mode, max_iters, mu0, nu0, tol_g, max_rejects) */
+    int32_t iters_per_check; /* LM iterations between cancellation checks (0: 10); the chunks resume
+                              * each other exactly, so results do not depend on it */
+    int32_t reserved;      /* 0 */
 } ba_server_options;
 
 typedef struct ba_request {  /* raw-sum clusters of one window (Eq. 2); host arrays, copied on submit */
@@ -331,6 +337,7 @@ typedef struct ba_request {  /* raw-sum clusters of one window (Eq. 2); host arr
 #define BA_REQ_RUNNING 1
 #define BA_REQ_DONE 2
 #define BA_REQ_FAILED 3
+#define BA_REQ_CANCELLED 4
 
 typedef struct ba_request_status {
     int32_t state;         /* BA_REQ_* */
@@ -360,6 +367,14 @@ ba_status ba_server_query(ba_server *s, int64_t id, ba_request_status *st);
  * may be NULL) and status, and forget the request.  BA_E_NOT_FOUND for an
  * unknown id. */
 ba_status ba_server_wait(ba_server *s, int64_t id, double *poses_out, ba_request_status *st);
+
+/* Cancel request `id`: a queued request leaves the queue at once; a running
+ * one stops at its next check (every iters_per_check LM iterations) and keeps
+ * the poses it reached.  Either way it ends in BA_REQ_CANCELLED and
+ * ba_server_wait returns BA_E_CANCELLED with those poses (the initial ones if
+ * it never ran).  A request that has already finished is not affected.  The
+ * other requests' results do not change.  BA_E_NOT_FOUND for an unknown id. */
+ba_status ba_server_cancel(ba_server *s, int64_t id);
 
 /* Finish the running requests, drop the queued ones, stop the slots. */
 ba_status ba_server_destroy(ba_server *s);

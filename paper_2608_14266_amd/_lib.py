@@ -52,7 +52,7 @@ class _Info(ct.Structure):
 
 class _LMOpts(ct.Structure):
     _fields_ = [("mode", ct.c_int32), ("max_iters", ct.c_int32), ("mu0", ct.c_double), ("nu0", ct.c_double),
-                ("tol_g", ct.c_double), ("max_rejects", ct.c_int32), ("reserved", ct.c_int32),
+                ("tol_g", ct.c_double), ("max_rejects", ct.c_int32), ("rejects0", ct.c_int32),
                 ("exact_below", ct.c_double)]
 
 
@@ -63,7 +63,7 @@ class _Tuning(ct.Structure):
 
 class _ServerOpts(ct.Structure):
     _fields_ = [("hbm_budget", ct.c_int64), ("slots", ct.c_int32), ("precision", ct.c_int32),
-                ("lm", _LMOpts)]
+                ("lm", _LMOpts), ("iters_per_check", ct.c_int32), ("reserved", ct.c_int32)]
 
 
 class _Request(ct.Structure):
@@ -76,7 +76,7 @@ class _LMReport(ct.Structure):
     _fields_ = [("iters", ct.c_int32), ("n_accepted", ct.c_int32), ("converged", ct.c_int32),
                 ("last_info", ct.c_int32), ("cost_initial", ct.c_double), ("cost_final", ct.c_double),
                 ("gnorm_final", ct.c_double), ("mu_final", ct.c_double), ("stalled", ct.c_int32),
-                ("reserved", ct.c_int32), ("nu_final", ct.c_double)]
+                ("rejects_final", ct.c_int32), ("nu_final", ct.c_double)]
 
 
 class _ReqStatus(ct.Structure):
@@ -166,6 +166,8 @@ def load():
     L.ba_server_query.argtypes = [P, ct.c_int64, ct.POINTER(_ReqStatus)]
     L.ba_server_wait.restype = i32
     L.ba_server_wait.argtypes = [P, ct.c_int64, P, ct.POINTER(_ReqStatus)]
+    L.ba_server_cancel.restype = i32
+    L.ba_server_cancel.argtypes = [P, ct.c_int64]
     L.ba_server_destroy.restype = i32
     L.ba_server_destroy.argtypes = [P]
     L.ba_voxelize.restype = i32
@@ -363,13 +365,13 @@ def solve_increment(mode: int, hess, grad, mu: float):
 
 def iterate(problem: Problem, poses, mode: int = MODE_MM, max_iters: int = 10, mu0: float = 1e-2,
             nu0: float = 2.0, tol_g: float = 0.0, trace: bool = True, max_rejects: int = 0,
-            exact_below: float = 0.0):
+            exact_below: float = 0.0, rejects0: int = 0):
     """ba_iterate: LM on the device, poses updated in place.  Synchronous.
     Returns (reports: list of dicts per window, trace ndarray (iters, W, 8) or None)."""
     if not (poses.is_cuda and poses.dtype == torch.float64 and poses.is_contiguous()):
         raise TypeError("poses must be a contiguous float64 device tensor (updated in place)")
     W = problem.info()["n_windows"]
-    o = _LMOpts(int(mode), int(max_iters), float(mu0), float(nu0), float(tol_g), int(max_rejects), 0,
+    o = _LMOpts(int(mode), int(max_iters), float(mu0), float(nu0), float(tol_g), int(max_rejects), int(rejects0),
                 float(exact_below))
     reps = (_LMReport * W)()
     tr = np.zeros((max(int(max_iters), 1), W, 8)) if trace else None
@@ -419,7 +421,7 @@ def autotune(problem, poses, reps: int = 5) -> dict:
     return {k: getattr(t, k) for k, _ in _Tuning._fields_}
 
 
-REQ_QUEUED, REQ_RUNNING, REQ_DONE, REQ_FAILED = 0, 1, 2, 3
+REQ_QUEUED, REQ_RUNNING, REQ_DONE, REQ_FAILED, REQ_CANCELLED = 0, 1, 2, 3, 4
 
 
 def _request(voxel, scan, count, sums, sumsq, n_scans, n_voxels, poses_init):
@@ -455,12 +457,13 @@ class Server:
 
     def __init__(self, hbm_budget: int, slots: int = 4, precision: int = PREC_F64, mode: int = MODE_MM,
                  max_iters: int = 50, tol_g: float = 1e-6, mu0: float = 0.0, nu0: float = 0.0,
-                 max_rejects: int = 10):
+                 max_rejects: int = 10, iters_per_check: int = 0):
         o = _ServerOpts()
         o.hbm_budget = int(hbm_budget)
         o.slots = int(slots)
         o.precision = int(precision)
         o.lm = _LMOpts(int(mode), int(max_iters), float(mu0), float(nu0), float(tol_g), int(max_rejects), 0)
+        o.iters_per_check = int(iters_per_check)
         h = ct.c_void_p()
         _check(load().ba_server_create(ct.byref(o), ct.byref(h)))
         self._h = h
@@ -480,6 +483,22 @@ class Server:
         st = _ReqStatus()
         _check(load().ba_server_query(self._h, int(rid), ct.byref(st)))
         return _status_dict(st)
+
+    def cancel(self, rid: int):
+        """ba_server_cancel: stop request `rid` (queued: at once; running: at its
+        next check).  wait() then raises BAError with status -9."""
+        _check(load().ba_server_cancel(self._h, int(rid)))
+
+    def wait_any(self, rid: int):
+        """Like wait(), but a cancelled request returns (poses reached, status)
+        instead of raising."""
+        poses = np.empty((self._n_scans[rid], 12))
+        st = _ReqStatus()
+        rc = load().ba_server_wait(self._h, int(rid), poses.ctypes.data_as(ct.c_void_p), ct.byref(st))
+        del self._n_scans[rid]
+        if rc not in (0, -9):
+            _check(rc)
+        return poses, _status_dict(st)
 
     def wait(self, rid: int):
         """Block until request `rid` is done: (poses (n_scans, 12), status dict)."""

@@ -131,7 +131,7 @@ namespace ba {
 static ba_status enqueue_lm(Problem *P, double *poses, const ba_lm_options *opt, double *dtrace, double mu0, double nu0,
                             hipStream_t s) {
     const int iters = opt->max_iters;
-    launch_lm_reset(P, mu0, nu0, s);
+    launch_lm_reset(P, mu0, nu0, opt->rejects0, s);
     launch_vox(P, poses, true, false, s);
     launch_lm_cost(P, s);
     for (int it = 0; it < iters; it++) {
@@ -174,7 +174,7 @@ struct IterGraph {
     hipGraphExec_t exec = nullptr;
     // key
     double *poses = nullptr, *trace = nullptr;
-    int32_t mode = -1, iters = -1, tune_gen = -1, max_rejects = 0;
+    int32_t mode = -1, iters = -1, tune_gen = -1, max_rejects = 0, rejects0 = 0;
     double mu0 = 0, nu0 = 0, tol_g = 0, exact_below = 0;
     ~IterGraph() {
         if (exec) (void)hipGraphExecDestroy(exec);
@@ -207,6 +207,7 @@ const char *ba_status_str(ba_status s) {
         case BA_E_NOMEM: return "out of device memory";
         case BA_E_BUDGET: return "request exceeds the device-memory budget";
         case BA_E_NOT_FOUND: return "unknown request";
+        case BA_E_CANCELLED: return "request cancelled";
         default: return "unknown status";
     }
 }
@@ -421,8 +422,8 @@ ba_status ba_iterate(ba_problem *p, double *poses_inout, const ba_lm_options *op
         set_error("unknown mode %d", opt->mode);
         return BA_E_UNSUPPORTED;
     }
-    if (opt->max_iters < 0) {
-        set_error("max_iters < 0");
+    if (opt->max_iters < 0 || opt->rejects0 < 0) {
+        set_error("max_iters < 0 or rejects0 < 0");
         return BA_E_ARG;
     }
     Problem *P = &p->P;
@@ -451,6 +452,7 @@ ba_status ba_iterate(ba_problem *p, double *poses_inout, const ba_lm_options *op
         const bool same = G && G->exec && G->poses == poses_inout && G->trace == dtrace && G->mode == opt->mode &&
                           G->iters == iters && G->mu0 == mu0 && G->nu0 == nu0 && G->tol_g == opt->tol_g &&
                           G->tune_gen == P->tune_gen && G->max_rejects == opt->max_rejects &&
+                          G->rejects0 == opt->rejects0 &&
                           G->exact_below == opt->exact_below;
         if (!same) {
             graph_release(P);
@@ -477,6 +479,7 @@ ba_status ba_iterate(ba_problem *p, double *poses_inout, const ba_lm_options *op
                 G->tol_g = opt->tol_g;
                 G->tune_gen = P->tune_gen;
                 G->max_rejects = opt->max_rejects;
+                G->rejects0 = opt->rejects0;
                 G->exact_below = opt->exact_below;
             } else {
                 graph_release(P);
@@ -499,7 +502,7 @@ ba_status ba_iterate(ba_problem *p, double *poses_inout, const ba_lm_options *op
             rep[w].n_accepted = st[w].n_accepted;
             rep[w].converged = st[w].done == 1;
             rep[w].stalled = st[w].done == 2;
-            rep[w].reserved = 0;
+            rep[w].rejects_final = st[w].rejects;
             rep[w].last_info = st[w].info;
             rep[w].cost_final = st[w].cost;
             rep[w].gnorm_final = st[w].gnorm;

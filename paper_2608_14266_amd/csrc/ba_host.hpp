@@ -34,7 +34,19 @@ struct ProfScope {
     ~ProfScope() { prof_end(s); }
 };
 
-// A set of device allocations released together.
+// A slot-owned block of device memory that allocations of the calling thread
+// are carved from (bump allocation, 256-byte aligned) while it is installed in
+// tl_slot_arena; the owner resets `off` when the work that used it is done.
+// Allocations that do not fit fall through to hipMalloc.
+struct SlotArena {
+    char *base = nullptr;
+    size_t cap = 0;
+    size_t off = 0;
+};
+extern thread_local SlotArena *tl_slot_arena;
+
+// A set of device allocations released together (memory carved from an
+// installed slot arena is returned by the arena's owner, not here).
 struct DevArena {
     std::vector<void *> ptrs;
     size_t bytes = 0;
@@ -50,6 +62,15 @@ struct DevArena {
     template <class T>
     ba_status alloc(T **p, int64_t count) {
         size_t nb = sizeof(T) * (size_t)(count > 0 ? count : 1);
+        if (SlotArena *a = tl_slot_arena) {
+            const size_t nba = (nb + 255) / 256 * 256;
+            if (a->off + nba <= a->cap) {
+                *p = (T *)(a->base + a->off);
+                a->off += nba;
+                bytes += nb;
+                return BA_OK;
+            }
+        }
         void *q = nullptr;
         hipError_t e = hipMalloc(&q, nb);
         if (e != hipSuccess) {

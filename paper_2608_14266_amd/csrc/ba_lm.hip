@@ -91,7 +91,7 @@ __device__ __forceinline__ int solve_pose(const double *__restrict__ h, const do
     return 0;
 }
 
-__global__ void k_lm_reset(int32_t W, LMState *__restrict__ lm, double mu0, double nu0,
+__global__ void k_lm_reset(int32_t W, LMState *__restrict__ lm, double mu0, double nu0, int32_t rejects0,
                            const int32_t *__restrict__ win_group_ptr) {
     const int w = blockIdx.x * blockDim.x + threadIdx.x;
     if (w >= W) return;
@@ -100,7 +100,7 @@ __global__ void k_lm_reset(int32_t W, LMState *__restrict__ lm, double mu0, doub
     s.gnorm = 0.0; s.maxdiag = 0.0; s.cost0 = 0.0;
     s.accepted = 0; s.need_eval = 1; s.info = 0;
     s.done = (win_group_ptr[w + 1] == win_group_ptr[w]) ? 1 : 0;   // a window without voxels has nothing to do
-    s.iters = 0; s.n_accepted = 0; s.cur = 0; s.rejects = 0;
+    s.iters = 0; s.n_accepted = 0; s.cur = 0; s.rejects = rejects0;
     lm[w] = s;
 }
 
@@ -362,8 +362,8 @@ void launch_solve_mm_plain(int32_t n, const double *H, const double *g, double m
     hipLaunchKernelGGL(k_solve_finish, dim3(1), dim3(256), 0, s, n, infos, dx, info);
 }
 
-void launch_lm_reset(Problem *P, double mu0, double nu0, hipStream_t s) {
-    hipLaunchKernelGGL(k_lm_reset, dim3(nblk(P->n_windows)), dim3(256), 0, s, P->n_windows, P->lm, mu0, nu0,
+void launch_lm_reset(Problem *P, double mu0, double nu0, int32_t rejects0, hipStream_t s) {
+    hipLaunchKernelGGL(k_lm_reset, dim3(nblk(P->n_windows)), dim3(256), 0, s, P->n_windows, P->lm, mu0, nu0, rejects0,
                        P->win_group_ptr);
 }
 

@@ -8,9 +8,19 @@
 // problem.  Slots run concurrently, so requests that arrive while others
 // iterate start as soon as a slot and memory are free and their kernels
 // overlap on the device with the running ones.
+//
+// Each slot keeps one device block (a slot arena, at most budget / slots
+// bytes) that a request's build and LM buffers are carved from; it grows to
+// the largest request the slot has served, so a steady request stream does
+// no device allocation or release (hipFree synchronises the whole device).
+// The LM runs in chunks of iters_per_check iterations, each resuming the last
+// exactly (damping, damping growth and rejection count carried over), so a
+// cancelled request stops at the next chunk boundary while the results of
+// uncancelled ones are those of one uninterrupted run.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <condition_variable>
 #include <cstring>
@@ -38,6 +48,7 @@ struct Request {
     int64_t footprint = 0;
     ba_request_status st{};
     std::string error;   // text of a failure, handed to the waiting thread
+    std::atomic<bool> cancel{false};
 };
 
 struct Server {
@@ -90,8 +101,48 @@ static ba_status validate_request(const ba_request *r) {
     return BA_OK;
 }
 
+// The LM of one request in chunks of opt.iters_per_check iterations, each
+// resuming the previous one exactly; stops early once the request is
+// cancelled, converged or stalled.  `rep` receives the whole run's report.
+static ba_status run_lm_chunked(Server *S, Request &R, ba_problem *p, double *d_poses, ba_lm_report &rep,
+                                bool &cancelled, hipStream_t stream) {
+    ba_lm_options o = S->opt.lm;
+    const int chunk = S->opt.iters_per_check > 0 ? S->opt.iters_per_check : 10;
+    int left = o.max_iters;
+    bool first = true;
+    std::memset(&rep, 0, sizeof(rep));
+    cancelled = false;
+    while (left > 0) {
+        if (R.cancel.load()) {
+            cancelled = true;
+            break;
+        }
+        o.max_iters = std::min(chunk, left);
+        ba_lm_report r{};
+        BA_TRY(ba_iterate(p, d_poses, &o, &r, nullptr, stream));
+        if (first) rep.cost_initial = r.cost_initial;
+        first = false;
+        rep.iters += r.iters;
+        rep.n_accepted += r.n_accepted;
+        rep.converged = r.converged;
+        rep.stalled = r.stalled;
+        rep.last_info = r.last_info;
+        rep.cost_final = r.cost_final;
+        rep.gnorm_final = r.gnorm_final;
+        rep.mu_final = r.mu_final;
+        rep.nu_final = r.nu_final;
+        rep.rejects_final = r.rejects_final;
+        if (r.converged || r.stalled || r.iters < o.max_iters) break;
+        left -= r.iters;
+        o.mu0 = r.mu_final;
+        o.nu0 = r.nu_final;
+        o.rejects0 = r.rejects_final;
+    }
+    return BA_OK;
+}
+
 // One request, start to finish, on `stream`.
-static ba_status run_request(Server *S, Request &R, hipStream_t stream) {
+static ba_status run_request(Server *S, Request &R, hipStream_t stream, bool &cancelled) {
     const int64_t n = R.n;
     DevArena in;
     int32_t *d_vox, *d_scan;
@@ -127,7 +178,7 @@ static ba_status run_request(Server *S, Request &R, hipStream_t stream) {
     std::unique_ptr<ba_problem> own(p);
     p->P.no_graph = true;   // one-shot problem: launch eagerly rather than capture
     ba_lm_report rep{};
-    ba_status st = ba_iterate(p, d_poses, &S->opt.lm, &rep, nullptr, stream);
+    ba_status st = run_lm_chunked(S, R, p, d_poses, rep, cancelled, stream);
     if (st == BA_OK) {
         R.st.report = rep;
         hipError_t e = hipMemcpyAsync(R.poses.data(), d_poses, sizeof(double) * 12 * R.n_scans,
@@ -142,10 +193,28 @@ static ba_status run_request(Server *S, Request &R, hipStream_t stream) {
     return st;
 }
 
+// Grows the slot's arena to hold a request of `need` bytes (never beyond the
+// slot's share of the budget; larger requests allocate directly).
+static void arena_reserve(Server *S, SlotArena &a, int64_t need) {
+    const int64_t share = S->opt.hbm_budget / S->opt.slots;
+    if ((int64_t)a.cap >= need || need > share) return;
+    if (a.base) (void)hipFree(a.base);
+    a.base = nullptr;
+    a.cap = 0;
+    void *q = nullptr;
+    if (hipMalloc(&q, (size_t)need) == hipSuccess) {
+        a.base = (char *)q;
+        a.cap = (size_t)need;
+    } else {
+        (void)hipGetLastError();   // this request allocates directly instead
+    }
+}
+
 static void slot_main(Server *S) {
     (void)hipSetDevice(S->device);
     hipStream_t stream = nullptr;
     const bool have_stream = hipStreamCreateWithFlags(&stream, hipStreamNonBlocking) == hipSuccess;
+    SlotArena arena;
     for (;;) {
         std::shared_ptr<Request> R;
         {
@@ -162,14 +231,23 @@ static void slot_main(Server *S) {
             R->st.t_admit = S->now();
         }
         S->cv.notify_all();   // the next head may fit too
-        ba_status st = have_stream ? run_request(S, *R, stream) : BA_E_HIP;
+        bool cancelled = false;
+        ba_status st = BA_E_HIP;
+        if (have_stream) {
+            arena_reserve(S, arena, R->footprint);
+            arena.off = 0;
+            tl_slot_arena = arena.base ? &arena : nullptr;
+            st = run_request(S, *R, stream, cancelled);
+            tl_slot_arena = nullptr;
+            arena.off = 0;   // the request's problem is released: the stream has drained
+        }
         const std::string err = st == BA_OK ? std::string() : std::string(ba_last_error());
         {
             std::lock_guard<std::mutex> lk(S->mu);
             R->error = err;
             S->reserved -= R->footprint;
-            R->st.status = st;
-            R->st.state = st == BA_OK ? BA_REQ_DONE : BA_REQ_FAILED;
+            R->st.status = cancelled ? BA_E_CANCELLED : st;
+            R->st.state = cancelled ? BA_REQ_CANCELLED : (st == BA_OK ? BA_REQ_DONE : BA_REQ_FAILED);
             R->st.t_done = S->now();
             // the request's input copies are no longer needed
             std::vector<int32_t>().swap(R->voxel);
@@ -181,7 +259,10 @@ static void slot_main(Server *S) {
         S->cv.notify_all();
     }
     if (have_stream) (void)hipStreamDestroy(stream);
+    if (arena.base) (void)hipFree(arena.base);
 }
+
+thread_local SlotArena *tl_slot_arena = nullptr;
 
 }  // namespace ba
 
@@ -204,7 +285,7 @@ ba_status ba_request_footprint(const ba_request *req, int32_t mode, int32_t prec
 
 ba_status ba_server_create(const ba_server_options *opt, ba_server **out) {
     using namespace ba;
-    if (!opt || !out || opt->hbm_budget <= 0 || opt->slots < 1 || opt->slots > 64 ||
+    if (!opt || !out || opt->hbm_budget <= 0 || opt->slots < 1 || opt->slots > 64 || opt->iters_per_check < 0 ||
         (opt->precision != BA_PREC_F64 && opt->precision != BA_PREC_F32) ||
         (opt->lm.mode != BA_MODE_MM && opt->lm.mode != BA_MODE_COUPLED) || opt->lm.max_iters < 1) {
         set_error("invalid server options");
@@ -317,18 +398,56 @@ ba_status ba_server_wait(ba_server *s, int64_t id, double *poses_out, ba_request
         return BA_E_NOT_FOUND;
     }
     std::shared_ptr<Request> R = it->second;
-    S->cv.wait(lk, [&] { return R->st.state == BA_REQ_DONE || R->st.state == BA_REQ_FAILED || S->stopping; });
-    if (R->st.state != BA_REQ_DONE && R->st.state != BA_REQ_FAILED) {
+    auto finished = [&] {
+        return R->st.state == BA_REQ_DONE || R->st.state == BA_REQ_FAILED || R->st.state == BA_REQ_CANCELLED;
+    };
+    S->cv.wait(lk, [&] { return finished() || S->stopping; });
+    if (!finished()) {
         set_error("server stopped before request %lld ran", (long long)id);
         return BA_E_ARG;
     }
-    if (poses_out && R->st.state == BA_REQ_DONE)
+    if (poses_out && (R->st.state == BA_REQ_DONE || R->st.state == BA_REQ_CANCELLED))
         std::memcpy(poses_out, R->poses.data(), sizeof(double) * R->poses.size());
     if (st) *st = R->st;
     S->all.erase(it);
     if (R->st.state == BA_REQ_DONE) return BA_OK;
+    if (R->st.state == BA_REQ_CANCELLED) {
+        set_error("request %lld was cancelled", (long long)id);
+        return BA_E_CANCELLED;
+    }
     set_error("served request %lld failed: %s", (long long)id, R->error.c_str());
     return R->st.status;
+}
+
+ba_status ba_server_cancel(ba_server *s, int64_t id) {
+    using namespace ba;
+    if (!s) {
+        set_error("null server");
+        return BA_E_ARG;
+    }
+    Server *S = &s->S;
+    {
+        std::lock_guard<std::mutex> lk(S->mu);
+        auto it = S->all.find(id);
+        if (it == S->all.end()) {
+            set_error("unknown request %lld", (long long)id);
+            return BA_E_NOT_FOUND;
+        }
+        std::shared_ptr<Request> R = it->second;
+        R->cancel.store(true);
+        if (R->st.state == BA_REQ_QUEUED) {
+            for (auto q = S->queue.begin(); q != S->queue.end(); ++q)
+                if ((*q)->id == id) {
+                    S->queue.erase(q);
+                    break;
+                }
+            R->st.state = BA_REQ_CANCELLED;
+            R->st.status = BA_E_CANCELLED;
+            R->st.t_done = S->now();
+        }
+    }
+    S->cv.notify_all();
+    return BA_OK;
 }
 
 ba_status ba_server_destroy(ba_server *s) {

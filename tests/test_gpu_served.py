@@ -158,3 +158,61 @@ def test_unknown_request_id(ba, dev):
         with pytest.raises(ba.BAError) as e:
             srv.query(12345)
         assert e.value.status == -8
+
+
+def test_chunked_lm_does_not_change_results(ba, dev, requests):
+    """The served LM runs in chunks of iters_per_check iterations that resume
+    each other exactly: every chunk length gives the same bits."""
+    say("served chunk lengths")
+    outs = []
+    for k in (1, 3, 0):
+        res = _serve(ba, requests[:3], 2, 8 * GB, max_iters=12, tol_g=1e-6, max_rejects=3, iters_per_check=k)
+        outs.append(res)
+    for res in outs[1:]:
+        for (pa, sa), (pb, sb) in zip(outs[0], res):
+            assert np.array_equal(pa, pb)
+            assert sa["report"] == sb["report"]
+
+
+def test_cancel_leaves_the_other_requests_unchanged(ba, dev, requests):
+    """Cancelling a running request (mid-run) and a queued one: both end
+    cancelled; every other request's poses and report are bitwise those it
+    gets served alone."""
+    import time
+    say("served cancel")
+    kw = dict(max_iters=400, tol_g=0.0, max_rejects=0, iters_per_check=1)
+    long_kw = dict(kw, max_iters=4000)
+    long_req = ss.request_scene(seed=5100, n_poses=300, vox_per_pose=60)
+    others = requests[:4]
+    # the long request's server runs 4000 iterations per request; the others
+    # are compared with their own 400-iteration runs alone, so they are served
+    # by a second server at the same time (both share the GPU)
+    with ba.Server(8 * GB, slots=1, **long_kw) as srv_long, ba.Server(8 * GB, slots=2, **kw) as srv:
+        rid_long = srv_long.submit_scene(long_req)
+        ids = [srv.submit_scene(r) for r in others]
+        rid_queued = srv.submit_scene(requests[4])
+        # the queued one: cancelled before any slot takes it
+        srv.cancel(rid_queued)
+        t0 = time.time()
+        while srv_long.query(rid_long)["state"] != ba._lib.REQ_RUNNING and time.time() - t0 < 60:
+            time.sleep(0.001)
+        time.sleep(0.2)   # let it run a number of iterations first
+        srv_long.cancel(rid_long)
+        P_long, st_long = srv_long.wait_any(rid_long)
+        P_q, st_q = srv.wait_any(rid_queued)
+        res = [srv.wait(i) for i in ids]
+    assert st_q["state"] == ba._lib.REQ_CANCELLED and st_q["report"]["iters"] == 0
+    assert np.array_equal(P_q, requests[4].poses_init)
+    assert st_long["state"] == ba._lib.REQ_CANCELLED
+    assert 0 < st_long["report"]["iters"] < long_kw["max_iters"]
+    assert st_long["report"]["cost_final"] < st_long["report"]["cost_initial"]
+    print(f"  cancelled the long request after {st_long['report']['iters']} iterations")
+    alone = [_serve(ba, [r], 1, 8 * GB, **kw)[0] for r in others]
+    for (pa, sa), (pm, sm) in zip(alone, res):
+        assert sm["state"] == ba._lib.REQ_DONE
+        assert np.array_equal(pa, pm)
+        assert sa["report"] == sm["report"]
+    with ba.Server(GB, slots=1) as srv:
+        with pytest.raises(ba.BAError) as e:
+            srv.cancel(777)
+        assert e.value.status == -8
