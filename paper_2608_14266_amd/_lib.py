@@ -335,12 +335,24 @@ def solve_increment_workspace(mode: int, n_scans: int) -> int:
     return int(load().ba_solve_increment_workspace(int(mode), int(n_scans)))
 
 
+def _solve_scans(mode: int, hess, grad) -> int:
+    """Number of scans of an increment solve, checked against both operands:
+    grad holds 6 N values, hess N 6x6 blocks (MM) or the (6N)^2 matrix."""
+    if grad.numel() == 0 or grad.numel() % 6:
+        raise ValueError(f"grad must hold 6 values per scan, got {grad.numel()}")
+    N = grad.numel() // 6
+    want = 36 * N if int(mode) == MODE_MM else (6 * N) ** 2
+    if hess.numel() != want:
+        raise ValueError(f"hess must hold {want} values for {N} scans in mode {int(mode)}, got {hess.numel()}")
+    return N
+
+
 def solve_increment_noalloc(mode: int, hess, grad, mu: float):
     """ba_solve_increment_noalloc: the same solve with the library's static
     device scratch as workspace (no device allocation by the library).
     Returns (dx (N,6), info (int32 device scalar))."""
     hess = _dev(hess, torch.float64, "hess"); grad = _dev(grad, torch.float64, "grad")
-    N = grad.numel() // 6
+    N = _solve_scans(mode, hess, grad)
     dev = grad.device
     dx = torch.empty((N, 6), dtype=torch.float64, device=dev)
     info = torch.empty(1, dtype=torch.int32, device=dev)
@@ -352,7 +364,7 @@ def solve_increment_noalloc(mode: int, hess, grad, mu: float):
 def solve_increment(mode: int, hess, grad, mu: float):
     """ba_solve_increment: returns (dx (N,6), info (int32 device scalar))."""
     hess = _dev(hess, torch.float64, "hess"); grad = _dev(grad, torch.float64, "grad")
-    N = grad.numel() // 6
+    N = _solve_scans(mode, hess, grad)
     dev = grad.device
     dx = torch.empty((N, 6), dtype=torch.float64, device=dev)
     info = torch.empty(1, dtype=torch.int32, device=dev)

@@ -391,20 +391,21 @@ __global__ void k_damp_copy(const DenseDesc *__restrict__ desc, const DenseParam
     if (t < d.n) work[d.v_off + t] = -g[6LL * d.pose0 + t];
 }
 
-// Broadcast lane `src` (compile-time) of a wave-wide double to every lane.
+// Broadcast lane `src` (wave-uniform) of a wave-wide double to every lane.
 __device__ __forceinline__ double bcast(double v, int src) {
     const int lo = __builtin_amdgcn_readlane(__double2loint(v), src);
     const int hi = __builtin_amdgcn_readlane(__double2hiint(v), src);
     return __hiloint2double(hi, lo);
 }
 
-// 1/sqrt(p): the hardware estimate refined by two Newton steps
-// r <- r (3 - p r^2) / 2 (about 1 ulp for a positive normal p).
+// 1/sqrt(p): the hardware estimate (about 23 bits) refined by one third-order
+// step.  With e = 1 - p r^2, 1/sqrt(p) = r (1 - e)^(-1/2) = r (1 + e/2 + 3e^2/8
+// + ...); the dropped terms are below 2^-66, so the result is within about
+// one ulp.
 __device__ __forceinline__ double rsq_refined(double p) {
-    double r = __builtin_amdgcn_rsq(p);
-    r = r * fma(-0.5 * p * r, r, 1.5);
-    r = r * fma(-0.5 * p * r, r, 1.5);
-    return r;
+    const double r = __builtin_amdgcn_rsq(p);
+    const double e = fma(-p * r, r, 1.0);
+    return fma(r * e, fma(e, 0.375, 0.5), r);
 }
 
 // Orders this lane's LDS writes before the other lanes' later reads within
@@ -415,117 +416,295 @@ __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+static constexpr int LTS = TB + 1;   // padded LDS row stride of the tile and the inverse
+static constexpr int PB = 16;        // panel / block width inside the diagonal block
+static constexpr int NPB = TB / PB;  // panels per diagonal block
+
+// One 16 x 16 x 16 product on matrix cores for the calling wave:
+// acc0 + acc1 += sgn * A B with A and B 16 x 16 blocks (row stride LTS) in
+// LDS, the K steps alternating between the two accumulators so that two
+// product chains are in flight; accumulator register r holds row lane/16 + 4r,
+// column lane%16 (the v_mfma_f64_16x16x4f64 layout).
+__device__ __forceinline__ void mma16(const double *__restrict__ Ab, const double *__restrict__ Bb, double sgn,
+                                      d4 &acc0, d4 &acc1) {
+    const int l = threadIdx.x & 63, li = l & 15, lk = l >> 4;
+#pragma unroll
+    for (int kk = 0; kk < PB; kk += 8) {
+        const double a0 = sgn * Ab[li * LTS + kk + lk], b0 = Bb[(kk + lk) * LTS + li];
+        const double a1 = sgn * Ab[li * LTS + kk + 4 + lk], b1 = Bb[(kk + 4 + lk) * LTS + li];
+        acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc0, 0, 0, 0);
+        acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc1, 0, 0, 0);
+    }
+}
+
+// The same with B given transposed: acc0 + acc1 += sgn * A C^T for 16 x 16
+// blocks A and C (row stride LTS) in LDS.
+__device__ __forceinline__ void mma16_nt(const double *__restrict__ Ab, const double *__restrict__ Cb, double sgn,
+                                         d4 &acc0, d4 &acc1) {
+    const int l = threadIdx.x & 63, li = l & 15, lk = l >> 4;
+#pragma unroll
+    for (int kk = 0; kk < PB; kk += 8) {
+        const double a0 = sgn * Ab[li * LTS + kk + lk], b0 = Cb[li * LTS + kk + lk];
+        const double a1 = sgn * Ab[li * LTS + kk + 4 + lk], b1 = Cb[li * LTS + kk + 4 + lk];
+        acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc0, 0, 0, 0);
+        acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc1, 0, 0, 0);
+    }
+}
+
+// X_qq = L_qq^-1 for the 16 x 16 diagonal block q of the factor in T, by one
+// wave: lane c < 16 solves L_qq x = e_c by forward substitution, taking
+// 1/L_rr from rd; the entries of column r + 1 are read from LDS while column
+// r is applied.
+__device__ __forceinline__ void inverse_diag_block(const double *__restrict__ T, double *__restrict__ X,
+                                                   const double *__restrict__ rd, int q) {
+    const int l = threadIdx.x & 63, c = l & 15;
+    const int b0 = PB * q;
+    double rdv[PB];
+#pragma unroll
+    for (int r = 0; r < PB; r++) rdv[r] = rd[b0 + r];
+    double x[PB];
+#pragma unroll
+    for (int r = 0; r < PB; r++) x[r] = (r == c) ? 1.0 : 0.0;
+    double lc[PB];
+#pragma unroll
+    for (int s = 1; s < PB; s++) lc[s] = T[(b0 + s) * LTS + b0];
+#pragma unroll
+    for (int r = 0; r < PB; r++) {
+        double ln[PB];
+        if (r + 1 < PB) {
+#pragma unroll
+            for (int s = r + 2; s < PB; s++) ln[s] = T[(b0 + s) * LTS + b0 + r + 1];
+        }
+        x[r] *= rdv[r];
+#pragma unroll
+        for (int s = r + 1; s < PB; s++) x[s] = fma(-lc[s], x[r], x[s]);
+        if (r + 1 < PB) {
+#pragma unroll
+            for (int s = r + 2; s < PB; s++) lc[s] = ln[s];
+        }
+    }
+    if (l < PB) {
+#pragma unroll
+        for (int r = 0; r < PB; r++) X[(b0 + r) * LTS + b0 + l] = x[r];
+    }
+}
+
+// X_qj = -X_qq sum_{k=j}^{q-1} L_qk X_kj for the column blocks j in [jb, je)
+// of row block q, by one wave on matrix cores (X_qq and the row blocks of X
+// above q must be complete).
+__device__ __forceinline__ void inverse_off_blocks(const double *__restrict__ T, double *__restrict__ X, int q,
+                                                   int jb, int je) {
+    const int l = threadIdx.x & 63, li = l & 15, lk = l >> 4;
+    const int b0 = PB * q;
+    for (int j = jb; j < je; j++) {
+        d4 s0 = {0.0, 0.0, 0.0, 0.0}, s1 = s0;
+        for (int k = j; k < q; k++) mma16(T + b0 * LTS + PB * k, X + PB * k * LTS + PB * j, 1.0, s0, s1);
+        // the accumulator of S is already in the B operand layout
+        const d4 s = s0 + s1;
+        d4 o0 = {0.0, 0.0, 0.0, 0.0}, o1 = o0;
+#pragma unroll
+        for (int r = 0; r < 4; r += 2) {
+            const double a0 = -X[(b0 + li) * LTS + b0 + 4 * r + lk];
+            const double a1 = -X[(b0 + li) * LTS + b0 + 4 * r + 4 + lk];
+            o0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, s[r], o0, 0, 0, 0);
+            o1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, s[r + 1], o1, 0, 0, 0);
+        }
+        const d4 o = o0 + o1;
+#pragma unroll
+        for (int r = 0; r < 4; r++) X[(b0 + lk + 4 * r) * LTS + PB * j + li] = o[r];
+    }
+}
+
+// Store, by one wave, the finished columns of panel pp (the lower triangle of
+// the nb x nb block within them) and the panel's rows of the forward result.
+__device__ __forceinline__ void write_panel_L(const double *__restrict__ T, const double *__restrict__ yv,
+                                              double *__restrict__ A, double *__restrict__ y, int64_t n, int64_t k0,
+                                              int nb, int pp, int lane) {
+    const int c = PB * pp + (lane & 15);
+#pragma unroll 4
+    for (int r = PB * pp + (lane >> 4); r < nb; r += 4)
+        if (c <= r) A[(k0 + r) * n + k0 + c] = T[r * LTS + c];
+    if (lane < PB && PB * pp + lane < nb) y[PB * pp + lane] = yv[PB * pp + lane];
+}
+
+// Store, by one wave, row block q of the inverse (64 columns, zero above the
+// diagonal block).
+__device__ __forceinline__ void write_inverse_rows(const double *__restrict__ X, double *__restrict__ linv, int q,
+                                                   int lane) {
+#pragma unroll
+    for (int r = PB * q; r < PB * (q + 1); r++)
+        linv[r * TB + lane] = (lane < PB * (q + 1)) ? X[r * LTS + lane] : 0.0;
+}
+
 // Factor diagonal block `step` (A_kk = L L^T), forward-substitute its slice of
-// the right-hand side (y = L^-1 b) and invert the factor (X = L^-1), with two
-// wavefronts working one chunk of POTF2_CHUNK steps apart.
-//  - wave 0, right-looking factorization: lane i holds row i of the tile in
-//    registers; step j scales column j, publishes it as row j of `lt` in LDS
-//    (lt[j][r] = L_rj) and updates the columns to its right from there (the
-//    row is read into registers in one burst before the FMAs, so the LDS
-//    latency is paid once per step rather than once per few columns).  The
-//    next pivot is formed from the lane's own entries and broadcast as a
-//    scalar, so it does not wait for the LDS round trip.  Entries above the
-//    diagonal (c > i) are never read, so updates run on all lanes unmasked.
-//    1/sqrt(pivot) comes from the hardware estimate refined by two Newton
-//    steps r <- r (3 - p r^2) / 2 (about 1 ulp).  y rides along in a register.
-//  - wave 1, inverse: lane c solves L x = e_c for column c of X, right-looking,
-//    reading each column of L from `lt` once wave 0 has published it.
-// A workgroup barrier separates the chunks; within wave 0 the column it
-// publishes is read back after a wavefront-level fence.  A pivot that is not
-// a positive normal number stops the factorization (prm.info = its index + 1).
-static constexpr int LTS = TB + 1;        // padded LDS row stride of the published columns
-static constexpr int POTF2_CHUNK = 8;     // factor steps between the two waves' barriers
-__global__ __launch_bounds__(128) void k_potf2(const DenseDesc *__restrict__ desc, DenseParam *__restrict__ prm,
+// the right-hand side (y = L^-1 b) and invert the factor (X = L^-1), with four
+// wavefronts and the tile held in LDS, blocked by 16 x 16 blocks:
+//  - factorization, right-looking by 16-column panels.  Wave 0 factors a
+//    panel with lane r holding row r's 16 panel entries in registers.  The
+//    pivot's column is taken from row pr of lane pr (the panel's diagonal
+//    block is read symmetrically from the lower triangle), broadcast through
+//    scalar registers in one batch per pivot, and the next pivot is formed
+//    from broadcast values as soon as 1/sqrt of the current one is known.  The
+//    update of a row uses w_r = L_r,pr / L_pr,pr against the unscaled pivot
+//    row (one fma per entry); the right-hand side is carried the same way and
+//    scaled once at the end of the panel.  Then the panel's rank-16 update of
+//    the trailing blocks runs on matrix cores (one 16 x 16 block per wave at a
+//    time);
+//  - inverse, by 16 x 16 blocks, one and two panels behind the factorization:
+//    while wave 0 factors panel p, wave 1 inverts diagonal block p - 1 and
+//    wave 2 forms the off-diagonal blocks of row block p - 2 on matrix cores
+//    (X_qj = -X_qq sum_k L_qk X_kj); what is left follows the last panel;
+//  - finished panels, right-hand side rows and inverse row blocks are stored
+//    by wave 3 while the factorization goes on.
+// Only the lower triangle of the tile is read; the 16 x 16 diagonal blocks are
+// mirrored in LDS and kept in both triangles by the trailing updates, so a
+// panel reads its rows straight from the tile.
+// A pivot that is not a positive normal number stops the factorization
+// (prm.info = its index + 1); the panels stored before it are left in the
+// work buffer, which no later kernel reads once info is set.
+__global__ __launch_bounds__(256) void k_potf2(const DenseDesc *__restrict__ desc, DenseParam *__restrict__ prm,
                                                double *__restrict__ work, int step) {
-    __shared__ __align__(16) double rdiag[TB];
-    __shared__ __align__(16) double lt[TB * LTS];
+    __shared__ __align__(16) double T[TB * LTS];
+    __shared__ __align__(16) double X[TB * LTS];
+    __shared__ double yv[TB];
+    __shared__ double rdiag[TB];
+    __shared__ double pvs[TB];
     __shared__ int sfail;
     const int m = blockIdx.y;
+    const DenseParam pm = prm[m];
     const DenseDesc d = desc[m];
-    if (!prm[m].active || prm[m].info) return;
+    if (!pm.active || pm.info) return;
     const int64_t k0 = (int64_t)TB * step;
     if (k0 >= d.n) return;
     const int nb = (int)std::min<int64_t>(TB, d.n - k0);
     double *A = work + d.a_off;
-    const int w = threadIdx.x >> 6;
-    const int i = threadIdx.x & 63;
-    // wave 0: a = row i of the tile (identity outside the nb x nb block);
-    // wave 1: a = column i of the identity, turned into column i of X
-    double a[TB];
-    double bi = 0.0;
-    if (w == 0) {
+    const int t = threadIdx.x;
+    const int w = t >> 6;
+    const int i = t & 63;
+    {   // the tile (identity outside the nb x nb block); only its lower
+        // triangle is used: inside the 16 x 16 diagonal blocks it is mirrored
+        // into the upper one.  The loads are unconditional from a clamped
+        // in-bounds address so that all of them are in flight at once; stores
+        // with nothing to write go to the unused padding column.
+        double v[TB / 4];
+        const int ci = std::min(i, nb - 1);
 #pragma unroll
-        for (int c = 0; c < TB; c++)
-            a[c] = (i < nb && c < nb) ? A[(k0 + i) * d.n + k0 + c] : (i == c ? 1.0 : 0.0);
-        bi = (i < nb) ? work[d.v_off + k0 + i] : 0.0;
-    } else {
+        for (int u = 0; u < TB / 4; u++) {
+            const int r = std::min(w + 4 * u, nb - 1);
+            v[u] = A[(k0 + r) * d.n + k0 + ci];
+        }
 #pragma unroll
-        for (int r = 0; r < TB; r++) a[r] = (r == i) ? 1.0 : 0.0;
+        for (int u = 0; u < TB / 4; u++) {
+            const int r = w + 4 * u;
+            const double e = (r < nb && i < nb) ? v[u] : (r == i ? 1.0 : 0.0);
+            const bool same = (r / PB) == (i / PB);
+            T[(i > r && same) ? r * LTS + TB : r * LTS + i] = e;
+            T[(i < r && same) ? i * LTS + r : r * LTS + TB] = e;
+        }
     }
-    if (threadIdx.x == 0) sfail = 0;
+    if (t < TB) yv[t] = work[d.v_off + k0 + std::min(t, nb - 1)] * (t < nb ? 1.0 : 0.0);
+    if (t == 0) sfail = 0;
     __syncthreads();
-    double p = bcast(a[0], 0);
-    double rn = rsq_refined(p);   // 1/sqrt of the next pivot, formed a step ahead
-    int fail = 0, stop = 0;
+#pragma unroll 1
+    for (int p = 0; p < NPB; p++) {
+        const int c0 = PB * p;
+        if (w == 0) {
+            // row i of the panel (the diagonal blocks are kept in both triangles)
+            double a[PB];
 #pragma unroll
-    for (int j = 0; j < TB + POTF2_CHUNK; j++) {
-        if (stop) continue;
-        if (w == 0 && j < TB && !fail) {
-            if (!(p >= 2.2250738585072014e-308)) {
-                fail = (int)(k0 + j + 1);
-            } else {
-                const double rj = rn;
-                const double dj = p * rj;
-                a[j] = (i == j) ? dj : a[j] * rj;
-                if (j + 1 < TB) p = bcast(fma(-a[j], a[j], a[j + 1]), j + 1);
-                const double yj = bcast(bi, j) * rj;
-                if (i > j) bi = fma(-a[j], yj, bi);
-                else if (i == j) bi = yj;
-                lt[j * LTS + i] = a[j];
-                if (i == 0) rdiag[j] = rj;
-                if (j + 1 < TB) {
-                    wave_sync();
-                    double l[TB];
+            for (int k = 0; k < PB; k++) a[k] = T[i * LTS + c0 + k];
+            double bi = yv[i];
+            double pv = bcast(a[0], c0);
+            double s[PB];
 #pragma unroll
-                    for (int c = j + 1; c < TB; c++) l[c] = lt[j * LTS + c];
+            for (int k = 1; k < PB; k++) s[k] = bcast(a[k], c0);
+            double dn = bcast(a[1], c0 + 1);
+            double bpr = bcast(bi, c0);
 #pragma unroll
-                    for (int c = j + 1; c < TB; c++) a[c] = fma(-a[j], l[c], a[c]);
-                    // the next step's reciprocal square root, free to interleave
-                    // with this step's updates
-                    rn = rsq_refined(p);
+            for (int j = 0; j < PB; j++) {
+                const int pr = c0 + j;
+                const double rj = rsq_refined(pv);
+                double pv_next = 0.0;
+                if (j + 1 < PB) pv_next = fma(-(s[j + 1] * rj) * rj, s[j + 1], dn);
+                const double lij = (i == pr) ? pv * rj : a[j] * rj;
+                const double wv = (i > pr) ? lij * rj : 0.0;
+                a[j] = lij;
+#pragma unroll
+                for (int k = j + 1; k < PB; k++) a[k] = fma(-wv, s[k], a[k]);
+                bi = fma(-wv, bpr, bi);
+                // rows above pr land in the unused upper triangle
+                T[i * LTS + pr] = lij;
+                rdiag[pr] = rj;
+                pvs[pr] = pv;
+                if (j + 1 < PB) {
+#pragma unroll
+                    for (int k = j + 2; k < PB; k++) s[k] = bcast(a[k], pr + 1);
+                    if (j + 2 < PB) dn = bcast(a[j + 2], pr + 2);
+                    bpr = bcast(bi, pr + 1);
+                    pv = pv_next;
                 }
             }
+            wave_sync();
+            // the panel's pivots checked at once; rows of the panel get
+            // y = residual / L_ii, the rows below keep their residual
+            const double pl = pvs[c0 + (i & 15)];
+            const bool bad = (i < PB) && !(pl >= 2.2250738585072014e-308 && pl <= 1.7976931348623157e308);
+            const unsigned long long bm = __ballot(bad);
+            if (i == 0 && bm) sfail = (int)(k0 + c0 + __builtin_ctzll(bm) + 1);
+            if (i >= c0) yv[i] = (i < c0 + PB) ? bi * rdiag[i] : bi;
+        } else if (w == 1 && p >= 1) {
+            inverse_diag_block(T, X, rdiag, p - 1);
+        } else if (w == 2 && p >= 2) {
+            inverse_off_blocks(T, X, p - 2, 0, p - 2);
+        } else if (w == 3 && p >= 1) {
+            // finished parts go out while the factorization continues: the
+            // columns and right-hand side rows of the previous panel, and the
+            // row block of the inverse completed two panels ago
+            write_panel_L(T, yv, A, work + d.v_off + k0, d.n, k0, nb, p - 1, i);
+            if (p >= 3) write_inverse_rows(X, work + d.linv_off + (int64_t)step * TB * TB, p - 3, i);
         }
-        if (w == 1 && j >= POTF2_CHUNK) {
-            const int r = j - POTF2_CHUNK;
-            a[r] *= rdiag[r];
-            double l[TB];
+        __syncthreads();
+        if (sfail) {
+            if (t == 0 && sfail <= d.n) prm[m].info = sfail;
+            return;
+        }
+        // rank-16 update of the trailing blocks (I >= J > p) on matrix cores
+        const int nt = NPB - 1 - p;
+        const int nblk = nt * (nt + 1) / 2;
+        for (int b = w; b < nblk; b += 4) {
+            int bi_ = 0;
+            while ((bi_ + 1) * (bi_ + 2) / 2 <= b) bi_++;
+            const int bj = b - bi_ * (bi_ + 1) / 2;
+            const int R = c0 + PB * (1 + bi_), Cc = c0 + PB * (1 + bj);
+            const int li = i & 15, lk = i >> 4;
+            d4 acc0, acc1 = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-            for (int q = r + 1; q < TB; q++) l[q] = lt[r * LTS + q];
+            for (int r = 0; r < 4; r++) acc0[r] = T[(R + lk + 4 * r) * LTS + Cc + li];
+            mma16_nt(T + R * LTS + c0, T + Cc * LTS + c0, -1.0, acc0, acc1);
+            const d4 acc = acc0 + acc1;
 #pragma unroll
-            for (int q = r + 1; q < TB; q++) a[q] = fma(-l[q], a[r], a[q]);
+            for (int r = 0; r < 4; r++) T[(R + lk + 4 * r) * LTS + Cc + li] = acc[r];
         }
-        if (j % POTF2_CHUNK == POTF2_CHUNK - 1) {
-            if (w == 0 && i == 0 && fail) sfail = fail;
-            __syncthreads();
-            stop = sfail;
-        }
+        if (nblk > 0) __syncthreads();
     }
-    if (stop) {
-        if (threadIdx.x == 0 && stop <= d.n) prm[m].info = stop;
-        return;
-    }
-    if (w == 0) {
-        if (i < nb) {
+    // the rest of the inverse: diagonal block 3 (wave 0) and the two
+    // off-diagonal blocks of row block 2 (waves 1, 2), then those of row
+    // block 3, one per wave; wave 3 writes the last panel meanwhile
+    double *linv = work + d.linv_off + (int64_t)step * TB * TB;
+    if (w == 0) inverse_diag_block(T, X, rdiag, NPB - 1);
+    else if (w == 1) inverse_off_blocks(T, X, NPB - 2, 1, 2);
+    else if (w == 2) inverse_off_blocks(T, X, NPB - 2, 0, 1);
+    else write_panel_L(T, yv, A, work + d.v_off + k0, d.n, k0, nb, NPB - 1, i);
+    __syncthreads();
+    if (w < NPB - 1) inverse_off_blocks(T, X, NPB - 1, w, w + 1);
+    else write_inverse_rows(X, linv, 1, i);
+    __syncthreads();
+    // row blocks 2 and 3 of the inverse (zero above the diagonal blocks)
 #pragma unroll
-            for (int c = 0; c < TB; c++)
-                if (c <= i && c < nb) A[(k0 + i) * d.n + k0 + c] = a[c];
-            work[d.v_off + k0 + i] = bi;
-        }
-    } else {
-        double *linv = work + d.linv_off + (int64_t)step * TB * TB;
-#pragma unroll
-        for (int r = 0; r < TB; r++) linv[r * TB + i] = a[r];
+    for (int u = 0; u < 2 * PB * TB / 256; u++) {
+        const int e = t + 256 * u;
+        const int r = 2 * PB + (e >> 6), c = e & 63;
+        linv[r * TB + c] = (r / PB >= c / PB) ? X[r * LTS + c] : 0.0;
     }
 }
 
@@ -1160,7 +1339,7 @@ static void launch_factor_solve(DenseState *D, int32_t nmat, int32_t max_n, cons
         for (int st = p; st < pe; st++) {
             {
                 ProfScope prof("k_potf2", s);
-                hipLaunchKernelGGL(k_potf2, dim3(1, nmat), dim3(128), 0, s, D->desc, D->prm, D->work, st);
+                hipLaunchKernelGGL(k_potf2, dim3(1, nmat), dim3(256), 0, s, D->desc, D->prm, D->work, st);
             }
             const int64_t below = nsteps - st - 1;
             if (below > 0) {

@@ -66,3 +66,20 @@ def test_solve_workspace_query(lib):
     assert lib.ba_solve_increment_workspace(0, 10) > 0
     assert lib.ba_solve_increment_workspace(0, 0) == 0
     assert lib.ba_solve_increment_workspace(7, 10) == 0
+
+
+def test_binding_checks_solve_shapes():
+    """The Python binding derives the scan count from grad and rejects a hess
+    whose size does not match it (no silent truncation to whole scans)."""
+    import torch
+    from paper_2608_14266_amd import _lib
+    g = torch.zeros(12, dtype=torch.float64)
+    assert _lib._solve_scans(_lib.MODE_MM, torch.zeros(72, dtype=torch.float64), g) == 2
+    assert _lib._solve_scans(_lib.MODE_COUPLED, torch.zeros(144, dtype=torch.float64), g) == 2
+    with pytest.raises(ValueError):
+        _lib._solve_scans(_lib.MODE_COUPLED, torch.zeros(72, dtype=torch.float64), g)
+    with pytest.raises(ValueError):
+        _lib._solve_scans(_lib.MODE_COUPLED, torch.zeros(200 * 200, dtype=torch.float64),
+                          torch.zeros(200, dtype=torch.float64))
+    with pytest.raises(ValueError):
+        _lib._solve_scans(_lib.MODE_MM, torch.zeros(0, dtype=torch.float64), torch.zeros(0, dtype=torch.float64))

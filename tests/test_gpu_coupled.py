@@ -87,6 +87,26 @@ def test_dense_cholesky_solve_against_lapack(ba, dev, orc, n):
             assert info_o == 0 and rel(dx.cpu().numpy().ravel(), ref_o) <= 1e-15 * cond * 10
 
 
+@pytest.mark.parametrize("n", [90, 198, 384])
+def test_dense_solve_reads_lower_triangle_only(ba, dev, n):
+    """The coupled solve uses the lower triangle of hess: noise in the strict
+    upper triangle (inside and outside the diagonal tiles) leaves dx bitwise
+    unchanged."""
+    import torch
+    say(f"dense solve lower triangle only n={n}")
+    rng = np.random.default_rng(7 * n)
+    Q = rng.standard_normal((n, n))
+    H = Q @ Q.T / n + np.diag(rng.uniform(0.5, 2.0, n))
+    g = rng.standard_normal(n)
+    Hn = H.copy()
+    iu = np.triu_indices(n, 1)
+    Hn[iu] = rng.standard_normal(len(iu[0])) * 1e3
+    dx1, i1 = ba.solve_increment(ba.MODE_COUPLED, torch.as_tensor(H, device=dev), torch.as_tensor(g, device=dev), 0.1)
+    dx2, i2 = ba.solve_increment(ba.MODE_COUPLED, torch.as_tensor(Hn, device=dev), torch.as_tensor(g, device=dev), 0.1)
+    assert int(i1.cpu().numpy()[0]) == int(i2.cpu().numpy()[0]) == 0
+    assert np.array_equal(dx1.cpu().numpy(), dx2.cpu().numpy())
+
+
 @pytest.mark.parametrize("bad", [3, 64, 65, 150])
 def test_dense_cholesky_reports_pivot(ba, dev, orc, bad):
     import torch
