@@ -98,15 +98,16 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--iters", type=int, default=20, help="LM iterations per solve")
-    ap.add_argument("--mode", choices=["mm", "coupled"], default="mm")
+    ap.add_argument("--mode", choices=["mm", "coupled"], default=None,
+                    help="Hessian form (default: mm; coupled for --workload served)")
     ap.add_argument("--workload", choices=["window", "tiny", "city", "batch", "served", "scaling", "pipeline"],
                     default="batch",
                     help="batch: 256 uneven windows (the headline); window: 500-pose single window; city: "
                          "2000-pose 5 km precision-form map; served: Poisson request stream; scaling: "
                          "build time against points and per-iteration times against clusters and poses; "
                          "pipeline: unlabelled points -> voxelize -> build -> solve")
-    ap.add_argument("--rate", type=float, default=20.0, help="served: request arrival rate (req/s)")
-    ap.add_argument("--requests", type=int, default=24, help="served: number of requests")
+    ap.add_argument("--rates", type=str, default="50,200,500", help="served: request arrival rates (req/s)")
+    ap.add_argument("--requests", type=int, default=120, help="served: number of requests per rate")
     ap.add_argument("--slots", type=int, default=4, help="served: concurrent requests")
     ap.add_argument("--windows", type=int, default=256, help="batch: number of windows")
     ap.add_argument("--sweep-poses", type=str, default="1000,2000,5000,10000,20000",
@@ -125,6 +126,8 @@ def main():
                     help="after the run, copy a buffer of this many MiB device to device three times "
                          "(a plain copy kernel of known size, to scale hardware byte counters)")
     args = ap.parse_args()
+    if args.mode is None:
+        args.mode = "coupled" if args.workload == "served" else "mm"
     if args.cpu_iters is None:
         args.cpu_iters = 50 if args.mode == "mm" else 1
     if args.gpus != 1:
