@@ -208,15 +208,28 @@ HBM_PEAK = HBM_PEAK_GBS
 
 
 def _cpu_model() -> str:
+    """The host CPU as /proc/cpuinfo names it (first processor): model name,
+    with family, model and stepping numbers and the current clock, since a
+    virtualised host may report only the product line."""
+    info = {}
     try:
         with open("/proc/cpuinfo") as f:
             for line in f:
-                if line.startswith("model name"):
-                    return line.split(":", 1)[1].strip()
+                if not line.strip():
+                    break
+                if ":" in line:
+                    k, v = line.split(":", 1)
+                    info.setdefault(k.strip(), v.strip())
     except OSError:
         pass
-    import platform
-    return platform.processor() or "unknown"
+    name = info.get("model name")
+    if not name:
+        import platform
+        return platform.processor() or "unknown"
+    extra = [f"{k} {info[k]}" for k in ("cpu family", "model", "stepping") if k in info]
+    if "cpu MHz" in info:
+        extra.append(f"{float(info['cpu MHz']):.0f} MHz")
+    return f"{name} ({', '.join(extra)})" if extra else name
 
 
 def _host_cores() -> int:

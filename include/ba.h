@@ -231,7 +231,8 @@ size_t ba_solve_increment_workspace(int32_t mode, int32_t n_scans);
  * scan no voxel constrains would otherwise make singular).
  *   BA_MODE_MM: n_scans independent 6x6 LDL^T factorizations; hess is [N][36].
  *   BA_MODE_COUPLED (or BA_MODE_EXACT): one dense Cholesky of the (6N)^2
- *   row-major hess, blocked, trailing updates on FP64 matrix cores.
+ *   row-major hess, blocked, trailing updates on FP64 matrix cores; hess
+ *   is symmetric and only its lower triangle is read.
  * hess, grad: device inputs (unchanged).  dx: device [N][6] output.
  * info: device int32 output, 0 or the 1-based index of the first
  * non-positive pivot (dx is then zero).  ws: device workspace of at least
