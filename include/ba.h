@@ -123,6 +123,10 @@ typedef struct ba_lm_options {
     double exact_below;  /* BA_MODE_COUPLED only: a window whose gradient norm at its current poses is below this
                           * takes the exact Hessian of Eq. 1 (BA_MODE_EXACT) for its step, the coupled one otherwise
                           * (FP64 problems; <= 0: never) */
+    const double *resume; /* NULL, or host [n_windows][4]: per window mu0 (> 0), nu0 (> 0), rejects0 (>= 0) and a
+                           * skip flag, in place of mu0 / nu0 / rejects0 above, so that each window of a batch resumes
+                           * its own earlier run exactly; a window with a nonzero skip flag is left as it is (its
+                           * poses unchanged, 0 iterations reported, its other report fields unspecified) */
 } ba_lm_options;
 
 typedef struct ba_lm_report {  /* one per window */
@@ -322,7 +326,9 @@ typedef struct ba_server_options {
     ba_lm_options lm;      /* LM options of every request (mode, max_iters, mu0, nu0, tol_g, max_rejects) */
     int32_t iters_per_check; /* LM iterations between cancellation checks (0: 10); the chunks resume
                               * each other exactly, so results do not depend on it */
-    int32_t reserved;      /* 0 */
+    int32_t batch;         /* requests a slot fuses into one multi-window problem (0 or 1: one per problem);
+                            * each window of the batch resumes its own run at every chunk, and a request is
+                            * finished as soon as its window stops, so results do not depend on it */
 } ba_server_options;
 
 typedef struct ba_request {  /* raw-sum clusters of one window (Eq. 2); host arrays, copied on submit */

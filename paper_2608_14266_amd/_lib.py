@@ -53,7 +53,7 @@ class _Info(ct.Structure):
 class _LMOpts(ct.Structure):
     _fields_ = [("mode", ct.c_int32), ("max_iters", ct.c_int32), ("mu0", ct.c_double), ("nu0", ct.c_double),
                 ("tol_g", ct.c_double), ("max_rejects", ct.c_int32), ("rejects0", ct.c_int32),
-                ("exact_below", ct.c_double)]
+                ("exact_below", ct.c_double), ("resume", ct.c_void_p)]
 
 
 class _Tuning(ct.Structure):
@@ -63,7 +63,7 @@ class _Tuning(ct.Structure):
 
 class _ServerOpts(ct.Structure):
     _fields_ = [("hbm_budget", ct.c_int64), ("slots", ct.c_int32), ("precision", ct.c_int32),
-                ("lm", _LMOpts), ("iters_per_check", ct.c_int32), ("reserved", ct.c_int32)]
+                ("lm", _LMOpts), ("iters_per_check", ct.c_int32), ("batch", ct.c_int32)]
 
 
 class _Request(ct.Structure):
@@ -377,14 +377,21 @@ def solve_increment(mode: int, hess, grad, mu: float):
 
 def iterate(problem: Problem, poses, mode: int = MODE_MM, max_iters: int = 10, mu0: float = 1e-2,
             nu0: float = 2.0, tol_g: float = 0.0, trace: bool = True, max_rejects: int = 0,
-            exact_below: float = 0.0, rejects0: int = 0):
+            exact_below: float = 0.0, rejects0: int = 0, resume=None):
     """ba_iterate: LM on the device, poses updated in place.  Synchronous.
+    resume: None, or per window (mu0, nu0, rejects0, skip) as an (n_windows, 4)
+    array (a window's earlier report's mu_final, nu_final, rejects_final).
     Returns (reports: list of dicts per window, trace ndarray (iters, W, 8) or None)."""
     if not (poses.is_cuda and poses.dtype == torch.float64 and poses.is_contiguous()):
         raise TypeError("poses must be a contiguous float64 device tensor (updated in place)")
     W = problem.info()["n_windows"]
     o = _LMOpts(int(mode), int(max_iters), float(mu0), float(nu0), float(tol_g), int(max_rejects), int(rejects0),
                 float(exact_below))
+    if resume is not None:
+        resume = np.ascontiguousarray(resume, dtype=np.float64)
+        if resume.shape != (W, 4):
+            raise ValueError(f"resume must be ({W}, 4), got {resume.shape}")
+        o.resume = resume.ctypes.data_as(ct.c_void_p)
     reps = (_LMReport * W)()
     tr = np.zeros((max(int(max_iters), 1), W, 8)) if trace else None
     trp = tr.ctypes.data_as(ct.c_void_p) if trace else ct.c_void_p(0)
@@ -469,13 +476,14 @@ class Server:
 
     def __init__(self, hbm_budget: int, slots: int = 4, precision: int = PREC_F64, mode: int = MODE_MM,
                  max_iters: int = 50, tol_g: float = 1e-6, mu0: float = 0.0, nu0: float = 0.0,
-                 max_rejects: int = 10, iters_per_check: int = 0):
+                 max_rejects: int = 10, iters_per_check: int = 0, batch: int = 0):
         o = _ServerOpts()
         o.hbm_budget = int(hbm_budget)
         o.slots = int(slots)
         o.precision = int(precision)
         o.lm = _LMOpts(int(mode), int(max_iters), float(mu0), float(nu0), float(tol_g), int(max_rejects), 0)
         o.iters_per_check = int(iters_per_check)
+        o.batch = int(batch)
         h = ct.c_void_p()
         _check(load().ba_server_create(ct.byref(o), ct.byref(h)))
         self._h = h

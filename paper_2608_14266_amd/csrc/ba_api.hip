@@ -131,7 +131,7 @@ namespace ba {
 static ba_status enqueue_lm(Problem *P, double *poses, const ba_lm_options *opt, double *dtrace, double mu0, double nu0,
                             hipStream_t s) {
     const int iters = opt->max_iters;
-    launch_lm_reset(P, mu0, nu0, opt->rejects0, s);
+    launch_lm_reset(P, mu0, nu0, opt->rejects0, opt->resume ? P->lm_init : nullptr, s);
     launch_vox(P, poses, true, false, s);
     launch_lm_cost(P, s);
     for (int it = 0; it < iters; it++) {
@@ -176,6 +176,7 @@ struct IterGraph {
     double *poses = nullptr, *trace = nullptr;
     int32_t mode = -1, iters = -1, tune_gen = -1, max_rejects = 0, rejects0 = 0;
     double mu0 = 0, nu0 = 0, tol_g = 0, exact_below = 0;
+    bool per_window = false;   // start from P->lm_init (filled before each launch)
     ~IterGraph() {
         if (exec) (void)hipGraphExecDestroy(exec);
         if (cap) (void)hipStreamDestroy(cap);
@@ -435,6 +436,17 @@ ba_status ba_iterate(ba_problem *p, double *poses_inout, const ba_lm_options *op
     const int iters = opt->max_iters;
     const double mu0 = opt->mu0 > 0 ? opt->mu0 : 1e-2;
     const double nu0 = opt->nu0 > 0 ? opt->nu0 : 2.0;
+    if (opt->resume) {
+        for (int w = 0; w < W; w++) {
+            const double *r = opt->resume + 4 * w;
+            if (!(r[0] > 0.0) || !(r[1] > 0.0) || !(r[2] >= 0.0) || r[2] > 2147483647.0 || r[2] != (double)(int32_t)r[2]) {
+                set_error("resume entry of window %d out of range (mu0 %g, nu0 %g, rejects0 %g)", w, r[0], r[1], r[2]);
+                return BA_E_ARG;
+            }
+        }
+        if (!P->lm_init) BA_TRY(P->mem.alloc(&P->lm_init, 4LL * W));
+        BA_HIP(hipMemcpyAsync(P->lm_init, opt->resume, sizeof(double) * 4 * W, hipMemcpyHostToDevice, stream));
+    }
     if (opt->mode == BA_MODE_COUPLED) BA_TRY(dense_prepare(P));
     double *dtrace = nullptr;
     if (trace && iters > 0) {
@@ -452,7 +464,7 @@ ba_status ba_iterate(ba_problem *p, double *poses_inout, const ba_lm_options *op
         const bool same = G && G->exec && G->poses == poses_inout && G->trace == dtrace && G->mode == opt->mode &&
                           G->iters == iters && G->mu0 == mu0 && G->nu0 == nu0 && G->tol_g == opt->tol_g &&
                           G->tune_gen == P->tune_gen && G->max_rejects == opt->max_rejects &&
-                          G->rejects0 == opt->rejects0 &&
+                          G->rejects0 == opt->rejects0 && G->per_window == (opt->resume != nullptr) &&
                           G->exact_below == opt->exact_below;
         if (!same) {
             graph_release(P);
@@ -480,6 +492,7 @@ ba_status ba_iterate(ba_problem *p, double *poses_inout, const ba_lm_options *op
                 G->tune_gen = P->tune_gen;
                 G->max_rejects = opt->max_rejects;
                 G->rejects0 = opt->rejects0;
+                G->per_window = opt->resume != nullptr;
                 G->exact_below = opt->exact_below;
             } else {
                 graph_release(P);

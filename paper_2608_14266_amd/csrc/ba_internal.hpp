@@ -145,6 +145,7 @@ struct Problem {
     int32_t *pose_info = nullptr;             // [N]
     LMState *lm = nullptr;                    // [n_windows]
     double *trace = nullptr;                  // [max_iters][n_windows][8]
+    double *lm_init = nullptr;                // [n_windows][4] per-window LM start (ba_lm_options.resume)
     int32_t trace_cap = 0;
 
     // dense coupled path

@@ -19,7 +19,7 @@ void launch_voxel_eig(Problem *P, double *out, hipStream_t s);
 size_t solve_mm_workspace(int32_t n);
 void launch_solve_mm_plain(int32_t n, const double *H, const double *g, double mu, double *dx, int32_t *info,
                            void *ws, hipStream_t s);
-void launch_lm_reset(Problem *P, double mu0, double nu0, int32_t rejects0, hipStream_t s);
+void launch_lm_reset(Problem *P, double mu0, double nu0, int32_t rejects0, const double *init, hipStream_t s);
 void launch_lm_cost(Problem *P, hipStream_t s);
 void launch_window_stats(Problem *P, double tol_g, hipStream_t s);
 void launch_window_solve_mm(Problem *P, const double *poses, double tol_g, hipStream_t s);

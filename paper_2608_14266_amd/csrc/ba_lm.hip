@@ -91,16 +91,22 @@ __device__ __forceinline__ int solve_pose(const double *__restrict__ h, const do
     return 0;
 }
 
+// init: NULL, or per window (mu0, nu0, rejects0, skip); a skipped window
+// starts stopped (done = 3), so no pass touches it.
 __global__ void k_lm_reset(int32_t W, LMState *__restrict__ lm, double mu0, double nu0, int32_t rejects0,
-                           const int32_t *__restrict__ win_group_ptr) {
+                           const double *__restrict__ init, const int32_t *__restrict__ win_group_ptr) {
     const int w = blockIdx.x * blockDim.x + threadIdx.x;
     if (w >= W) return;
     LMState s;
-    s.mu = mu0; s.nu = nu0; s.cost = 0.0; s.cost_trial = 0.0; s.q = 0.0; s.rho = 0.0;
+    s.mu = init ? init[4 * w] : mu0;
+    s.nu = init ? init[4 * w + 1] : nu0;
+    s.cost = 0.0; s.cost_trial = 0.0; s.q = 0.0; s.rho = 0.0;
     s.gnorm = 0.0; s.maxdiag = 0.0; s.cost0 = 0.0;
     s.accepted = 0; s.need_eval = 1; s.info = 0;
     s.done = (win_group_ptr[w + 1] == win_group_ptr[w]) ? 1 : 0;   // a window without voxels has nothing to do
-    s.iters = 0; s.n_accepted = 0; s.cur = 0; s.rejects = rejects0;
+    if (init && init[4 * w + 3] != 0.0) s.done = 3;
+    s.iters = 0; s.n_accepted = 0; s.cur = 0;
+    s.rejects = init ? (int32_t)init[4 * w + 2] : rejects0;
     lm[w] = s;
 }
 
@@ -362,8 +368,9 @@ void launch_solve_mm_plain(int32_t n, const double *H, const double *g, double m
     hipLaunchKernelGGL(k_solve_finish, dim3(1), dim3(256), 0, s, n, infos, dx, info);
 }
 
-void launch_lm_reset(Problem *P, double mu0, double nu0, int32_t rejects0, hipStream_t s) {
+void launch_lm_reset(Problem *P, double mu0, double nu0, int32_t rejects0, const double *init, hipStream_t s) {
     hipLaunchKernelGGL(k_lm_reset, dim3(nblk(P->n_windows)), dim3(256), 0, s, P->n_windows, P->lm, mu0, nu0, rejects0,
+                       init,
                        P->win_group_ptr);
 }
 

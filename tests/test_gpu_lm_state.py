@@ -77,3 +77,71 @@ def test_resume_with_reported_damping_is_exact(ba, wide, mode):
     assert np.array_equal(np.concatenate([t1, t2]), t3)
     assert r2[0]["cost_final"] == r3[0]["cost_final"] and r2[0]["mu_final"] == r3[0]["mu_final"]
     assert r2[0]["nu_final"] == r3[0]["nu_final"] and r2[0]["gnorm_final"] == r3[0]["gnorm_final"]
+
+
+@pytest.fixture(scope="module")
+def three():
+    # three windows of 12, 30 and 20 poses in one problem
+    return ss.batch_windows(seed=5300, n_windows=3, poses=[12, 30, 20], vox_range=(400, 2000), workers=1)
+
+
+@pytest.mark.parametrize("mode", ["mm", "coupled"])
+def test_per_window_resume_is_exact(ba, three, mode):
+    """Chunks resumed per window (each window's own mu, nu and rejection
+    count from the previous chunk's report) give the bits of one uninterrupted
+    run, for every window of a batched problem."""
+    import torch
+    dev = torch.device("cuda:0")
+    m = ba.MODE_MM if mode == "mm" else ba.MODE_COUPLED
+    k1, k2 = (4, 5) if mode == "mm" else (2, 3)
+    say(f"per-window resume {mode}")
+    prob = build_gpu_sums(ba, three, dev)
+    try:
+        P = torch.as_tensor(three.poses_init, device=dev).contiguous()
+        r1, t1 = ba.iterate(prob, P, m, max_iters=k1, max_rejects=3)
+        res = np.array([[r["mu_final"], r["nu_final"], r["rejects_final"], 0.0] for r in r1])
+        r2, t2 = ba.iterate(prob, P, m, max_iters=k2, max_rejects=3, resume=res)
+        Q = torch.as_tensor(three.poses_init, device=dev).contiguous()
+        r3, t3 = ba.iterate(prob, Q, m, max_iters=k1 + k2, max_rejects=3)
+    finally:
+        prob.close()
+    assert np.array_equal(P.cpu().numpy(), Q.cpu().numpy())
+    assert np.array_equal(np.concatenate([t1, t2]), t3)
+    for a, b in zip(r2, r3):
+        for k in ("cost_final", "gnorm_final", "mu_final", "nu_final", "rejects_final", "converged", "stalled"):
+            assert a[k] == b[k], k
+
+
+def test_skipped_window_is_left_alone(ba, three):
+    """A window skipped through the per-window start keeps its poses and runs
+    no iteration; the other windows are bitwise what they are without the skip."""
+    import torch
+    dev = torch.device("cuda:0")
+    say("skipped window")
+    prob = build_gpu_sums(ba, three, dev)
+    try:
+        base = np.array([[1e-2, 2.0, 0.0, 0.0]] * 3)
+        P = torch.as_tensor(three.poses_init, device=dev).contiguous()
+        ra, _ = ba.iterate(prob, P, ba.MODE_MM, max_iters=6, resume=base)
+        skip = base.copy()
+        skip[1, 3] = 1.0
+        Q = torch.as_tensor(three.poses_init, device=dev).contiguous()
+        rb, _ = ba.iterate(prob, Q, ba.MODE_MM, max_iters=6, resume=skip)
+        # per-window start equal to the scalar defaults gives the default run
+        R = torch.as_tensor(three.poses_init, device=dev).contiguous()
+        rc, _ = ba.iterate(prob, R, ba.MODE_MM, max_iters=6)
+        with pytest.raises(ba.BAError):
+            bad = base.copy()
+            bad[2, 0] = 0.0
+            ba.iterate(prob, R, ba.MODE_MM, max_iters=1, resume=bad)
+    finally:
+        prob.close()
+    sw = three.scan_window
+    P, Q, R = P.cpu().numpy(), Q.cpu().numpy(), R.cpu().numpy()
+    w1 = sw == 1
+    assert np.array_equal(Q[w1], three.poses_init[w1])
+    assert rb[1]["iters"] == 0
+    assert np.array_equal(Q[~w1], P[~w1])
+    for w in (0, 2):
+        assert rb[w] == ra[w]
+    assert np.array_equal(P, R) and ra == rc
