@@ -109,6 +109,8 @@ def main():
     ap.add_argument("--rates", type=str, default="50,200,500", help="served: request arrival rates (req/s)")
     ap.add_argument("--requests", type=int, default=120, help="served: number of requests per rate")
     ap.add_argument("--slots", type=int, default=8, help="served: concurrent requests")
+    ap.add_argument("--batch", type=int, default=1,
+                    help="served: queued requests a slot fuses into one problem of windows (1: one per problem)")
     ap.add_argument("--windows", type=int, default=256, help="batch: number of windows")
     ap.add_argument("--sweep-poses", type=str, default="1000,2000,5000,10000,20000",
                     help="scaling: pose counts of the city-law sweep")

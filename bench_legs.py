@@ -536,13 +536,13 @@ def served(args):
     opts = dict(mode=mode, max_iters=50, tol_g=1e-6, max_rejects=10)
     budget = 200 << 30
 
-    def serve(prec, slots, arr):
+    def serve(prec, slots, arr, batch=1):
         res = [None] * R
-        with ba.Server(budget, slots=slots, precision=prec, **opts) as srv:
-            # warm-up (first kernels loaded; slot arenas grown to the largest
-            # request, so the measured stream allocates nothing)
+        with ba.Server(budget, slots=slots, precision=prec, batch=batch, **opts) as srv:
+            # warm-up (first kernels loaded; slot arenas grown to a batch of the
+            # largest requests, so the measured stream allocates nothing)
             big = int(np.argmax(sizes))
-            for rid in [srv.submit_scene(reqs[big]) for _ in range(slots)]:
+            for rid in [srv.submit_scene(reqs[big]) for _ in range(slots * batch)]:
                 srv.wait(rid)
             base = time.perf_counter()
             ids = []
@@ -566,7 +566,7 @@ def served(args):
     for rate in rates:
         gaps = np.random.Generator(np.random.Philox(key=5001 + int(rate))).exponential(1.0 / rate, size=R)
         arrivals = np.cumsum(gaps) - gaps[0]
-        res = serve(ba.PREC_F32, args.slots, arrivals)
+        res = serve(ba.PREC_F32, args.slots, arrivals, args.batch)
         lat = np.array([s["t_done"] - s["t_submit"] for _, s in res])
         first = min(s["t_submit"] for _, s in res)
         last = max(s["t_done"] for _, s in res)
@@ -605,7 +605,8 @@ def served(args):
             "config": {"workload": f"served Poisson at {', '.join(f'{r:g}' for r in rates)} req/s, {R} requests of "
                                    f"20..1000 poses (~400 planes per pose), solve to ||g|| < 1e-6, 10 rejections in "
                                    f"a row or 50 iterations ({mode_name})",
-                       "slots": args.slots, "hbm_budget_bytes": budget, "value_is": f"p99 at {rates[-1]:g} req/s"},
+                       "slots": args.slots, "batch": args.batch, "hbm_budget_bytes": budget,
+                       "value_is": f"p99 at {rates[-1]:g} req/s"},
             "serial_plain_f64_service_ms_mean": float(service.mean() * 1e3),
             "serial_plain_f64_converged": conv64, "serial_plain_f64_gnorm_final_max": float(g64.max()),
             "rates": rows}

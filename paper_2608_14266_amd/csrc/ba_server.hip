@@ -17,6 +17,15 @@
 // exactly (damping, damping growth and rejection count carried over), so a
 // cancelled request stops at the next chunk boundary while the results of
 // uncancelled ones are those of one uninterrupted run.
+//
+// With opt.batch > 1 a free slot admits up to that many queued requests (in
+// queue order, while they fit the budget) and fuses them into one problem of
+// independent windows: one launch per pass then serves all of them.  The LM
+// runs in chunks with every window resuming its own run (per-window damping,
+// growth and rejection count); a request is finished as soon as its window
+// converges, stalls, uses its iterations or is cancelled, and its window is
+// skipped from then on.  A window's arithmetic does not depend on the other
+// windows of its problem, so every result equals the request's result alone.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -210,13 +219,171 @@ static void arena_reserve(Server *S, SlotArena &a, int64_t need) {
     }
 }
 
+// Marks a request finished (under the server lock) and drops its input copies.
+static void finish_request(Server *S, Request &R, ba_status st, bool cancelled, const std::string &err) {
+    std::lock_guard<std::mutex> lk(S->mu);
+    R.error = err;
+    R.st.status = cancelled ? BA_E_CANCELLED : st;
+    R.st.state = cancelled ? BA_REQ_CANCELLED : (st == BA_OK ? BA_REQ_DONE : BA_REQ_FAILED);
+    R.st.t_done = S->now();
+    std::vector<int32_t>().swap(R.voxel);
+    std::vector<int32_t>().swap(R.scan);
+    std::vector<int64_t>().swap(R.count);
+    std::vector<double>().swap(R.sum);
+    std::vector<double>().swap(R.sumsq);
+}
+
+// Several requests as the windows of one problem, on `stream` (see above).
+// Each request is finished (finish_request) as soon as its window stops;
+// returns a status for the requests still open when the problem fails.
+static ba_status run_batch(Server *S, std::vector<std::shared_ptr<Request>> &B, hipStream_t stream) {
+    const int W = (int)B.size();
+    int64_t n = 0;
+    int32_t ns = 0, nv = 0;
+    for (auto &R : B) {
+        n += R->n;
+        ns += R->n_scans;
+        nv += R->n_voxels;
+    }
+    // concatenated inputs: voxel and scan ids shifted per request, one window per request
+    std::vector<int32_t> vox(n), scan(n), win(ns);
+    std::vector<int64_t> cnt(n);
+    std::vector<double> sum(3 * n), sq(6 * n), poses(12LL * ns);
+    std::vector<int32_t> s0(W + 1, 0);
+    {
+        int64_t o = 0;
+        int32_t so = 0, vo = 0;
+        for (int w = 0; w < W; w++) {
+            const Request &R = *B[w];
+            for (int64_t i = 0; i < R.n; i++) {
+                vox[o + i] = R.voxel[i] + vo;
+                scan[o + i] = R.scan[i] + so;
+            }
+            std::copy(R.count.begin(), R.count.end(), cnt.begin() + o);
+            std::copy(R.sum.begin(), R.sum.end(), sum.begin() + 3 * o);
+            std::copy(R.sumsq.begin(), R.sumsq.end(), sq.begin() + 6 * o);
+            std::copy(R.poses.begin(), R.poses.end(), poses.begin() + 12LL * so);
+            for (int32_t j = 0; j < R.n_scans; j++) win[so + j] = w;
+            s0[w] = so;
+            o += R.n;
+            so += R.n_scans;
+            vo += R.n_voxels;
+        }
+        s0[W] = so;
+    }
+    DevArena in;
+    int32_t *d_vox, *d_scan;
+    int64_t *d_cnt;
+    double *d_sum, *d_sq, *d_poses;
+    BA_TRY(in.alloc(&d_vox, n));
+    BA_TRY(in.alloc(&d_scan, n));
+    BA_TRY(in.alloc(&d_cnt, n));
+    BA_TRY(in.alloc(&d_sum, 3 * n));
+    BA_TRY(in.alloc(&d_sq, 6 * n));
+    BA_TRY(in.alloc(&d_poses, 12LL * ns));
+    BA_HIP(hipMemcpyAsync(d_vox, vox.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, stream));
+    BA_HIP(hipMemcpyAsync(d_scan, scan.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, stream));
+    BA_HIP(hipMemcpyAsync(d_cnt, cnt.data(), sizeof(int64_t) * n, hipMemcpyHostToDevice, stream));
+    BA_HIP(hipMemcpyAsync(d_sum, sum.data(), sizeof(double) * 3 * n, hipMemcpyHostToDevice, stream));
+    BA_HIP(hipMemcpyAsync(d_sq, sq.data(), sizeof(double) * 6 * n, hipMemcpyHostToDevice, stream));
+    BA_HIP(hipMemcpyAsync(d_poses, poses.data(), sizeof(double) * 12 * ns, hipMemcpyHostToDevice, stream));
+    ba_cluster_sums cs;
+    cs.n = n;
+    cs.voxel = d_vox;
+    cs.scan = d_scan;
+    cs.count = d_cnt;
+    cs.sum = d_sum;
+    cs.sumsq = d_sq;
+    cs.n_scans = ns;
+    cs.n_voxels = nv;
+    ba_build_options bo;
+    std::memset(&bo, 0, sizeof(bo));
+    bo.n_windows = W;
+    bo.scan_window = win.data();
+    bo.precision = S->opt.precision;
+    bo.ref_poses = S->opt.precision == BA_PREC_F32 ? d_poses : nullptr;
+    ba_problem *p = nullptr;
+    BA_TRY(ba_build_clusters_from_sums(&cs, &bo, &p, stream));
+    std::unique_ptr<ba_problem> own(p);
+    p->P.no_graph = true;   // one-shot problem: launch eagerly rather than capture
+    // chunked LM, every window resuming its own run
+    ba_lm_options o = S->opt.lm;
+    const int chunk = S->opt.iters_per_check > 0 ? S->opt.iters_per_check : 10;
+    std::vector<double> resume(4LL * W);
+    std::vector<ba_lm_report> acc(W), rep(W);
+    std::vector<char> open(W, 1), first(W, 1);
+    for (int w = 0; w < W; w++) {
+        resume[4 * w] = o.mu0 > 0 ? o.mu0 : 1e-2;
+        resume[4 * w + 1] = o.nu0 > 0 ? o.nu0 : 2.0;
+        resume[4 * w + 2] = o.rejects0;
+        std::memset(&acc[w], 0, sizeof(ba_lm_report));
+    }
+    auto close = [&](int w, bool cancelled) -> ba_status {
+        Request &R = *B[w];
+        R.st.report = acc[w];
+        hipError_t e = hipMemcpyAsync(R.poses.data(), d_poses + 12LL * s0[w], sizeof(double) * 12 * R.n_scans,
+                                      hipMemcpyDeviceToHost, stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(stream);
+        if (e != hipSuccess) {
+            set_error("copy of served poses failed: %s", hipGetErrorString(e));
+            return BA_E_HIP;
+        }
+        finish_request(S, R, BA_OK, cancelled, std::string());
+        open[w] = 0;
+        return BA_OK;
+    };
+    int left = o.max_iters;
+    for (;;) {
+        for (int w = 0; w < W; w++)
+            if (open[w] && B[w]->cancel.load()) BA_TRY(close(w, true));
+        bool any = false;
+        for (int w = 0; w < W; w++) any = any || open[w];
+        if (!any) break;
+        if (left <= 0) {
+            for (int w = 0; w < W; w++)
+                if (open[w]) BA_TRY(close(w, false));
+            break;
+        }
+        for (int w = 0; w < W; w++) resume[4 * w + 3] = open[w] ? 0.0 : 1.0;
+        o.max_iters = std::min(chunk, left);
+        o.resume = resume.data();
+        BA_TRY(ba_iterate(p, d_poses, &o, rep.data(), nullptr, stream));
+        for (int w = 0; w < W; w++) {
+            if (!open[w]) continue;
+            const ba_lm_report &r = rep[w];
+            ba_lm_report &a = acc[w];
+            if (first[w]) a.cost_initial = r.cost_initial;
+            first[w] = 0;
+            a.iters += r.iters;
+            a.n_accepted += r.n_accepted;
+            a.converged = r.converged;
+            a.stalled = r.stalled;
+            a.last_info = r.last_info;
+            a.cost_final = r.cost_final;
+            a.gnorm_final = r.gnorm_final;
+            a.mu_final = r.mu_final;
+            a.nu_final = r.nu_final;
+            a.rejects_final = r.rejects_final;
+            resume[4 * w] = r.mu_final;
+            resume[4 * w + 1] = r.nu_final;
+            resume[4 * w + 2] = r.rejects_final;
+            if (r.converged || r.stalled || r.iters < o.max_iters) BA_TRY(close(w, false));
+        }
+        left -= o.max_iters;
+    }
+    (void)hipStreamSynchronize(stream);
+    return BA_OK;
+}
+
 static void slot_main(Server *S) {
     (void)hipSetDevice(S->device);
     hipStream_t stream = nullptr;
     const bool have_stream = hipStreamCreateWithFlags(&stream, hipStreamNonBlocking) == hipSuccess;
+    const int batch = std::max(1, (int)S->opt.batch);
     SlotArena arena;
     for (;;) {
-        std::shared_ptr<Request> R;
+        std::vector<std::shared_ptr<Request>> B;
+        int64_t need = 0;
         {
             std::unique_lock<std::mutex> lk(S->mu);
             S->cv.wait(lk, [&] {
@@ -224,37 +391,48 @@ static void slot_main(Server *S) {
                        (!S->queue.empty() && S->reserved + S->queue.front()->footprint <= S->opt.hbm_budget);
             });
             if (S->stopping) break;
-            R = S->queue.front();
-            S->queue.pop_front();
-            S->reserved += R->footprint;
-            R->st.state = BA_REQ_RUNNING;
-            R->st.t_admit = S->now();
+            // the head, and the requests behind it while they fit (queue order);
+            // requests admitted together share their admission time
+            const double t_admit = S->now();
+            while (!S->queue.empty() && (int)B.size() < batch &&
+                   S->reserved + S->queue.front()->footprint <= S->opt.hbm_budget) {
+                std::shared_ptr<Request> R = S->queue.front();
+                S->queue.pop_front();
+                S->reserved += R->footprint;
+                need += R->footprint;
+                R->st.state = BA_REQ_RUNNING;
+                R->st.t_admit = t_admit;
+                B.push_back(R);
+            }
         }
         S->cv.notify_all();   // the next head may fit too
-        bool cancelled = false;
         ba_status st = BA_E_HIP;
+        bool cancelled = false;
         if (have_stream) {
-            arena_reserve(S, arena, R->footprint);
+            arena_reserve(S, arena, need);
             arena.off = 0;
             tl_slot_arena = arena.base ? &arena : nullptr;
-            st = run_request(S, *R, stream, cancelled);
+            if (B.size() == 1)
+                st = run_request(S, *B[0], stream, cancelled);
+            else
+                st = run_batch(S, B, stream);
             tl_slot_arena = nullptr;
-            arena.off = 0;   // the request's problem is released: the stream has drained
+            arena.off = 0;   // the problem is released: the stream has drained
         }
         const std::string err = st == BA_OK ? std::string() : std::string(ba_last_error());
+        for (auto &R : B) {
+            bool open;
+            {
+                std::lock_guard<std::mutex> lk(S->mu);
+                open = R->st.state == BA_REQ_RUNNING;
+            }
+            // a batch finishes its requests itself; what is still open failed
+            if (B.size() == 1 || open) finish_request(S, *R, B.size() == 1 ? st : (st == BA_OK ? BA_E_HIP : st),
+                                                      B.size() == 1 && cancelled, err);
+        }
         {
             std::lock_guard<std::mutex> lk(S->mu);
-            R->error = err;
-            S->reserved -= R->footprint;
-            R->st.status = cancelled ? BA_E_CANCELLED : st;
-            R->st.state = cancelled ? BA_REQ_CANCELLED : (st == BA_OK ? BA_REQ_DONE : BA_REQ_FAILED);
-            R->st.t_done = S->now();
-            // the request's input copies are no longer needed
-            std::vector<int32_t>().swap(R->voxel);
-            std::vector<int32_t>().swap(R->scan);
-            std::vector<int64_t>().swap(R->count);
-            std::vector<double>().swap(R->sum);
-            std::vector<double>().swap(R->sumsq);
+            S->reserved -= need;
         }
         S->cv.notify_all();
     }
@@ -287,7 +465,8 @@ ba_status ba_server_create(const ba_server_options *opt, ba_server **out) {
     using namespace ba;
     if (!opt || !out || opt->hbm_budget <= 0 || opt->slots < 1 || opt->slots > 64 || opt->iters_per_check < 0 ||
         (opt->precision != BA_PREC_F64 && opt->precision != BA_PREC_F32) ||
-        (opt->lm.mode != BA_MODE_MM && opt->lm.mode != BA_MODE_COUPLED) || opt->lm.max_iters < 1) {
+        (opt->lm.mode != BA_MODE_MM && opt->lm.mode != BA_MODE_COUPLED) || opt->lm.max_iters < 1 ||
+        opt->batch < 0 || opt->batch > 256 || opt->lm.resume) {
         set_error("invalid server options");
         return BA_E_ARG;
     }

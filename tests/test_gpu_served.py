@@ -216,3 +216,76 @@ def test_cancel_leaves_the_other_requests_unchanged(ba, dev, requests):
         with pytest.raises(ba.BAError) as e:
             srv.cancel(777)
         assert e.value.status == -8
+
+
+def _blocked_serve(ba, reqs, budget, **kw):
+    """Serve `reqs` on one slot behind a long blocker request, so that they
+    are all queued when the slot takes them (batches form deterministically)."""
+    import time
+    blocker = ss.request_scene(seed=5102, n_poses=1000, vox_per_pose=100)
+    with ba.Server(budget, slots=1, **kw) as srv:
+        rb = srv.submit_scene(blocker)
+        t0 = time.time()
+        while srv.query(rb)["state"] == ba._lib.REQ_QUEUED and time.time() - t0 < 60:
+            time.sleep(0.001)
+        ids = [srv.submit_scene(r) for r in reqs]
+        assert srv.query(rb)["state"] == ba._lib.REQ_RUNNING, "the blocker ended before the requests were queued"
+        out = [srv.wait_any(i) for i in ids]
+        srv.wait(rb)
+    return out
+
+
+@pytest.mark.parametrize("prec,mode", [("f32", "mm"), ("f64", "coupled")])
+def test_batched_admission_equals_alone(ba, dev, requests, prec, mode):
+    """A slot that fuses up to four queued requests into one problem of
+    windows gives every request the poses and report it gets served alone
+    (each window resumes its own run at every chunk and stops on its own)."""
+    say(f"served batched admission {prec} {mode}")
+    kw = dict(precision=ba.PREC_F64 if prec == "f64" else ba.PREC_F32,
+              mode=ba.MODE_MM if mode == "mm" else ba.MODE_COUPLED,
+              max_iters=30 if mode == "mm" else 12, tol_g=1e-6, max_rejects=10, iters_per_check=3)
+    alone = [_serve(ba, [r], 1, 8 * GB, **kw)[0] for r in requests]
+    fused = _blocked_serve(ba, requests, 8 * GB, batch=4, **kw)
+    for (pa, sa), (pb, sb) in zip(alone, fused):
+        assert sa["state"] == sb["state"] == ba._lib.REQ_DONE
+        assert np.array_equal(pa, pb)
+        assert sa["report"] == sb["report"]
+    # the eight queued requests went in two batches of four
+    admits = [s["t_admit"] for _, s in fused]
+    assert len(set(admits)) == 2 and admits.count(admits[0]) == 4
+    # each request finished when its own window stopped, not with its batch
+    done = [s["t_done"] for _, s in fused]
+    print(f"  {prec}/{mode}: distinct completion times {len(set(done))} of {len(done)}")
+
+
+def test_cancel_inside_a_batch(ba, dev, requests):
+    """Cancelling one request of a running batch: it ends cancelled with the
+    poses it reached; the other requests of the batch are bitwise those they
+    get served alone."""
+    import time
+    say("served cancel inside a batch")
+    kw = dict(max_iters=400, tol_g=0.0, max_rejects=0, iters_per_check=1)
+    reqs = requests[:4]
+    alone = [_serve(ba, [r], 1, 8 * GB, **kw)[0] for r in reqs]
+    blocker = ss.request_scene(seed=5103, n_poses=600, vox_per_pose=60)
+    with ba.Server(8 * GB, slots=1, batch=4, **kw) as srv:
+        rb = srv.submit_scene(blocker)
+        t0 = time.time()
+        while srv.query(rb)["state"] == ba._lib.REQ_QUEUED and time.time() - t0 < 60:
+            time.sleep(0.001)
+        ids = [srv.submit_scene(r) for r in reqs]
+        while srv.query(ids[2])["state"] != ba._lib.REQ_RUNNING and time.time() - t0 < 60:
+            time.sleep(0.001)
+        time.sleep(0.02)
+        srv.cancel(ids[2])
+        res = [srv.wait_any(i) for i in ids]
+        srv.wait(rb)
+    Pc, sc_ = res[2]
+    assert sc_["state"] == ba._lib.REQ_CANCELLED
+    assert 0 < sc_["report"]["iters"] < 400
+    assert not np.array_equal(Pc, reqs[2].poses_init)
+    for k in (0, 1, 3):
+        assert res[k][1]["state"] == ba._lib.REQ_DONE
+        assert np.array_equal(res[k][0], alone[k][0])
+        assert res[k][1]["report"] == alone[k][1]["report"]
+    assert len({s["t_admit"] for _, s in res}) == 1
