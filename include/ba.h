@@ -133,7 +133,7 @@ typedef struct ba_lm_report {  /* one per window */
     int32_t iters;        /* solves run */
     int32_t n_accepted;
     int32_t converged;    /* ||g|| < tol_g reached */
-    int32_t last_info;    /* pivot failure of the last solve (0 = none) */
+    int32_t last_info;    /* solve failure of the last step: 0 none, a pivot index + 1, or -1 (dataflow wait gave up) */
     double cost_initial;
     double cost_final;
     double gnorm_final;   /* ||g|| at the last evaluated point */
@@ -235,11 +235,13 @@ size_t ba_solve_increment_workspace(int32_t mode, int32_t n_scans);
  * scan no voxel constrains would otherwise make singular).
  *   BA_MODE_MM: n_scans independent 6x6 LDL^T factorizations; hess is [N][36].
  *   BA_MODE_COUPLED (or BA_MODE_EXACT): one dense Cholesky of the (6N)^2
- *   row-major hess, blocked, trailing updates on FP64 matrix cores; hess
- *   is symmetric and only its lower triangle is read.
+ *   row-major hess by 64 x 64 tiles on FP64 matrix cores: up to 6144 rows
+ *   in one persistent dataflow launch, larger ones blocked with one launch
+ *   per step; hess is symmetric and only its lower triangle is read.
  * hess, grad: device inputs (unchanged).  dx: device [N][6] output.
- * info: device int32 output, 0 or the 1-based index of the first
- * non-positive pivot (dx is then zero).  ws: device workspace of at least
+ * info: device int32 output, 0, the 1-based index of the first
+ * non-positive pivot, or -1 if a bounded wait of the dataflow launch gave
+ * up (dx is zero unless info is 0).  ws: device workspace of at least
  * ba_solve_increment_workspace(mode, n_scans) bytes.  Asynchronous.
  */
 ba_status ba_solve_increment(int32_t mode, int32_t n_scans, const double *hess, const double *grad, double mu,

@@ -337,18 +337,14 @@ __device__ __forceinline__ void store_chunk(double *__restrict__ lds, const doub
     }
 }
 
-// tile(64x64) = A(rows ra.., cols ka..ka+kw-1) * B(rows rb.., cols kb..kb+kw-1)^T,
-// result in acc.  The next K chunk is loaded into registers while the
-// matrix cores work on the current one.
-__device__ __forceinline__ void tile_gemm_nt(double *__restrict__ As, double *__restrict__ Bs,
-                                             const double *__restrict__ A, int64_t lda, int64_t ra, int64_t ka,
-                                             int64_t nra, int64_t nca, const double *__restrict__ B, int64_t ldb,
-                                             int64_t rb, int64_t kb, int64_t nrb, int64_t ncb, d4 acc[2][2],
-                                             int kw = 64) {
-#pragma unroll
-    for (int i = 0; i < 2; i++)
-#pragma unroll
-        for (int j = 0; j < 2; j++) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+// acc += A(rows ra.., cols ka..ka+kw-1) * B(rows rb.., cols kb..kb+kw-1)^T for
+// a 64 x 64 tile (kw a multiple of 32).  The next K chunk is loaded into
+// registers while the matrix cores work on the current one.
+__device__ __forceinline__ void tile_gemm_nt_acc(double *__restrict__ As, double *__restrict__ Bs,
+                                                 const double *__restrict__ A, int64_t lda, int64_t ra, int64_t ka,
+                                                 int64_t nra, int64_t nca, const double *__restrict__ B, int64_t ldb,
+                                                 int64_t rb, int64_t kb, int64_t nrb, int64_t ncb, d4 acc[2][2],
+                                                 int kw) {
     double va[8], vb[8];
     load_chunk(va, A, lda, ra, ka, nra, nca);
     load_chunk(vb, B, ldb, rb, kb, nrb, ncb);
@@ -363,6 +359,19 @@ __device__ __forceinline__ void tile_gemm_nt(double *__restrict__ As, double *__
         mma_chunk(As, Bs, acc);
         __syncthreads();
     }
+}
+
+// The same product into a cleared accumulator.
+__device__ __forceinline__ void tile_gemm_nt(double *__restrict__ As, double *__restrict__ Bs,
+                                             const double *__restrict__ A, int64_t lda, int64_t ra, int64_t ka,
+                                             int64_t nra, int64_t nca, const double *__restrict__ B, int64_t ldb,
+                                             int64_t rb, int64_t kb, int64_t nrb, int64_t ncb, d4 acc[2][2],
+                                             int kw = 64) {
+#pragma unroll
+    for (int i = 0; i < 2; i++)
+#pragma unroll
+        for (int j = 0; j < 2; j++) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+    tile_gemm_nt_acc(As, Bs, A, lda, ra, ka, nra, nca, B, ldb, rb, kb, nrb, ncb, acc, kw);
 }
 
 // element (row, col) of the 64x64 tile held in acc[rb][cb][r] by this lane
@@ -515,15 +524,18 @@ __device__ __forceinline__ void inverse_off_blocks(const double *__restrict__ T,
     }
 }
 
-// Store, by one wave, the finished columns of panel pp (the lower triangle of
-// the nb x nb block within them) and the panel's rows of the forward result.
+// Store, by one wave, the panel's rows of the forward result and (store_L)
+// the finished columns of panel pp (the lower triangle of the nb x nb block
+// within them).
 __device__ __forceinline__ void write_panel_L(const double *__restrict__ T, const double *__restrict__ yv,
                                               double *__restrict__ A, double *__restrict__ y, int64_t n, int64_t k0,
-                                              int nb, int pp, int lane) {
+                                              int nb, int pp, int lane, bool store_L) {
     const int c = PB * pp + (lane & 15);
+    if (store_L) {
 #pragma unroll 4
-    for (int r = PB * pp + (lane >> 4); r < nb; r += 4)
-        if (c <= r) A[(k0 + r) * n + k0 + c] = T[r * LTS + c];
+        for (int r = PB * pp + (lane >> 4); r < nb; r += 4)
+            if (c <= r) A[(k0 + r) * n + k0 + c] = T[r * LTS + c];
+    }
     if (lane < PB && PB * pp + lane < nb) y[PB * pp + lane] = yv[PB * pp + lane];
 }
 
@@ -536,9 +548,21 @@ __device__ __forceinline__ void write_inverse_rows(const double *__restrict__ X,
         linv[r * TB + lane] = (lane < PB * (q + 1)) ? X[r * LTS + lane] : 0.0;
 }
 
-// Factor diagonal block `step` (A_kk = L L^T), forward-substitute its slice of
-// the right-hand side (y = L^-1 b) and invert the factor (X = L^-1), with four
-// wavefronts and the tile held in LDS, blocked by 16 x 16 blocks:
+// Element (r, c) of a diagonal tile into the LDS layout the factor expects:
+// the lower triangle in place and, inside the 16 x 16 diagonal blocks, its
+// mirror in the upper one (identity outside the nb x nb block).  Stores with
+// nothing to write go to the unused padding column.
+__device__ __forceinline__ void put_diag_elem(double *__restrict__ T, int r, int c, int nb, double v) {
+    const double e = (r < nb && c < nb) ? v : (r == c ? 1.0 : 0.0);
+    const bool same = (r / PB) == (c / PB);
+    T[(c > r && same) ? r * LTS + TB : r * LTS + c] = e;
+    T[(c < r && same) ? c * LTS + r : r * LTS + TB] = e;
+}
+
+// Factor one 64 x 64 diagonal block (A_kk = L L^T), forward-substitute its
+// slice of the right-hand side (y = L^-1 b) and invert the factor
+// (X = L^-1), with four wavefronts and the tile held in LDS, blocked by
+// 16 x 16 blocks:
 //  - factorization, right-looking by 16-column panels.  Wave 0 factors a
 //    panel with lane r holding row r's 16 panel entries in registers.  The
 //    pivot's column is taken from row pr of lane pr (the panel's diagonal
@@ -559,52 +583,24 @@ __device__ __forceinline__ void write_inverse_rows(const double *__restrict__ X,
 // Only the lower triangle of the tile is read; the 16 x 16 diagonal blocks are
 // mirrored in LDS and kept in both triangles by the trailing updates, so a
 // panel reads its rows straight from the tile.
-// A pivot that is not a positive normal number stops the factorization
-// (prm.info = its index + 1); the panels stored before it are left in the
-// work buffer, which no later kernel reads once info is set.
-__global__ __launch_bounds__(256) void k_potf2(const DenseDesc *__restrict__ desc, DenseParam *__restrict__ prm,
-                                               double *__restrict__ work, int step) {
-    __shared__ __align__(16) double T[TB * LTS];
-    __shared__ __align__(16) double X[TB * LTS];
-    __shared__ double yv[TB];
-    __shared__ double rdiag[TB];
-    __shared__ double pvs[TB];
-    __shared__ int sfail;
-    const int m = blockIdx.y;
-    const DenseParam pm = prm[m];
-    const DenseDesc d = desc[m];
-    if (!pm.active || pm.info) return;
-    const int64_t k0 = (int64_t)TB * step;
-    if (k0 >= d.n) return;
-    const int nb = (int)std::min<int64_t>(TB, d.n - k0);
-    double *A = work + d.a_off;
+// The block is held in T (layout of put_diag_elem) with the right-hand side
+// slice in yv; X, rdiag, pvs and sfail are LDS work space (sfail zero on
+// entry).  The caller has synchronised after filling them.  Writes y to
+// y[0..nb), L^-1 (64 x 64, zero above the diagonal) to linv and, with
+// store_L, the lower triangle of L to the block at A[k0.., k0..] (row stride
+// n; no later step reads it: the solves use L^-1).  Returns 0,
+// or the 1-based row index of a pivot that is not a positive normal number:
+// the factorization stops there (the caller records it as prm.info; the
+// panels stored before it are left in the work buffer, which no later kernel
+// reads once info is set).
+__device__ __forceinline__ int factor_diag_tile(double *__restrict__ T, double *__restrict__ X,
+                                                double *__restrict__ yv, double *__restrict__ rdiag,
+                                                double *__restrict__ pvs, int &sfail, double *__restrict__ A,
+                                                int64_t n, int64_t k0, int nb, double *__restrict__ y,
+                                                double *__restrict__ linv, bool store_L) {
     const int t = threadIdx.x;
     const int w = t >> 6;
     const int i = t & 63;
-    {   // the tile (identity outside the nb x nb block); only its lower
-        // triangle is used: inside the 16 x 16 diagonal blocks it is mirrored
-        // into the upper one.  The loads are unconditional from a clamped
-        // in-bounds address so that all of them are in flight at once; stores
-        // with nothing to write go to the unused padding column.
-        double v[TB / 4];
-        const int ci = std::min(i, nb - 1);
-#pragma unroll
-        for (int u = 0; u < TB / 4; u++) {
-            const int r = std::min(w + 4 * u, nb - 1);
-            v[u] = A[(k0 + r) * d.n + k0 + ci];
-        }
-#pragma unroll
-        for (int u = 0; u < TB / 4; u++) {
-            const int r = w + 4 * u;
-            const double e = (r < nb && i < nb) ? v[u] : (r == i ? 1.0 : 0.0);
-            const bool same = (r / PB) == (i / PB);
-            T[(i > r && same) ? r * LTS + TB : r * LTS + i] = e;
-            T[(i < r && same) ? i * LTS + r : r * LTS + TB] = e;
-        }
-    }
-    if (t < TB) yv[t] = work[d.v_off + k0 + std::min(t, nb - 1)] * (t < nb ? 1.0 : 0.0);
-    if (t == 0) sfail = 0;
-    __syncthreads();
 #pragma unroll 1
     for (int p = 0; p < NPB; p++) {
         const int c0 = PB * p;
@@ -660,14 +656,11 @@ __global__ __launch_bounds__(256) void k_potf2(const DenseDesc *__restrict__ des
             // finished parts go out while the factorization continues: the
             // columns and right-hand side rows of the previous panel, and the
             // row block of the inverse completed two panels ago
-            write_panel_L(T, yv, A, work + d.v_off + k0, d.n, k0, nb, p - 1, i);
-            if (p >= 3) write_inverse_rows(X, work + d.linv_off + (int64_t)step * TB * TB, p - 3, i);
+            write_panel_L(T, yv, A, y, n, k0, nb, p - 1, i, store_L);
+            if (p >= 3) write_inverse_rows(X, linv, p - 3, i);
         }
         __syncthreads();
-        if (sfail) {
-            if (t == 0 && sfail <= d.n) prm[m].info = sfail;
-            return;
-        }
+        if (sfail) return sfail;
         // rank-16 update of the trailing blocks (I >= J > p) on matrix cores
         const int nt = NPB - 1 - p;
         const int nblk = nt * (nt + 1) / 2;
@@ -690,11 +683,10 @@ __global__ __launch_bounds__(256) void k_potf2(const DenseDesc *__restrict__ des
     // the rest of the inverse: diagonal block 3 (wave 0) and the two
     // off-diagonal blocks of row block 2 (waves 1, 2), then those of row
     // block 3, one per wave; wave 3 writes the last panel meanwhile
-    double *linv = work + d.linv_off + (int64_t)step * TB * TB;
     if (w == 0) inverse_diag_block(T, X, rdiag, NPB - 1);
     else if (w == 1) inverse_off_blocks(T, X, NPB - 2, 1, 2);
     else if (w == 2) inverse_off_blocks(T, X, NPB - 2, 0, 1);
-    else write_panel_L(T, yv, A, work + d.v_off + k0, d.n, k0, nb, NPB - 1, i);
+    else write_panel_L(T, yv, A, y, n, k0, nb, NPB - 1, i, store_L);
     __syncthreads();
     if (w < NPB - 1) inverse_off_blocks(T, X, NPB - 1, w, w + 1);
     else write_inverse_rows(X, linv, 1, i);
@@ -706,6 +698,47 @@ __global__ __launch_bounds__(256) void k_potf2(const DenseDesc *__restrict__ des
         const int r = 2 * PB + (e >> 6), c = e & 63;
         linv[r * TB + c] = (r / PB >= c / PB) ? X[r * LTS + c] : 0.0;
     }
+    return 0;
+}
+
+__global__ __launch_bounds__(256) void k_potf2(const DenseDesc *__restrict__ desc, DenseParam *__restrict__ prm,
+                                               double *__restrict__ work, int step) {
+    __shared__ __align__(16) double T[TB * LTS];
+    __shared__ __align__(16) double X[TB * LTS];
+    __shared__ double yv[TB];
+    __shared__ double rdiag[TB];
+    __shared__ double pvs[TB];
+    __shared__ int sfail;
+    const int m = blockIdx.y;
+    const DenseParam pm = prm[m];
+    const DenseDesc d = desc[m];
+    if (!pm.active || pm.info) return;
+    const int64_t k0 = (int64_t)TB * step;
+    if (k0 >= d.n) return;
+    const int nb = (int)std::min<int64_t>(TB, d.n - k0);
+    double *A = work + d.a_off;
+    const int t = threadIdx.x;
+    const int w = t >> 6;
+    const int i = t & 63;
+    {   // the tile; only its lower triangle is read.  The loads are
+        // unconditional from a clamped in-bounds address so that all of them
+        // are in flight at once.
+        double v[TB / 4];
+        const int ci = std::min(i, nb - 1);
+#pragma unroll
+        for (int u = 0; u < TB / 4; u++) {
+            const int r = std::min(w + 4 * u, nb - 1);
+            v[u] = A[(k0 + r) * d.n + k0 + ci];
+        }
+#pragma unroll
+        for (int u = 0; u < TB / 4; u++) put_diag_elem(T, w + 4 * u, i, nb, v[u]);
+    }
+    if (t < TB) yv[t] = work[d.v_off + k0 + std::min(t, nb - 1)] * (t < nb ? 1.0 : 0.0);
+    if (t == 0) sfail = 0;
+    __syncthreads();
+    const int f = factor_diag_tile(T, X, yv, rdiag, pvs, sfail, A, d.n, k0, nb, work + d.v_off + k0,
+                                   work + d.linv_off + (int64_t)step * TB * TB, true);
+    if (f && t == 0 && f <= d.n) prm[m].info = f;
 }
 
 // Panel solve on matrix cores: rows below block `step`:  P <- P L_kk^-T,
@@ -948,6 +981,479 @@ __global__ __launch_bounds__(256) void k_backsub2(const DenseDesc *__restrict__ 
     }
 }
 
+// ---------------------------------------------------------------- dataflow factorization
+// One persistent launch factors a set of matrices and forward-substitutes
+// their right-hand sides (A = L L^T, y = L^-1 b, and L_kk^-1 per diagonal
+// block for the back substitution), with the same 64 x 64 tiles as the
+// launch-per-step path.  Work is taken from one queue by running workgroups
+// (an atomic ticket), in this order:
+//  - one walker per matrix.  For j = 0, 1, ... it takes the diagonal tile's
+//    partial sum P_jj = A_jj - sum_{k<j-1} L_jk L_jk^T, subtracts the last
+//    term L_j,j-1 L_j,j-1^T (held in LDS from its previous step), factors and
+//    inverts the block (factor_diag_tile), then solves the tile below,
+//    L_j+1,j = P_j+1,j L_jj^-T, with the inverse still in LDS.  Only the
+//    walker's work lies on the critical path, and it never waits for a
+//    launch boundary;
+//  - by column c = 0, 1, ...: tile tasks L_ic = (A_ic - sum_{k<c} L_ik L_ck^T)
+//    L_cc^-T for i >= c + 2, then the two partial sums of row r = c + 2 that
+//    the walker takes at its steps r - 1 and r: P_r,r-1 = A_r,r-1 -
+//    sum_{k<=c} L_rk L_r-1,k^T, and P_rr with the right-hand side rows
+//    b_r - sum_{k<=c} L_rk y_k, each left in place.
+// A task accumulates its sums over k in order as the tiles L_.k become final,
+// so each result is formed in a fixed order whatever the schedule.
+// Completion is published with per-tile flags: every thread's stores, an
+// agent-scope release fence (written back from the XCD's L2), then the flag;
+// a consumer polls the flag and takes an agent-scope acquire fence before
+// reading.  A task waits only for tasks earlier in the queue, and a task is
+// taken only by a running workgroup, so the earliest unfinished task can
+// always proceed.  Every wait is bounded: after `limit` polls the launch is
+// aborted (all waits end, prm.info = -1 for the matrices not finished);
+// a pivot failure abandons the matrix (prm.info as in k_potf2).
+struct FlowTask {
+    int32_t m, kind, i, c;
+};
+static constexpr int FLOW_WALK = 0, FLOW_TILE = 1, FLOW_POFF = 2, FLOW_PDIAG = 3;
+static constexpr int FLOW_MAX_MATS = 128;     // walkers per launch
+static constexpr int32_t FLOW_MAX_N = 6144;   // larger matrices take the launch-per-step path
+static constexpr int FLOW_SPIN = 1 << 20;     // polls before a wait gives up (each about 1 us)
+
+// Flags of one matrix with T tile rows: T*T tile flags (i, k), T diagonal
+// flags, T + T partial-sum flags and one "abandoned" flag.
+static inline int64_t flow_flag_ints(int64_t T) { return T * T + 3 * T + 1; }
+
+struct FlowMat {
+    int *fl;   // fl[i * T + k]: tile (i, k) of L final
+    int *dg;   // dg[k]: diagonal block k factored; its inverse and y rows final
+    int *po;   // po[r]: partial sum of tile (r, r - 1) in place
+    int *pd;   // pd[r]: partial sums of tile (r, r) and of rows r of b in place
+    int *ab;   // matrix abandoned
+    int T;
+};
+
+__device__ __forceinline__ int flag_get(int *f) {
+    return __hip_atomic_load(f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Thread 0: polls *f until it is set.  False if the matrix was abandoned, the
+// launch aborted, or `limit` polls went by (which aborts the launch); a
+// negative limit gives up at once.
+__device__ __forceinline__ bool flow_poll(int *f, int *ab, int *gab, int limit) {
+    if (limit < 0) {
+        __hip_atomic_store(gab, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        return false;
+    }
+    for (int it = 0;; it++) {
+        if (flag_get(f)) return true;
+        if (flag_get(ab) || flag_get(gab)) return false;
+        if (it >= limit) {
+            __hip_atomic_store(gab, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            return false;
+        }
+        __builtin_amdgcn_s_sleep(2);
+    }
+}
+
+// All threads: waits until *f is set; false on abandon or abort.
+__device__ __forceinline__ bool flow_wait(int *f, int *ab, int *gab, int limit, int *s_val) {
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        *s_val = flow_poll(f, ab, gab, limit) ? 1 : 0;
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    }
+    __syncthreads();
+    return *s_val != 0;
+}
+
+// All threads: waits until the tiles (rows[q], klo) of L are final and
+// returns the end of the run of columns k in [klo, kend) whose tiles
+// (rows[q], k) all are; -1 on abandon or abort.
+template <int NR>
+__device__ __forceinline__ int flow_wait_cols(const FlowMat &fm, const int (&rows)[NR], int klo, int kend, int *gab,
+                                              int limit, int *s_val) {
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        bool ok = true;
+        for (int q = 0; q < NR && ok; q++) ok = flow_poll(fm.fl + rows[q] * fm.T + klo, fm.ab, gab, limit);
+        int khi = -1;
+        if (ok) {
+            khi = klo + 1;
+            for (; khi < kend; khi++) {
+                bool all = true;
+                for (int q = 0; q < NR; q++) all = all && flag_get(fm.fl + rows[q] * fm.T + khi) != 0;
+                if (!all) break;
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        *s_val = khi;
+    }
+    __syncthreads();
+    return *s_val;
+}
+
+// All threads: makes this workgroup's stores visible at agent scope, then
+// sets *f.
+__device__ __forceinline__ void flow_publish(int *f) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __syncthreads();
+    if (threadIdx.x == 0) __hip_atomic_store(f, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// All threads: waits until *f1 and *f2 are set; false on abandon or abort.
+__device__ __forceinline__ bool flow_wait2(int *f1, int *f2, int *ab, int *gab, int limit, int *s_val) {
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        *s_val = (flow_poll(f1, ab, gab, limit) && flow_poll(f2, ab, gab, limit)) ? 1 : 0;
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    }
+    __syncthreads();
+    return *s_val != 0;
+}
+
+// flow_publish of two flags behind one fence.
+__device__ __forceinline__ void flow_publish2(int *f1, int *f2) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __hip_atomic_store(f1, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(f2, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
+// Tile M[r0.., c0..] (row stride ld) into LDS S (row stride LTS), zero
+// outside nr x nc; the loads are unconditional from clamped addresses.
+__device__ __forceinline__ void tile_to_lds(double *__restrict__ S, const double *__restrict__ M, int64_t ld,
+                                            int64_t r0, int64_t c0, int nr, int nc) {
+    const int c = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int cc = min(c, nc - 1);
+    double v[TB / 4];
+#pragma unroll
+    for (int u = 0; u < TB / 4; u++) v[u] = M[(r0 + min(w + 4 * u, nr - 1)) * ld + c0 + cc];
+#pragma unroll
+    for (int u = 0; u < TB / 4; u++) {
+        const int r = w + 4 * u;
+        S[r * LTS + c] = (r < nr && c < nc) ? v[u] : 0.0;
+    }
+}
+
+// This thread's elements of tile M[r0.., c0..] in the accumulator layout,
+// zero outside nr x nc.
+__device__ __forceinline__ void tile_to_acc(d4 acc[2][2], const double *__restrict__ M, int64_t ld, int64_t r0,
+                                            int64_t c0, int nr, int nc) {
+    double v[16];
+#pragma unroll
+    for (int rb = 0; rb < 2; rb++)
+#pragma unroll
+        for (int cb = 0; cb < 2; cb++)
+#pragma unroll
+            for (int r = 0; r < 4; r++)
+                v[8 * rb + 4 * cb + r] =
+                    M[(r0 + min((int)ACC_ROW(rb, r), nr - 1)) * ld + c0 + min((int)ACC_COL(cb), nc - 1)];
+#pragma unroll
+    for (int rb = 0; rb < 2; rb++)
+#pragma unroll
+        for (int cb = 0; cb < 2; cb++)
+#pragma unroll
+            for (int r = 0; r < 4; r++)
+                acc[rb][cb][r] = ((int)ACC_ROW(rb, r) < nr && (int)ACC_COL(cb) < nc) ? v[8 * rb + 4 * cb + r] : 0.0;
+}
+
+__device__ __forceinline__ void acc_to_global(const d4 acc[2][2], double *__restrict__ M, int64_t ld, int64_t r0,
+                                              int64_t c0, int nr, int nc) {
+#pragma unroll
+    for (int rb = 0; rb < 2; rb++)
+#pragma unroll
+        for (int cb = 0; cb < 2; cb++)
+#pragma unroll
+            for (int r = 0; r < 4; r++)
+                if ((int)ACC_ROW(rb, r) < nr && (int)ACC_COL(cb) < nc)
+                    M[(r0 + ACC_ROW(rb, r)) * ld + c0 + ACC_COL(cb)] = acc[rb][cb][r];
+}
+
+// Into LDS (row stride LTS), rows >= nr cleared.
+__device__ __forceinline__ void acc_to_lds(const d4 acc[2][2], double *__restrict__ S, int nr) {
+#pragma unroll
+    for (int rb = 0; rb < 2; rb++)
+#pragma unroll
+        for (int cb = 0; cb < 2; cb++)
+#pragma unroll
+            for (int r = 0; r < 4; r++)
+                S[ACC_ROW(rb, r) * LTS + ACC_COL(cb)] = ((int)ACC_ROW(rb, r) < nr) ? acc[rb][cb][r] : 0.0;
+}
+
+__device__ __forceinline__ void acc_sub(d4 a[2][2], const d4 b[2][2]) {
+#pragma unroll
+    for (int rb = 0; rb < 2; rb++)
+#pragma unroll
+        for (int cb = 0; cb < 2; cb++) a[rb][cb] -= b[rb][cb];
+}
+
+__device__ __forceinline__ void acc_zero(d4 a[2][2]) {
+#pragma unroll
+    for (int rb = 0; rb < 2; rb++)
+#pragma unroll
+        for (int cb = 0; cb < 2; cb++) a[rb][cb] = d4{0.0, 0.0, 0.0, 0.0};
+}
+
+// acc += sgn P Q^T for 64 x 64 P and Q in LDS (row stride LTS), this wave's
+// 32 x 32 quadrant.  LOWER: Q is block lower triangular by 16 x 16 blocks and
+// its blocks above the diagonal hold stale data (read as zero).
+template <bool LOWER>
+__device__ __forceinline__ void mma64_nt(const double *__restrict__ P, const double *__restrict__ Q, double sgn,
+                                         d4 acc[2][2]) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int r0 = 32 * (w >> 1), c0 = 32 * (w & 1);
+    const int li = lane & 15, lk = lane >> 4;
+#pragma unroll 4
+    for (int kk = 0; kk < TB; kk += 4) {
+        const int k = kk + lk;
+        const double a0 = sgn * P[(r0 + li) * LTS + k], a1 = sgn * P[(r0 + 16 + li) * LTS + k];
+        double b0 = Q[(c0 + li) * LTS + k], b1 = Q[(c0 + 16 + li) * LTS + k];
+        if (LOWER) {
+            b0 = (k / PB <= (c0 + li) / PB) ? b0 : 0.0;
+            b1 = (k / PB <= (c0 + 16 + li) / PB) ? b1 : 0.0;
+        }
+        acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
+        acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
+        acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
+        acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
+    }
+}
+
+// This thread's share of row t/4 of S y (64 x 64 S in LDS, row stride LTS;
+// the four threads of a row take every fourth column).
+__device__ __forceinline__ double lds_gemv_part(const double *__restrict__ S, const double *__restrict__ y) {
+    const int row = threadIdx.x >> 2, part = threadIdx.x & 3;
+    double s = 0.0;
+#pragma unroll
+    for (int q = 0; q < TB / 4; q++) s = fma(S[row * LTS + part + 4 * q], y[part + 4 * q], s);
+    return s;
+}
+
+__device__ __forceinline__ double row_sum4(double s) {
+    s += __shfl_xor(s, 1, 64);
+    s += __shfl_xor(s, 2, 64);
+    return s;
+}
+
+// acc += L_i. L_i.^T over the columns [ka, ka + kw) (kw a multiple of 32) of
+// the tile row at ra, and this thread's share of L_i. y over the same columns
+// (q, as in lds_gemv_part).  The next K chunk is loaded while the current one
+// is used.
+__device__ __forceinline__ void tile_syrk_y(double *__restrict__ lds, const double *__restrict__ A, int64_t n,
+                                            int64_t ra, int64_t ka, int kw, const double *__restrict__ y,
+                                            d4 acc[2][2], double &q) {
+    double *As = lds, *ys = lds + TB * LDK;
+    const int t = threadIdx.x, row = t >> 2, part = t & 3;
+    double va[8], vy = 0.0;
+    load_chunk(va, A, n, ra, ka, n, n);
+    if (t < 32) vy = y[ka + t];
+    for (int kc = 0; kc < kw; kc += 32) {
+        store_chunk(As, va);
+        if (t < 32) ys[t] = vy;
+        __syncthreads();
+        if (kc + 32 < kw) {
+            load_chunk(va, A, n, ra, ka + kc + 32, n, n);
+            if (t < 32) vy = y[ka + kc + 32 + t];
+        }
+        mma_chunk(As, As, acc);
+#pragma unroll
+        for (int e = 0; e < 8; e++) q = fma(As[row * LDK + part + 4 * e], ys[part + 4 * e], q);
+        __syncthreads();
+    }
+}
+
+// L_ic = P L_cc^-T with P = A_ic - acc: P and the inverse (from global) in
+// LDS, the result in l; the caller stores it.
+__device__ __forceinline__ void flow_solve_tile(const double *__restrict__ A, int64_t n, int64_t R0, int64_t C0,
+                                                int nr, const double *__restrict__ linv_c, const d4 acc[2][2],
+                                                double *__restrict__ Pl, double *__restrict__ Xl, d4 l[2][2]) {
+    d4 p[2][2];
+    tile_to_acc(p, A, n, R0, C0, nr, TB);
+    acc_sub(p, acc);
+    acc_to_lds(p, Pl, nr);
+    tile_to_lds(Xl, linv_c, TB, 0, 0, TB, TB);
+    __syncthreads();
+    acc_zero(l);
+    mma64_nt<false>(Pl, Xl, 1.0, l);
+}
+
+// Helper task on tile row i: the final tile L_ic (FLOW_TILE, i >= c + 2),
+// or a partial sum left in place for the walker (FLOW_POFF: tile (i, i - 1);
+// FLOW_PDIAG: tile (i, i) and rows i of the right-hand side; c = i - 2).
+__device__ __forceinline__ void flow_task(const DenseDesc &d, double *__restrict__ work, const FlowMat &fm,
+                                          int kind, int i, int c, int *gab, int limit, double *__restrict__ lds,
+                                          int *s_val) {
+    const int64_t n = d.n;
+    double *A = work + d.a_off, *v = work + d.v_off;
+    const int j = kind == FLOW_TILE ? c : (kind == FLOW_POFF ? i - 1 : i);   // block row of the second factor
+    const int kend = kind == FLOW_TILE ? c : c + 1;                          // sum over k < kend
+    const int64_t R0 = (int64_t)TB * i, J0 = (int64_t)TB * j;
+    const int nr = (int)std::min<int64_t>(TB, n - R0);
+    d4 acc[2][2];
+    acc_zero(acc);
+    double q = 0.0;
+    const int rows[2] = {i, j};
+    for (int klo = 0; klo < kend;) {
+        const int khi = flow_wait_cols<2>(fm, rows, klo, kend, gab, limit, s_val);
+        if (khi < 0) return;
+        const int64_t ka = (int64_t)TB * klo;
+        if (kind == FLOW_PDIAG)
+            tile_syrk_y(lds, A, n, R0, ka, TB * (khi - klo), v, acc, q);
+        else
+            tile_gemm_nt_acc(lds, lds + TB * LDK, A, n, R0, ka, n, n, A, n, J0, ka, n, n, acc, TB * (khi - klo));
+        klo = khi;
+    }
+    if (kind == FLOW_TILE) {
+        if (!flow_wait(fm.dg + c, fm.ab, gab, limit, s_val)) return;
+        d4 l[2][2];
+        flow_solve_tile(A, n, R0, J0, nr, work + d.linv_off + (int64_t)c * TB * TB, acc, lds, lds + TB * LTS, l);
+        acc_to_global(l, A, n, R0, J0, nr, TB);
+        flow_publish(fm.fl + i * fm.T + c);
+        return;
+    }
+    const int nc = j == i ? nr : TB;
+    d4 p[2][2];
+    tile_to_acc(p, A, n, R0, J0, nr, nc);
+    acc_sub(p, acc);
+    acc_to_global(p, A, n, R0, J0, nr, nc);
+    if (kind == FLOW_PDIAG) {
+        q = row_sum4(q);
+        const int row = threadIdx.x >> 2;
+        if ((threadIdx.x & 3) == 0 && row < nr) v[R0 + row] -= q;
+        flow_publish(fm.pd + i);
+    } else {
+        flow_publish(fm.po + i);
+    }
+}
+
+// Marks the matrix abandoned: a pivot failure (f > 0) or an aborted wait.
+__device__ __forceinline__ void flow_abandon(DenseParam *__restrict__ pm, const FlowMat &fm, int f) {
+    if (threadIdx.x == 0) {
+        pm->info = f;
+        __hip_atomic_store(fm.ab, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
+// Walker of one matrix (see above).  LDS: the factor's tile and inverse
+// (lds, lds + TB * LTS), its vectors, and ybuf (y of the previous block).
+// Step j factors D_j (held in dacc, b_j in bq), then waits once for both
+// partial sums of block row j + 1, loads them together, solves L_j+1,j,
+// publishes block j and that tile behind one fence, and forms D_j+1 and
+// b_j+1 with the last terms.  L_jj itself is not stored.
+__device__ __forceinline__ void flow_walk(const DenseDesc &d, DenseParam *__restrict__ pm, double *__restrict__ work,
+                                          const FlowMat &fm, int *gab, int limit, double *__restrict__ lds,
+                                          double *__restrict__ yv, double *__restrict__ rdiag,
+                                          double *__restrict__ pvs, double *__restrict__ ybuf, int &sfail,
+                                          int *s_val) {
+    const int64_t n = d.n;
+    double *A = work + d.a_off, *v = work + d.v_off;
+    double *Tl = lds, *Xl = lds + TB * LTS;
+    const int t = threadIdx.x, row = t >> 2;
+    // block 0 has no partial sums
+    int nb = (int)std::min<int64_t>(TB, n);
+    d4 dacc[2][2];
+    tile_to_acc(dacc, A, n, 0, 0, nb, nb);
+    double bq = (row < nb) ? v[std::min(row, nb - 1)] : 0.0;
+    for (int j = 0; j < fm.T; j++) {
+        const int64_t k0 = (int64_t)TB * j;
+#pragma unroll
+        for (int rb = 0; rb < 2; rb++)
+#pragma unroll
+            for (int cb = 0; cb < 2; cb++)
+#pragma unroll
+                for (int r = 0; r < 4; r++)
+                    put_diag_elem(Tl, (int)ACC_ROW(rb, r), (int)ACC_COL(cb), nb, dacc[rb][cb][r]);
+        if ((t & 3) == 0) yv[row] = bq;
+        if (t == 0) sfail = 0;
+        __syncthreads();
+        const int f = factor_diag_tile(Tl, Xl, yv, rdiag, pvs, sfail, A, n, k0, nb, v + k0,
+                                       work + d.linv_off + (int64_t)j * TB * TB, false);
+        if (f) {
+            flow_abandon(pm, fm, f);
+            return;
+        }
+        __syncthreads();
+        if (t < TB) ybuf[t] = yv[t];
+        if (j + 1 >= fm.T) {
+            flow_publish(fm.dg + j);
+            break;
+        }
+        // partial sums of block row j + 1 (raw for j = 0)
+        if (j >= 1 && !flow_wait2(fm.po + j + 1, fm.pd + j + 1, fm.ab, gab, limit, s_val)) {
+            flow_abandon(pm, fm, -1);
+            return;
+        }
+        const int64_t r0 = k0 + TB;
+        const int nr = (int)std::min<int64_t>(TB, n - r0);
+        tile_to_lds(Tl, A, n, r0, k0, nr, TB);
+        tile_to_acc(dacc, A, n, r0, r0, nr, nr);
+        bq = (row < nr) ? v[r0 + std::min(row, nr - 1)] : 0.0;
+        __syncthreads();
+        // L_j+1,j = P_j+1,j L_jj^-T with the inverse in LDS
+        d4 l[2][2];
+        acc_zero(l);
+        mma64_nt<true>(Tl, Xl, 1.0, l);
+        acc_to_global(l, A, n, r0, k0, nr, TB);
+        flow_publish2(fm.dg + j, fm.fl + (j + 1) * fm.T + j);
+        acc_to_lds(l, Xl, nr);
+        __syncthreads();
+        // D_j+1 and b_j+1: the last terms
+        mma64_nt<false>(Xl, Xl, -1.0, dacc);
+        bq -= row_sum4(lds_gemv_part(Xl, ybuf));
+        nb = nr;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_chol_flow(const DenseDesc *__restrict__ desc, DenseParam *__restrict__ prm,
+                                                   double *__restrict__ work, const FlowTask *__restrict__ tasks,
+                                                   int32_t n_tasks, int *__restrict__ flags,
+                                                   const int64_t *__restrict__ fo, int *__restrict__ queue,
+                                                   int *__restrict__ gab, int limit) {
+    __shared__ __align__(16) double lds[2 * TB * LTS];
+    __shared__ double yv[TB], rdiag[TB], pvs[TB], ybuf[TB];
+    __shared__ int s_task, s_val, sfail;
+    for (;;) {
+        __syncthreads();
+        if (threadIdx.x == 0) s_task = atomicAdd(queue, 1);
+        __syncthreads();
+        const int ti = s_task;
+        if (ti >= n_tasks) return;
+        const FlowTask tk = tasks[ti];
+        const DenseParam pm = prm[tk.m];
+        if (!pm.active || pm.info) continue;
+        const DenseDesc d = desc[tk.m];
+        const int T = (d.n + TB - 1) / TB;
+        int *fb = flags + fo[tk.m];
+        const FlowMat fm{fb, fb + T * T, fb + T * T + T, fb + T * T + 2 * T, fb + T * T + 3 * T, T};
+        if (tk.kind == FLOW_WALK)
+            flow_walk(d, prm + tk.m, work, fm, gab, limit, lds, yv, rdiag, pvs, ybuf, sfail, &s_val);
+        else
+            flow_task(d, work, fm, tk.kind, tk.i, tk.c, gab, limit, lds, &s_val);
+    }
+}
+
+// Task list of one matrix with T tile rows (the standalone solve): thread c
+// writes the tasks of column c after the walker.
+__global__ void k_flow_tasks_one(int32_t T, FlowTask *__restrict__ tasks) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c == 0) tasks[0] = FlowTask{0, FLOW_WALK, 0, 0};
+    if (c >= T) return;
+    int64_t o = 1;
+    for (int cc = 0; cc < c; cc++) o += std::max(0, T - cc - 2) + (cc + 2 <= T - 1 ? 2 : 0);
+    for (int i = c + 2; i < T; i++) tasks[o++] = FlowTask{0, FLOW_TILE, i, c};
+    if (c + 2 <= T - 1) {
+        tasks[o] = FlowTask{0, FLOW_POFF, c + 2, c};
+        tasks[o + 1] = FlowTask{0, FLOW_PDIAG, c + 2, c};
+    }
+}
+
+__global__ void k_fill_i32(int64_t n, int *__restrict__ p, int v) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+static int64_t flow_task_count(int64_t T) { return 1 + (T >= 3 ? (T - 2) * (T - 1) / 2 + 2 * (T - 2) : 0); }
+
 // ---------------------------------------------------------------- LM glue
 // Per-window damping parameters from the LM state and the dense diagonal.
 // Gradient norm of every window with fresh derivatives, formed exactly as
@@ -1120,6 +1626,14 @@ struct DenseState {
     double *work = nullptr;
     double *hdx = nullptr;
     int32_t max_n = 0;
+    // dataflow factorization (every matrix at most FLOW_MAX_N): task list,
+    // per-matrix flags at flow_fo[m], then one queue ticket per launch and the
+    // abort flag; launch q takes tasks [flow_first[q], + flow_count[q])
+    FlowTask *flow_tasks = nullptr;
+    int *flow_flags = nullptr;
+    int64_t *flow_fo = nullptr;
+    int64_t flow_ints = 0;
+    std::vector<int32_t> flow_first, flow_count;
 };
 
 static DenseState *dense_state(Problem *P) { return (DenseState *)P->dense_state; }
@@ -1259,6 +1773,42 @@ ba_status dense_prepare(Problem *P) {
     BA_HIP(hipMemcpy(D->h_off, hoff.data(), sizeof(int64_t) * (W + 1), hipMemcpyHostToDevice));
     BA_HIP(hipMemcpy(D->x_off, xoff.data(), sizeof(int64_t) * W, hipMemcpyHostToDevice));
     BA_HIP(hipMemset(P->dense, 0, sizeof(double) * std::max<int64_t>(h_tot, 1)));
+    if (D->max_n <= FLOW_MAX_N) {
+        // walkers of up to FLOW_MAX_MATS matrices per launch, then their
+        // tasks by column
+        std::vector<FlowTask> tasks;
+        std::vector<int64_t> fo(W);
+        int64_t ints = 0;
+        for (int32_t w = 0; w < W; w++) {
+            fo[w] = ints;
+            ints += flow_flag_ints((desc[w].n + TB - 1) / TB);
+        }
+        for (int32_t m0 = 0; m0 < W; m0 += FLOW_MAX_MATS) {
+            const int32_t m1 = std::min<int32_t>(W, m0 + FLOW_MAX_MATS);
+            D->flow_first.push_back((int32_t)tasks.size());
+            int32_t maxT = 0;
+            for (int32_t m = m0; m < m1; m++) {
+                tasks.push_back(FlowTask{m, FLOW_WALK, 0, 0});
+                maxT = std::max<int32_t>(maxT, (desc[m].n + TB - 1) / TB);
+            }
+            for (int32_t c = 0; c < maxT; c++)
+                for (int32_t m = m0; m < m1; m++) {
+                    const int32_t T = (desc[m].n + TB - 1) / TB;
+                    for (int32_t i = c + 2; i < T; i++) tasks.push_back(FlowTask{m, FLOW_TILE, i, c});
+                    if (c + 2 <= T - 1) {
+                        tasks.push_back(FlowTask{m, FLOW_POFF, c + 2, c});
+                        tasks.push_back(FlowTask{m, FLOW_PDIAG, c + 2, c});
+                    }
+                }
+            D->flow_count.push_back((int32_t)tasks.size() - D->flow_first.back());
+        }
+        D->flow_ints = ints;
+        BA_TRY(D->mem.alloc(&D->flow_tasks, (int64_t)tasks.size()));
+        BA_TRY(D->mem.alloc(&D->flow_flags, ints + (int64_t)D->flow_first.size() + 1));
+        BA_TRY(D->mem.alloc(&D->flow_fo, W));
+        BA_HIP(hipMemcpy(D->flow_tasks, tasks.data(), sizeof(FlowTask) * tasks.size(), hipMemcpyHostToDevice));
+        BA_HIP(hipMemcpy(D->flow_fo, fo.data(), sizeof(int64_t) * W, hipMemcpyHostToDevice));
+    }
     D->ready = true;
     return BA_OK;
 }
@@ -1323,16 +1873,48 @@ ba_status dense_assemble_exact(Problem *P, const double *poses, double *hess_out
     return BA_OK;
 }
 
-static void launch_factor_solve(DenseState *D, int32_t nmat, int32_t max_n, const double *H, const int64_t *h_off,
-                                const double *g, double *x, const int64_t *x_off, hipStream_t s) {
-    const int nsteps = (max_n + TB - 1) / TB;
-    const int64_t nn = (int64_t)max_n * max_n;
-    hipLaunchKernelGGL(k_damp_copy, dim3((unsigned)std::min<int64_t>(nblk(nn), 4096), nmat), dim3(256), 0, s,
-                       D->desc, D->prm, H, h_off, g, D->work);
-    // blocked right-looking Cholesky: panels of PANEL 64-wide steps; a step
-    // updates the rest of its panel, each panel then the trailing matrix with
-    // K = the panel's width (one read and write of the trailing matrix per
-    // panel instead of per step)
+// Compute units of the current device.
+static int cu_count() {
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+        cus = 256;
+    return cus;
+}
+
+// Polls before a wait of the dataflow factorization gives up: FLOW_SPIN, or
+// the environment's BA_FLOW_SPIN (a negative value gives up at once, which
+// the tests use to exercise the abort path).
+static int flow_spin_limit() {
+    const char *e = getenv("BA_FLOW_SPIN");
+    return e ? atoi(e) : FLOW_SPIN;
+}
+
+// Dataflow factorization and forward substitution (k_chol_flow): flags,
+// tickets and the abort flag cleared by a kernel (no memset node in a
+// captured graph), then one persistent launch per group of matrices.
+static void launch_flow_factor(DenseState *D, hipStream_t s) {
+    const int nl = (int)D->flow_first.size();
+    const int64_t nint = D->flow_ints + nl + 1;
+    hipLaunchKernelGGL(k_fill_i32, dim3((unsigned)std::min<int64_t>(nblk(nint), 1024)), dim3(256), 0, s, nint,
+                       D->flow_flags, 0);
+    const int limit = flow_spin_limit();
+    // one workgroup per compute unit: the walker's factor and the row task's
+    // three accumulators need more than half of the register file
+    const int slots = cu_count();
+    for (int q = 0; q < nl; q++) {
+        ProfScope prof("k_chol_flow", s);
+        hipLaunchKernelGGL(k_chol_flow, dim3((unsigned)std::min(D->flow_count[q], slots)), dim3(256), 0, s, D->desc,
+                           D->prm, D->work, D->flow_tasks + D->flow_first[q], D->flow_count[q], D->flow_flags,
+                           D->flow_fo, D->flow_flags + D->flow_ints + q, D->flow_flags + D->flow_ints + nl, limit);
+    }
+}
+
+// Blocked right-looking factorization, one launch per step: panels of PANEL
+// 64-wide steps; a step updates the rest of its panel, each panel then the
+// trailing matrix with K = the panel's width (one read and write of the
+// trailing matrix per panel instead of per step).
+static void launch_blocked_factor(DenseState *D, int32_t nmat, int nsteps, hipStream_t s) {
     constexpr int PANEL = 4;
     for (int p = 0; p < nsteps; p += PANEL) {
         const int pe = std::min(p + PANEL, nsteps);
@@ -1364,6 +1946,18 @@ static void launch_factor_solve(DenseState *D, int32_t nmat, int32_t max_n, cons
                                D->prm, D->work, p, TB * (pe - p), pe, nsteps);
         }
     }
+}
+
+static void launch_factor_solve(DenseState *D, int32_t nmat, int32_t max_n, const double *H, const int64_t *h_off,
+                                const double *g, double *x, const int64_t *x_off, hipStream_t s) {
+    const int nsteps = (max_n + TB - 1) / TB;
+    const int64_t nn = (int64_t)max_n * max_n;
+    hipLaunchKernelGGL(k_damp_copy, dim3((unsigned)std::min<int64_t>(nblk(nn), 4096), nmat), dim3(256), 0, s,
+                       D->desc, D->prm, H, h_off, g, D->work);
+    if (D->flow_tasks && max_n <= FLOW_MAX_N)
+        launch_flow_factor(D, s);
+    else
+        launch_blocked_factor(D, nmat, nsteps, s);
     // backward substitution two block rows per launch, the first row alone
     // when the count is odd
     int st = nsteps - 1;
@@ -1396,9 +1990,21 @@ ba_status dense_lm_step(Problem *P, const double *poses, double tol_g, hipStream
 }
 
 // ---------------------------------------------------------------- standalone solve
+// Workspace of the standalone solve: descriptors, the matrix, the inverse
+// blocks and the right-hand side, then (dataflow path) flags, ticket, abort
+// flag and task list.
+static size_t solve_head_bytes() { return align_up(sizeof(DenseDesc) + sizeof(DenseParam) + 4 * sizeof(int64_t), 256); }
+static size_t solve_work_bytes(int64_t n) {
+    return align_up(sizeof(double) * (size_t)(n * n + linv_doubles(n) + n), 256);
+}
+static size_t solve_flag_bytes(int64_t n) {
+    const int64_t T = (n + TB - 1) / TB;
+    return n <= FLOW_MAX_N ? align_up(sizeof(int) * (size_t)(flow_flag_ints(T) + 2), 256) : 0;
+}
 size_t dense_solve_workspace(int64_t n) {
-    return align_up(sizeof(DenseDesc) + sizeof(DenseParam) + 4 * sizeof(int64_t), 256) +
-           sizeof(double) * (size_t)(n * n + linv_doubles(n) + n) + 256;
+    const int64_t T = (n + TB - 1) / TB;
+    const size_t tasks = n <= FLOW_MAX_N ? sizeof(FlowTask) * (size_t)flow_task_count(T) : 0;
+    return solve_head_bytes() + solve_work_bytes(n) + solve_flag_bytes(n) + tasks + 256;
 }
 
 __global__ void k_solve_setup(int64_t n, const double *__restrict__ H, double mu, DenseDesc *__restrict__ desc,
@@ -1428,6 +2034,7 @@ __global__ void k_solve_setup(int64_t n, const double *__restrict__ H, double mu
         prm[0] = p;
         offs[0] = 0;  // h_off
         offs[1] = 0;  // x_off
+        offs[2] = 0;  // offset of the matrix's flags
     }
 }
 
@@ -1445,12 +2052,22 @@ ba_status dense_solve(int64_t n, const double *A, const double *g, double mu, do
     DenseDesc *desc = (DenseDesc *)p;
     DenseParam *prm = (DenseParam *)(p + sizeof(DenseDesc));
     int64_t *offs = (int64_t *)(p + sizeof(DenseDesc) + sizeof(DenseParam));
-    double *work = (double *)(p + align_up(sizeof(DenseDesc) + sizeof(DenseParam) + 4 * sizeof(int64_t), 256));
+    double *work = (double *)(p + solve_head_bytes());
     hipLaunchKernelGGL(k_solve_setup, dim3(1), dim3(256), 0, s, n, A, mu, desc, prm, offs);
     DenseState tmp;
     tmp.desc = desc;
     tmp.prm = prm;
     tmp.work = work;
+    if (n <= FLOW_MAX_N) {
+        const int64_t T = (n + TB - 1) / TB;
+        tmp.flow_flags = (int *)(p + solve_head_bytes() + solve_work_bytes(n));
+        tmp.flow_tasks = (FlowTask *)(p + solve_head_bytes() + solve_work_bytes(n) + solve_flag_bytes(n));
+        tmp.flow_fo = offs + 2;
+        tmp.flow_ints = flow_flag_ints(T);
+        tmp.flow_first.push_back(0);
+        tmp.flow_count.push_back((int32_t)flow_task_count(T));
+        hipLaunchKernelGGL(k_flow_tasks_one, dim3(nblk(T)), dim3(256), 0, s, (int32_t)T, tmp.flow_tasks);
+    }
     launch_factor_solve(&tmp, 1, (int32_t)n, A, offs, g, dx, offs + 1, s);
     hipLaunchKernelGGL(k_solve_final, dim3(nblk(n)), dim3(256), 0, s, n, prm, dx, info);
     BA_HIP(hipGetLastError());

@@ -78,6 +78,31 @@ def test_batched_windows_equal_solo_bitwise(ba, dev, batch, prec, mode):
         s0 += sw.n_scans
 
 
+def test_coupled_many_windows_equal_solo_bitwise(ba, dev):
+    """More windows than one dataflow launch takes (128): the coupled LM of
+    windows in the first and second launch equals each window alone."""
+    import torch
+    sc = ss.batch_windows(seed=4300, n_windows=130, poses_range=(4, 14), vox_per_pose=20, vox_range=(100, 400),
+                          workers=1)
+    say(f"coupled batch of {sc.n_windows} windows")
+    pb = build_gpu_sums(ba, sc, dev)
+    P = torch.as_tensor(sc.poses_init, device=dev).contiguous()
+    reps, tr = ba.iterate(pb, P, ba.MODE_COUPLED, max_iters=4)
+    pb.close()
+    Pb = P.cpu().numpy()
+    starts = np.concatenate([[0], np.cumsum([ss.window_of(sc, w).n_scans for w in range(sc.n_windows)])])
+    for w in (0, 1, 127, 128, 129):
+        sw = ss.window_of(sc, w)
+        ps = build_gpu_sums(ba, sw, dev)
+        Q = torch.as_tensor(sw.poses_init, device=dev).contiguous()
+        r1, t1 = ba.iterate(ps, Q, ba.MODE_COUPLED, max_iters=4)
+        ps.close()
+        assert np.array_equal(Q.cpu().numpy(), Pb[starts[w]:starts[w + 1]]), f"window {w} poses"
+        assert np.array_equal(t1[:, 0, :], tr[:, w, :]), f"window {w} trace"
+        for k in ("iters", "n_accepted", "cost_final", "gnorm_final", "mu_final"):
+            assert r1[0][k] == reps[w][k], (w, k)
+
+
 @pytest.mark.parametrize("sizes", [(8, 255, 256, 257, 513), (255, 257, 513, 1030)])
 def test_solve_forms_equal_bitwise(ba, dev, sizes):
     """The MM increment solve covers a window with one block per 256 poses,

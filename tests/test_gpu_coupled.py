@@ -87,6 +87,52 @@ def test_dense_cholesky_solve_against_lapack(ba, dev, orc, n):
             assert info_o == 0 and rel(dx.cpu().numpy().ravel(), ref_o) <= 1e-15 * cond * 10
 
 
+@pytest.mark.parametrize("n", [1026, 4098, 6000, 6144])
+def test_dense_solve_large_against_lapack(ba, dev, n):
+    """Sizes where the dataflow factorization has many tile rows, with ragged
+    last tiles (1026, 4098, 6000) and at its size limit (6144)."""
+    import torch
+    say(f"dense solve random SPD n={n}")
+    rng = np.random.default_rng(n)
+    Q = rng.standard_normal((n, 256))
+    H = Q @ Q.T / 256 + np.diag(rng.uniform(0.5, 2.0, n))
+    g = rng.standard_normal(n)
+    dx, info = ba.solve_increment(ba.MODE_COUPLED, torch.as_tensor(H, device=dev), torch.as_tensor(g, device=dev), 0.1)
+    assert int(info.cpu().numpy()[0]) == 0
+    D = np.diag(H)
+    A = H + 0.1 * np.diag(D)
+    ref = np.linalg.solve(A, -g)
+    x = dx.cpu().numpy().ravel()
+    # normwise backward error against LAPACK's own on the same system
+    be = np.linalg.norm(A @ x + g) / (np.linalg.norm(A, 1) * np.linalg.norm(x) + np.linalg.norm(g))
+    be_ref = np.linalg.norm(A @ ref + g) / (np.linalg.norm(A, 1) * np.linalg.norm(ref) + np.linalg.norm(g))
+    assert be <= 16 * max(be_ref, np.finfo(float).eps)
+    assert rel(x, ref) <= 10 * np.finfo(float).eps * np.linalg.cond(A)
+
+
+def test_dense_flow_gives_up_when_told(ba, dev, monkeypatch):
+    """A wait of the dataflow factorization that gives up (forced from the
+    host with a negative poll limit) aborts the launch: the solve reports
+    info = -1 with dx = 0, every kernel ends, and the next solve is exact."""
+    import torch
+    n = 384
+    say(f"dense solve abort path n={n}")
+    rng = np.random.default_rng(11)
+    Q = rng.standard_normal((n, n))
+    H = Q @ Q.T / n + np.eye(n)
+    g = rng.standard_normal(n)
+    Ht, gt = torch.as_tensor(H, device=dev), torch.as_tensor(g, device=dev)
+    monkeypatch.setenv("BA_FLOW_SPIN", "-1")
+    dx, info = ba.solve_increment(ba.MODE_COUPLED, Ht, gt, 0.0)
+    assert int(info.cpu().numpy()[0]) == -1
+    assert np.all(dx.cpu().numpy() == 0)
+    monkeypatch.delenv("BA_FLOW_SPIN")
+    dx, info = ba.solve_increment(ba.MODE_COUPLED, Ht, gt, 0.0)
+    assert int(info.cpu().numpy()[0]) == 0
+    ref = np.linalg.solve(H, -g)
+    assert rel(dx.cpu().numpy().ravel(), ref) <= 1e-15 * np.linalg.cond(H) * 10
+
+
 @pytest.mark.parametrize("n", [90, 198, 384])
 def test_dense_solve_reads_lower_triangle_only(ba, dev, n):
     """The coupled solve uses the lower triangle of hess: noise in the strict
