@@ -982,10 +982,10 @@ __global__ __launch_bounds__(256) void k_backsub2(const DenseDesc *__restrict__ 
 }
 
 // ---------------------------------------------------------------- dataflow factorization
-// One persistent launch factors a set of matrices and forward-substitutes
-// their right-hand sides (A = L L^T, y = L^-1 b, and L_kk^-1 per diagonal
-// block for the back substitution), with the same 64 x 64 tiles as the
-// launch-per-step path.  Work is taken from one queue by running workgroups
+// One persistent launch factors a set of damped matrices and forward-
+// substitutes their right-hand sides (A = L L^T, y = L^-1 b, and L_kk^-1 per
+// diagonal block for the back substitution), with the same 64 x 64 tiles as
+// the launch-per-step path.  Work is taken from one queue by running workgroups
 // (an atomic ticket), in this order:
 //  - one walker per matrix.  For j = 0, 1, ... it takes the diagonal tile's
 //    partial sum P_jj = A_jj - sum_{k<j-1} L_jk L_jk^T, subtracts the last
@@ -995,12 +995,20 @@ __global__ __launch_bounds__(256) void k_backsub2(const DenseDesc *__restrict__ 
 //    walker's work lies on the critical path, and it never waits for a
 //    launch boundary;
 //  - by column c = 0, 1, ...: tile tasks L_ic = (A_ic - sum_{k<c} L_ik L_ck^T)
-//    L_cc^-T for i >= c + 2, then the two partial sums of row r = c + 2 that
-//    the walker takes at its steps r - 1 and r: P_r,r-1 = A_r,r-1 -
-//    sum_{k<=c} L_rk L_r-1,k^T, and P_rr with the right-hand side rows
-//    b_r - sum_{k<=c} L_rk y_k, each left in place.
-// A task accumulates its sums over k in order as the tiles L_.k become final,
-// so each result is formed in a fixed order whatever the schedule.
+//    L_cc^-T for i >= c + 3, then the two partial sums of row r = c + 2 that
+//    the walker takes at its steps r - 1 and r, each left in place: P_rr with
+//    the right-hand side rows b_r - sum_{k<=c} L_rk y_k, and P_r,r-1 =
+//    A_r,r-1 - sum_{k<=c} L_rk L_r-1,k^T.  Both tasks form L_rc themselves
+//    (the same arithmetic, so the same bits), beside their partial sums and
+//    from the raw tile (r, c) they load first; the off-diagonal task stores
+//    and publishes it once the diagonal task has read the raw tile.
+// The raw tiles come straight from the undamped matrix H (damped on the
+// diagonal as they are loaded, A = H + mu max(diag H, floor)) and the raw
+// right-hand side from g (b = -g): each is read once, by the task that first
+// uses it, and no damped copy is made.  Partial sums and L go to the work
+// matrix.  A task accumulates its sums over k in order as the tiles L_.k
+// become final, so each result is formed in a fixed order whatever the
+// schedule.
 // Completion is published with per-tile flags: every thread's stores, an
 // agent-scope release fence (written back from the XCD's L2), then the flag;
 // a consumer polls the flag and takes an agent-scope acquire fence before
@@ -1012,41 +1020,57 @@ __global__ __launch_bounds__(256) void k_backsub2(const DenseDesc *__restrict__ 
 struct FlowTask {
     int32_t m, kind, i, c;
 };
-static constexpr int FLOW_WALK = 0, FLOW_TILE = 1, FLOW_POFF = 2, FLOW_PDIAG = 3;
+static constexpr int FLOW_WALK = 0, FLOW_TILE = 1, FLOW_PDIAG = 2, FLOW_POFF = 3;
 static constexpr int FLOW_MAX_MATS = 128;     // walkers per launch
 static constexpr int32_t FLOW_MAX_N = 6144;   // larger matrices take the launch-per-step path
 static constexpr int FLOW_SPIN = 1 << 20;     // polls before a wait gives up (each about 1 us)
 
 // Flags of one matrix with T tile rows: T*T tile flags (i, k), T diagonal
-// flags, T + T partial-sum flags and one "abandoned" flag.
-static inline int64_t flow_flag_ints(int64_t T) { return T * T + 3 * T + 1; }
+// flags, 3 T flags of the partial-sum tasks and one "abandoned" flag.
+static inline int64_t flow_flag_ints(int64_t T) { return T * T + 4 * T + 1; }
+
+// Pointers with their address space spelled out: the task bodies below are
+// compiled out of line (each with its own register allocation), and their
+// LDS and global accesses must still compile to ds_ and global_ instructions.
+typedef __attribute__((address_space(3))) double lds_f64;
+typedef __attribute__((address_space(3))) int lds_i32;
+typedef __attribute__((address_space(1))) double glb_f64;
+typedef __attribute__((address_space(1))) int glb_i32;
 
 struct FlowMat {
-    int *fl;   // fl[i * T + k]: tile (i, k) of L final
-    int *dg;   // dg[k]: diagonal block k factored; its inverse and y rows final
-    int *po;   // po[r]: partial sum of tile (r, r - 1) in place
-    int *pd;   // pd[r]: partial sums of tile (r, r) and of rows r of b in place
-    int *ab;   // matrix abandoned
+    glb_i32 *fl;   // fl[i * T + k]: tile (i, k) of L final
+    glb_i32 *dg;   // dg[k]: diagonal block k factored; its inverse and y rows final
+    glb_i32 *po;   // po[r]: partial sum of tile (r, r - 1) in place
+    glb_i32 *pd;   // pd[r]: partial sums of tile (r, r) and of rows r of b in place
+    glb_i32 *ra;   // ra[r]: raw tile (r, r - 2) read by the diagonal task
+    glb_i32 *ab;   // matrix abandoned
     int T;
 };
 
-__device__ __forceinline__ int flag_get(int *f) {
-    return __hip_atomic_load(f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+__device__ __forceinline__ int flag_get(glb_i32 *f) {
+    return __hip_atomic_load((int *)f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ void flag_set(glb_i32 *f, int order) {
+    if (order == __ATOMIC_RELEASE)
+        __hip_atomic_store((int *)f, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    else
+        __hip_atomic_store((int *)f, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // Thread 0: polls *f until it is set.  False if the matrix was abandoned, the
 // launch aborted, or `limit` polls went by (which aborts the launch); a
 // negative limit gives up at once.
-__device__ __forceinline__ bool flow_poll(int *f, int *ab, int *gab, int limit) {
+__device__ __forceinline__ bool flow_poll(glb_i32 *f, glb_i32 *ab, glb_i32 *gab, int limit) {
     if (limit < 0) {
-        __hip_atomic_store(gab, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        flag_set(gab, __ATOMIC_RELAXED);
         return false;
     }
     for (int it = 0;; it++) {
         if (flag_get(f)) return true;
         if (flag_get(ab) || flag_get(gab)) return false;
         if (it >= limit) {
-            __hip_atomic_store(gab, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            flag_set(gab, __ATOMIC_RELAXED);
             return false;
         }
         __builtin_amdgcn_s_sleep(2);
@@ -1054,7 +1078,7 @@ __device__ __forceinline__ bool flow_poll(int *f, int *ab, int *gab, int limit) 
 }
 
 // All threads: waits until *f is set; false on abandon or abort.
-__device__ __forceinline__ bool flow_wait(int *f, int *ab, int *gab, int limit, int *s_val) {
+__device__ __forceinline__ bool flow_wait(glb_i32 *f, glb_i32 *ab, glb_i32 *gab, int limit, lds_i32 *s_val) {
     __syncthreads();
     if (threadIdx.x == 0) {
         *s_val = flow_poll(f, ab, gab, limit) ? 1 : 0;
@@ -1068,8 +1092,8 @@ __device__ __forceinline__ bool flow_wait(int *f, int *ab, int *gab, int limit, 
 // returns the end of the run of columns k in [klo, kend) whose tiles
 // (rows[q], k) all are; -1 on abandon or abort.
 template <int NR>
-__device__ __forceinline__ int flow_wait_cols(const FlowMat &fm, const int (&rows)[NR], int klo, int kend, int *gab,
-                                              int limit, int *s_val) {
+__device__ __forceinline__ int flow_wait_cols(const FlowMat &fm, const int (&rows)[NR], int klo, int kend,
+                                              glb_i32 *gab, int limit, lds_i32 *s_val) {
     __syncthreads();
     if (threadIdx.x == 0) {
         bool ok = true;
@@ -1092,14 +1116,15 @@ __device__ __forceinline__ int flow_wait_cols(const FlowMat &fm, const int (&row
 
 // All threads: makes this workgroup's stores visible at agent scope, then
 // sets *f.
-__device__ __forceinline__ void flow_publish(int *f) {
+__device__ __forceinline__ void flow_publish(glb_i32 *f) {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     __syncthreads();
-    if (threadIdx.x == 0) __hip_atomic_store(f, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    if (threadIdx.x == 0) flag_set(f, __ATOMIC_RELEASE);
 }
 
 // All threads: waits until *f1 and *f2 are set; false on abandon or abort.
-__device__ __forceinline__ bool flow_wait2(int *f1, int *f2, int *ab, int *gab, int limit, int *s_val) {
+__device__ __forceinline__ bool flow_wait2(glb_i32 *f1, glb_i32 *f2, glb_i32 *ab, glb_i32 *gab, int limit,
+                                           lds_i32 *s_val) {
     __syncthreads();
     if (threadIdx.x == 0) {
         *s_val = (flow_poll(f1, ab, gab, limit) && flow_poll(f2, ab, gab, limit)) ? 1 : 0;
@@ -1110,12 +1135,12 @@ __device__ __forceinline__ bool flow_wait2(int *f1, int *f2, int *ab, int *gab, 
 }
 
 // flow_publish of two flags behind one fence.
-__device__ __forceinline__ void flow_publish2(int *f1, int *f2) {
+__device__ __forceinline__ void flow_publish2(glb_i32 *f1, glb_i32 *f2) {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     __syncthreads();
     if (threadIdx.x == 0) {
-        __hip_atomic_store(f1, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-        __hip_atomic_store(f2, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        flag_set(f1, __ATOMIC_RELEASE);
+        flag_set(f2, __ATOMIC_RELAXED);
     }
 }
 
@@ -1262,114 +1287,346 @@ __device__ __forceinline__ void tile_syrk_y(double *__restrict__ lds, const doub
     }
 }
 
-// L_ic = P L_cc^-T with P = A_ic - acc: P and the inverse (from global) in
-// LDS, the result in l; the caller stores it.
-__device__ __forceinline__ void flow_solve_tile(const double *__restrict__ A, int64_t n, int64_t R0, int64_t C0,
-                                                int nr, const double *__restrict__ linv_c, const d4 acc[2][2],
-                                                double *__restrict__ Pl, double *__restrict__ Xl, d4 l[2][2]) {
+// ---- the walker's tile products, shaped by their triangular operands
+// A 64 x 64 diagonal tile by its ten lower 16 x 16 blocks (rb >= cb, taken
+// in the order (0,0), (1,0), (1,1), (2,0), ..., (3,3)): wave w holds blocks
+// w, w + 4 and (waves 0, 1) w + 8, each in the v_mfma_f64_16x16x4f64
+// accumulator layout.
+struct LowTile {
+    d4 b[3];
+};
+
+__device__ __forceinline__ void low_block(int q, int &rb, int &cb) {
+    rb = q >= 6 ? 3 : (q >= 3 ? 2 : (q >= 1 ? 1 : 0));
+    cb = q - rb * (rb + 1) / 2;
+}
+
+// Loads the lower blocks of tile M[r0.., r0..] (row stride ld), zero outside
+// nb x nb (loads from clamped addresses).
+__device__ __forceinline__ void low_load(LowTile &D, const double *__restrict__ M, int64_t ld, int64_t r0, int nb) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, li = lane & 15, lk = lane >> 4;
+    double v[12];
+#pragma unroll
+    for (int s = 0; s < 3; s++) {
+        int rb, cb;
+        low_block(w + 4 * s, rb, cb);
+        if (s == 2 && w >= 2) rb = cb = 0;
+#pragma unroll
+        for (int r = 0; r < 4; r++) {
+            const int row = 16 * rb + lk + 4 * r, col = 16 * cb + li;
+            v[4 * s + r] = M[(r0 + min(row, nb - 1)) * ld + r0 + min(col, nb - 1)];
+        }
+    }
+#pragma unroll
+    for (int s = 0; s < 3; s++) {
+        int rb, cb;
+        low_block(w + 4 * s, rb, cb);
+#pragma unroll
+        for (int r = 0; r < 4; r++) {
+            const int row = 16 * rb + lk + 4 * r, col = 16 * cb + li;
+            D.b[s][r] = (row < nb && col < nb) ? v[4 * s + r] : 0.0;
+        }
+    }
+}
+
+// The damped diagonal of a tile of H (as in damp_diag_tile).
+__device__ __forceinline__ void low_damp(LowTile &D, double mu, double floor_) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, li = lane & 15, lk = lane >> 4;
+#pragma unroll
+    for (int s = 0; s < 3; s++) {
+        int rb, cb;
+        low_block(w + 4 * s, rb, cb);
+        if (rb != cb || (s == 2 && w >= 2)) continue;
+#pragma unroll
+        for (int r = 0; r < 4; r++)
+            if (lk + 4 * r == li) {
+                const double x = D.b[s][r];
+                D.b[s][r] = x + mu * (x > floor_ ? x : floor_);
+            }
+    }
+}
+
+// D -= L L^T on the lower blocks, L (64 x 64) in LDS with row stride LTS.
+__device__ __forceinline__ void low_syrk_sub(LowTile &D, const double *__restrict__ L) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, li = lane & 15, lk = lane >> 4;
+#pragma unroll
+    for (int s = 0; s < 3; s++) {
+        if (s == 2 && w >= 2) break;
+        int rb, cb;
+        low_block(w + 4 * s, rb, cb);
+        d4 a0 = D.b[s], a1 = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int kk = 0; kk < TB; kk += 8) {
+            const double x0 = -L[(16 * rb + li) * LTS + kk + lk], y0 = L[(16 * cb + li) * LTS + kk + lk];
+            const double x1 = -L[(16 * rb + li) * LTS + kk + 4 + lk], y1 = L[(16 * cb + li) * LTS + kk + 4 + lk];
+            a0 = __builtin_amdgcn_mfma_f64_16x16x4f64(x0, y0, a0, 0, 0, 0);
+            a1 = __builtin_amdgcn_mfma_f64_16x16x4f64(x1, y1, a1, 0, 0, 0);
+        }
+        D.b[s] = a0 + a1;
+    }
+}
+
+// The lower blocks into the factor's LDS layout (put_diag_elem); the blocks
+// above the diagonal are never read.
+__device__ __forceinline__ void low_put(const LowTile &D, double *__restrict__ T, int nb) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, li = lane & 15, lk = lane >> 4;
+#pragma unroll
+    for (int s = 0; s < 3; s++) {
+        if (s == 2 && w >= 2) break;
+        int rb, cb;
+        low_block(w + 4 * s, rb, cb);
+#pragma unroll
+        for (int r = 0; r < 4; r++) put_diag_elem(T, 16 * rb + lk + 4 * r, 16 * cb + li, nb, D.b[s][r]);
+    }
+}
+
+// L = P X^T for P (64 x 64) and X lower triangular (64 x 64, blocks above its
+// diagonal blocks stale), both in LDS with row stride LTS: wave w forms row
+// block w, each column block cb over k < 16 (cb + 1) only.  Element (cb, r)
+// of this lane is row 16 w + lane/16 + 4 r, column 16 cb + lane%16.
+struct RowTile {
+    d4 c[4];
+};
+
+__device__ __forceinline__ void rows_trsm(const double *__restrict__ P, const double *__restrict__ X, RowTile &L) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, li = lane & 15, lk = lane >> 4;
+#pragma unroll
+    for (int cb = 0; cb < 4; cb++) L.c[cb] = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int kk = 0; kk < TB; kk += 4) {
+        const double a = P[(16 * w + li) * LTS + kk + lk];
+#pragma unroll
+        for (int cb = kk / 16; cb < 4; cb++)
+            L.c[cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, X[(16 * cb + li) * LTS + kk + lk], L.c[cb], 0, 0, 0);
+    }
+}
+
+__device__ __forceinline__ void rows_to_global(const RowTile &L, double *__restrict__ M, int64_t ld, int64_t r0,
+                                               int64_t c0, int nr) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, li = lane & 15, lk = lane >> 4;
+#pragma unroll
+    for (int cb = 0; cb < 4; cb++)
+#pragma unroll
+        for (int r = 0; r < 4; r++) {
+            const int row = 16 * w + lk + 4 * r;
+            if (row < nr) M[(r0 + row) * ld + c0 + 16 * cb + li] = L.c[cb][r];
+        }
+}
+
+// Into LDS (row stride LTS), rows >= nr cleared.
+__device__ __forceinline__ void rows_to_lds(const RowTile &L, double *__restrict__ S, int nr) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, li = lane & 15, lk = lane >> 4;
+#pragma unroll
+    for (int cb = 0; cb < 4; cb++)
+#pragma unroll
+        for (int r = 0; r < 4; r++) {
+            const int row = 16 * w + lk + 4 * r;
+            S[row * LTS + 16 * cb + li] = row < nr ? L.c[cb][r] : 0.0;
+        }
+}
+
+// Raw operands of one matrix: H (its row-major undamped block), g (its slice
+// of the gradient) and the damping.
+struct FlowRaw {
+    glb_f64 *H;
+    glb_f64 *g;
+    double mu, floor_;
+};
+
+// A diagonal tile of H in the accumulator layout, damped on the diagonal
+// as the damped system has it.
+__device__ __forceinline__ void damp_diag_tile(d4 a[2][2], const FlowRaw &rw) {
+#pragma unroll
+    for (int rb = 0; rb < 2; rb++)
+#pragma unroll
+        for (int cb = 0; cb < 2; cb++)
+#pragma unroll
+            for (int r = 0; r < 4; r++)
+                if (ACC_ROW(rb, r) == ACC_COL(cb)) {
+                    const double v = a[rb][cb][r];
+                    a[rb][cb][r] = v + rw.mu * (v > rw.floor_ ? v : rw.floor_);
+                }
+}
+
+// L_ic = P L_cc^-T with P = raw - acc (raw: the tile A_ic as loaded): P
+// and the inverse (from global) in LDS, the result in l (rows_trsm layout);
+// the caller stores it.
+__device__ __forceinline__ void flow_solve_tile(const d4 raw[2][2], int nr, const double *__restrict__ linv_c,
+                                                const d4 acc[2][2], double *__restrict__ Pl, double *__restrict__ Xl,
+                                                RowTile &l) {
     d4 p[2][2];
-    tile_to_acc(p, A, n, R0, C0, nr, TB);
-    acc_sub(p, acc);
+#pragma unroll
+    for (int rb = 0; rb < 2; rb++)
+#pragma unroll
+        for (int cb = 0; cb < 2; cb++) p[rb][cb] = raw[rb][cb] - acc[rb][cb];
     acc_to_lds(p, Pl, nr);
     tile_to_lds(Xl, linv_c, TB, 0, 0, TB, TB);
     __syncthreads();
-    acc_zero(l);
-    mma64_nt<false>(Pl, Xl, 1.0, l);
+    rows_trsm(Pl, Xl, l);
 }
 
-// Helper task on tile row i: the final tile L_ic (FLOW_TILE, i >= c + 2),
-// or a partial sum left in place for the walker (FLOW_POFF: tile (i, i - 1);
-// FLOW_PDIAG: tile (i, i) and rows i of the right-hand side; c = i - 2).
-__device__ __forceinline__ void flow_task(const DenseDesc &d, double *__restrict__ work, const FlowMat &fm,
-                                          int kind, int i, int c, int *gab, int limit, double *__restrict__ lds,
-                                          int *s_val) {
+// Diagonal partial task of row r = c + 2: P_rr = A_rr - sum_{k<=c} L_rk L_rk^T
+// and b_r - sum_{k<=c} L_rk y_k, with L_rc formed here from the raw tile; the
+// results go to the work matrix and right-hand side.
+__device__ __noinline__ void flow_pdiag(const DenseDesc d, glb_f64 *gwork, const FlowRaw rw, const FlowMat fm, int r,
+                                       int c, glb_i32 *gab, int limit, lds_f64 *glds, lds_i32 *s_val) {
+    double *work = (double *)gwork, *lds = (double *)glds;
+    const double *H = (const double *)rw.H, *g = (const double *)rw.g;
     const int64_t n = d.n;
     double *A = work + d.a_off, *v = work + d.v_off;
-    const int j = kind == FLOW_TILE ? c : (kind == FLOW_POFF ? i - 1 : i);   // block row of the second factor
-    const int kend = kind == FLOW_TILE ? c : c + 1;                          // sum over k < kend
-    const int64_t R0 = (int64_t)TB * i, J0 = (int64_t)TB * j;
+    const int64_t R0 = (int64_t)TB * r, C0 = (int64_t)TB * c;
+    const int nr = (int)std::min<int64_t>(TB, n - R0);
+    d4 raw[2][2], rrr[2][2];
+    tile_to_acc(raw, H, n, R0, C0, nr, TB);
+    tile_to_acc(rrr, H, n, R0, R0, nr, nr);
+    damp_diag_tile(rrr, rw);
+    const int row = threadIdx.x >> 2;
+    const double graw = g[R0 + std::min(row, nr - 1)];
+    flow_publish(fm.ra + r);   // the raw tile (r, c) is read
+    d4 aa[2][2], ac[2][2];
+    acc_zero(aa);
+    acc_zero(ac);
+    double q = 0.0;
+    const int rows[2] = {r, c};
+    for (int klo = 0; klo < c;) {
+        const int khi = flow_wait_cols<2>(fm, rows, klo, c, gab, limit, s_val);
+        if (khi < 0) return;
+        const int64_t ka = (int64_t)TB * klo;
+        tile_gemm_nt_acc(lds, lds + TB * LDK, A, n, R0, ka, n, n, A, n, C0, ka, n, n, aa, TB * (khi - klo));
+        tile_syrk_y(lds, A, n, R0, ka, TB * (khi - klo), v, ac, q);
+        klo = khi;
+    }
+    if (!flow_wait(fm.dg + c, fm.ab, gab, limit, s_val)) return;
+    double *Pl = lds, *Xl = lds + TB * LTS, *ys = lds + 2 * TB * LTS;
+    RowTile l;
+    flow_solve_tile(raw, nr, work + d.linv_off + (int64_t)c * TB * TB, aa, Pl, Xl, l);
+    __syncthreads();
+    rows_to_lds(l, Pl, nr);
+    if (threadIdx.x < TB) ys[threadIdx.x] = v[C0 + threadIdx.x];
+    __syncthreads();
+    mma64_nt<false>(Pl, Pl, 1.0, ac);
+    q += lds_gemv_part(Pl, ys);
+    acc_sub(rrr, ac);
+    acc_to_global(rrr, A, n, R0, R0, nr, nr);
+    q = row_sum4(q);
+    if ((threadIdx.x & 3) == 0 && row < nr) v[R0 + row] = -graw - q;
+    flow_publish(fm.pd + r);
+}
+
+// Off-diagonal partial task of row r = c + 2: L_rc (its sums formed beside
+// those of the partial) and P_r,r-1 with the last term L_rc L_c+1,c^T (the
+// walker's tile of step c), published behind one fence.
+__device__ __noinline__ void flow_poff(const DenseDesc d, glb_f64 *gwork, const FlowRaw rw, const FlowMat fm, int r,
+                                      int c, glb_i32 *gab, int limit, lds_f64 *glds, lds_i32 *s_val) {
+    double *work = (double *)gwork, *lds = (double *)glds;
+    const double *H = (const double *)rw.H;
+    const int64_t n = d.n;
+    double *A = work + d.a_off;
+    const int64_t R0 = (int64_t)TB * r, C0 = (int64_t)TB * c, C1 = C0 + TB;
+    const int nr = (int)std::min<int64_t>(TB, n - R0);
+    d4 raw[2][2], rrp[2][2];
+    tile_to_acc(raw, H, n, R0, C0, nr, TB);
+    tile_to_acc(rrp, H, n, R0, C1, nr, TB);
+    // L_rc goes to the tile (r, c) in place: first the diagonal task (earlier
+    // in the queue) must have read the raw tile
+    if (!flow_wait(fm.ra + r, fm.ab, gab, limit, s_val)) return;
+    d4 aa[2][2], ab[2][2];
+    acc_zero(aa);
+    acc_zero(ab);
+    const int rows[3] = {r, c, c + 1};
+    for (int klo = 0; klo < c;) {
+        const int khi = flow_wait_cols<3>(fm, rows, klo, c, gab, limit, s_val);
+        if (khi < 0) return;
+        const int64_t ka = (int64_t)TB * klo;
+        tile_gemm_nt_acc(lds, lds + TB * LDK, A, n, R0, ka, n, n, A, n, C0, ka, n, n, aa, TB * (khi - klo));
+        tile_gemm_nt_acc(lds, lds + TB * LDK, A, n, R0, ka, n, n, A, n, C1, ka, n, n, ab, TB * (khi - klo));
+        klo = khi;
+    }
+    if (!flow_wait2(fm.dg + c, fm.fl + (c + 1) * fm.T + c, fm.ab, gab, limit, s_val)) return;
+    double *Pl = lds, *Xl = lds + TB * LTS, *Ll = lds + 2 * TB * LTS;
+    tile_to_lds(Ll, A, n, C1, C0, TB, TB);   // L_c+1,c, loaded beside the inverse
+    RowTile l;
+    flow_solve_tile(raw, nr, work + d.linv_off + (int64_t)c * TB * TB, aa, Pl, Xl, l);
+    rows_to_global(l, A, n, R0, C0, nr);    // stored while the last term is formed
+    __syncthreads();
+    rows_to_lds(l, Pl, nr);
+    __syncthreads();
+    mma64_nt<false>(Pl, Ll, 1.0, ab);
+    acc_sub(rrp, ab);
+    acc_to_global(rrp, A, n, R0, C1, nr, TB);
+    flow_publish2(fm.po + r, fm.fl + r * fm.T + c);
+}
+
+// Tile task: L_ic = (A_ic - sum_{k<c} L_ik L_ck^T) L_cc^-T for i >= c + 3.
+__device__ __noinline__ void flow_tile(const DenseDesc d, glb_f64 *gwork, const FlowRaw rw, const FlowMat fm, int i,
+                                      int c, glb_i32 *gab, int limit, lds_f64 *glds, lds_i32 *s_val) {
+    double *work = (double *)gwork, *lds = (double *)glds;
+    const double *H = (const double *)rw.H;
+    const int64_t n = d.n;
+    double *A = work + d.a_off;
+    const int64_t R0 = (int64_t)TB * i, C0 = (int64_t)TB * c;
     const int nr = (int)std::min<int64_t>(TB, n - R0);
     d4 acc[2][2];
     acc_zero(acc);
-    double q = 0.0;
-    const int rows[2] = {i, j};
-    for (int klo = 0; klo < kend;) {
-        const int khi = flow_wait_cols<2>(fm, rows, klo, kend, gab, limit, s_val);
+    const int rows[2] = {i, c};
+    for (int klo = 0; klo < c;) {
+        const int khi = flow_wait_cols<2>(fm, rows, klo, c, gab, limit, s_val);
         if (khi < 0) return;
         const int64_t ka = (int64_t)TB * klo;
-        if (kind == FLOW_PDIAG)
-            tile_syrk_y(lds, A, n, R0, ka, TB * (khi - klo), v, acc, q);
-        else
-            tile_gemm_nt_acc(lds, lds + TB * LDK, A, n, R0, ka, n, n, A, n, J0, ka, n, n, acc, TB * (khi - klo));
+        tile_gemm_nt_acc(lds, lds + TB * LDK, A, n, R0, ka, n, n, A, n, C0, ka, n, n, acc, TB * (khi - klo));
         klo = khi;
     }
-    if (kind == FLOW_TILE) {
-        if (!flow_wait(fm.dg + c, fm.ab, gab, limit, s_val)) return;
-        d4 l[2][2];
-        flow_solve_tile(A, n, R0, J0, nr, work + d.linv_off + (int64_t)c * TB * TB, acc, lds, lds + TB * LTS, l);
-        acc_to_global(l, A, n, R0, J0, nr, TB);
-        flow_publish(fm.fl + i * fm.T + c);
-        return;
-    }
-    const int nc = j == i ? nr : TB;
-    d4 p[2][2];
-    tile_to_acc(p, A, n, R0, J0, nr, nc);
-    acc_sub(p, acc);
-    acc_to_global(p, A, n, R0, J0, nr, nc);
-    if (kind == FLOW_PDIAG) {
-        q = row_sum4(q);
-        const int row = threadIdx.x >> 2;
-        if ((threadIdx.x & 3) == 0 && row < nr) v[R0 + row] -= q;
-        flow_publish(fm.pd + i);
-    } else {
-        flow_publish(fm.po + i);
-    }
+    d4 raw[2][2];
+    tile_to_acc(raw, H, n, R0, C0, nr, TB);
+    if (!flow_wait(fm.dg + c, fm.ab, gab, limit, s_val)) return;
+    RowTile l;
+    flow_solve_tile(raw, nr, work + d.linv_off + (int64_t)c * TB * TB, acc, lds, lds + TB * LTS, l);
+    rows_to_global(l, A, n, R0, C0, nr);
+    flow_publish(fm.fl + i * fm.T + c);
 }
 
 // Marks the matrix abandoned: a pivot failure (f > 0) or an aborted wait.
-__device__ __forceinline__ void flow_abandon(DenseParam *__restrict__ pm, const FlowMat &fm, int f) {
+__device__ __forceinline__ void flow_abandon(glb_i32 *info, const FlowMat &fm, int f) {
     if (threadIdx.x == 0) {
-        pm->info = f;
-        __hip_atomic_store(fm.ab, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        *info = f;
+        flag_set(fm.ab, __ATOMIC_RELEASE);
     }
 }
 
 // Walker of one matrix (see above).  LDS: the factor's tile and inverse
 // (lds, lds + TB * LTS), its vectors, and ybuf (y of the previous block).
 // Step j factors D_j (held in dacc, b_j in bq), then waits once for both
-// partial sums of block row j + 1, loads them together, solves L_j+1,j,
-// publishes block j and that tile behind one fence, and forms D_j+1 and
-// b_j+1 with the last terms.  L_jj itself is not stored.
-__device__ __forceinline__ void flow_walk(const DenseDesc &d, DenseParam *__restrict__ pm, double *__restrict__ work,
-                                          const FlowMat &fm, int *gab, int limit, double *__restrict__ lds,
-                                          double *__restrict__ yv, double *__restrict__ rdiag,
-                                          double *__restrict__ pvs, double *__restrict__ ybuf, int &sfail,
-                                          int *s_val) {
+// partial sums of block row j + 1, solves L_j+1,j while D_j+1 and b_j+1 load,
+// forms their last terms, and publishes block j and that tile behind one
+// fence.  L_jj itself is not stored.
+__device__ __noinline__ void flow_walk(const DenseDesc d, glb_i32 *info, glb_f64 *gwork, const FlowRaw rw,
+                                      const FlowMat fm, glb_i32 *gab, int limit, lds_f64 *glds, lds_f64 *gyv,
+                                      lds_f64 *grdiag, lds_f64 *gpvs, lds_f64 *gybuf, lds_i32 *gsfail,
+                                      lds_i32 *s_val) {
+    double *work = (double *)gwork, *lds = (double *)glds, *yv = (double *)gyv, *rdiag = (double *)grdiag;
+    const double *H = (const double *)rw.H, *g = (const double *)rw.g;
+    double *pvs = (double *)gpvs, *ybuf = (double *)gybuf;
+    int &sfail = *(int *)gsfail;
     const int64_t n = d.n;
     double *A = work + d.a_off, *v = work + d.v_off;
     double *Tl = lds, *Xl = lds + TB * LTS;
     const int t = threadIdx.x, row = t >> 2;
-    // block 0 has no partial sums
+    // blocks 0 and 1 have no partial sums: raw tiles
     int nb = (int)std::min<int64_t>(TB, n);
-    d4 dacc[2][2];
-    tile_to_acc(dacc, A, n, 0, 0, nb, nb);
-    double bq = (row < nb) ? v[std::min(row, nb - 1)] : 0.0;
+    LowTile dt;
+    low_load(dt, H, n, 0, nb);
+    low_damp(dt, rw.mu, rw.floor_);
+    double bq = (row < nb) ? -g[std::min(row, nb - 1)] : 0.0;
     for (int j = 0; j < fm.T; j++) {
         const int64_t k0 = (int64_t)TB * j;
-#pragma unroll
-        for (int rb = 0; rb < 2; rb++)
-#pragma unroll
-            for (int cb = 0; cb < 2; cb++)
-#pragma unroll
-                for (int r = 0; r < 4; r++)
-                    put_diag_elem(Tl, (int)ACC_ROW(rb, r), (int)ACC_COL(cb), nb, dacc[rb][cb][r]);
+        low_put(dt, Tl, nb);
         if ((t & 3) == 0) yv[row] = bq;
         if (t == 0) sfail = 0;
         __syncthreads();
         const int f = factor_diag_tile(Tl, Xl, yv, rdiag, pvs, sfail, A, n, k0, nb, v + k0,
                                        work + d.linv_off + (int64_t)j * TB * TB, false);
         if (f) {
-            flow_abandon(pm, fm, f);
+            flow_abandon(info, fm, f);
             return;
         }
         __syncthreads();
@@ -1380,36 +1637,42 @@ __device__ __forceinline__ void flow_walk(const DenseDesc &d, DenseParam *__rest
         }
         // partial sums of block row j + 1 (raw for j = 0)
         if (j >= 1 && !flow_wait2(fm.po + j + 1, fm.pd + j + 1, fm.ab, gab, limit, s_val)) {
-            flow_abandon(pm, fm, -1);
+            flow_abandon(info, fm, -1);
             return;
         }
         const int64_t r0 = k0 + TB;
         const int nr = (int)std::min<int64_t>(TB, n - r0);
-        tile_to_lds(Tl, A, n, r0, k0, nr, TB);
-        tile_to_acc(dacc, A, n, r0, r0, nr, nr);
-        bq = (row < nr) ? v[r0 + std::min(row, nr - 1)] : 0.0;
+        const double *Pj = j == 0 ? H : A;
+        tile_to_lds(Tl, Pj, n, r0, k0, nr, TB);
         __syncthreads();
-        // L_j+1,j = P_j+1,j L_jj^-T with the inverse in LDS
-        d4 l[2][2];
-        acc_zero(l);
-        mma64_nt<true>(Tl, Xl, 1.0, l);
-        acc_to_global(l, A, n, r0, k0, nr, TB);
-        flow_publish2(fm.dg + j, fm.fl + (j + 1) * fm.T + j);
-        acc_to_lds(l, Xl, nr);
+        // D_j+1 and b_j+1 are loaded while L_j+1,j = P_j+1,j L_jj^-T is formed
+        // with the inverse in LDS
+        low_load(dt, Pj, n, r0, nr);
+        bq = (row < nr) ? (j == 0 ? -g[r0 + std::min(row, nr - 1)] : v[r0 + std::min(row, nr - 1)]) : 0.0;
+        RowTile l;
+        rows_trsm(Tl, Xl, l);
+        rows_to_global(l, A, n, r0, k0, nr);
         __syncthreads();
-        // D_j+1 and b_j+1: the last terms
-        mma64_nt<false>(Xl, Xl, -1.0, dacc);
+        rows_to_lds(l, Xl, nr);
+        __syncthreads();
+        // the last terms of D_j+1 and b_j+1 (the stores of L_j+1,j complete
+        // meanwhile), then block j and that tile are published
+        if (j == 0) low_damp(dt, rw.mu, rw.floor_);
+        low_syrk_sub(dt, Xl);
         bq -= row_sum4(lds_gemv_part(Xl, ybuf));
+        flow_publish2(fm.dg + j, fm.fl + (j + 1) * fm.T + j);
         nb = nr;
     }
 }
 
 __global__ __launch_bounds__(256) void k_chol_flow(const DenseDesc *__restrict__ desc, DenseParam *__restrict__ prm,
-                                                   double *__restrict__ work, const FlowTask *__restrict__ tasks,
+                                                   const double *__restrict__ H, const int64_t *__restrict__ h_off,
+                                                   const double *__restrict__ g, double *__restrict__ work,
+                                                   const FlowTask *__restrict__ tasks,
                                                    int32_t n_tasks, int *__restrict__ flags,
                                                    const int64_t *__restrict__ fo, int *__restrict__ queue,
                                                    int *__restrict__ gab, int limit) {
-    __shared__ __align__(16) double lds[2 * TB * LTS];
+    __shared__ __align__(16) double lds[3 * TB * LTS];
     __shared__ double yv[TB], rdiag[TB], pvs[TB], ybuf[TB];
     __shared__ int s_task, s_val, sfail;
     for (;;) {
@@ -1423,12 +1686,22 @@ __global__ __launch_bounds__(256) void k_chol_flow(const DenseDesc *__restrict__
         if (!pm.active || pm.info) continue;
         const DenseDesc d = desc[tk.m];
         const int T = (d.n + TB - 1) / TB;
-        int *fb = flags + fo[tk.m];
-        const FlowMat fm{fb, fb + T * T, fb + T * T + T, fb + T * T + 2 * T, fb + T * T + 3 * T, T};
+        glb_i32 *fb = (glb_i32 *)(flags + fo[tk.m]);
+        glb_i32 *fs = fb + T * T;
+        const FlowMat fm{fb, fs, fs + T, fs + 2 * T, fs + 3 * T, fs + 4 * T, T};
+        glb_f64 *gw = (glb_f64 *)work;
+        const FlowRaw rw{(glb_f64 *)(H + h_off[tk.m]), (glb_f64 *)(g + 6LL * d.pose0), pm.mu, pm.floor_};
+        glb_i32 *ga = (glb_i32 *)gab;
+        lds_i32 *sv = (lds_i32 *)&s_val;
         if (tk.kind == FLOW_WALK)
-            flow_walk(d, prm + tk.m, work, fm, gab, limit, lds, yv, rdiag, pvs, ybuf, sfail, &s_val);
+            flow_walk(d, (glb_i32 *)&prm[tk.m].info, gw, rw, fm, ga, limit, (lds_f64 *)lds, (lds_f64 *)yv,
+                      (lds_f64 *)rdiag, (lds_f64 *)pvs, (lds_f64 *)ybuf, (lds_i32 *)&sfail, sv);
+        else if (tk.kind == FLOW_TILE)
+            flow_tile(d, gw, rw, fm, tk.i, tk.c, ga, limit, (lds_f64 *)lds, sv);
+        else if (tk.kind == FLOW_PDIAG)
+            flow_pdiag(d, gw, rw, fm, tk.i, tk.c, ga, limit, (lds_f64 *)lds, sv);
         else
-            flow_task(d, work, fm, tk.kind, tk.i, tk.c, gab, limit, lds, &s_val);
+            flow_poff(d, gw, rw, fm, tk.i, tk.c, ga, limit, (lds_f64 *)lds, sv);
     }
 }
 
@@ -1439,11 +1712,11 @@ __global__ void k_flow_tasks_one(int32_t T, FlowTask *__restrict__ tasks) {
     if (c == 0) tasks[0] = FlowTask{0, FLOW_WALK, 0, 0};
     if (c >= T) return;
     int64_t o = 1;
-    for (int cc = 0; cc < c; cc++) o += std::max(0, T - cc - 2) + (cc + 2 <= T - 1 ? 2 : 0);
-    for (int i = c + 2; i < T; i++) tasks[o++] = FlowTask{0, FLOW_TILE, i, c};
+    for (int cc = 0; cc < c; cc++) o += std::max(0, T - cc - 3) + (cc + 2 <= T - 1 ? 2 : 0);
+    for (int i = c + 3; i < T; i++) tasks[o++] = FlowTask{0, FLOW_TILE, i, c};
     if (c + 2 <= T - 1) {
-        tasks[o] = FlowTask{0, FLOW_POFF, c + 2, c};
-        tasks[o + 1] = FlowTask{0, FLOW_PDIAG, c + 2, c};
+        tasks[o] = FlowTask{0, FLOW_PDIAG, c + 2, c};
+        tasks[o + 1] = FlowTask{0, FLOW_POFF, c + 2, c};
     }
 }
 
@@ -1452,7 +1725,7 @@ __global__ void k_fill_i32(int64_t n, int *__restrict__ p, int v) {
         p[i] = v;
 }
 
-static int64_t flow_task_count(int64_t T) { return 1 + (T >= 3 ? (T - 2) * (T - 1) / 2 + 2 * (T - 2) : 0); }
+static int64_t flow_task_count(int64_t T) { return 1 + (T >= 3 ? (T - 2) * (T - 3) / 2 + 2 * (T - 2) : 0); }
 
 // ---------------------------------------------------------------- LM glue
 // Per-window damping parameters from the LM state and the dense diagonal.
@@ -1794,10 +2067,10 @@ ba_status dense_prepare(Problem *P) {
             for (int32_t c = 0; c < maxT; c++)
                 for (int32_t m = m0; m < m1; m++) {
                     const int32_t T = (desc[m].n + TB - 1) / TB;
-                    for (int32_t i = c + 2; i < T; i++) tasks.push_back(FlowTask{m, FLOW_TILE, i, c});
+                    for (int32_t i = c + 3; i < T; i++) tasks.push_back(FlowTask{m, FLOW_TILE, i, c});
                     if (c + 2 <= T - 1) {
-                        tasks.push_back(FlowTask{m, FLOW_POFF, c + 2, c});
                         tasks.push_back(FlowTask{m, FLOW_PDIAG, c + 2, c});
+                        tasks.push_back(FlowTask{m, FLOW_POFF, c + 2, c});
                     }
                 }
             D->flow_count.push_back((int32_t)tasks.size() - D->flow_first.back());
@@ -1893,20 +2166,22 @@ static int flow_spin_limit() {
 // Dataflow factorization and forward substitution (k_chol_flow): flags,
 // tickets and the abort flag cleared by a kernel (no memset node in a
 // captured graph), then one persistent launch per group of matrices.
-static void launch_flow_factor(DenseState *D, hipStream_t s) {
+static void launch_flow_factor(DenseState *D, const double *H, const int64_t *h_off, const double *g,
+                               hipStream_t s) {
     const int nl = (int)D->flow_first.size();
     const int64_t nint = D->flow_ints + nl + 1;
     hipLaunchKernelGGL(k_fill_i32, dim3((unsigned)std::min<int64_t>(nblk(nint), 1024)), dim3(256), 0, s, nint,
                        D->flow_flags, 0);
     const int limit = flow_spin_limit();
-    // one workgroup per compute unit: the walker's factor and the row task's
-    // three accumulators need more than half of the register file
+    // one workgroup per compute unit: the walker's factor and the partial
+    // tasks' accumulators need more than half of the register file
     const int slots = cu_count();
     for (int q = 0; q < nl; q++) {
         ProfScope prof("k_chol_flow", s);
         hipLaunchKernelGGL(k_chol_flow, dim3((unsigned)std::min(D->flow_count[q], slots)), dim3(256), 0, s, D->desc,
-                           D->prm, D->work, D->flow_tasks + D->flow_first[q], D->flow_count[q], D->flow_flags,
-                           D->flow_fo, D->flow_flags + D->flow_ints + q, D->flow_flags + D->flow_ints + nl, limit);
+                           D->prm, H, h_off, g, D->work, D->flow_tasks + D->flow_first[q], D->flow_count[q],
+                           D->flow_flags, D->flow_fo, D->flow_flags + D->flow_ints + q,
+                           D->flow_flags + D->flow_ints + nl, limit);
     }
 }
 
@@ -1952,12 +2227,13 @@ static void launch_factor_solve(DenseState *D, int32_t nmat, int32_t max_n, cons
                                 const double *g, double *x, const int64_t *x_off, hipStream_t s) {
     const int nsteps = (max_n + TB - 1) / TB;
     const int64_t nn = (int64_t)max_n * max_n;
-    hipLaunchKernelGGL(k_damp_copy, dim3((unsigned)std::min<int64_t>(nblk(nn), 4096), nmat), dim3(256), 0, s,
-                       D->desc, D->prm, H, h_off, g, D->work);
-    if (D->flow_tasks && max_n <= FLOW_MAX_N)
-        launch_flow_factor(D, s);
-    else
+    if (D->flow_tasks && max_n <= FLOW_MAX_N) {
+        launch_flow_factor(D, H, h_off, g, s);   // reads H and g directly
+    } else {
+        hipLaunchKernelGGL(k_damp_copy, dim3((unsigned)std::min<int64_t>(nblk(nn), 4096), nmat), dim3(256), 0, s,
+                           D->desc, D->prm, H, h_off, g, D->work);
         launch_blocked_factor(D, nmat, nsteps, s);
+    }
     // backward substitution two block rows per launch, the first row alone
     // when the count is odd
     int st = nsteps - 1;
