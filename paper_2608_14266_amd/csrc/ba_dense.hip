@@ -1879,6 +1879,26 @@ __global__ void k_dense_zero_stale(int32_t W, const DenseDesc *__restrict__ desc
 // ---------------------------------------------------------------- host side
 static inline unsigned nblk(int64_t n, int t = 256) { return (unsigned)((n + t - 1) / t); }
 
+// Compute units of the current device.
+static int cu_count() {
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+        cus = 256;
+    return cus;
+}
+
+// Polls before a wait of the dataflow factorization gives up: FLOW_SPIN, or
+// the environment's BA_FLOW_SPIN (a negative value gives up at once, which
+// the tests use to exercise the abort path).
+static int flow_spin_limit() {
+    const char *e = getenv("BA_FLOW_SPIN");
+    return e ? atoi(e) : FLOW_SPIN;
+}
+
+// Dataflow factorization and forward substitution (k_chol_flow): flags,
+// tickets and the abort flag cleared by a kernel (no memset node in a
+// captured graph), then one persistent launch per group of matrices.
 struct DenseState {
     DevArena mem;
     bool ready = false;
@@ -1907,6 +1927,8 @@ struct DenseState {
     int64_t *flow_fo = nullptr;
     int64_t flow_ints = 0;
     std::vector<int32_t> flow_first, flow_count;
+    std::vector<int32_t> flow_mats;   // matrices (walkers) of each launch
+    std::vector<int64_t> flow_work;   // sum of T^2 over the launch's matrices (sets its helper count)
 };
 
 static DenseState *dense_state(Problem *P) { return (DenseState *)P->dense_state; }
@@ -2056,8 +2078,11 @@ ba_status dense_prepare(Problem *P) {
             fo[w] = ints;
             ints += flow_flag_ints((desc[w].n + TB - 1) / TB);
         }
-        for (int32_t m0 = 0; m0 < W; m0 += FLOW_MAX_MATS) {
-            const int32_t m1 = std::min<int32_t>(W, m0 + FLOW_MAX_MATS);
+        // walkers of a launch hold at most half of the compute units, so that
+        // every launch keeps workgroups for its helpers
+        const int32_t per_launch = std::max(1, std::min(FLOW_MAX_MATS, cu_count() / 2));
+        for (int32_t m0 = 0; m0 < W; m0 += per_launch) {
+            const int32_t m1 = std::min<int32_t>(W, m0 + per_launch);
             D->flow_first.push_back((int32_t)tasks.size());
             int32_t maxT = 0;
             for (int32_t m = m0; m < m1; m++) {
@@ -2074,6 +2099,13 @@ ba_status dense_prepare(Problem *P) {
                     }
                 }
             D->flow_count.push_back((int32_t)tasks.size() - D->flow_first.back());
+            int64_t work = 0;
+            for (int32_t m = m0; m < m1; m++) {
+                const int64_t T = (desc[m].n + TB - 1) / TB;
+                work += T * T;
+            }
+            D->flow_mats.push_back(m1 - m0);
+            D->flow_work.push_back(work);
         }
         D->flow_ints = ints;
         BA_TRY(D->mem.alloc(&D->flow_tasks, (int64_t)tasks.size()));
@@ -2146,26 +2178,6 @@ ba_status dense_assemble_exact(Problem *P, const double *poses, double *hess_out
     return BA_OK;
 }
 
-// Compute units of the current device.
-static int cu_count() {
-    int dev = 0, cus = 0;
-    if (hipGetDevice(&dev) != hipSuccess ||
-        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
-        cus = 256;
-    return cus;
-}
-
-// Polls before a wait of the dataflow factorization gives up: FLOW_SPIN, or
-// the environment's BA_FLOW_SPIN (a negative value gives up at once, which
-// the tests use to exercise the abort path).
-static int flow_spin_limit() {
-    const char *e = getenv("BA_FLOW_SPIN");
-    return e ? atoi(e) : FLOW_SPIN;
-}
-
-// Dataflow factorization and forward substitution (k_chol_flow): flags,
-// tickets and the abort flag cleared by a kernel (no memset node in a
-// captured graph), then one persistent launch per group of matrices.
 static void launch_flow_factor(DenseState *D, const double *H, const int64_t *h_off, const double *g,
                                hipStream_t s) {
     const int nl = (int)D->flow_first.size();
@@ -2173,12 +2185,17 @@ static void launch_flow_factor(DenseState *D, const double *H, const int64_t *h_
     hipLaunchKernelGGL(k_fill_i32, dim3((unsigned)std::min<int64_t>(nblk(nint), 1024)), dim3(256), 0, s, nint,
                        D->flow_flags, 0);
     const int limit = flow_spin_limit();
-    // one workgroup per compute unit: the walker's factor and the partial
-    // tasks' accumulators need more than half of the register file
-    const int slots = cu_count();
+    // one workgroup per compute unit (the walker's factor and the partial
+    // tasks' accumulators need more than half of the register file): the
+    // walkers plus helpers in proportion to the tiles, so that the early
+    // steps of a large matrix have the whole device while small problems
+    // solved side by side (concurrent streams) leave room for each other
+    const int cus = cu_count();
     for (int q = 0; q < nl; q++) {
+        const int64_t helpers = std::max<int64_t>(32, D->flow_work[q] / 8);
+        const int grid = (int)std::min<int64_t>({(int64_t)D->flow_count[q], (int64_t)cus, D->flow_mats[q] + helpers});
         ProfScope prof("k_chol_flow", s);
-        hipLaunchKernelGGL(k_chol_flow, dim3((unsigned)std::min(D->flow_count[q], slots)), dim3(256), 0, s, D->desc,
+        hipLaunchKernelGGL(k_chol_flow, dim3((unsigned)grid), dim3(256), 0, s, D->desc,
                            D->prm, H, h_off, g, D->work, D->flow_tasks + D->flow_first[q], D->flow_count[q],
                            D->flow_flags, D->flow_fo, D->flow_flags + D->flow_ints + q,
                            D->flow_flags + D->flow_ints + nl, limit);
@@ -2342,6 +2359,8 @@ ba_status dense_solve(int64_t n, const double *A, const double *g, double mu, do
         tmp.flow_ints = flow_flag_ints(T);
         tmp.flow_first.push_back(0);
         tmp.flow_count.push_back((int32_t)flow_task_count(T));
+        tmp.flow_mats.push_back(1);
+        tmp.flow_work.push_back(T * T);
         hipLaunchKernelGGL(k_flow_tasks_one, dim3(nblk(T)), dim3(256), 0, s, (int32_t)T, tmp.flow_tasks);
     }
     launch_factor_solve(&tmp, 1, (int32_t)n, A, offs, g, dx, offs + 1, s);
