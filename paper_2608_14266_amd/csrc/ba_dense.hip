@@ -834,151 +834,105 @@ __global__ __launch_bounds__(256) void k_syrk(const DenseDesc *__restrict__ desc
             }
 }
 
-// Backward substitution, block row `step` (descending): x_k = L_kk^-T y_k and
-// y_J -= L_kJ^T x_k for the column tiles J < k (one tile per workgroup).  The
-// factorization runs it for block row 0 when the row count is odd; the other
-// rows go two per launch (k_backsub2).
-// Four threads share each 64-term dot product.  The L_kJ tile is loaded
-// before x_k is formed, so the two global reads overlap.
-__global__ __launch_bounds__(256) void k_backsub(const DenseDesc *__restrict__ desc,
-                                                 const DenseParam *__restrict__ prm, double *__restrict__ work,
-                                                 double *__restrict__ x, const int64_t *__restrict__ x_off, int step) {
-    __shared__ double xk[TB];
-    __shared__ double yk[TB];
+// Backward substitution, R block rows per launch: rows k, k-1, ..., k-R+1
+// (those >= 0 that the matrix has; k = `step`).  Every workgroup forms the
+// rows' solutions in order, x_r = L_rr^-T (y_r - sum of L_r'r^T x_r' over the
+// rows r' above r in the group), and workgroup J below the group applies
+// y_J <- y_J - sum_r L_rJ^T x_r (rows in order); workgroup 0 stores x.  All
+// tiles are loaded before the first product.  Four threads share each
+// 64-term dot product.
+template <int R>
+__global__ __launch_bounds__(256) void k_backsub_rows(const DenseDesc *__restrict__ desc,
+                                                      const DenseParam *__restrict__ prm, double *__restrict__ work,
+                                                      double *__restrict__ x, const int64_t *__restrict__ x_off,
+                                                      int step) {
+    __shared__ double xs[R][TB], ys[R][TB];
     const int m = blockIdx.y;
     const DenseDesc d = desc[m];
     if (!prm[m].active || prm[m].info) return;
-    const int64_t k0 = (int64_t)TB * step;
-    if (k0 >= d.n) return;
+    const int lo = step - R + 1;   // lowest row of the group (may be < 0)
+    if ((int64_t)TB * std::max(lo, 0) >= d.n) return;   // the group lies beyond this (smaller) matrix
     const int64_t J = blockIdx.x;
-    if (J > 0 && J >= step) return;
-    const int nb = (int)std::min<int64_t>(TB, d.n - k0);
-    const double *linv = work + d.linv_off + (int64_t)step * TB * TB;
+    if (J > 0 && J >= lo) return;
+    const bool upd = J < lo;
     const int t = threadIdx.x, o = t >> 2, part = t & 3;
-    const bool upd = J < step;
     const double *A = work + d.a_off;
-    double lkj[16];
+    int nb[R];
 #pragma unroll
-    for (int q = 0; q < 16; q++) {
-        const int r = part + 4 * q;
-        lkj[q] = (upd && r < nb) ? A[(k0 + r) * d.n + TB * J + o] : 0.0;
+    for (int i = 0; i < R; i++) {
+        const int64_t r0 = (int64_t)TB * (step - i);
+        nb[i] = (step - i >= 0 && r0 < d.n) ? (int)std::min<int64_t>(TB, d.n - r0) : 0;
     }
-    double li[16];
+    double li[R][16], lj[R][16], lc[R > 1 ? R * (R - 1) / 2 : 1][16];
 #pragma unroll
-    for (int q = 0; q < 16; q++) li[q] = linv[(part + 4 * q) * TB + o];
-    if (t < TB) yk[t] = (t < nb) ? work[d.v_off + k0 + t] : 0.0;
-    __syncthreads();
-    {   // x_k[o] = sum_c Linv[c][o] y[c]
-        double s = 0.0;
+    for (int i = 0; i < R; i++) {
+        const int64_t r0 = (int64_t)TB * (step - i);
 #pragma unroll
-        for (int q = 0; q < 16; q++) s += li[q] * yk[part + 4 * q];
-        s += __shfl_xor(s, 1, 64);
-        s += __shfl_xor(s, 2, 64);
-        if (part == 0) xk[o] = s;
-    }
-    __syncthreads();
-    if (J == 0 && t < nb) x[x_off[m] + k0 + t] = xk[t];
-    if (!upd) return;
-    {   // y_J[o] -= sum_r L[k0 + r][64 J + o] x_k[r]
-        double s = 0.0;
-#pragma unroll
-        for (int q = 0; q < 16; q++) s += lkj[q] * xk[part + 4 * q];
-        s += __shfl_xor(s, 1, 64);
-        s += __shfl_xor(s, 2, 64);
-        if (part == 0) work[d.v_off + TB * J + o] -= s;
-    }
-}
-
-// Two steps of the backward substitution in one launch, block rows `step`
-// (k) and step - 1 (h), with the arithmetic of two k_backsub launches in the
-// same order.  Every workgroup forms x_k, then y_h - L_kh^T x_k and x_h itself
-// (the L_kh tile and both inverse factors are read by every workgroup, all
-// loads issued before the first product), and workgroup J < h applies
-// y_J <- (y_J - L_kJ^T x_k) - L_hJ^T x_h.  A matrix smaller than block row k
-// takes only the step h part.
-__global__ __launch_bounds__(256) void k_backsub2(const DenseDesc *__restrict__ desc,
-                                                  const DenseParam *__restrict__ prm, double *__restrict__ work,
-                                                  double *__restrict__ x, const int64_t *__restrict__ x_off,
-                                                  int step) {
-    __shared__ double xk[TB], yk[TB], xh[TB], yh[TB];
-    const int m = blockIdx.y;
-    const DenseDesc d = desc[m];
-    if (!prm[m].active || prm[m].info) return;
-    const int64_t k0 = (int64_t)TB * step, h0 = k0 - TB;
-    if (h0 >= d.n) return;
-    const int64_t J = blockIdx.x;
-    const int hstep = step - 1;
-    if (J > 0 && J >= hstep) return;
-    const bool has_k = k0 < d.n;
-    const int nbk = has_k ? (int)std::min<int64_t>(TB, d.n - k0) : 0;   // block row h is full when k exists
-    const int nbh = (int)std::min<int64_t>(TB, d.n - h0);
-    const int t = threadIdx.x, o = t >> 2, part = t & 3;
-    const bool upd = J < hstep;
-    const double *A = work + d.a_off;
-    const double *linv_k = work + d.linv_off + (int64_t)step * TB * TB;
-    const double *linv_h = work + d.linv_off + (int64_t)hstep * TB * TB;
-    double lkj[16], lhj[16], lkh[16], lik[16], lih[16];
-#pragma unroll
-    for (int q = 0; q < 16; q++) {
-        const int r = part + 4 * q;
-        lkj[q] = (upd && r < nbk) ? A[(k0 + r) * d.n + TB * J + o] : 0.0;
-        lhj[q] = (upd && r < nbh) ? A[(h0 + r) * d.n + TB * J + o] : 0.0;
-        lkh[q] = (r < nbk) ? A[(k0 + r) * d.n + h0 + o] : 0.0;
-        lik[q] = has_k ? linv_k[r * TB + o] : 0.0;
-        lih[q] = linv_h[r * TB + o];
-    }
-    if (t < TB) {
-        yk[t] = (t < nbk) ? work[d.v_off + k0 + t] : 0.0;
-        yh[t] = (t < nbh) ? work[d.v_off + h0 + t] : 0.0;
-    }
-    __syncthreads();
-    {   // x_k[o] = sum_c Linv_k[c][o] y_k[c]
-        double s = 0.0;
-#pragma unroll
-        for (int q = 0; q < 16; q++) s += lik[q] * yk[part + 4 * q];
-        s += __shfl_xor(s, 1, 64);
-        s += __shfl_xor(s, 2, 64);
-        if (part == 0) xk[o] = s;
-    }
-    __syncthreads();
-    if (J == 0 && t < nbk) x[x_off[m] + k0 + t] = xk[t];
-    {   // y_h[o] -= sum_r L[k0 + r][h0 + o] x_k[r]
-        double s = 0.0;
-#pragma unroll
-        for (int q = 0; q < 16; q++) s += lkh[q] * xk[part + 4 * q];
-        s += __shfl_xor(s, 1, 64);
-        s += __shfl_xor(s, 2, 64);
-        if (part == 0 && has_k) yh[o] -= s;
-    }
-    __syncthreads();
-    {   // x_h[o] = sum_c Linv_h[c][o] y_h[c]
-        double s = 0.0;
-#pragma unroll
-        for (int q = 0; q < 16; q++) s += lih[q] * yh[part + 4 * q];
-        s += __shfl_xor(s, 1, 64);
-        s += __shfl_xor(s, 2, 64);
-        if (part == 0) xh[o] = s;
-    }
-    __syncthreads();
-    if (J == 0 && t < nbh) x[x_off[m] + h0 + t] = xh[t];
-    if (!upd) return;
-    {   // y_J[o] <- (y_J[o] - sum_r L[k0 + r][64 J + o] x_k[r]) - sum_r L[h0 + r][64 J + o] x_h[r]
-        double sk = 0.0, sh = 0.0;
-#pragma unroll
-        for (int q = 0; q < 16; q++) sk += lkj[q] * xk[part + 4 * q];
-#pragma unroll
-        for (int q = 0; q < 16; q++) sh += lhj[q] * xh[part + 4 * q];
-        sk += __shfl_xor(sk, 1, 64);
-        sk += __shfl_xor(sk, 2, 64);
-        sh += __shfl_xor(sh, 1, 64);
-        sh += __shfl_xor(sh, 2, 64);
-        if (part == 0) {
-            double *yJ = work + d.v_off + TB * J + o;
-            double v = *yJ;
-            if (has_k) v -= sk;
-            *yJ = v - sh;
+        for (int q = 0; q < 16; q++) {
+            const int r = part + 4 * q;
+            li[i][q] = nb[i] ? work[d.linv_off + (int64_t)(step - i) * TB * TB + r * TB + o] : 0.0;
+            lj[i][q] = (upd && r < nb[i]) ? A[(r0 + r) * d.n + TB * J + o] : 0.0;
         }
     }
+    // lc[p(i, i')]: the tile (row block step - i', column block step - i), i' < i
+#pragma unroll
+    for (int i = 1; i < R; i++)
+#pragma unroll
+        for (int ip = 0; ip < i; ip++) {
+            const int p = i * (i - 1) / 2 + ip;
+            const int64_t r0 = (int64_t)TB * (step - ip), c0 = (int64_t)TB * (step - i);
+#pragma unroll
+            for (int q = 0; q < 16; q++) {
+                const int r = part + 4 * q;
+                lc[p][q] = (nb[i] && r < nb[ip]) ? A[(r0 + r) * d.n + c0 + o] : 0.0;
+            }
+        }
+    if (t < TB) {
+#pragma unroll
+        for (int i = 0; i < R; i++)
+            ys[i][t] = t < nb[i] ? work[d.v_off + (int64_t)TB * (step - i) + t] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < R; i++) {
+        if (i > 0) {   // y_i -= L_i'i^T x_i' for the rows above, in order
+            double yi = ys[i][o];
+#pragma unroll
+            for (int ip = 0; ip < i; ip++) {
+                const int p = i * (i - 1) / 2 + ip;
+                double sum = 0.0;
+#pragma unroll
+                for (int q = 0; q < 16; q++) sum += lc[p][q] * xs[ip][part + 4 * q];
+                sum += __shfl_xor(sum, 1, 64);
+                sum += __shfl_xor(sum, 2, 64);
+                yi -= sum;
+            }
+            __syncthreads();
+            if (part == 0) ys[i][o] = yi;
+            __syncthreads();
+        }
+        double sum = 0.0;   // x_i[o] = sum_c Linv_i[c][o] y_i[c]
+#pragma unroll
+        for (int q = 0; q < 16; q++) sum += li[i][q] * ys[i][part + 4 * q];
+        sum += __shfl_xor(sum, 1, 64);
+        sum += __shfl_xor(sum, 2, 64);
+        if (part == 0) xs[i][o] = sum;
+        __syncthreads();
+        if (J == 0 && t < nb[i]) x[x_off[m] + (int64_t)TB * (step - i) + t] = xs[i][t];
+    }
+    if (!upd) return;
+    double yJ = 0.0;   // y_J[o] <- ((y_J[o] - L_0J^T x_0) - L_1J^T x_1) - ...
+#pragma unroll
+    for (int i = 0; i < R; i++) {
+        double sum = 0.0;
+#pragma unroll
+        for (int q = 0; q < 16; q++) sum += lj[i][q] * xs[i][part + 4 * q];
+        sum += __shfl_xor(sum, 1, 64);
+        sum += __shfl_xor(sum, 2, 64);
+        if (i == 0) yJ = work[d.v_off + TB * J + o];
+        yJ -= sum;
+    }
+    if (part == 0) work[d.v_off + TB * J + o] = yJ;
 }
 
 // ---------------------------------------------------------------- dataflow factorization
@@ -2251,14 +2205,13 @@ static void launch_factor_solve(DenseState *D, int32_t nmat, int32_t max_n, cons
                            D->desc, D->prm, H, h_off, g, D->work);
         launch_blocked_factor(D, nmat, nsteps, s);
     }
-    // backward substitution two block rows per launch, the first row alone
-    // when the count is odd
-    int st = nsteps - 1;
-    for (; st >= 1; st -= 2)
-        hipLaunchKernelGGL(k_backsub2, dim3((unsigned)std::max(st - 1, 1), nmat), dim3(256), 0, s, D->desc,
-                           D->prm, D->work, x, x_off, st);
-    if (st == 0)
-        hipLaunchKernelGGL(k_backsub, dim3(1, nmat), dim3(256), 0, s, D->desc, D->prm, D->work, x, x_off, 0);
+    // backward substitution three block rows per launch
+    constexpr int BR = 3;
+    for (int st = nsteps - 1; st >= 0; st -= BR) {
+        ProfScope prof("k_backsub_rows", s);
+        hipLaunchKernelGGL(k_backsub_rows<BR>, dim3((unsigned)std::max(st - BR + 1, 1), nmat), dim3(256), 0, s,
+                           D->desc, D->prm, D->work, x, x_off, st);
+    }
 }
 
 void launch_dense_gnorm(Problem *P, hipStream_t s, double tol_g) {
