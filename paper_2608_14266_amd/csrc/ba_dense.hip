@@ -2205,8 +2205,10 @@ static void launch_factor_solve(DenseState *D, int32_t nmat, int32_t max_n, cons
                            D->desc, D->prm, H, h_off, g, D->work);
         launch_blocked_factor(D, nmat, nsteps, s);
     }
-    // backward substitution three block rows per launch
-    constexpr int BR = 3;
+    // backward substitution two block rows per launch (every workgroup loads
+    // the rows' inverse and cross tiles: with three rows its 145 loads per
+    // thread need three rounds of outstanding loads, 15 us a launch)
+    constexpr int BR = 2;
     for (int st = nsteps - 1; st >= 0; st -= BR) {
         ProfScope prof("k_backsub_rows", s);
         hipLaunchKernelGGL(k_backsub_rows<BR>, dim3((unsigned)std::max(st - BR + 1, 1), nmat), dim3(256), 0, s,
