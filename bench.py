@@ -219,6 +219,7 @@ def main():
     syrk_ms, syrk_n = ba.profile_query("k_syrk")
     trsm_ms, trsm_n = ba.profile_query("k_trsm")
     potf2_ms, potf2_n = ba.profile_query("k_potf2")
+    flow_ms, flow_n = ba.profile_query("k_chol_flow")
     ba.profile_reset()
     elapsed = t1 - t0
     ms_per_step = 1e3 * elapsed / args.steps
@@ -246,7 +247,17 @@ def main():
     roof = {"kernel": dom, "bound": "hbm", "achieved": round(kern[dom]["gbs"], 2), "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": round(kern[dom]["gbs"] / HBM_PEAK_GBS, 4), "traffic": traffic,
             "bytes_per_launch": kern[dom]["bytes"], "avg_launch_us": round(kern[dom]["avg_us"], 3)}
-    if args.mode == "coupled" and syrk_n > 0:
+    if args.mode == "coupled" and flow_n > 0:
+        # dataflow factorization (one launch per solve, matrices up to 6144
+        # rows): algorithmic flops n^3/3 of one 6N x 6N Cholesky per launch
+        n = 6 * N
+        fl = n ** 3 / 3
+        tfs = fl * flow_n / (flow_ms * 1e-3) / 1e12
+        kern["k_chol_flow"] = dict(avg_us=1e3 * flow_ms / flow_n, launches=flow_n, flops=fl)
+        roof = {"kernel": "k_chol_flow", "bound": "mfma", "achieved": round(tfs, 3),
+                "peak": FP64_MFMA_PEAK_TFS, "unit": "TFLOP/s", "frac": round(tfs / FP64_MFMA_PEAK_TFS, 4),
+                "traffic": None, "flops_per_factorization": fl, "avg_launch_us": round(1e3 * flow_ms / flow_n, 3)}
+    elif args.mode == "coupled" and syrk_n > 0:
         # dense factorization on FP64 matrix cores: algorithmic flops of the
         # panel solves (rows below x 64 x 64 x 2) and trailing updates
         # (rows below^2 x 64, lower half) of one 6N x 6N factorization
