@@ -59,13 +59,15 @@ struct SrcF32 {
     const float *N, *mu, *S;
     const double *ref_poses;   // [n_poses][12]
     const double *ref;         // [slots][4]
-    const double *pdelta;      // [n_poses][16] pose changes of the evaluated poses (residual pass)
+    const double *pdelta;      // [n_poses][16] pose changes of the evaluated poses: E (9), w (3) (residual pass)
     const int32_t *cidx;       // [C] (voxel, scan)-order index of each pose-major cluster
     double *h;                 // [C][6] coupled pair vectors, written when not null
 };
 
 // Pose change of every scan for the precision form's residual pass:
-// E = R R0^T - I, dt = t - t0 and t0 (one thread per pose).
+// E = R R0^T - I and w = dt - E t0 with dt = t - t0 (one thread per pose),
+// so that a cluster's offset from its voxel's reference point c is
+// d = mu' + E (mu' + c) + w.
 __global__ void k_pose_delta(int32_t n, const double *__restrict__ poses, const double *__restrict__ ref_poses,
                              double *__restrict__ pdelta) {
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
@@ -75,15 +77,15 @@ __global__ void k_pose_delta(int32_t n, const double *__restrict__ poses, const 
     load_pose(ref_poses, j, P0);
     PoseDelta D;
     pose_delta(P, P0, D);
+    double Et0[3];
+    rot(D.E, P0.t, Et0);
     double *o = pdelta + 16LL * j;
 #pragma unroll
     for (int e = 0; e < 9; e++) o[e] = D.E[e];
 #pragma unroll
-    for (int e = 0; e < 3; e++) {
-        o[9 + e] = D.dt[e];
-        o[12 + e] = P0.t[e];
-    }
-    o[15] = 0.0;
+    for (int e = 0; e < 3; e++) o[9 + e] = D.dt[e] - Et0[e];
+#pragma unroll
+    for (int e = 12; e < 16; e++) o[e] = 0.0;
 }
 
 template <typename T>
@@ -142,10 +144,12 @@ __device__ __forceinline__ void vox_accumulate(const GroupDesc &g, int64_t slot,
 }
 
 // FP32 storage: the reference is the voxel's reference point c.  With the
-// pose change (E, dt) of the cluster's scan, d = m - c = mu' + E mu' + b where
-// b = E (c - t0) + dt, and St = S' + D(E, S').  The arithmetic stays FP64:
-// the residual feeds the LM gain ratio, whose cost differences reach 1e-12
-// relative near convergence, below the noise of any FP32 product here.
+// pose change (E, w) of the cluster's scan, d = m - c = mu' + E (mu' + c) + w
+// (w = dt - E t0: the reference translation is folded in per scan, so each
+// cluster gathers 12 doubles of its scan, not 15), and St = S' + D(E, S').
+// The arithmetic stays FP64: the residual feeds the LM gain ratio, whose cost
+// differences reach 1e-12 relative near convergence, below the noise of any
+// FP32 product here; E c and E t0 round at about 1e-16 |E| |c|.
 __device__ __forceinline__ void vox_accumulate(const GroupDesc &g, int64_t slot, int lane, int k0, int kstep,
                                                int64_t c_pad, const SrcF32 &src, const int32_t *__restrict__ vpose,
                                                const double *__restrict__ poses, VoxSums &a) {
@@ -165,18 +169,16 @@ __device__ __forceinline__ void vox_accumulate(const GroupDesc &g, int64_t slot,
         for (int q = 0; q < 6; q++) S[q] = (double)src.S[q * c_pad + idx];
         // pose change of scan j, formed once per evaluation (k_pose_delta)
         const double *pd = src.pdelta + 16LL * j;
-        PoseDelta D;
+        double E[9], w[3];
 #pragma unroll
-        for (int e = 0; e < 9; e++) D.E[e] = pd[e];
+        for (int e = 0; e < 9; e++) E[e] = pd[e];
 #pragma unroll
-        for (int e = 0; e < 3; e++) D.dt[e] = pd[9 + e];
-        const double q[3] = {a.r[0] - pd[12], a.r[1] - pd[13], a.r[2] - pd[14]};
-        double Em[3], Eq[3], Dl[6];
-        rot(D.E, mu, Em);
-        rot(D.E, q, Eq);
-        delta_sym(D.E, S, Dl);
-        const double d[3] = {mu[0] + (Em[0] + (Eq[0] + D.dt[0])), mu[1] + (Em[1] + (Eq[1] + D.dt[1])),
-                             mu[2] + (Em[2] + (Eq[2] + D.dt[2]))};
+        for (int e = 0; e < 3; e++) w[e] = pd[9 + e];
+        const double mc[3] = {mu[0] + a.r[0], mu[1] + a.r[1], mu[2] + a.r[2]};
+        double Emc[3], Dl[6];
+        rot(E, mc, Emc);
+        delta_sym(E, S, Dl);
+        const double d[3] = {mu[0] + (Emc[0] + w[0]), mu[1] + (Emc[1] + w[1]), mu[2] + (Emc[2] + w[2])};
         double St[6];
 #pragma unroll
         for (int e = 0; e < 6; e++) St[e] = S[e] + Dl[e];

@@ -115,7 +115,7 @@ struct Problem {
     float *p_mu32 = nullptr, *p_S32 = nullptr, *p_N32 = nullptr;  // [3][C], [6][C], [C]
     double *v_ref = nullptr;      // [n_groups*64][4] reference point c_i of each voxel slot (xyz, pad)
     double *ref_poses = nullptr;  // [n_poses][12] poses that placed the references
-    double *pdelta = nullptr;     // [n_poses][16] pose change of the evaluated poses: E (9), dt (3), t0 (3)
+    double *pdelta = nullptr;     // [n_poses][16] pose change of the evaluated poses: E (9), w = dt - E t0 (3)
 
     // pose-sorted layout (length n_clusters per component)
     double *p_mu = nullptr;     // [3][C]
