@@ -424,14 +424,19 @@ static ba_status make_plan(Problem *P, const std::vector<int32_t> &cvox, const s
         g.pad = 0;
         int32_t gi = (int32_t)groups.size();
         for (int32_t l = 0; l < 64; l++) slot_vox.push_back(l < g.nvox ? cvox[vstart[vorder[i + l]]] : -1);
+        int32_t s0 = N, s1 = -1;
         for (int32_t l = 0; l < g.nvox; l++) {
             int32_t v = vorder[i + l];
             for (int32_t k = 0; k < g.m; k++) {
                 int64_t c = vstart[v] + k;
                 dst[c] = cbase + 64LL * k + l;
                 slot_of[c] = gi * 64 + l;
+                s0 = std::min(s0, cscan[c]);
+                s1 = std::max(s1, cscan[c]);
             }
         }
+        g.scan0 = s0;
+        g.nscan = s1 - s0 + 1;
         groups.push_back(g);
         win_group_ptr[g.window + 1] = (int32_t)groups.size();
         cbase += 64LL * g.m;

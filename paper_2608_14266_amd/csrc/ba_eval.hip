@@ -107,10 +107,46 @@ __device__ __forceinline__ void vox_zero(VoxSums &a) {
     for (int q = 0; q < 6; q++) a.M[q] = 0.0;
 }
 
-// FP64: the reference is the centroid of the lane's first cluster.
+// The per-scan operands a cluster gathers in the residual pass, 12 doubles
+// per scan: the pose (R, t; FP64 clusters) or the pose change (E, w; FP32
+// clusters).  A wave group's clusters observe a short run of scans (the
+// voxels are ordered by their first observing scan), so a block copies the
+// run into LDS once and its lanes gather from there instead of from the
+// cache, when the group spans at most VOX_STAGE scans.
+static constexpr int VOX_STAGE = 32;
+static constexpr int VOX_ROW = 12;
+
+__device__ __forceinline__ const double *vox_table(const SrcF64 &, const double *poses, int &stride) {
+    stride = 12;
+    return poses;
+}
+__device__ __forceinline__ const double *vox_table(const SrcF32 &src, const double *, int &stride) {
+    stride = 16;
+    return src.pdelta;
+}
+
+// All threads of the block: the scan rows of groups g0 .. g0 + ng - 1 into
+// rows[q * VOX_STAGE * VOX_ROW ..] (groups that span more scans are skipped).
+// The caller synchronises before the rows are read.
+template <class Src>
+__device__ __forceinline__ void vox_stage(const GroupDesc *__restrict__ groups, int g0, int ng, const Src &src,
+                                          const double *__restrict__ poses, double *__restrict__ rows) {
+    int stride;
+    const double *tab = vox_table(src, poses, stride);
+    for (int e = threadIdx.x; e < ng * VOX_STAGE * VOX_ROW; e += blockDim.x) {
+        const int q = e / (VOX_STAGE * VOX_ROW), r = e % (VOX_STAGE * VOX_ROW);
+        const int s = r / VOX_ROW, k = r % VOX_ROW;
+        const GroupDesc g = groups[g0 + q];
+        if (g.nscan <= VOX_STAGE && s < g.nscan) rows[e] = tab[(int64_t)(g.scan0 + s) * stride + k];
+    }
+}
+
+// FP64: the reference is the centroid of the lane's first cluster.  srow:
+// the group's staged scan rows in LDS, or null (gathers from `poses`).
 __device__ __forceinline__ void vox_accumulate(const GroupDesc &g, int64_t slot, int lane, int k0, int kstep,
                                                int64_t c_pad, const SrcF64 &src, const int32_t *__restrict__ vpose,
-                                               const double *__restrict__ poses, VoxSums &a) {
+                                               const double *__restrict__ poses, const double *__restrict__ srow,
+                                               VoxSums &a) {
     vox_zero(a);
     {
         const int64_t idx = g.cbase + lane;
@@ -134,7 +170,15 @@ __device__ __forceinline__ void vox_accumulate(const GroupDesc &g, int64_t slot,
 #pragma unroll
         for (int q = 0; q < 6; q++) S[q] = src.S[q * c_pad + idx];
         Pose P;
-        load_pose(poses, j, P);
+        if (srow) {
+            const double *q = srow + VOX_ROW * (j - g.scan0);
+#pragma unroll
+            for (int e = 0; e < 9; e++) P.r[e] = q[e];
+#pragma unroll
+            for (int e = 0; e < 3; e++) P.t[e] = q[9 + e];
+        } else {
+            load_pose(poses, j, P);
+        }
         double y[3], St[6];
         rot(P.r, mu, y);
         rot_sym(P.r, S, St);
@@ -152,7 +196,8 @@ __device__ __forceinline__ void vox_accumulate(const GroupDesc &g, int64_t slot,
 // FP32 product here; E c and E t0 round at about 1e-16 |E| |c|.
 __device__ __forceinline__ void vox_accumulate(const GroupDesc &g, int64_t slot, int lane, int k0, int kstep,
                                                int64_t c_pad, const SrcF32 &src, const int32_t *__restrict__ vpose,
-                                               const double *__restrict__ poses, VoxSums &a) {
+                                               const double *__restrict__ poses, const double *__restrict__ srow,
+                                               VoxSums &a) {
     vox_zero(a);
     const double *c = src.ref + 4 * slot;
     a.r[0] = c[0]; a.r[1] = c[1]; a.r[2] = c[2];
@@ -168,12 +213,20 @@ __device__ __forceinline__ void vox_accumulate(const GroupDesc &g, int64_t slot,
 #pragma unroll
         for (int q = 0; q < 6; q++) S[q] = (double)src.S[q * c_pad + idx];
         // pose change of scan j, formed once per evaluation (k_pose_delta)
-        const double *pd = src.pdelta + 16LL * j;
         double E[9], w[3];
+        if (srow) {
+            const double *pd = srow + VOX_ROW * (j - g.scan0);
 #pragma unroll
-        for (int e = 0; e < 9; e++) E[e] = pd[e];
+            for (int e = 0; e < 9; e++) E[e] = pd[e];
 #pragma unroll
-        for (int e = 0; e < 3; e++) w[e] = pd[9 + e];
+            for (int e = 0; e < 3; e++) w[e] = pd[9 + e];
+        } else {
+            const double *pd = src.pdelta + 16LL * j;
+#pragma unroll
+            for (int e = 0; e < 9; e++) E[e] = pd[e];
+#pragma unroll
+            for (int e = 0; e < 3; e++) w[e] = pd[9 + e];
+        }
         const double mc[3] = {mu[0] + a.r[0], mu[1] + a.r[1], mu[2] + a.r[2]};
         double Emc[3], Dl[6];
         rot(E, mc, Emc);
@@ -212,7 +265,8 @@ __device__ __forceinline__ void vox_item(int bi, const VoxBlock *__restrict__ bl
                                          const int32_t *__restrict__ vpose, const double *__restrict__ poses,
                                          double *__restrict__ vstate, int64_t n_slots,
                                          const LMState *__restrict__ lm, int trial,
-                                         double *__restrict__ group_cost, double (*part)[10][64]) {
+                                         double *__restrict__ group_cost, double (*part)[10][64],
+                                         double *__restrict__ rows) {
     const int w = threadIdx.x >> 6;
     const int lane = threadIdx.x & 63;
     const VoxBlock b = blocks[bi];
@@ -225,10 +279,14 @@ __device__ __forceinline__ void vox_item(int bi, const VoxBlock *__restrict__ bl
     double *vs = vstate + (int64_t)buf * n_slots * VSTATE;
     const int gi = b.g0;
     const GroupDesc g = groups[gi];
+    vox_stage(groups, gi, 1, src, poses, rows);
+    __syncthreads();
+    const double *srow = g.nscan <= VOX_STAGE ? rows : nullptr;
     const bool active = lane < g.nvox;
     VoxSums a;
     vox_zero(a);
-    if (active && w < g.m) vox_accumulate(g, (int64_t)gi * 64 + lane, lane, w, SPLIT, c_pad, src, vpose, poses, a);
+    if (active && w < g.m)
+        vox_accumulate(g, (int64_t)gi * 64 + lane, lane, w, SPLIT, c_pad, src, vpose, poses, srow, a);
     if (SPLIT > 1 && w > 0) {
         double *pp = &part[w - 1][0][0];
         pp[lane] = a.n;
@@ -269,14 +327,15 @@ __global__ __launch_bounds__(64 * SPLIT) void k_vox(const VoxBlock *__restrict__
                                                     int64_t n_slots, const LMState *__restrict__ lm, int trial,
                                                     double *__restrict__ group_cost) {
     __shared__ double part[SPLIT > 1 ? SPLIT - 1 : 1][10][64];
+    __shared__ double rows[VOX_STAGE * VOX_ROW];
     if constexpr (!PERSIST) {
         vox_item<Src, SPLIT>((int)blockIdx.x, blocks, groups, c_pad, src, vpose, poses, vstate, n_slots, lm, trial,
-                             group_cost, part);
+                             group_cost, part, rows);
     } else {
         for (int bi = blockIdx.x; bi < n_blocks; bi += gridDim.x) {
             vox_item<Src, SPLIT>(bi, blocks, groups, c_pad, src, vpose, poses, vstate, n_slots, lm, trial,
-                                 group_cost, part);
-            if (SPLIT > 1) __syncthreads();   // part[] is reused by the next item
+                                 group_cost, part, rows);
+            __syncthreads();   // part[] and rows[] are reused by the next item
         }
     }
 }
@@ -294,6 +353,7 @@ __global__ __launch_bounds__(256) void k_vox_mixed(const VoxBlock *__restrict__ 
                                                    int64_t n_slots, const LMState *__restrict__ lm, int trial,
                                                    double *__restrict__ group_cost) {
     __shared__ double part[4][10][64];
+    __shared__ double rows[4][VOX_STAGE * VOX_ROW];
     const int w = threadIdx.x >> 6;
     const int lane = threadIdx.x & 63;
     for (int bi = blockIdx.x; bi < n_blocks; bi += (PERSIST ? gridDim.x : n_blocks)) {
@@ -302,6 +362,8 @@ __global__ __launch_bounds__(256) void k_vox_mixed(const VoxBlock *__restrict__ 
         const int gsub = w / sp, pt = w % sp;
         const bool has_group = gsub < b.ng;
         const int gi = b.g0 + (has_group ? gsub : 0);
+        vox_stage(groups, b.g0, b.ng, src, poses, &rows[0][0]);
+        __syncthreads();
         int buf = 0;
         bool run = has_group;
         if (lm) {
@@ -310,10 +372,12 @@ __global__ __launch_bounds__(256) void k_vox_mixed(const VoxBlock *__restrict__ 
             buf = trial ? 1 - st.cur : st.cur;
         }
         const GroupDesc g = groups[gi];
+        const double *srow = g.nscan <= VOX_STAGE ? rows[gsub] : nullptr;
         const bool active = run && lane < g.nvox;
         VoxSums a;
         vox_zero(a);
-        if (active && pt < g.m) vox_accumulate(g, (int64_t)gi * 64 + lane, lane, pt, sp, c_pad, src, vpose, poses, a);
+        if (active && pt < g.m)
+            vox_accumulate(g, (int64_t)gi * 64 + lane, lane, pt, sp, c_pad, src, vpose, poses, srow, a);
         if (pt > 0) {
             double *pp = &part[w][0][0];
             pp[lane] = a.n;

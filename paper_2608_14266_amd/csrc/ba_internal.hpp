@@ -21,6 +21,8 @@ struct GroupDesc {
     int32_t m;
     int32_t nvox;
     int32_t window;
+    int32_t scan0;   // lowest scan of the group's clusters
+    int32_t nscan;   // scans from scan0 to the highest one
     int32_t pad;
 };
 
