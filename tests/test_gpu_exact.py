@@ -154,7 +154,20 @@ def test_hybrid_lm_matches_oracle(ba, dev, orc):
           f"oracle spread {np.max(dtr[:k, 0:2] / (1e-12 * scale)):.2e}, pose spread {dPs.max():.2e}")
     assert np.all(err <= np.maximum(1e-12 * scale, 10 * dtr[:k, 0:2]))
     assert abs(reps[0]["cost_final"] - c_ref) <= max(1e-12 * c_ref, 10 * dc)
-    assert reps[0]["converged"] == 1
+    if reps[0]["converged"] != 1:
+        # The oracle's last step predicts a decrease of 3.4e-20 on a cost of
+        # 1.29, below the cost's rounding unit: its gain ratio (actual over
+        # predicted decrease) is rounding noise (+4.6e4 here), so whether
+        # that step is accepted depends on the summation order.  A run that
+        # rejects it instead stops at the same gradient norm, and every step
+        # it rejects predicts a decrease below the rounding unit.
+        n = reps[0]["iters"]
+        rej = tr[:n][tr[:n, 4] == 0]
+        assert len(rej) > 0
+        assert np.all(rej[:, 7] <= 4 * np.finfo(np.float64).eps * rej[:, 0])
+        assert reps[0]["gnorm_final"] <= 2 * rep_ref[-1, 5]
+        # its poses are then the oracle's iterate before that last step
+        P_ref = orc.lm(orc.COUPLED, cl, sc.poses_init, len(rep_ref) - 1, tol_g=1e-9, exact_below=0.1)[0]
     dP = np.abs(P.cpu().numpy() - P_ref)
     assert np.all(dP <= np.maximum(1e-11 * (1.0 + np.abs(P_ref)), 10 * dPs))
 
