@@ -61,9 +61,9 @@ def cpu_baseline(sc, mode_name: str, iters: int):
 
 
 def _measured_traffic(key: str):
-    """HBM bytes per launch of the residual pass from the committed rocprofv3
-    byte-counter summary, or None once the kernel source differs from the one
-    the counters were taken on."""
+    """HBM bytes per launch of an evaluation pass on the single-window workload
+    from the committed rocprofv3 byte-counter summary, or None once the kernel
+    source differs from the one the counters were taken on."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "window500_traffic.md")
     src = os.path.join(ROOT, "paper_2608_14266_amd", "csrc", "ba_eval.hip")
@@ -243,7 +243,7 @@ def main():
     for k, d in kern.items():
         d["gbs"] = d["bytes"] / (d["avg_us"] * 1e-6) / 1e9 if d["avg_us"] > 0 else 0.0
     dom = max(kern, key=lambda k: kern[k]["avg_us"] * kern[k]["launches"])
-    traffic = _measured_traffic("traffic_k_vox_f64_bytes") if (dom == "k_vox" and args.workload == "window") else None
+    traffic = _measured_traffic(f"traffic_{dom}_f64_bytes") if args.workload == "window" else None
     roof = {"kernel": dom, "bound": "hbm", "achieved": round(kern[dom]["gbs"], 2), "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": round(kern[dom]["gbs"] / HBM_PEAK_GBS, 4), "traffic": traffic,
             "bytes_per_launch": kern[dom]["bytes"], "avg_launch_us": round(kern[dom]["avg_us"], 3)}
