@@ -220,6 +220,7 @@ def main():
     trsm_ms, trsm_n = ba.profile_query("k_trsm")
     potf2_ms, potf2_n = ba.profile_query("k_potf2")
     flow_ms, flow_n = ba.profile_query("k_chol_flow")
+    bs_ms, bs_n = ba.profile_query("k_backsub_flow")
     ba.profile_reset()
     elapsed = t1 - t0
     ms_per_step = 1e3 * elapsed / args.steps
@@ -254,6 +255,8 @@ def main():
         fl = n ** 3 / 3
         tfs = fl * flow_n / (flow_ms * 1e-3) / 1e12
         kern["k_chol_flow"] = dict(avg_us=1e3 * flow_ms / flow_n, launches=flow_n, flops=fl)
+        if bs_n > 0:
+            kern["k_backsub_flow"] = dict(avg_us=1e3 * bs_ms / bs_n, launches=bs_n)
         roof = {"kernel": "k_chol_flow", "bound": "mfma", "achieved": round(tfs, 3),
                 "peak": FP64_MFMA_PEAK_TFS, "unit": "TFLOP/s", "frac": round(tfs / FP64_MFMA_PEAK_TFS, 4),
                 "traffic": None, "flops_per_factorization": fl, "avg_launch_us": round(1e3 * flow_ms / flow_n, 3)}

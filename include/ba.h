@@ -236,11 +236,13 @@ size_t ba_solve_increment_workspace(int32_t mode, int32_t n_scans);
  *   BA_MODE_MM: n_scans independent 6x6 LDL^T factorizations; hess is [N][36].
  *   BA_MODE_COUPLED (or BA_MODE_EXACT): one dense Cholesky of the (6N)^2
  *   row-major hess by 64 x 64 tiles on FP64 matrix cores: up to 6144 rows
- *   in one persistent dataflow launch, larger ones blocked with one launch
- *   per step; hess is symmetric and only its lower triangle is read.
+ *   in one persistent dataflow launch for the factorization and forward
+ *   substitution and one for the back substitution, larger ones blocked
+ *   with one launch per step; hess is symmetric and only its lower
+ *   triangle is read.
  * hess, grad: device inputs (unchanged).  dx: device [N][6] output.
  * info: device int32 output, 0, the 1-based index of the first
- * non-positive pivot, or -1 if a bounded wait of the dataflow launch gave
+ * non-positive pivot, or -1 if a bounded wait of a dataflow launch gave
  * up (dx is zero unless info is 0).  ws: device workspace of at least
  * ba_solve_increment_workspace(mode, n_scans) bytes.  Asynchronous.
  */

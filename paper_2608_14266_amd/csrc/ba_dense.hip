@@ -981,7 +981,7 @@ static constexpr int FLOW_SPIN = 1 << 20;     // polls before a wait gives up (e
 
 // Flags of one matrix with T tile rows: T*T tile flags (i, k), T diagonal
 // flags, 3 T flags of the partial-sum tasks and one "abandoned" flag.
-static inline int64_t flow_flag_ints(int64_t T) { return T * T + 4 * T + 1; }
+__host__ __device__ static inline int64_t flow_flag_ints(int64_t T) { return T * T + 4 * T + 1; }
 
 // Pointers with their address space spelled out: the task bodies below are
 // compiled out of line (each with its own register allocation), and their
@@ -1674,6 +1674,134 @@ __global__ void k_flow_tasks_one(int32_t T, FlowTask *__restrict__ tasks) {
     }
 }
 
+// ---------------------------------------------------------------- dataflow back substitution
+// One launch solves L^T x = y for every matrix of a set, after the dataflow
+// factorization (y = L^-1 b and the inverse diagonal blocks are in place).
+// Task (m, p) owns block rows hi = T - 1 - 2p and lo = hi - 1 of matrix m (no
+// lo at the top of an odd T).  Tasks are taken from a queue ticket in chain
+// order (p-major), and task (m, p) waits for the flags of tasks (m, 0), ...,
+// (m, p - 1) in turn, which hold earlier tickets: their workgroups are running
+// or done, so the chain cannot deadlock.  Before each wait the task loads the
+// four tiles of L that couple that pair of rows to its own, so the loads
+// overlap the wait; it then subtracts L_kr^T x_k from y_r for k descending,
+// as the two-row launches do.  With every update in, x_hi = L_hi^-T y_hi,
+// y_lo -= L_(hi,lo)^T x_hi and x_lo = L_lo^-T y_lo, and one flag publishes
+// both rows.  Each wait is bounded; a give-up marks the matrix failed
+// (info = -1) and abandons its other tasks.
+struct BsTask {
+    int32_t m, p;
+};
+
+// (sum_q l[q] v[part + 4 q]) summed over the four parts of a column
+__device__ __forceinline__ double bs_dot16(const double (&l)[16], const double *v, int part) {
+    double s = 0.0;
+#pragma unroll
+    for (int q = 0; q < 16; q++) s += l[q] * v[part + 4 * q];
+    s += __shfl_xor(s, 1, 64);
+    s += __shfl_xor(s, 2, 64);
+    return s;
+}
+
+__global__ __launch_bounds__(256) void k_backsub_flow(const DenseDesc *__restrict__ desc, DenseParam *__restrict__ prm,
+                                                     const double *__restrict__ work, double *__restrict__ x,
+                                                     const int64_t *__restrict__ x_off,
+                                                     const BsTask *__restrict__ tasks, int32_t n_tasks,
+                                                     int *__restrict__ flags, const int64_t *__restrict__ bo,
+                                                     int *__restrict__ queue, int *__restrict__ gab_, int limit) {
+    __shared__ double xs[2][TB], ys[2][TB];
+    __shared__ int s_task;
+    __shared__ int s_val;
+    const int t = threadIdx.x, o = t >> 2, part = t & 3;
+    glb_i32 *gab = (glb_i32 *)gab_;
+    for (;;) {
+        __syncthreads();   // the previous task's shared values are no longer read
+        if (t == 0) s_task = atomicAdd(queue, 1);
+        __syncthreads();
+        const int ti = s_task;
+        if (ti >= n_tasks) return;
+        const BsTask tk = tasks[ti];
+        const int m = tk.m;
+        const DenseDesc d = desc[m];
+        if (!prm[m].active || __hip_atomic_load(&prm[m].info, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) continue;
+        const int T = (d.n + TB - 1) / TB;
+        glb_i32 *fl = (glb_i32 *)(flags + bo[m]);
+        glb_i32 *ab = fl + T;
+        const int hi = T - 1 - 2 * tk.p, lo = hi - 1;   // lo < 0: none
+        const int nh = min(TB, d.n - TB * hi);          // only the last block row can be partial
+        const int64_t n = d.n;
+        const double *A = work + d.a_off;
+        const int64_t xo = x_off[m];
+        double lih[16], lil[16], lc[16];
+#pragma unroll
+        for (int q = 0; q < 16; q++) {
+            const int r = part + 4 * q;
+            lih[q] = work[d.linv_off + (int64_t)hi * TB * TB + r * TB + o];
+            lil[q] = lo >= 0 ? work[d.linv_off + (int64_t)lo * TB * TB + r * TB + o] : 0.0;
+            lc[q] = (lo >= 0 && r < nh) ? A[((int64_t)TB * hi + r) * n + (int64_t)TB * lo + o] : 0.0;
+        }
+        double yh = o < nh ? work[d.v_off + (int64_t)TB * hi + o] : 0.0;
+        double yl = lo >= 0 ? work[d.v_off + (int64_t)TB * lo + o] : 0.0;
+        bool ok = true;
+        for (int pp = 0; pp < tk.p; pp++) {
+            const int k1 = T - 1 - 2 * pp, k2 = k1 - 1;   // k2 > hi
+            const int n1 = min(TB, d.n - TB * k1);
+            double t1h[16], t2h[16], t1l[16], t2l[16];
+#pragma unroll
+            for (int q = 0; q < 16; q++) {
+                const int r = part + 4 * q;
+                const int64_t r1 = ((int64_t)TB * k1 + r) * n, r2 = ((int64_t)TB * k2 + r) * n;
+                t1h[q] = r < n1 ? A[r1 + (int64_t)TB * hi + o] : 0.0;
+                t2h[q] = A[r2 + (int64_t)TB * hi + o];
+                t1l[q] = (lo >= 0 && r < n1) ? A[r1 + (int64_t)TB * lo + o] : 0.0;
+                t2l[q] = lo >= 0 ? A[r2 + (int64_t)TB * lo + o] : 0.0;
+            }
+            if (!flow_wait(fl + pp, ab, gab, limit, (lds_i32 *)&s_val)) {
+                ok = false;
+                break;
+            }
+            if (t < TB) {
+                xs[0][t] = t < n1 ? x[xo + (int64_t)TB * k1 + t] : 0.0;
+                xs[1][t] = x[xo + (int64_t)TB * k2 + t];
+            }
+            __syncthreads();
+            yh -= bs_dot16(t1h, xs[0], part);
+            yh -= bs_dot16(t2h, xs[1], part);
+            yl -= bs_dot16(t1l, xs[0], part);
+            yl -= bs_dot16(t2l, xs[1], part);
+        }
+        if (!ok) {
+            if (t == 0) {
+                flag_set(ab, __ATOMIC_RELAXED);
+                __hip_atomic_store(&prm[m].info, -1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
+            continue;
+        }
+        if (part == 0) ys[0][o] = yh;
+        __syncthreads();
+        const double xh = bs_dot16(lih, ys[0], part);
+        if (part == 0) xs[0][o] = xh;
+        __syncthreads();
+        double xl = 0.0;
+        if (lo >= 0) {
+            yl -= bs_dot16(lc, xs[0], part);
+            if (part == 0) ys[1][o] = yl;
+            __syncthreads();
+            xl = bs_dot16(lil, ys[1], part);
+        }
+        if (part == 0) {
+            if (o < nh) x[xo + (int64_t)TB * hi + o] = xh;
+            if (lo >= 0) x[xo + (int64_t)TB * lo + o] = xl;
+        }
+        flow_publish(fl + tk.p);
+    }
+}
+
+// Back-substitution tasks of one matrix with T block rows (the standalone solve).
+__global__ void k_bs_tasks_one(int32_t T, BsTask *__restrict__ tasks) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p < (T + 1) / 2) tasks[p] = BsTask{0, p};
+}
+
 __global__ void k_fill_i32(int64_t n, int *__restrict__ p, int v) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
         p[i] = v;
@@ -1883,6 +2011,13 @@ struct DenseState {
     std::vector<int32_t> flow_first, flow_count;
     std::vector<int32_t> flow_mats;   // matrices (walkers) of each launch
     std::vector<int64_t> flow_work;   // sum of T^2 over the launch's matrices (sets its helper count)
+    // dataflow back substitution: its flags follow the factorization's in
+    // flow_flags (per matrix T + 1 at bs_bo[m], then a queue ticket and an
+    // abort flag at bs_ticket, bs_ticket + 1); bs_ints counts them all
+    BsTask *bs_tasks = nullptr;
+    int32_t bs_count = 0;
+    int64_t *bs_bo = nullptr;
+    int64_t bs_ticket = 0, bs_ints = 0;
 };
 
 static DenseState *dense_state(Problem *P) { return (DenseState *)P->dense_state; }
@@ -2062,11 +2197,35 @@ ba_status dense_prepare(Problem *P) {
             D->flow_work.push_back(work);
         }
         D->flow_ints = ints;
+        // back substitution: tasks p-major over the matrices, flags after the
+        // factorization's tickets and abort flag
+        std::vector<BsTask> bs;
+        std::vector<int64_t> bo(W);
+        int64_t bints = ints + (int64_t)D->flow_first.size() + 1;
+        const int64_t bs_base = bints;
+        int32_t maxP = 0;
+        for (int32_t w = 0; w < W; w++) {
+            const int32_t T = (desc[w].n + TB - 1) / TB;
+            bo[w] = bints;
+            bints += T + 1;
+            maxP = std::max(maxP, (T + 1) / 2);
+        }
+        for (int32_t p = 0; p < maxP; p++)
+            for (int32_t w = 0; w < W; w++)
+                if (p < ((desc[w].n + TB - 1) / TB + 1) / 2) bs.push_back(BsTask{w, p});
+        D->bs_ticket = bints;
+        D->bs_ints = bints + 2 - bs_base;
+        D->bs_count = (int32_t)bs.size();
         BA_TRY(D->mem.alloc(&D->flow_tasks, (int64_t)tasks.size()));
-        BA_TRY(D->mem.alloc(&D->flow_flags, ints + (int64_t)D->flow_first.size() + 1));
+        BA_TRY(D->mem.alloc(&D->flow_flags, bints + 2));
         BA_TRY(D->mem.alloc(&D->flow_fo, W));
+        BA_TRY(D->mem.alloc(&D->bs_tasks, std::max<int64_t>(D->bs_count, 1)));
+        BA_TRY(D->mem.alloc(&D->bs_bo, W));
         BA_HIP(hipMemcpy(D->flow_tasks, tasks.data(), sizeof(FlowTask) * tasks.size(), hipMemcpyHostToDevice));
         BA_HIP(hipMemcpy(D->flow_fo, fo.data(), sizeof(int64_t) * W, hipMemcpyHostToDevice));
+        if (!bs.empty())
+            BA_HIP(hipMemcpy(D->bs_tasks, bs.data(), sizeof(BsTask) * bs.size(), hipMemcpyHostToDevice));
+        BA_HIP(hipMemcpy(D->bs_bo, bo.data(), sizeof(int64_t) * W, hipMemcpyHostToDevice));
     }
     D->ready = true;
     return BA_OK;
@@ -2135,7 +2294,7 @@ ba_status dense_assemble_exact(Problem *P, const double *poses, double *hess_out
 static void launch_flow_factor(DenseState *D, const double *H, const int64_t *h_off, const double *g,
                                hipStream_t s) {
     const int nl = (int)D->flow_first.size();
-    const int64_t nint = D->flow_ints + nl + 1;
+    const int64_t nint = D->flow_ints + nl + 1 + D->bs_ints;   // the back substitution's flags follow
     hipLaunchKernelGGL(k_fill_i32, dim3((unsigned)std::min<int64_t>(nblk(nint), 1024)), dim3(256), 0, s, nint,
                        D->flow_flags, 0);
     const int limit = flow_spin_limit();
@@ -2199,15 +2358,26 @@ static void launch_factor_solve(DenseState *D, int32_t nmat, int32_t max_n, cons
     const int nsteps = (max_n + TB - 1) / TB;
     const int64_t nn = (int64_t)max_n * max_n;
     if (D->flow_tasks && max_n <= FLOW_MAX_N) {
-        launch_flow_factor(D, H, h_off, g, s);   // reads H and g directly
+        launch_flow_factor(D, H, h_off, g, s);   // reads H and g directly (and clears both kernels' flags)
+        // back substitution in one launch: tasks of a matrix mostly wait on
+        // each other, so a few per compute unit
+        const int grid = (int)std::min<int64_t>(D->bs_count, 2LL * cu_count());
+        if (grid > 0) {
+            ProfScope prof("k_backsub_flow", s);
+            hipLaunchKernelGGL(k_backsub_flow, dim3((unsigned)grid), dim3(256), 0, s, D->desc, D->prm, D->work, x,
+                               x_off, D->bs_tasks, D->bs_count, D->flow_flags, D->bs_bo,
+                               D->flow_flags + D->bs_ticket, D->flow_flags + D->bs_ticket + 1, flow_spin_limit());
+        }
+        return;
     } else {
         hipLaunchKernelGGL(k_damp_copy, dim3((unsigned)std::min<int64_t>(nblk(nn), 4096), nmat), dim3(256), 0, s,
                            D->desc, D->prm, H, h_off, g, D->work);
         launch_blocked_factor(D, nmat, nsteps, s);
     }
-    // backward substitution two block rows per launch (every workgroup loads
-    // the rows' inverse and cross tiles: with three rows its 145 loads per
-    // thread need three rounds of outstanding loads, 15 us a launch)
+    // launch-per-step path: backward substitution two block rows per launch
+    // (every workgroup loads the rows' inverse and cross tiles: with three rows
+    // its 145 loads per thread need three rounds of outstanding loads, 15 us a
+    // launch)
     constexpr int BR = 2;
     for (int st = nsteps - 1; st >= 0; st -= BR) {
         ProfScope prof("k_backsub_rows", s);
@@ -2245,14 +2415,21 @@ static size_t solve_head_bytes() { return align_up(sizeof(DenseDesc) + sizeof(De
 static size_t solve_work_bytes(int64_t n) {
     return align_up(sizeof(double) * (size_t)(n * n + linv_doubles(n) + n), 256);
 }
+// Flags of the standalone dataflow path: the factorization's, its ticket and
+// abort flag, then the back substitution's T + 1, its ticket and abort flag.
+static int64_t solve_flag_ints(int64_t T) { return flow_flag_ints(T) + 2 + (T + 1) + 2; }
 static size_t solve_flag_bytes(int64_t n) {
     const int64_t T = (n + TB - 1) / TB;
-    return n <= FLOW_MAX_N ? align_up(sizeof(int) * (size_t)(flow_flag_ints(T) + 2), 256) : 0;
+    return n <= FLOW_MAX_N ? align_up(sizeof(int) * (size_t)solve_flag_ints(T), 256) : 0;
+}
+static size_t solve_task_bytes(int64_t n) {
+    const int64_t T = (n + TB - 1) / TB;
+    return n <= FLOW_MAX_N ? align_up(sizeof(FlowTask) * (size_t)flow_task_count(T), 256) : 0;
 }
 size_t dense_solve_workspace(int64_t n) {
     const int64_t T = (n + TB - 1) / TB;
-    const size_t tasks = n <= FLOW_MAX_N ? sizeof(FlowTask) * (size_t)flow_task_count(T) : 0;
-    return solve_head_bytes() + solve_work_bytes(n) + solve_flag_bytes(n) + tasks + 256;
+    const size_t bs = n <= FLOW_MAX_N ? sizeof(BsTask) * (size_t)((T + 1) / 2) : 0;
+    return solve_head_bytes() + solve_work_bytes(n) + solve_flag_bytes(n) + solve_task_bytes(n) + bs + 256;
 }
 
 __global__ void k_solve_setup(int64_t n, const double *__restrict__ H, double mu, DenseDesc *__restrict__ desc,
@@ -2280,9 +2457,11 @@ __global__ void k_solve_setup(int64_t n, const double *__restrict__ H, double mu
         p.active = 1;
         p.info = 0;
         prm[0] = p;
+        const int64_t T = (n + TB - 1) / TB;
         offs[0] = 0;  // h_off
         offs[1] = 0;  // x_off
-        offs[2] = 0;  // offset of the matrix's flags
+        offs[2] = 0;  // offset of the matrix's factorization flags
+        offs[3] = flow_flag_ints(T) + 2;   // offset of its back-substitution flags
     }
 }
 
@@ -2316,7 +2495,14 @@ ba_status dense_solve(int64_t n, const double *A, const double *g, double mu, do
         tmp.flow_count.push_back((int32_t)flow_task_count(T));
         tmp.flow_mats.push_back(1);
         tmp.flow_work.push_back(T * T);
+        tmp.bs_tasks = (BsTask *)(p + solve_head_bytes() + solve_work_bytes(n) + solve_flag_bytes(n) +
+                                  solve_task_bytes(n));
+        tmp.bs_count = (int32_t)((T + 1) / 2);
+        tmp.bs_bo = offs + 3;
+        tmp.bs_ticket = flow_flag_ints(T) + 2 + T + 1;
+        tmp.bs_ints = T + 1 + 2;
         hipLaunchKernelGGL(k_flow_tasks_one, dim3(nblk(T)), dim3(256), 0, s, (int32_t)T, tmp.flow_tasks);
+        hipLaunchKernelGGL(k_bs_tasks_one, dim3(nblk((T + 1) / 2)), dim3(256), 0, s, (int32_t)T, tmp.bs_tasks);
     }
     launch_factor_solve(&tmp, 1, (int32_t)n, A, offs, g, dx, offs + 1, s);
     hipLaunchKernelGGL(k_solve_final, dim3(nblk(n)), dim3(256), 0, s, n, prm, dx, info);
