@@ -103,6 +103,34 @@ def test_coupled_many_windows_equal_solo_bitwise(ba, dev):
             assert r1[0][k] == reps[w][k], (w, k)
 
 
+def test_coupled_long_chains_equal_solo_bitwise(ba, dev):
+    """Windows of 3, 5, 6, 9 and 17 block rows of 64 (n = 6 x poses) share one
+    dataflow back-substitution launch, whose tasks each wait on the pairs of
+    block rows below them; every window's coupled LM run equals the window
+    solved alone."""
+    import torch
+    sizes = (30, 53, 64, 96, 181)
+    sc = ss.batch_windows(seed=4400, n_windows=len(sizes), poses=list(sizes), vox_per_pose=12,
+                          vox_range=(300, 3000), workers=1)
+    say(f"coupled chains: windows {sizes}, {sc.n_clusters} clusters")
+    pb = build_gpu_sums(ba, sc, dev)
+    P = torch.as_tensor(sc.poses_init, device=dev).contiguous()
+    reps, tr = ba.iterate(pb, P, ba.MODE_COUPLED, max_iters=4)
+    pb.close()
+    Pb = P.cpu().numpy()
+    s0 = 0
+    for w in range(sc.n_windows):
+        sw = ss.window_of(sc, w)
+        ps = build_gpu_sums(ba, sw, dev)
+        Q = torch.as_tensor(sw.poses_init, device=dev).contiguous()
+        r1, t1 = ba.iterate(ps, Q, ba.MODE_COUPLED, max_iters=4)
+        ps.close()
+        assert reps[w]["n_accepted"] >= 1 and reps[w]["last_info"] == 0, (w, reps[w])
+        assert np.array_equal(Q.cpu().numpy(), Pb[s0:s0 + sw.n_scans]), f"window {w} poses"
+        assert np.array_equal(t1[:, 0, :], tr[:, w, :]), f"window {w} trace"
+        s0 += sw.n_scans
+
+
 @pytest.mark.parametrize("sizes", [(8, 255, 256, 257, 513), (255, 257, 513, 1030)])
 def test_solve_forms_equal_bitwise(ba, dev, sizes):
     """The MM increment solve covers a window with one block per 256 poses,
