@@ -2034,6 +2034,70 @@ double *dense_hvec(Problem *P) {
     return D ? D->h : nullptr;
 }
 
+// ---------------------------------------------------------------- pair plan
+// Every (voxel, i <= j) pair of a voxel's clusters, in the order of the voxels
+// and, within one, cluster i outer and j inner, keyed by their scans
+// (j_i << bits_b | j_j); a voxel's clusters are in scan order, so j_i <= j_j.
+// A stable sort by the key then lists the pairs by (j_i, j_j) with ties in
+// this order.
+__global__ void k_pair_emit(int32_t n_vx, const int64_t *__restrict__ vptr, const int64_t *__restrict__ poff,
+                            const int32_t *__restrict__ cscan, int bits_b, uint64_t *__restrict__ keys,
+                            uint32_t *__restrict__ vals, int32_t *__restrict__ ea, int32_t *__restrict__ eb) {
+    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= n_vx) return;
+    const int64_t a = vptr[v], b = vptr[v + 1];
+    int64_t q = poff[v];
+    for (int64_t i = a; i < b; i++) {
+        const uint64_t ki = (uint64_t)cscan[i] << bits_b;
+        for (int64_t j = i; j < b; j++, q++) {
+            keys[q] = ki | (uint64_t)cscan[j];
+            vals[q] = (uint32_t)q;
+            ea[q] = (int32_t)i;
+            eb[q] = (int32_t)j;
+        }
+    }
+}
+
+__global__ void k_inv_perm(int64_t C, const int32_t *__restrict__ perm, int32_t *__restrict__ inv) {
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q < C) inv[perm[q]] = (int32_t)q;
+}
+
+// Sorted pairs: their clusters in the order h is kept in (qc maps a
+// voxel-major cluster to it; null: voxel-major) and a 1 at each new key.
+__global__ void k_pair_out(int64_t E, const uint64_t *__restrict__ keys, const uint32_t *__restrict__ vals,
+                           const int32_t *__restrict__ ea, const int32_t *__restrict__ eb,
+                           const int32_t *__restrict__ qc, int32_t *__restrict__ spa, int32_t *__restrict__ spb,
+                           int64_t *__restrict__ head) {
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= E) return;
+    const uint32_t o = vals[r];
+    const int32_t a = ea[o], b = eb[o];
+    spa[r] = qc ? qc[a] : a;
+    spb[r] = qc ? qc[b] : b;
+    head[r] = (r == 0 || keys[r] != keys[r - 1]) ? 1 : 0;
+}
+
+// One segment per key: its start (sidx = exclusive scan of the key heads),
+// then its length from the next segment's start.
+__global__ void k_seg_emit(int64_t E, const uint64_t *__restrict__ keys, const int64_t *__restrict__ sidx,
+                           int bits_b, PairSeg *__restrict__ segs) {
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= E || !(r == 0 || keys[r] != keys[r - 1])) return;
+    PairSeg sg;
+    sg.start = r;
+    sg.count = 0;
+    sg.ja = (int32_t)(keys[r] >> bits_b);
+    sg.jb = (int32_t)(keys[r] & ((1ULL << bits_b) - 1));
+    sg.pad = 0;
+    segs[sidx[r]] = sg;
+}
+
+__global__ void k_seg_count(int64_t n_seg, int64_t E, PairSeg *__restrict__ segs) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n_seg) segs[i].count = (int32_t)((i + 1 < n_seg ? segs[i + 1].start : E) - segs[i].start);
+}
+
 int64_t dense_device_bytes(const Problem *P) {
     const DenseState *D = (const DenseState *)P->dense_state;
     return D ? (int64_t)D->mem.bytes : 0;
@@ -2046,79 +2110,76 @@ ba_status dense_prepare(Problem *P) {
     P->dense_state = D;
     const int64_t C = P->n_clusters;
     const int32_t W = P->n_windows;
-    std::vector<int32_t> cvox(C), cscan(C);
+    // voxel runs of the voxel-major clusters and their pair counts (host),
+    // then the pairs themselves, sorted by their scan pair on the device
+    std::vector<int32_t> cvox(C);
     BA_HIP(hipMemcpy(cvox.data(), P->c_vox, sizeof(int32_t) * C, hipMemcpyDeviceToHost));
-    BA_HIP(hipMemcpy(cscan.data(), P->c_scan, sizeof(int32_t) * C, hipMemcpyDeviceToHost));
-    // every (voxel, j <= k) pair, keyed by (j, k): the clusters of a voxel are
-    // in scan order, so a pair (i <= j) of its clusters has j_scan >= i_scan
-    std::vector<int32_t> pa, pb;
-    std::vector<int64_t> vptr;
+    std::vector<int64_t> vptr, poff;
+    vptr.reserve((size_t)C / 2 + 2);
+    poff.reserve((size_t)C / 2 + 2);
+    int64_t E = 0;
     for (int64_t a = 0; a < C;) {
         int64_t b = a;
         while (b < C && cvox[b] == cvox[a]) b++;
         vptr.push_back(a);
-        for (int64_t i = a; i < b; i++)
-            for (int64_t j = i; j < b; j++) {
-                pa.push_back((int32_t)i);
-                pb.push_back((int32_t)j);
-            }
+        poff.push_back(E);
+        E += (b - a) * (b - a + 1) / 2;
         a = b;
     }
     vptr.push_back(C);
+    poff.push_back(E);
     D->n_vx = (int32_t)vptr.size() - 1;
+    if (E >= (int64_t)UINT32_MAX) {
+        set_error("%lld cluster pairs exceed the pair plan's 2^32 limit", (long long)E);
+        return BA_E_UNSUPPORTED;
+    }
     BA_TRY(D->mem.alloc(&D->vptr, (int64_t)vptr.size()));
     BA_HIP(hipMemcpy(D->vptr, vptr.data(), sizeof(int64_t) * vptr.size(), hipMemcpyHostToDevice));
-    const int64_t E = (int64_t)pa.size();
-    // stable two-pass counting sort: by the second scan, then by the first
-    const int32_t NP = P->n_poses;
-    std::vector<int64_t> o1(E), ord(E), cnt(NP + 1);
-    std::fill(cnt.begin(), cnt.end(), 0);
-    for (int64_t q = 0; q < E; q++) cnt[cscan[pb[q]] + 1]++;
-    for (int32_t j = 0; j < NP; j++) cnt[j + 1] += cnt[j];
-    for (int64_t q = 0; q < E; q++) o1[cnt[cscan[pb[q]]]++] = q;
-    std::fill(cnt.begin(), cnt.end(), 0);
-    for (int64_t q = 0; q < E; q++) cnt[cscan[pa[q]] + 1]++;
-    for (int32_t j = 0; j < NP; j++) cnt[j + 1] += cnt[j];
-    for (int64_t r = 0; r < E; r++) {
-        const int64_t q = o1[r];
-        ord[cnt[cscan[pa[q]]]++] = q;
-    }
-    // the precision form keeps h in pose-major order (written by the
-    // derivative pass): the pair lists then index that order
-    std::vector<int32_t> q_of_c;
-    if (P->prec == BA_PREC_F32) {
-        std::vector<int32_t> cidx(C);
-        BA_HIP(hipMemcpy(cidx.data(), P->p_cidx, sizeof(int32_t) * C, hipMemcpyDeviceToHost));
-        q_of_c.resize(C);
-        for (int64_t q = 0; q < C; q++) q_of_c[cidx[q]] = (int32_t)q;
-    }
-    std::vector<int32_t> spa(E), spb(E);
-    std::vector<PairSeg> segs;
-    for (int64_t q = 0; q < E; q++) {
-        const int64_t o = ord[q];
-        spa[q] = q_of_c.empty() ? pa[o] : q_of_c[pa[o]];
-        spb[q] = q_of_c.empty() ? pb[o] : q_of_c[pb[o]];
-        const int32_t ja = cscan[pa[o]], jb = cscan[pb[o]];
-        if (q == 0 || ja != segs.back().ja || jb != segs.back().jb) {
-            PairSeg sg;
-            sg.start = q;
-            sg.count = 0;
-            sg.ja = ja;
-            sg.jb = jb;
-            sg.pad = 0;
-            segs.push_back(sg);
-        }
-        segs.back().count++;
-    }
-    D->n_seg = (int32_t)segs.size();
-    BA_TRY(D->mem.alloc(&D->segs, std::max<int64_t>(D->n_seg, 1)));
     BA_TRY(D->mem.alloc(&D->pa, std::max<int64_t>(E, 1)));
     BA_TRY(D->mem.alloc(&D->pb, std::max<int64_t>(E, 1)));
     BA_TRY(D->mem.alloc(&D->h, 6 * std::max<int64_t>(C, 1)));
-    if (D->n_seg) BA_HIP(hipMemcpy(D->segs, segs.data(), sizeof(PairSeg) * segs.size(), hipMemcpyHostToDevice));
-    if (E) {
-        BA_HIP(hipMemcpy(D->pa, spa.data(), sizeof(int32_t) * E, hipMemcpyHostToDevice));
-        BA_HIP(hipMemcpy(D->pb, spb.data(), sizeof(int32_t) * E, hipMemcpyHostToDevice));
+    D->n_seg = 0;
+    if (E > 0) {
+        const int32_t NP = P->n_poses;
+        int bits_b = 1;
+        while (bits_b < 31 && (int64_t(1) << bits_b) < NP) bits_b++;
+        DevArena tmp;
+        int64_t *d_poff, *head, *d_total;
+        uint64_t *keys;
+        uint32_t *vals;
+        int32_t *ea, *eb, *qc = nullptr;
+        char *ws;
+        const size_t ws_bytes = std::max(radix_sort_workspace_bytes(E), scan_workspace_bytes(E));
+        BA_TRY(tmp.alloc(&d_poff, (int64_t)poff.size()));
+        BA_TRY(tmp.alloc(&keys, E));
+        BA_TRY(tmp.alloc(&vals, E));
+        BA_TRY(tmp.alloc(&ea, E));
+        BA_TRY(tmp.alloc(&eb, E));
+        BA_TRY(tmp.alloc(&head, E));
+        BA_TRY(tmp.alloc(&d_total, 1));
+        BA_TRY(tmp.alloc(&ws, (int64_t)ws_bytes));
+        BA_HIP(hipMemcpy(d_poff, poff.data(), sizeof(int64_t) * poff.size(), hipMemcpyHostToDevice));
+        hipLaunchKernelGGL(k_pair_emit, dim3(nblk(D->n_vx)), dim3(256), 0, s, D->n_vx, D->vptr, d_poff, P->c_scan,
+                           bits_b, keys, vals, ea, eb);
+        BA_HIP(radix_sort_pairs(keys, vals, E, 2 * bits_b, ws, s));
+        // the precision form keeps h in the order of its derivative pass's
+        // cluster copy: the pair lists then index that order
+        if (P->prec == BA_PREC_F32) {
+            BA_TRY(tmp.alloc(&qc, C));
+            hipLaunchKernelGGL(k_inv_perm, dim3(nblk(C)), dim3(256), 0, s, C, P->p_cidx, qc);
+        }
+        hipLaunchKernelGGL(k_pair_out, dim3(nblk(E)), dim3(256), 0, s, E, keys, vals, ea, eb, qc, D->pa, D->pb,
+                           head);
+        BA_HIP(exclusive_scan_i64(head, head, E, d_total, ws, s));
+        int64_t n_seg = 0;
+        BA_HIP(hipMemcpy(&n_seg, d_total, sizeof(int64_t), hipMemcpyDeviceToHost));
+        D->n_seg = (int32_t)n_seg;
+        BA_TRY(D->mem.alloc(&D->segs, std::max<int64_t>(n_seg, 1)));
+        hipLaunchKernelGGL(k_seg_emit, dim3(nblk(E)), dim3(256), 0, s, E, keys, head, bits_b, D->segs);
+        hipLaunchKernelGGL(k_seg_count, dim3(nblk(n_seg)), dim3(256), 0, s, n_seg, E, D->segs);
+        BA_HIP(hipStreamSynchronize(s));   // before the temporaries go
+    } else {
+        BA_TRY(D->mem.alloc(&D->segs, 1));
     }
     // per-window dense matrices
     std::vector<DenseDesc> desc(W);

@@ -96,6 +96,7 @@ static int64_t footprint_bytes(int64_t C, int64_t V, int64_t N, int32_t mode, in
     if (mode == BA_MODE_COUPLED) {
         const double n6 = 6.0 * (double)N;
         b += 8.0 * C * 10.0 + 48.0 * C;             // pose-pair lists (<= 10 pairs per cluster here) and h vectors
+        b += 40.0 * C * 10.0;                       // the pair plan's sort keys, values and workspace (build time)
         b += 3.0 * n6 * n6 * 8.0;                   // the dense matrix and the factorization buffers
     }
     return (int64_t)(1.25 * b) + (16LL << 20);
