@@ -398,20 +398,32 @@ static ba_status make_plan(Problem *P, const std::vector<int32_t> &cvox, const s
         max_m = std::max(max_m, m[v]);
     }
     P->max_m = max_m;
-    // voxel order: (window, m, first observing scan, voxel id)
+    // voxel order: (window, m, first observing scan, voxel id), by three
+    // stable counting passes (first scan, then m, then window)
     std::vector<int32_t> vorder(V);
-    std::iota(vorder.begin(), vorder.end(), 0);
-    std::stable_sort(vorder.begin(), vorder.end(), [&](int32_t a, int32_t b) {
-        if (win[a] != win[b]) return win[a] < win[b];
-        if (m[a] != m[b]) return m[a] < m[b];
-        return minpose[a] < minpose[b];
-    });
-    // wave groups
+    {
+        std::vector<int32_t> other(V);
+        std::iota(other.begin(), other.end(), 0);
+        auto pass = [&](const std::vector<int32_t> &key, int32_t nkeys, const std::vector<int32_t> &in,
+                        std::vector<int32_t> &out) {
+            std::vector<int32_t> cnt((size_t)nkeys + 1, 0);
+            for (int32_t i = 0; i < V; i++) cnt[key[in[i]] + 1]++;
+            for (int32_t k = 0; k < nkeys; k++) cnt[k + 1] += cnt[k];
+            for (int32_t i = 0; i < V; i++) out[cnt[key[in[i]]]++] = in[i];
+        };
+        pass(minpose, N, other, vorder);
+        pass(m, max_m + 1, vorder, other);
+        pass(win, W, other, vorder);
+    }
+    // wave groups: runs of up to 64 voxels of one window and one m in that
+    // order; the group and lane of every voxel, then the clusters' places in
+    // one pass over the clusters
     std::vector<GroupDesc> groups;
     std::vector<int32_t> win_group_ptr(W + 1, 0);
     std::vector<int64_t> dst(C);
     std::vector<int32_t> slot_of(C);
     std::vector<int32_t> slot_vox;
+    std::vector<int32_t> gv(V), lv(V);
     int64_t cbase = 0;
     for (int32_t i = 0; i < V;) {
         int32_t j = i;
@@ -421,26 +433,33 @@ static ba_status make_plan(Problem *P, const std::vector<int32_t> &cvox, const s
         g.m = m[vorder[i]];
         g.nvox = j - i;
         g.window = win[vorder[i]];
+        g.scan0 = N;
+        g.nscan = 0;
         g.pad = 0;
-        int32_t gi = (int32_t)groups.size();
+        const int32_t gi = (int32_t)groups.size();
         for (int32_t l = 0; l < 64; l++) slot_vox.push_back(l < g.nvox ? cvox[vstart[vorder[i + l]]] : -1);
-        int32_t s0 = N, s1 = -1;
         for (int32_t l = 0; l < g.nvox; l++) {
-            int32_t v = vorder[i + l];
-            for (int32_t k = 0; k < g.m; k++) {
-                int64_t c = vstart[v] + k;
-                dst[c] = cbase + 64LL * k + l;
-                slot_of[c] = gi * 64 + l;
-                s0 = std::min(s0, cscan[c]);
-                s1 = std::max(s1, cscan[c]);
-            }
+            gv[vorder[i + l]] = gi;
+            lv[vorder[i + l]] = l;
         }
-        g.scan0 = s0;
-        g.nscan = s1 - s0 + 1;
         groups.push_back(g);
         win_group_ptr[g.window + 1] = (int32_t)groups.size();
         cbase += 64LL * g.m;
         i = j;
+    }
+    {
+        std::vector<int32_t> s1(groups.size(), -1);
+        for (int32_t v = 0; v < V; v++) {
+            GroupDesc &g = groups[gv[v]];
+            const int32_t l = lv[v];
+            for (int64_t c = vstart[v], k = 0; c < vstart[v + 1]; c++, k++) {
+                dst[c] = g.cbase + 64LL * k + l;
+                slot_of[c] = gv[v] * 64 + l;
+                g.scan0 = std::min(g.scan0, cscan[c]);
+                s1[gv[v]] = std::max(s1[gv[v]], cscan[c]);
+            }
+        }
+        for (size_t gi = 0; gi < groups.size(); gi++) groups[gi].nscan = s1[gi] - groups[gi].scan0 + 1;
     }
     for (int32_t w = 0; w < W; w++) win_group_ptr[w + 1] = std::max(win_group_ptr[w + 1], win_group_ptr[w]);
     P->n_groups = (int32_t)groups.size();
