@@ -259,6 +259,16 @@ __device__ __forceinline__ double vox_finish(const VoxSums &a, double *__restric
     return lam0;
 }
 
+// Stores the records of a group's nvox voxels (64 bytes each, contiguous in
+// LDS at R) to their slots: every store instruction of the block covers whole
+// consecutive lines, where each lane storing its own record would touch 64
+// lines with 16 bytes each.
+__device__ __forceinline__ void store_records(const double *R, double *__restrict__ dst, int nvox) {
+    const double2 *src = reinterpret_cast<const double2 *>(R);
+    double2 *d = reinterpret_cast<double2 *>(dst);
+    for (int p = threadIdx.x; p < 4 * nvox; p += blockDim.x) d[p] = src[p];
+}
+
 template <class Src, int SPLIT>
 __device__ __forceinline__ void vox_item(int bi, const VoxBlock *__restrict__ blocks,
                                          const GroupDesc *__restrict__ groups, int64_t c_pad, const Src &src,
@@ -297,6 +307,7 @@ __device__ __forceinline__ void vox_item(int bi, const VoxBlock *__restrict__ bl
     if (SPLIT > 1) __syncthreads();
     if (w == 0) {
         double lam0 = 0.0;
+        double rec[VSTATE];
         if (active) {
             for (int v = 0; v < SPLIT - 1; v++) {
                 const double *pp = &part[v][0][0];
@@ -305,11 +316,17 @@ __device__ __forceinline__ void vox_item(int bi, const VoxBlock *__restrict__ bl
 #pragma unroll
                 for (int q = 0; q < 6; q++) a.M[q] += pp[(4 + q) * 64 + lane];
             }
-            lam0 = vox_finish(a, vs + ((int64_t)gi * 64 + lane) * VSTATE);
+            lam0 = vox_finish(a, rec);
+            // the group's records through LDS (part[0], read above by this wave only)
+            double *R = &part[0][0][0];
+#pragma unroll
+            for (int k = 0; k < VSTATE; k++) R[lane * VSTATE + k] = rec[k];
         }
         const double c = wave_sum(lam0);
         if (lane == 0) group_cost[gi] = c;
     }
+    __syncthreads();
+    store_records(&part[0][0][0], vs + (int64_t)gi * 64 * VSTATE, g.nvox);
 }
 
 // Residual pass.  One work item per group of 64 voxels with equal cluster
@@ -387,8 +404,8 @@ __global__ __launch_bounds__(256) void k_vox_mixed(const VoxBlock *__restrict__ 
         }
         __syncthreads();
         if (pt == 0 && run) {
-            double *vs = vstate + (int64_t)buf * n_slots * VSTATE;
             double lam0 = 0.0;
+            double rec[VSTATE];
             if (active) {
                 for (int v = 1; v < sp; v++) {
                     const double *pp = &part[w + v][0][0];
@@ -397,10 +414,21 @@ __global__ __launch_bounds__(256) void k_vox_mixed(const VoxBlock *__restrict__ 
 #pragma unroll
                     for (int q = 0; q < 6; q++) a.M[q] += pp[(4 + q) * 64 + lane];
                 }
-                lam0 = vox_finish(a, vs + ((int64_t)gi * 64 + lane) * VSTATE);
+                lam0 = vox_finish(a, rec);
+                // the group's records through this wave's own (unused) part[w]
+                double *R = &part[w][0][0];
+#pragma unroll
+                for (int k = 0; k < VSTATE; k++) R[lane * VSTATE + k] = rec[k];
             }
             const double c = wave_sum(lam0);
             if (lane == 0) group_cost[gi] = c;
+        }
+        __syncthreads();
+        if (pt == 0 && run) {
+            // the finishing wave stores its group's records as whole lines
+            const double2 *src2 = reinterpret_cast<const double2 *>(&part[w][0][0]);
+            double2 *d = reinterpret_cast<double2 *>(vstate + ((int64_t)buf * n_slots + (int64_t)gi * 64) * VSTATE);
+            for (int p = lane; p < 4 * g.nvox; p += 64) d[p] = src2[p];
         }
         if (PERSIST) __syncthreads();   // part[] is reused by the next item
     }
