@@ -89,7 +89,7 @@ typedef struct ba_cluster_sums {
 } ba_cluster_sums;
 
 typedef struct ba_build_options {
-    int32_t chunk_len;          /* clusters per pose chunk of the derivative pass: 0 = default (256), else 32..2^20 */
+    int32_t chunk_len;          /* clusters per pose chunk of the derivative pass: 0 = default (256), else 32..1024 */
     int32_t n_windows;          /* 0 or 1 = one problem; > 1 = independent windows (batched form) */
     const int32_t *scan_window; /* host, n_scans entries, non-decreasing window id per scan; NULL if n_windows <= 1 */
     int32_t precision;          /* BA_PREC_F64 (default) or BA_PREC_F32 */
@@ -155,7 +155,7 @@ typedef struct ba_tuning {
                          * group by its clusters per voxel (1 up to 4, 2 up to 8, 4 beyond) */
     int32_t vox_grid;   /* residual pass: 0 = one block per group; 1..64 = persistent grid of that many blocks per CU */
     int32_t pose_grid;  /* derivative pass: 0 = one wavefront per chunk; 1..64 = persistent, blocks of 4 waves per CU */
-    int32_t chunk_len;  /* clusters per derivative-pass chunk, 32..2^20 */
+    int32_t chunk_len;  /* clusters per derivative-pass chunk, 32..1024 */
 } ba_tuning;
 
 /* ---------------------------------------------------------------------- */

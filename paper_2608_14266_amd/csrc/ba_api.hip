@@ -535,7 +535,7 @@ namespace ba {
 static ba_status check_tuning(const ba_tuning *t) {
     if (!(t->vox_split == 0 || t->vox_split == 1 || t->vox_split == 2 || t->vox_split == 4) || t->vox_grid < 0 ||
         t->vox_grid > 64 ||
-        t->pose_grid < 0 || t->pose_grid > 64 || t->chunk_len < MIN_CHUNK || t->chunk_len > (1 << 20)) {
+        t->pose_grid < 0 || t->pose_grid > 64 || t->chunk_len < MIN_CHUNK || t->chunk_len > MAX_CHUNK) {
         set_error("tuning out of range (vox_split %d, vox_grid %d, pose_grid %d, chunk_len %d)", t->vox_split,
                   t->vox_grid, t->pose_grid, t->chunk_len);
         return BA_E_ARG;

@@ -336,8 +336,8 @@ static int bit_length(uint64_t v) {
 // Cuts every pose's range of the pose-major layout into chunks of at most
 // chunk_len clusters and uploads the chunk tables (synchronous).
 ba_status replan_chunks(Problem *P, int32_t chunk_len, hipStream_t s) {
-    if (chunk_len < MIN_CHUNK || chunk_len > (1 << 20)) {
-        set_error("chunk_len %d out of range [%d, 2^20]", chunk_len, MIN_CHUNK);
+    if (chunk_len < MIN_CHUNK || chunk_len > MAX_CHUNK) {
+        set_error("chunk_len %d out of range [%d, %d]", chunk_len, MIN_CHUNK, MAX_CHUNK);
         return BA_E_ARG;
     }
     const int32_t N = P->n_poses;

@@ -436,11 +436,12 @@ __global__ __launch_bounds__(256) void k_vox_mixed(const VoxBlock *__restrict__ 
 
 // Per-cluster surrogate gradient and Hessian terms (formulas in the header of
 // this file) in arithmetic T from y = R mu (lever arm), e = u^T (m - mbar)
-// (FP64), St and u, added into the FP64 accumulators with the voxel scale
-// sc = 2 / N_i.
-template <typename T>
+// (FP64), St and u, with the voxel scale sc = 2 / N_i: the gradient terms
+// added into FP64 accumulators (acc), the 21 Hessian terms into accumulators
+// of type H (hacc).
+template <typename T, typename H>
 __device__ __forceinline__ void pose_terms(T n, const T *y, double e64, const T *St, const T *u, double sc,
-                                           double *acc, bool grad = true) {
+                                           double *acc, H *hacc, bool grad = true) {
     const T e = (T)e64;
     T su[3];
     sym_mv(St, u, su);
@@ -459,21 +460,17 @@ __device__ __forceinline__ void pose_terms(T n, const T *y, double e64, const T 
         acc[4] = fma(sne, (double)u[1], acc[4]);
         acc[5] = fma(sne, (double)u[2], acc[5]);
     }
-    // [u]x St [u]x^T : B = [u]x St, C = B [u]x^T
-    const T Sf[3][3] = {{St[0], St[1], St[2]}, {St[1], St[3], St[4]}, {St[2], St[4], St[5]}};
-    const T K[3][3] = {{T(0), -u[2], u[1]}, {u[2], T(0), -u[0]}, {-u[1], u[0], T(0)}};
-    T B[3][3];
-#pragma unroll
-    for (int r = 0; r < 3; r++)
-#pragma unroll
-        for (int c = 0; c < 3; c++) B[r][c] = K[r][0] * Sf[0][c] + K[r][1] * Sf[1][c] + K[r][2] * Sf[2][c];
+    // [u]x St [u]x^T for symmetric St, expanded: with u = (a, b, c) each entry
+    // is a combination of the six products of u's components
+    const T ua = u[0], ub = u[1], uc = u[2];
+    const T aa = ua * ua, bb = ub * ub, cc = uc * uc, ab = ua * ub, ac = ua * uc, bc = ub * uc;
     T Cu[6];
-    Cu[0] = B[0][0] * K[0][0] + B[0][1] * K[0][1] + B[0][2] * K[0][2];
-    Cu[1] = B[0][0] * K[1][0] + B[0][1] * K[1][1] + B[0][2] * K[1][2];
-    Cu[2] = B[0][0] * K[2][0] + B[0][1] * K[2][1] + B[0][2] * K[2][2];
-    Cu[3] = B[1][0] * K[1][0] + B[1][1] * K[1][1] + B[1][2] * K[1][2];
-    Cu[4] = B[1][0] * K[2][0] + B[1][1] * K[2][1] + B[1][2] * K[2][2];
-    Cu[5] = B[2][0] * K[2][0] + B[2][1] * K[2][1] + B[2][2] * K[2][2];
+    Cu[0] = cc * St[3] - T(2) * bc * St[4] + bb * St[5];
+    Cu[1] = bc * St[2] - cc * St[1] + ac * St[4] - ab * St[5];
+    Cu[2] = bc * St[1] - bb * St[2] - ac * St[3] + ab * St[4];
+    Cu[3] = aa * St[5] - T(2) * ac * St[2] + cc * St[0];
+    Cu[4] = ab * St[2] - bc * St[0] + ac * St[1] - aa * St[4];
+    Cu[5] = bb * St[0] - T(2) * ab * St[1] + aa * St[3];
     const T uw = dot(u, w);
     const int ii[6] = {0, 0, 0, 1, 1, 2}, jj[6] = {0, 1, 2, 1, 2, 2};
 #pragma unroll
@@ -481,16 +478,15 @@ __device__ __forceinline__ void pose_terms(T n, const T *y, double e64, const T 
         const int r = ii[k], c = jj[k];
         T h = n * a[r] * a[c] + Cu[k] + T(0.5) * (u[r] * w[c] + w[r] * u[c]);
         if (r == c) h -= uw;
-        acc[6 + k] = fma(sc, (double)h, acc[6 + k]);
+        hacc[k] = fmaT((H)sc, (H)h, hacc[k]);
     }
-    const double sn = sc * (double)n;
+    const H sn = (H)(sc * (double)n);
 #pragma unroll
     for (int r = 0; r < 3; r++)
 #pragma unroll
-        for (int c = 0; c < 3; c++)
-            acc[12 + 3 * r + c] = fma(sn * (double)a[r], (double)u[c], acc[12 + 3 * r + c]);
+        for (int c = 0; c < 3; c++) hacc[6 + 3 * r + c] = fmaT(sn * (H)a[r], (H)u[c], hacc[6 + 3 * r + c]);
 #pragma unroll
-    for (int k = 0; k < 6; k++) acc[21 + k] = fma(sn * (double)u[ii[k]], (double)u[jj[k]], acc[21 + k]);
+    for (int k = 0; k < 6; k++) hacc[15 + k] = fmaT(sn * (H)u[ii[k]], (H)u[jj[k]], hacc[15 + k]);
 }
 
 // Pose context of a chunk: the pose, and for the FP32 form its reference
@@ -513,7 +509,7 @@ __device__ __forceinline__ void pose_cluster(const SrcF64 &src, const PoseCtx &c
     rot(cx.P.r, mu, y);
     rot_sym(cx.P.r, S, St);
     const double d[3] = {y[0] + cx.P.t[0] - st[3], y[1] + cx.P.t[1] - st[4], y[2] + cx.P.t[2] - st[5]};
-    pose_terms(n, y, dot(u, d), St, u, st[6], acc);
+    pose_terms(n, y, dot(u, d), St, u, st[6], acc, acc + 6);
 }
 
 // FP32 form: with q = c - t0 and G = I + E the pose change,
@@ -522,7 +518,7 @@ __device__ __forceinline__ void pose_cluster(const SrcF64 &src, const PoseCtx &c
 // cluster; D(E, S') and the Hessian terms in FP32 (FP64 in the coupled form).
 template <bool HESS64>
 __device__ __forceinline__ void pose_cluster(const SrcF32 &src, const PoseCtx &cx, int64_t q, int64_t C,
-                                             const double *st, int32_t slot, double *acc) {
+                                             const double *st, int32_t slot, double *acc, float *hacc) {
     const float n = src.N[q];
     const double mu[3] = {(double)src.mu[q], (double)src.mu[C + q], (double)src.mu[2 * C + q]};
     float S[6];
@@ -559,7 +555,7 @@ __device__ __forceinline__ void pose_cluster(const SrcF32 &src, const PoseCtx &c
         delta_sym(cx.D.E, Sd, Dl64);
 #pragma unroll
         for (int k = 0; k < 6; k++) S64[k] = Sd[k] + Dl64[k];
-        pose_terms((double)n, y64, e, S64, u64, st[6], acc);
+        pose_terms((double)n, y64, e, S64, u64, st[6], acc, acc + 6);
         return;
     }
     // St = S' + D(E, S') with D in FP32 (of the size of the pose change)
@@ -569,7 +565,8 @@ __device__ __forceinline__ void pose_cluster(const SrcF32 &src, const PoseCtx &c
     // so their rounding sets the accuracy of the result; the Hessian terms
     // (most of the arithmetic) only steer the steps and stay FP32, except for
     // the coupled form (HESS64), whose dense Newton-like step amplifies their
-    // rounding along the nearly singular gauge directions
+    // rounding along the nearly singular gauge directions; they are summed
+    // per lane in FP32 (at most 16 terms between FP64 additions)
     {
         double S64[6], su[3];
 #pragma unroll
@@ -593,7 +590,7 @@ __device__ __forceinline__ void pose_cluster(const SrcF32 &src, const PoseCtx &c
     float St[6];
 #pragma unroll
     for (int k = 0; k < 6; k++) St[k] = S[k] + Dl[k];
-    pose_terms(n, y, e, St, u, st[6], acc, false);
+    pose_terms(n, y, e, St, u, st[6], acc, hacc, false);
 }
 
 // Block b of a launch runs on XCD b mod 8.  Renumbering the blocks so that
@@ -640,14 +637,24 @@ __global__ __launch_bounds__(256) void k_pose(const ChunkDesc *__restrict__ chun
         double acc[NPART];
 #pragma unroll
         for (int q = 0; q < NPART; q++) acc[q] = 0.0;
+        // precision form: the FP32 Hessian terms summed per lane in FP32 (a
+        // chunk holds at most MAX_CHUNK clusters: 16 terms per lane), then
+        // converted once for the FP64 reduction
+        float hacc[NPART - 6];
+#pragma unroll
+        for (int q = 0; q < NPART - 6; q++) hacc[q] = 0.0f;
 #pragma unroll 1
         for (int i = lane; i < ch.count; i += 64) {
             const int64_t q = ch.start + i;
             const int32_t slot = pslot[q];
             if constexpr (sizeof(*src.N) == 4)
-                pose_cluster<HESS64>(src, cx, q, C, vs + (int64_t)slot * VSTATE, slot, acc);
+                pose_cluster<HESS64>(src, cx, q, C, vs + (int64_t)slot * VSTATE, slot, acc, hacc);
             else
                 pose_cluster(src, cx, q, C, vs + (int64_t)slot * VSTATE, slot, acc);
+        }
+        if constexpr (sizeof(*src.N) == 4 && !HESS64) {
+#pragma unroll
+            for (int q = 0; q < NPART - 6; q++) acc[6 + q] = (double)hacc[q];
         }
         // reduce-scatter over the wave: lane l ends with the sum of value l / 2
         double red[32];

@@ -79,6 +79,7 @@ struct Tuning {
 };
 
 static constexpr int32_t MIN_CHUNK = 32;   // smallest chunk length the chunk tables are sized for
+static constexpr int32_t MAX_CHUNK = 1024; // longest chunk (the FP32 Hessian sums of a lane hold at most 16 terms)
 
 struct Problem {
     int device = 0;

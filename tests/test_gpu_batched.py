@@ -252,7 +252,7 @@ def test_autotune_applies_a_valid_choice(ba, dev, batch, tmp_path):
 
 def test_bad_tuning_is_rejected(ba, dev, batch):
     pb = build_gpu_sums(ba, batch, dev)
-    for bad in (dict(vox_split=3), dict(vox_grid=-1), dict(pose_grid=65), dict(chunk_len=16)):
+    for bad in (dict(vox_split=3), dict(vox_grid=-1), dict(pose_grid=65), dict(chunk_len=16), dict(chunk_len=2048)):
         with pytest.raises(ba.BAError) as e:
             ba.problem_set_tuning(pb, bad)
         assert e.value.status == -1
