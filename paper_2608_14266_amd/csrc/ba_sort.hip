@@ -1,10 +1,10 @@
 // Device-wide primitives for the one-time problem build (paper Sec. IV-A,
 // "Standard Primitives": sort_by_key, exclusive_scan, scatter):
 //   * exclusive prefix scan of int64 (reduce-then-scan, three launches);
-//   * stable LSD radix sort of (uint64 key, uint32 value) pairs with 4-bit
+//   * stable LSD radix sort of (uint64 key, uint32 value) pairs with 8-bit
 //     digits: per-tile digit histograms, a scan of the (digit, tile) counts
-//     and a stable scatter whose within-tile ranks come from a 2-D scan over
-//     (digit, thread) in LDS, so equal keys keep their input order.
+//     and a stable scatter whose within-tile ranks come from wave ballots
+//     and per-wave digit counts, so equal keys keep their input order.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -128,35 +128,53 @@ hipError_t exclusive_scan_i64(const int64_t *in, int64_t *out, int64_t n, int64_
 
 // ---------------------------------------------------------------- radix sort
 static constexpr int RS_THREADS = 256;
+static constexpr int RS_WAVES = RS_THREADS / 64;
 static constexpr int RS_IPT = 16;
 static constexpr int RS_TILE = RS_THREADS * RS_IPT;
-static constexpr int RS_BINS = 16;
+static constexpr int RS_BITS = 8;                 // bits per pass
+static constexpr int RS_BINS = 1 << RS_BITS;      // one digit per thread of a block
+static_assert(RS_BINS == RS_THREADS, "a block handles one digit per thread");
 
 __device__ __forceinline__ int digit_of(uint64_t k, int shift) { return (int)((k >> shift) & (RS_BINS - 1)); }
 
+// Lanes of the wave holding the same digit d (d == RS_BINS marks an empty
+// slot): a ballot per bit of d, RS_BITS + 1 bits.
+__device__ __forceinline__ uint64_t same_digit_lanes(int d) {
+    uint64_t same = ~0ull;
+#pragma unroll
+    for (int b = 0; b <= RS_BITS; b++) {
+        const bool bit = (d >> b) & 1;
+        const uint64_t bal = __ballot(bit);
+        same &= bit ? bal : ~bal;
+    }
+    return same;
+}
+
 // Tiles of RS_TILE keys; thread t of a block handles the items
-// tile + 256 k + t (k = 0..15), so every load and store row is coalesced.
+// tile + 256 k + t (k = 0..15), so every load row is coalesced.  Per row, the
+// first lane of each digit group adds the group's size to its wave's count of
+// that digit (no two lanes of a wave add to one count).
 __global__ __launch_bounds__(RS_THREADS) void k_radix_hist(const uint64_t *__restrict__ keys, int64_t n, int shift,
                                                            int64_t *__restrict__ hist, int64_t nblocks) {
-    __shared__ uint32_t cnt[RS_BINS][RS_THREADS];
-    const int t = threadIdx.x;
+    __shared__ uint32_t cnt[RS_WAVES][RS_BINS];
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
 #pragma unroll
-    for (int d = 0; d < RS_BINS; d++) cnt[d][t] = 0;
+    for (int v = 0; v < RS_WAVES; v++) cnt[v][t] = 0;
+    __syncthreads();
     const int64_t base = (int64_t)blockIdx.x * RS_TILE + t;
 #pragma unroll 4
     for (int k = 0; k < RS_IPT; k++) {
         const int64_t i = base + (int64_t)k * RS_THREADS;
-        if (i < n) cnt[digit_of(keys[i], shift)][t]++;
+        const int d = i < n ? digit_of(keys[i], shift) : RS_BINS;
+        const uint64_t same = same_digit_lanes(d);
+        if (d < RS_BINS && (same & lt_mask) == 0) cnt[w][d] += (uint32_t)__popcll(same);
     }
     __syncthreads();
-    // 16 bins x 256 threads: wave w sums bins 4w..4w+3
-    const int lane = t & 63, w = t >> 6;
-    for (int d = 4 * w; d < 4 * w + 4; d++) {
-        uint32_t s = cnt[d][lane] + cnt[d][lane + 64] + cnt[d][lane + 128] + cnt[d][lane + 192];
+    uint32_t s = 0;
 #pragma unroll
-        for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
-        if (lane == 0) hist[(int64_t)d * nblocks + blockIdx.x] = s;
-    }
+    for (int v = 0; v < RS_WAVES; v++) s += cnt[v][t];
+    hist[(int64_t)t * nblocks + blockIdx.x] = s;
 }
 
 // Stable scatter of one tile: every item gets its rank among the tile's
@@ -171,9 +189,10 @@ __global__ __launch_bounds__(RS_THREADS) void k_radix_scatter(const uint64_t *__
                                                               uint32_t *__restrict__ vals_out) {
     __shared__ uint64_t sk[RS_TILE];
     __shared__ uint32_t sv[RS_TILE];
-    __shared__ uint32_t wcnt[RS_THREADS / 64][RS_BINS];
+    __shared__ uint32_t wcnt[RS_WAVES][RS_BINS];
     __shared__ uint32_t run[RS_BINS];
     __shared__ uint32_t dstart[RS_BINS];
+    __shared__ uint32_t wsum[RS_WAVES];
     __shared__ int64_t gbase[RS_BINS];
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
     const int64_t tile0 = (int64_t)blockIdx.x * RS_TILE;
@@ -192,22 +211,15 @@ __global__ __launch_bounds__(RS_THREADS) void k_radix_scatter(const uint64_t *__
         dg[k] = ok ? digit_of(key[k], shift) : RS_BINS;   // RS_BINS marks an empty slot
         rank[k] = 0;
     }
-    if (t < RS_BINS) {
-        run[t] = 0;
-        gbase[t] = gofs[(int64_t)t * nblocks + blockIdx.x];
-    }
+    run[t] = 0;
+    gbase[t] = gofs[(int64_t)t * nblocks + blockIdx.x];
 #pragma unroll
     for (int k = 0; k < RS_IPT; k++) {
-        if (t < (RS_THREADS / 64) * RS_BINS) wcnt[t / RS_BINS][t % RS_BINS] = 0;
+#pragma unroll
+        for (int v = 0; v < RS_WAVES; v++) wcnt[v][t] = 0;
         __syncthreads();
         const int d = dg[k];
-        uint64_t same = ~0ull;
-#pragma unroll
-        for (int b = 0; b < 5; b++) {
-            const bool bit = (d >> b) & 1;
-            const uint64_t bal = __ballot(bit);
-            same &= bit ? bal : ~bal;
-        }
+        const uint64_t same = same_digit_lanes(d);
         const uint32_t rw = (uint32_t)__popcll(same & lt_mask);
         if (rw == 0 && d < RS_BINS) wcnt[w][d] = (uint32_t)__popcll(same);
         __syncthreads();
@@ -217,15 +229,26 @@ __global__ __launch_bounds__(RS_THREADS) void k_radix_scatter(const uint64_t *__
             rank[k] = off + rw;
         }
         __syncthreads();
-        if (t < RS_BINS) run[t] += wcnt[0][t] + wcnt[1][t] + wcnt[2][t] + wcnt[3][t];
+        uint32_t add = 0;
+#pragma unroll
+        for (int v = 0; v < RS_WAVES; v++) add += wcnt[v][t];
+        run[t] += add;
     }
     __syncthreads();
-    if (t == 0) {
-        uint32_t a = 0;
-        for (int d = 0; d < RS_BINS; d++) {
-            dstart[d] = a;
-            a += run[d];
+    // dstart = exclusive scan of run over the digits (thread t holds digit t)
+    {
+        const uint32_t r = run[t];
+        uint32_t inc = r;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const uint32_t y = __shfl_up(inc, o, 64);
+            if (lane >= o) inc += y;
         }
+        if (lane == 63) wsum[w] = inc;
+        __syncthreads();
+        uint32_t before = 0;
+        for (int v = 0; v < w; v++) before += wsum[v];
+        dstart[t] = before + inc - r;
     }
     __syncthreads();
 #pragma unroll
@@ -274,9 +297,9 @@ hipError_t radix_sort_pairs(uint64_t *keys, uint32_t *vals, int64_t n, int bits,
     uint32_t *v2 = (uint32_t *)(p + align_up((size_t)n * sizeof(uint64_t), 8));
     uint64_t *ka = keys, *kb = k2;
     uint32_t *va = vals, *vb = v2;
-    int passes = (bits + 3) / 4;
+    const int passes = (bits + RS_BITS - 1) / RS_BITS;
     for (int pass = 0; pass < passes; pass++) {
-        int shift = 4 * pass;
+        const int shift = RS_BITS * pass;
         hipLaunchKernelGGL(k_radix_hist, dim3((unsigned)nb), dim3(RS_THREADS), 0, s, ka, n, shift, hist, nb);
         hipError_t e = exclusive_scan_i64(hist, hist, nb * RS_BINS, nullptr, scan_ws, s);
         if (e != hipSuccess) return e;
