@@ -11,7 +11,7 @@
 //   k_vx_keys_points  packed (cell offsets, scan) key per point
 //   k_vx_keys_up      packed key of the parent cell per cluster
 //   (stable LSD radix sort of the keys, head flags, exclusive scan)
-//   k_vx_sum_points   thread per level-1 cluster: raw sums of its points
+//   k_vx_sum_points   8 lanes per level-1 cluster: raw sums of its points
 //   k_vx_sum_clusters thread per level-k cluster: sums of its child clusters
 //   k_vx_select       thread per cell: voxel covariance, eigenvalues, decision
 //   k_vx_emit         thread per kept cell: its clusters into the output
@@ -209,28 +209,45 @@ __global__ void k_vx_starts(int64_t n, const uint64_t *__restrict__ keys, int sh
     if (i == 0) starts[n_seg] = n;
 }
 
-// raw sums of one level-1 cluster, its points taken in sorted (stable) order
+// raw sums of one level-1 cluster: VX_SUM_LANES lanes per cluster, lane g
+// summing the points g, g + VX_SUM_LANES, ... of the cluster's sorted
+// (stable) run, then the group adding its lanes' sums in a fixed tree
+static constexpr int VX_SUM_LANES = 8;
 __global__ void k_vx_sum_points(int64_t C, const int64_t *__restrict__ starts, const uint64_t *__restrict__ keys,
                                 const uint32_t *__restrict__ idx, const double *__restrict__ x,
                                 const double *__restrict__ y, const double *__restrict__ z,
                                 uint64_t *__restrict__ ckey, int64_t *__restrict__ count, double *__restrict__ s1,
                                 double *__restrict__ s2) {
-    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= C) return;
-    const int64_t a = starts[c], b = starts[c + 1];
+    const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t c = tid / VX_SUM_LANES;
+    const int g = (int)(tid % VX_SUM_LANES);
     double m[3] = {0, 0, 0}, q[6] = {0, 0, 0, 0, 0, 0};
-    for (int64_t k = a; k < b; k++) {
-        const uint32_t i = idx[k];
-        const double p[3] = {x[i], y[i], z[i]};
+    int64_t a = 0, b = 0;
+    if (c < C) {
+        a = starts[c];
+        b = starts[c + 1];
+        for (int64_t k = a + g; k < b; k += VX_SUM_LANES) {
+            const uint32_t i = idx[k];
+            const double p[3] = {x[i], y[i], z[i]};
 #pragma unroll
-        for (int r = 0; r < 3; r++) m[r] += p[r];
-        q[0] = fma(p[0], p[0], q[0]);
-        q[1] = fma(p[0], p[1], q[1]);
-        q[2] = fma(p[0], p[2], q[2]);
-        q[3] = fma(p[1], p[1], q[3]);
-        q[4] = fma(p[1], p[2], q[4]);
-        q[5] = fma(p[2], p[2], q[5]);
+            for (int r = 0; r < 3; r++) m[r] += p[r];
+            q[0] = fma(p[0], p[0], q[0]);
+            q[1] = fma(p[0], p[1], q[1]);
+            q[2] = fma(p[0], p[2], q[2]);
+            q[3] = fma(p[1], p[1], q[3]);
+            q[4] = fma(p[1], p[2], q[4]);
+            q[5] = fma(p[2], p[2], q[5]);
+        }
     }
+    // every lane takes part in the shuffles (groups are aligned within a wave)
+#pragma unroll
+    for (int o = VX_SUM_LANES / 2; o > 0; o >>= 1) {
+#pragma unroll
+        for (int r = 0; r < 3; r++) m[r] += __shfl_xor(m[r], o, VX_SUM_LANES);
+#pragma unroll
+        for (int r = 0; r < 6; r++) q[r] += __shfl_xor(q[r], o, VX_SUM_LANES);
+    }
+    if (c >= C || g != 0) return;
     ckey[c] = keys[a];
     count[c] = b - a;
 #pragma unroll
@@ -502,7 +519,7 @@ static ba_status vx_form_level(DevArena &tmp, VxWork &w, int64_t m, const double
     BA_TRY(tmp.alloc(&cur.s1, 3 * cur.C));
     BA_TRY(tmp.alloc(&cur.s2, 6 * cur.C));
     if (x)
-        hipLaunchKernelGGL(k_vx_sum_points, dim3(vx_nblk(cur.C)), dim3(VX_THREADS), 0, s, cur.C, starts, w.keys, w.vals,
+        hipLaunchKernelGGL(k_vx_sum_points, dim3(vx_nblk(cur.C * VX_SUM_LANES)), dim3(VX_THREADS), 0, s, cur.C, starts, w.keys, w.vals,
                            x, y, z, cur.ckey, cur.count, cur.s1, cur.s2);
     else
         hipLaunchKernelGGL(k_vx_sum_clusters, dim3(vx_nblk(cur.C)), dim3(VX_THREADS), 0, s, cur.C, starts, w.keys,
