@@ -302,7 +302,7 @@ def _cpu_baseline_batch(sc, iters, sample_every):
         cn = list(ex.map(run, prep))
     tn = time.perf_counter() - t0
     assert cn == c1, "oracle results differ between the serial and the threaded run"
-    sample = (f"{len(windows)} of {sc.n_windows} windows (every {sample_every}th; {C} clusters, {V} voxels), "
+    sample = (f"{len(windows)} of {sc.n_windows} windows (one window in {sample_every}; {C} clusters, {V} voxels), "
               f"{iters} LM iterations each (MM, FP64); cluster centring untimed ({t_prep:.1f}s)")
     cpu = {"value": V * iters / t1, "unit": "plane-voxel evals/s", "cores": 1, "kind": "oracle", "sample": sample,
            "seconds": round(t1, 3), "cpu_model": _cpu_model(), "nproc": os.cpu_count()}
